@@ -1,0 +1,870 @@
+/*
+ * hdof_oracle.c -- plain FP64 CPU oracle of the hybrid depth-of-field hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only callers.  The GPU library never
+ * links, loads or calls this file and shares no code with it: the two sides
+ * are written independently from the same reading of the paper
+ * (Tan, Chua, Biette, Bhojan: "Hybrid DoF: Ray-Traced and Post-Processed
+ * Hybrid Depth of Field Effect for Real-Time Rendering", SIGGRAPH 2020 posters).
+ *
+ * Everything is double precision; inputs arrive as float32 values widened
+ * exactly by the caller.  Loops are the plainest form of each step; OpenMP
+ * only splits independent pixels or rays over host threads.
+ *
+ * Map of the paper to the functions here (section names of the paper):
+ *   Design (thin lens of Potmesil & Chakravarty, near/far by the focus plane)
+ *       or_coc, or_lens_ray
+ *   Design (G-buffer with a sharp rasterised image, deferred shading)
+ *       or_gbuffer, shade()
+ *   Ray Trace (adaptive ray mask: Gaussian, Sobel on normal and depth,
+ *   temporally accumulated luminance variance)
+ *       or_mask, or_var_reproject, or_var_update
+ *   Ray Trace (lens samples in a circle, near/far split by Z, hit ratio)
+ *       or_trace
+ *   Design (post-process filter) + Reconstruction (CoC-radius rejection)
+ *       or_postfilter
+ *   Composite (focus zone below sqrt(2), near rule, far hit-ratio blend)
+ *       or_composite
+ * Closest hits come from a median-split BVH over the triangles and carry an
+ * ambiguity flag: a ray is ambiguous when another correct implementation in
+ * a different precision could legitimately pick a different triangle.
+ *
+ * Parity unpinned: none of these functions is left without a pin; the only
+ * unpinned claim is whole-frame visual fidelity against the paper's images,
+ * which are not available.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_ZMAX 1.0e4
+#define OR_SQRT2 1.4142135623730951
+#define OR_PI 3.14159265358979323846
+#define OR_EPS 1.0e-5      /* ambiguity band: edges, ties, thresholds */
+#define OR_BOX_MARGIN 1.0e-3 /* absolute box growth so near misses are visited */
+#define OR_LEAF 4
+#define OR_MAX_CAND 96
+
+/* ------------------------------------------------------------------------- */
+/* small vector helpers                                                       */
+/* ------------------------------------------------------------------------- */
+static inline void v_sub(const double* a, const double* b, double* o) { o[0]=a[0]-b[0]; o[1]=a[1]-b[1]; o[2]=a[2]-b[2]; }
+static inline double v_dot(const double* a, const double* b) { return a[0]*b[0]+a[1]*b[1]+a[2]*b[2]; }
+static inline void v_cross(const double* a, const double* b, double* o) {
+  o[0] = a[1]*b[2] - a[2]*b[1];
+  o[1] = a[2]*b[0] - a[0]*b[2];
+  o[2] = a[0]*b[1] - a[1]*b[0];
+}
+static inline double v_len(const double* a) { return sqrt(v_dot(a, a)); }
+static inline double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+static inline double maxd(double a, double b) { return a > b ? a : b; }
+static inline double mind(double a, double b) { return a < b ? a : b; }
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Camera and thin lens                                                       */
+/* cam[13] = eye(3), right(3), up(3), fwd(3), tan_half_fov_x                  */
+/* lens[3] = focal length f, aperture diameter A, focus distance S1           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double e[3], r[3], u[3], w[3];
+  double tx, ty, spx;
+  int W, H;
+} cam_t;
+
+static cam_t mk_cam(const double* c, int W, int H) {
+  cam_t k;
+  for (int i = 0; i < 3; ++i) { k.e[i]=c[i]; k.r[i]=c[3+i]; k.u[i]=c[6+i]; k.w[i]=c[9+i]; }
+  k.tx = c[12];
+  k.ty = c[12] * (double)H / (double)W;     /* square pixels */
+  k.spx = (double)W / (2.0 * c[12]);         /* pixels per unit of tan-space */
+  k.W = W; k.H = H;
+  return k;
+}
+
+/* Direction through the centre of pixel (x, y) with unit forward component:
+ * v = w + sx r + sy u, image y pointing down, centres at +0.5. */
+static void pixel_dir(const cam_t* k, int x, int y, double* v) {
+  double sx = (2.0 * (x + 0.5) / k->W - 1.0) * k->tx;
+  double sy = (1.0 - 2.0 * (y + 0.5) / k->H) * k->ty;
+  for (int i = 0; i < 3; ++i) v[i] = k->w[i] + sx * k->r[i] + sy * k->u[i];
+}
+
+/* Signed circle-of-confusion diameter in pixels for axial depth z under the
+ * thin-lens model: A (1/S1 - 1/z) s_px.  Negative in front of the focus plane
+ * (near field), positive behind it (far field). */
+static double coc_px(const cam_t* k, const double* lens, double z) {
+  return lens[1] * (1.0 / lens[2] - 1.0 / z) * k->spx;
+}
+
+double or_coc(const double* cam, int W, int H, const double* lens, double z) {
+  cam_t k = mk_cam(cam, W, H);
+  return coc_px(&k, lens, z);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11). */
+/* Ten rounds of two 64x64->128 multiplies; the key is bumped by the two      */
+/* Weyl constants between rounds.                                             */
+/* ------------------------------------------------------------------------- */
+static const uint64_t PH_M0 = 0xD2E7470EE14C6C93ULL;
+static const uint64_t PH_M1 = 0xCA5A826395121157ULL;
+static const uint64_t PH_W0 = 0x9E3779B97F4A7C15ULL;
+static const uint64_t PH_W1 = 0xBB67AE8584CAA73BULL;
+
+void or_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k0 += PH_W0; k1 += PH_W1; }
+    unsigned __int128 p0 = (unsigned __int128)PH_M0 * x0;
+    unsigned __int128 p1 = (unsigned __int128)PH_M1 * x2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t y0 = hi1 ^ x1 ^ k0;
+    uint64_t y1 = lo1;
+    uint64_t y2 = hi0 ^ x3 ^ k1;
+    uint64_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Lens-sample uniforms: the top 24 bits of the first two outputs, scaled by
+ * 2^-24 (exact in both float and double).  Counter = (pixel, sample, view, 0),
+ * key = (seed, frame). */
+static void lens_uniforms(uint64_t pix, uint64_t j, uint64_t view, uint64_t seed, uint64_t frame,
+                          double* u0, double* u1) {
+  uint64_t c[4] = {pix, j, view, 0}, kk[2] = {seed, frame}, o[4];
+  or_philox4x64_10(c, kk, o);
+  *u0 = (double)(o[0] >> 40) * (1.0 / 16777216.0);
+  *u1 = (double)(o[1] >> 40) * (1.0 / 16777216.0);
+}
+
+/* Thin-lens ray for sample j of pixel p: a uniform point on the lens disk of
+ * radius A/2 (polar mapping sqrt(u0), 2 pi u1), aimed through the point where
+ * the pixel's pinhole ray meets the focus plane.  Origin O = e + l,
+ * direction D = S1 v - l (not normalised; D . w = S1, so axial depth = t S1). */
+static void lens_ray(const cam_t* k, const double* lens, int x, int y, uint64_t j,
+                     uint64_t seed, uint64_t frame, uint64_t view, int pinhole,
+                     double* O, double* D) {
+  double v[3];
+  pixel_dir(k, x, y, v);
+  double l[3] = {0, 0, 0};
+  if (!pinhole) {
+    double u0, u1;
+    lens_uniforms((uint64_t)y * k->W + x, j, view, seed, frame, &u0, &u1);
+    double rho = 0.5 * lens[1] * sqrt(u0);
+    double th = 2.0 * OR_PI * u1;
+    double lx = rho * cos(th), ly = rho * sin(th);
+    for (int i = 0; i < 3; ++i) l[i] = lx * k->r[i] + ly * k->u[i];
+  }
+  for (int i = 0; i < 3; ++i) { O[i] = k->e[i] + l[i]; D[i] = lens[2] * v[i] - l[i]; }
+}
+
+void or_lens_ray(const double* cam, int W, int H, const double* lens, int x, int y, uint64_t j,
+                 uint64_t seed, uint64_t frame, uint64_t view, int pinhole, double* O, double* D) {
+  cam_t k = mk_cam(cam, W, H);
+  lens_ray(&k, lens, x, y, j, seed, frame, view, pinhole, O, D);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scene + median-split BVH                                                   */
+/* ------------------------------------------------------------------------- */
+typedef struct { double lo[3], hi[3]; int left, right, first, count; } onode_t;
+
+typedef struct {
+  int n;
+  double* v;    /* n * 9 */
+  double* alb;  /* n * 3 */
+  int* idx;     /* permutation of triangles, leaves own contiguous ranges */
+  onode_t* nodes;
+  int nnodes;
+  double* cen;  /* centroids, n * 3 (build only) */
+} or_scene;
+
+static void tri_bounds(const or_scene* s, int t, double* lo, double* hi) {
+  const double* v = s->v + 9 * (size_t)t;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = mind(v[a], mind(v[3 + a], v[6 + a]));
+    hi[a] = maxd(v[a], maxd(v[3 + a], v[6 + a]));
+  }
+}
+
+/* quickselect on idx[lo, hi) by centroid coordinate `axis` so that position
+ * `k` holds the element of rank k (nth_element). */
+static void select_kth(const or_scene* s, int* idx, int lo, int hi, int k, int axis) {
+  while (hi - lo > 1) {
+    int mid = lo + (hi - lo) / 2;
+    double pv = s->cen[3 * (size_t)idx[mid] + axis];
+    int i = lo, j = hi - 1;
+    while (i <= j) {
+      while (s->cen[3 * (size_t)idx[i] + axis] < pv) ++i;
+      while (s->cen[3 * (size_t)idx[j] + axis] > pv) --j;
+      if (i <= j) { int t = idx[i]; idx[i] = idx[j]; idx[j] = t; ++i; --j; }
+    }
+    if (k <= j) hi = j + 1;
+    else if (k >= i) lo = i;
+    else return;
+  }
+}
+
+static int build_rec(or_scene* s, int first, int count) {
+  int id = s->nnodes++;
+  onode_t* nd = &s->nodes[id];
+  for (int a = 0; a < 3; ++a) { nd->lo[a] = INFINITY; nd->hi[a] = -INFINITY; }
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = first; i < first + count; ++i) {
+    double lo[3], hi[3];
+    tri_bounds(s, s->idx[i], lo, hi);
+    for (int a = 0; a < 3; ++a) {
+      nd->lo[a] = mind(nd->lo[a], lo[a]); nd->hi[a] = maxd(nd->hi[a], hi[a]);
+      double c = s->cen[3 * (size_t)s->idx[i] + a];
+      clo[a] = mind(clo[a], c); chi[a] = maxd(chi[a], c);
+    }
+  }
+  if (count <= OR_LEAF) {
+    nd->left = nd->right = -1; nd->first = first; nd->count = count;
+    return id;
+  }
+  int axis = 0;
+  for (int a = 1; a < 3; ++a) if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+  int half = count / 2;
+  select_kth(s, s->idx, first, first + count, first + half, axis);
+  nd->count = 0; nd->first = -1;
+  int l = build_rec(s, first, half);
+  int r = build_rec(s, first + half, count - half);
+  s->nodes[id].left = l; s->nodes[id].right = r;
+  return id;
+}
+
+or_scene* or_scene_create(const double* verts, const double* albedo, int n) {
+  or_scene* s = (or_scene*)calloc(1, sizeof(or_scene));
+  s->n = n;
+  s->v = (double*)malloc(sizeof(double) * 9 * (size_t)n);
+  s->alb = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  memcpy(s->v, verts, sizeof(double) * 9 * (size_t)n);
+  memcpy(s->alb, albedo, sizeof(double) * 3 * (size_t)n);
+  s->idx = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  s->cen = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  for (int i = 0; i < n; ++i) {
+    s->idx[i] = i;
+    for (int a = 0; a < 3; ++a)
+      s->cen[3 * (size_t)i + a] = (s->v[9 * (size_t)i + a] + s->v[9 * (size_t)i + 3 + a] + s->v[9 * (size_t)i + 6 + a]) / 3.0;
+  }
+  s->nodes = (onode_t*)malloc(sizeof(onode_t) * (size_t)(2 * (n > 0 ? n : 1)));
+  s->nnodes = 0;
+  if (n > 0) build_rec(s, 0, n);
+  free(s->cen); s->cen = NULL;
+  return s;
+}
+
+void or_scene_destroy(or_scene* s) {
+  if (!s) return;
+  free(s->v); free(s->alb); free(s->idx); free(s->nodes); free(s);
+}
+
+int or_scene_nodes(const or_scene* s) { return s->nnodes; }
+
+/* ------------------------------------------------------------------------- */
+/* Closest hit with ambiguity                                                 */
+/* ------------------------------------------------------------------------- */
+typedef struct { double t, mu; int id; } cand_t;
+
+/* Angular margin of the ray (O, D) against triangle t.  For each edge (i, j)
+ * the quantity  Dn . (a_i x a_j) / |a_i x a_j|  (a = vertex - O, Dn = unit D)
+ * is the sine of the angle between the ray and the plane through O and that
+ * edge.  The ray passes through the triangle iff the three have one sign;
+ * mu = the smallest of them after orienting by that sign is positive inside
+ * (the angular distance to the nearest edge) and negative outside.
+ * t is the parameter of the hit with the triangle's plane.  Returns 0 for
+ * degenerate triangles and rays parallel to the plane. */
+static int tri_eval(const or_scene* s, int tri, const double* O, const double* D, const double* Dn,
+                    double* t_out, double* mu_out) {
+  const double* v = s->v + 9 * (size_t)tri;
+  double a0[3], a1[3], a2[3];
+  v_sub(v, O, a0); v_sub(v + 3, O, a1); v_sub(v + 6, O, a2);
+  double c01[3], c12[3], c20[3];
+  v_cross(a0, a1, c01); v_cross(a1, a2, c12); v_cross(a2, a0, c20);
+  double l01 = v_len(c01), l12 = v_len(c12), l20 = v_len(c20);
+  double e01 = v_dot(Dn, c01), e12 = v_dot(Dn, c12), e20 = v_dot(Dn, c20);
+  double sum = e01 + e12 + e20;
+  double e1[3], e2[3], n[3];
+  v_sub(v + 3, v, e1); v_sub(v + 6, v, e2); v_cross(e1, e2, n);
+  double den = v_dot(n, D);
+  if (den == 0.0 || sum == 0.0) return 0;
+  if (l01 == 0.0 || l12 == 0.0 || l20 == 0.0) return 0;
+  double sg = sum > 0 ? 1.0 : -1.0;
+  double m0 = sg * e01 / l01, m1 = sg * e12 / l12, m2 = sg * e20 / l20;
+  *mu_out = mind(m0, mind(m1, m2));
+  *t_out = v_dot(n, a0) / den;
+  return 1;
+}
+
+static int box_hit(const onode_t* nd, const double* O, const double* invD, double tlim) {
+  double t0 = 0.0, t1 = tlim;
+  for (int a = 0; a < 3; ++a) {
+    double lo = nd->lo[a] - OR_BOX_MARGIN, hi = nd->hi[a] + OR_BOX_MARGIN;
+    if (isinf(invD[a])) {
+      if (O[a] < lo || O[a] > hi) return 0;
+      continue;
+    }
+    double ta = (lo - O[a]) * invD[a], tb = (hi - O[a]) * invD[a];
+    if (ta > tb) { double x = ta; ta = tb; tb = x; }
+    t0 = maxd(t0, ta); t1 = mind(t1, tb);
+    if (t0 > t1) return 0;
+  }
+  return 1;
+}
+
+typedef struct { double t; int id; int amb; } ohit_t;
+
+/* Closest hit: smallest t > 0 among triangles the ray passes through
+ * (boundary counts as inside), ties to the lowest triangle index.  The ray is
+ * ambiguous when the chosen triangle is within OR_EPS (angular) of an edge,
+ * when another triangle within OR_EPS of being hit lies closer, or when a
+ * second hit lies within relative OR_EPS in t. */
+static ohit_t cast_ray(const or_scene* s, const double* O, const double* D, int brute) {
+  double dl = v_len(D);
+  double Dn[3] = {D[0] / dl, D[1] / dl, D[2] / dl};
+  double invD[3];
+  for (int a = 0; a < 3; ++a) invD[a] = D[a] != 0.0 ? 1.0 / D[a] : INFINITY;
+  cand_t cand[OR_MAX_CAND];
+  int nc = 0, overflow = 0;
+  double tbest = INFINITY;
+  int best = -1;
+  double best_mu = 0.0;
+
+#define OR_CONSIDER(tri)                                                         \
+  do {                                                                           \
+    double tt, mu;                                                               \
+    if (tri_eval(s, (tri), O, D, Dn, &tt, &mu) && tt > 0.0 && mu > -OR_EPS) {    \
+      if (nc < OR_MAX_CAND) { cand[nc].t = tt; cand[nc].mu = mu; cand[nc].id = (tri); ++nc; } \
+      else overflow = 1;                                                         \
+      if (mu >= 0.0 && (tt < tbest || (tt == tbest && (tri) < best))) {          \
+        tbest = tt; best = (tri); best_mu = mu;                                  \
+      }                                                                          \
+    }                                                                            \
+  } while (0)
+
+  if (brute || s->nnodes == 0) {
+    for (int tri = 0; tri < s->n; ++tri) OR_CONSIDER(tri);
+  } else {
+    int stack[256], sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+      const onode_t* nd = &s->nodes[stack[--sp]];
+      double tlim = isinf(tbest) ? INFINITY : tbest * (1.0 + 4.0 * OR_EPS) + OR_BOX_MARGIN;
+      if (!box_hit(nd, O, invD, tlim)) continue;
+      if (nd->count > 0) {
+        for (int i = nd->first; i < nd->first + nd->count; ++i) OR_CONSIDER(s->idx[i]);
+      } else {
+        if (sp + 2 > 256) { overflow = 1; break; }
+        stack[sp++] = nd->right;
+        stack[sp++] = nd->left;
+      }
+    }
+  }
+#undef OR_CONSIDER
+  ohit_t h;
+  h.t = tbest; h.id = best; h.amb = overflow;
+  if (best >= 0 && best_mu < OR_EPS) h.amb = 1;
+  for (int i = 0; i < nc; ++i) {
+    if (cand[i].id == best) continue;
+    if (best < 0) { h.amb = 1; break; }          /* a near miss on a missing ray */
+    if (cand[i].t <= tbest * (1.0 + OR_EPS)) { h.amb = 1; break; }
+  }
+  return h;
+}
+
+/* Batch of rays: O, D are n*3; outputs t (inf on miss), id (-1 on miss), amb. */
+void or_cast_rays(const or_scene* s, int n, const double* O, const double* D, int brute,
+                  double* t, int* id, int* amb) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int i = 0; i < n; ++i) {
+    ohit_t h = cast_ray(s, O + 3 * (size_t)i, D + 3 * (size_t)i, brute);
+    t[i] = h.t; id[i] = h.id; amb[i] = h.amb;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Shading (our reading of "deferred shading"): two-sided Lambertian face      */
+/* normal, one point light with inverse-square falloff, ambient term, no      */
+/* shadow rays.  light[9] = position, rgb intensity, rgb ambient.             */
+/* ------------------------------------------------------------------------- */
+static void shade(const or_scene* s, const double* light, int tri, const double* O, const double* D,
+                  double t, double* L, double* n_out) {
+  const double* v = s->v + 9 * (size_t)tri;
+  double e1[3], e2[3], n[3];
+  v_sub(v + 3, v, e1); v_sub(v + 6, v, e2); v_cross(e1, e2, n);
+  double nl = v_len(n);
+  for (int a = 0; a < 3; ++a) n[a] /= nl;
+  if (v_dot(n, D) > 0.0) for (int a = 0; a < 3; ++a) n[a] = -n[a];
+  double P[3], l[3];
+  for (int a = 0; a < 3; ++a) P[a] = O[a] + t * D[a];
+  v_sub(light, P, l);
+  double d2 = v_dot(l, l);
+  double d = sqrt(d2);
+  double cosv = d > 0.0 ? v_dot(n, l) / d : 0.0;
+  double irr = maxd(0.0, cosv) / maxd(d2, 1e-4);
+  const double* al = s->alb + 3 * (size_t)tri;
+  for (int c = 0; c < 3; ++c) L[c] = al[c] * (light[6 + c] + light[3 + c] * irr);
+  if (n_out) for (int a = 0; a < 3; ++a) n_out[a] = n[a];
+}
+
+static inline double luminance(const double* L) { return 0.2126 * L[0] + 0.7152 * L[1] + 0.0722 * L[2]; }
+
+/* ------------------------------------------------------------------------- */
+/* G-buffer: one pinhole ray through each pixel centre (lens offset 0).       */
+/* Planar outputs [C][H][W]: depth z (axial, OR_ZMAX on miss), face normal,   */
+/* albedo, shaded colour C_r, triangle id (-1 on miss), ambiguity flag.       */
+/* `pix` lists linear pixel indices (NULL = all pixels, then n = W*H); the    */
+/* outputs are indexed by list position.                                      */
+/* ------------------------------------------------------------------------- */
+void or_gbuffer(const or_scene* s, const double* cam, int W, int H, const double* lens,
+                const double* light, const int64_t* pix, int64_t n,
+                double* z, double* nrm, double* alb, double* col, int* id, int* amb) {
+  cam_t k = mk_cam(cam, W, H);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t p = pix ? pix[i] : i;
+    int x = (int)(p % W), y = (int)(p / W);
+    double O[3], D[3];
+    lens_ray(&k, lens, x, y, 0, 0, 0, 0, 1, O, D);
+    ohit_t h = cast_ray(s, O, D, 0);
+    double L[3] = {0, 0, 0}, nn[3] = {0, 0, 0}, al[3] = {0, 0, 0};
+    double zz = OR_ZMAX;
+    if (h.id >= 0) {
+      shade(s, light, h.id, O, D, h.t, L, nn);
+      for (int c = 0; c < 3; ++c) al[c] = s->alb[3 * (size_t)h.id + c];
+      zz = h.t * lens[2];
+    }
+    z[i] = zz;
+    for (int c = 0; c < 3; ++c) {
+      nrm[(size_t)c * n + i] = nn[c];
+      alb[(size_t)c * n + i] = al[c];
+      col[(size_t)c * n + i] = L[c];
+    }
+    id[i] = h.id;
+    amb[i] = h.amb;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adaptive ray mask                                                          */
+/*  1. Gaussian (sigma; taps exp(-i^2 / 2 sigma^2), radius floor(3 sigma+0.5),*/
+/*     normalised; separable x then y; clamp to edge) on min(z, zmax), n.     */
+/*  2. 3x3 Sobel (clamp to edge) on the blurred channels:                     */
+/*     g_z = |grad z~| / (8 max(z~, 1e-3)),  g_n = sqrt(sum_c |grad n~_c|^2)/8.*/
+/*  3. m = max(g_z / tau_z, g_n / tau_n, V / tau_v).                         */
+/*  4. s_raw = 0 if m < 1, else min(spp_max, ceil(m)).                       */
+/*  5. tile max over tile x tile pixels, then max over tiles within          */
+/*     Chebyshev tile distance `dilate`; s(p) = value of p's tile.           */
+/*  6. offsets = exclusive prefix sum of s in row-major pixel order.         */
+/* s_lo / s_hi bound s when m moves by a relative OR_EPS (threshold ambiguity)*/
+/* ------------------------------------------------------------------------- */
+static int s_of_m(double m, int spp_max) {
+  if (!(m >= 1.0)) return 0;
+  if (isinf(m)) return spp_max;
+  double c = ceil(m);
+  return c >= (double)spp_max ? spp_max : (int)c;
+}
+
+void or_gauss_taps(double sigma, int* radius, double* taps /* >= 13 */) {
+  int R = (int)floor(3.0 * sigma + 0.5);
+  double sum = 0.0;
+  for (int i = -R; i <= R; ++i) { taps[i + R] = exp(-(double)(i * i) / (2.0 * sigma * sigma)); sum += taps[i + R]; }
+  for (int i = -R; i <= R; ++i) taps[i + R] /= sum;
+  *radius = R;
+}
+
+static inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int or_mask(int W, int H, const double* z, const double* nrm, const double* V,
+            double sigma, double tau_z, double tau_n, double tau_v,
+            int spp_max, int tile, int dilate,
+            double* blur /* 4*W*H, may be NULL */, double* gz_out, double* gn_out, double* m_out,
+            int* s, int* s_lo, int* s_hi, int64_t* offsets, int64_t* total) {
+  size_t N = (size_t)W * H;
+  int R;
+  double taps[32];
+  if (sigma <= 0.0 || sigma > 4.0) return 1;
+  or_gauss_taps(sigma, &R, taps);
+  double* ch = (double*)malloc(sizeof(double) * 4 * N);
+  double* tmp = (double*)malloc(sizeof(double) * 4 * N);
+  for (size_t i = 0; i < N; ++i) {
+    ch[i] = mind(z[i], OR_ZMAX);
+    for (int c = 0; c < 3; ++c) ch[(size_t)(c + 1) * N + i] = nrm[(size_t)c * N + i];
+  }
+  /* separable Gaussian: x pass then y pass */
+#pragma omp parallel for
+  for (int y = 0; y < H; ++y)
+    for (int c = 0; c < 4; ++c)
+      for (int x = 0; x < W; ++x) {
+        double acc = 0.0;
+        for (int i = -R; i <= R; ++i) acc += taps[i + R] * ch[(size_t)c * N + (size_t)y * W + clampi(x + i, 0, W - 1)];
+        tmp[(size_t)c * N + (size_t)y * W + x] = acc;
+      }
+#pragma omp parallel for
+  for (int y = 0; y < H; ++y)
+    for (int c = 0; c < 4; ++c)
+      for (int x = 0; x < W; ++x) {
+        double acc = 0.0;
+        for (int i = -R; i <= R; ++i) acc += taps[i + R] * tmp[(size_t)c * N + (size_t)clampi(y + i, 0, H - 1) * W + x];
+        ch[(size_t)c * N + (size_t)y * W + x] = acc;
+      }
+  if (blur) memcpy(blur, ch, sizeof(double) * 4 * N);
+  int* sr = (int*)malloc(sizeof(int) * N);
+  int* srl = (int*)malloc(sizeof(int) * N);
+  int* srh = (int*)malloc(sizeof(int) * N);
+#pragma omp parallel for
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      double gsq[4];
+      for (int c = 0; c < 4; ++c) {
+        const double* b = ch + (size_t)c * N;
+#define B(xx, yy) b[(size_t)clampi((yy), 0, H - 1) * W + clampi((xx), 0, W - 1)]
+        double gx = (B(x + 1, y - 1) - B(x - 1, y - 1)) + 2.0 * (B(x + 1, y) - B(x - 1, y)) + (B(x + 1, y + 1) - B(x - 1, y + 1));
+        double gy = (B(x - 1, y + 1) - B(x - 1, y - 1)) + 2.0 * (B(x, y + 1) - B(x, y - 1)) + (B(x + 1, y + 1) - B(x + 1, y - 1));
+#undef B
+        gsq[c] = gx * gx + gy * gy;
+      }
+      size_t p = (size_t)y * W + x;
+      double gz = sqrt(gsq[0]) / (8.0 * maxd(ch[p], 1e-3));
+      double gn = sqrt(gsq[1] + gsq[2] + gsq[3]) / 8.0;
+      double vv = V ? V[p] : 0.0;
+      double m = maxd(gz / tau_z, maxd(gn / tau_n, vv / tau_v));
+      if (gz_out) gz_out[p] = gz;
+      if (gn_out) gn_out[p] = gn;
+      if (m_out) m_out[p] = m;
+      sr[p] = s_of_m(m, spp_max);
+      srl[p] = isinf(m) ? spp_max : s_of_m(m * (1.0 - OR_EPS), spp_max);
+      srh[p] = isinf(m) ? spp_max : s_of_m(m * (1.0 + OR_EPS), spp_max);
+    }
+  /* tile max then dilation over tiles */
+  int TW = (W + tile - 1) / tile, TH = (H + tile - 1) / tile;
+  int* tm = (int*)calloc((size_t)TW * TH * 3, sizeof(int));
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x, t = (size_t)(y / tile) * TW + x / tile;
+      if (sr[p] > tm[3 * t]) tm[3 * t] = sr[p];
+      if (srl[p] > tm[3 * t + 1]) tm[3 * t + 1] = srl[p];
+      if (srh[p] > tm[3 * t + 2]) tm[3 * t + 2] = srh[p];
+    }
+  int* td = (int*)calloc((size_t)TW * TH * 3, sizeof(int));
+  for (int ty = 0; ty < TH; ++ty)
+    for (int tx = 0; tx < TW; ++tx)
+      for (int dy = -dilate; dy <= dilate; ++dy)
+        for (int dx = -dilate; dx <= dilate; ++dx) {
+          int yy = ty + dy, xx = tx + dx;
+          if (yy < 0 || yy >= TH || xx < 0 || xx >= TW) continue;
+          for (int q = 0; q < 3; ++q) {
+            int v = tm[3 * ((size_t)yy * TW + xx) + q];
+            if (v > td[3 * ((size_t)ty * TW + tx) + q]) td[3 * ((size_t)ty * TW + tx) + q] = v;
+          }
+        }
+  int64_t run = 0;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x, t = (size_t)(y / tile) * TW + x / tile;
+      s[p] = td[3 * t];
+      if (s_lo) s_lo[p] = td[3 * t + 1];
+      if (s_hi) s_hi[p] = td[3 * t + 2];
+      if (offsets) offsets[p] = run;
+      run += s[p];
+    }
+  if (total) *total = run;
+  free(ch); free(tmp); free(sr); free(srl); free(srh); free(tm); free(td);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Thin-lens distributed ray trace + per-pixel reduction                      */
+/* For listed pixel i (linear index pix[i]) with s = spp[i] samples:          */
+/*   per ray j: lens ray, closest hit, shade -> L_j, axial depth z_j          */
+/*   (OR_ZMAX on miss), luminance Y_j (Rec. 709).                              */
+/*   near weight w_j = clamp(0.5 - c(z_j) / (2 sqrt 2), 0, 1): 1 in front of */
+/*   the focus zone, 0 behind it, linear across |c| <= sqrt 2 (our reading of */
+/*   "split ... based on its Z-distance from the separating focus plane").    */
+/*   C_tn = sum w L / sum w, C_tf = sum (1-w) L / sum (1-w) (0 if empty),      */
+/*   h = sum w / s (hit ratio), lum_m1 = mean Y, lum_m2 = mean Y^2.           */
+/* Per-ray outputs (nullable) go to ray_base[i] + j; ray_base = exclusive      */
+/* prefix sum of spp over the list.  px_amb = any ray of the pixel ambiguous. */
+/* ------------------------------------------------------------------------- */
+void or_trace(const or_scene* s, const double* cam, int W, int H, const double* lens, const double* light,
+              const int64_t* pix, const int* spp, int64_t n, const int64_t* ray_base,
+              uint64_t seed, uint64_t frame, uint64_t view,
+              int* ray_id, double* ray_z, double* ray_L, int* ray_amb, int64_t n_rays,
+              double* c_near, double* c_far, double* hit, double* m1, double* m2, int* px_amb) {
+  cam_t k = mk_cam(cam, W, H);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t p = pix ? pix[i] : i;
+    int x = (int)(p % W), y = (int)(p / W);
+    int ns = spp[i];
+    double Nw = 0.0, Fw = 0.0, sn[3] = {0, 0, 0}, sf[3] = {0, 0, 0}, sy = 0.0, sy2 = 0.0;
+    int pa = 0;
+    for (int j = 0; j < ns; ++j) {
+      double O[3], D[3];
+      lens_ray(&k, lens, x, y, (uint64_t)j, seed, frame, view, 0, O, D);
+      ohit_t h = cast_ray(s, O, D, 0);
+      double L[3] = {0, 0, 0}, zz = OR_ZMAX;
+      if (h.id >= 0) { shade(s, light, h.id, O, D, h.t, L, NULL); zz = h.t * lens[2]; }
+      double Y = luminance(L);
+      double c = coc_px(&k, lens, zz);
+      double w = clampd(0.5 - c / (2.0 * OR_SQRT2), 0.0, 1.0);
+      Nw += w; Fw += 1.0 - w;
+      for (int q = 0; q < 3; ++q) { sn[q] += w * L[q]; sf[q] += (1.0 - w) * L[q]; }
+      sy += Y; sy2 += Y * Y;
+      pa |= h.amb;
+      if (ray_base) {
+        int64_t r = ray_base[i] + j;
+        if (r >= 0 && r < n_rays) {
+          if (ray_id) ray_id[r] = h.id;
+          if (ray_z) ray_z[r] = zz;
+          if (ray_L) for (int q = 0; q < 3; ++q) ray_L[(size_t)q * n_rays + r] = L[q];
+          if (ray_amb) ray_amb[r] = h.amb;
+        }
+      }
+    }
+    for (int q = 0; q < 3; ++q) {
+      c_near[(size_t)q * n + i] = Nw > 0.0 ? sn[q] / Nw : 0.0;
+      c_far[(size_t)q * n + i] = Fw > 0.0 ? sf[q] / Fw : 0.0;
+    }
+    hit[i] = ns > 0 ? Nw / ns : 0.0;
+    m1[i] = ns > 0 ? sy / ns : 0.0;
+    m2[i] = ns > 0 ? sy2 / ns : 0.0;
+    if (px_amb) px_amb[i] = pa;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Temporally accumulated luminance variance (our reading of the paper's      */
+/* SVGF-style estimate, reprojected with depth like Lehtinen et al.)          */
+/* History per pixel: lum_m1, lum_m2, flags (bit0 valid, bit1 new), depth.    */
+/* Reprojection: X = e + z v; project with the previous camera, round to the  */
+/* nearest pixel; valid if in bounds, previous entry valid and               */
+/* |z_prev - z_expected| / z_expected <= 0.01.                                */
+/* V = +inf if the reprojected entry is new, max(0, m2 - m1^2) if valid,      */
+/* 0 if invalid.  amb marks rounding within OR_EPS of a pixel boundary or a   */
+/* depth ratio within OR_EPS of the bound.                                    */
+/* ------------------------------------------------------------------------- */
+#define OR_VALID 1
+#define OR_NEW 2
+
+void or_var_reproject(const double* cam, int W, int H, const double* z,
+                      const double* pcam, int PW, int PH,
+                      const double* pm1, const double* pm2, const int* pflags, const double* pz,
+                      double* rm1, double* rm2, int* rflags, double* V, int* amb) {
+  cam_t k = mk_cam(cam, W, H), kp = mk_cam(pcam, PW, PH);
+#pragma omp parallel for
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x;
+      double v[3], X[3], d[3];
+      pixel_dir(&k, x, y, v);
+      for (int a = 0; a < 3; ++a) X[a] = k.e[a] + z[p] * v[a];
+      v_sub(X, kp.e, d);
+      double zc = v_dot(d, kp.w);
+      int ok = 0, am = 0;
+      double a1 = 0, a2 = 0;
+      int fl = 0;
+      if (zc > 0.0) {
+        double sxp = v_dot(d, kp.r) / zc, syp = v_dot(d, kp.u) / zc;
+        double fx = (sxp / kp.tx + 1.0) * 0.5 * PW;
+        double fy = (1.0 - syp / kp.ty) * 0.5 * PH;
+        double px = floor(fx), py = floor(fy);
+        if (fx - px < OR_EPS * maxd(1.0, fabs(fx)) || px + 1.0 - fx < OR_EPS * maxd(1.0, fabs(fx))) am = 1;
+        if (fy - py < OR_EPS * maxd(1.0, fabs(fy)) || py + 1.0 - fy < OR_EPS * maxd(1.0, fabs(fy))) am = 1;
+        if (px >= 0 && px < PW && py >= 0 && py < PH) {
+          size_t q = (size_t)py * PW + (size_t)px;
+          if (pflags[q] & OR_VALID) {
+            double rel = fabs(pz[q] - zc) / zc;
+            if (fabs(rel - 0.01) < OR_EPS) am = 1;
+            if (rel <= 0.01) { ok = 1; a1 = pm1[q]; a2 = pm2[q]; fl = pflags[q]; }
+          }
+        }
+      }
+      rm1[p] = ok ? a1 : 0.0;
+      rm2[p] = ok ? a2 : 0.0;
+      rflags[p] = ok ? fl : 0;
+      V[p] = ok ? ((fl & OR_NEW) ? INFINITY : maxd(0.0, a2 - a1 * a1)) : 0.0;
+      if (amb) amb[p] = am;
+    }
+}
+
+/* After the trace: EMA with weight alpha where traced with valid history,
+ * restart (and mark new) where traced without history, carry where untraced. */
+void or_var_update(int W, int H, const int* spp, const double* rm1, const double* rm2, const int* rflags,
+                   const double* ybar, const double* y2bar, double alpha, const double* z,
+                   double* m1, double* m2, int* flags, double* zh) {
+  size_t N = (size_t)W * H;
+  for (size_t p = 0; p < N; ++p) {
+    if (spp[p] > 0) {
+      if (rflags[p] & OR_VALID) {
+        m1[p] = (1.0 - alpha) * rm1[p] + alpha * ybar[p];
+        m2[p] = (1.0 - alpha) * rm2[p] + alpha * y2bar[p];
+        flags[p] = OR_VALID;
+      } else {
+        m1[p] = ybar[p]; m2[p] = y2bar[p]; flags[p] = OR_VALID | OR_NEW;
+      }
+    } else {
+      m1[p] = rm1[p]; m2[p] = rm2[p]; flags[p] = rflags[p];
+    }
+    zh[p] = z[p];
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Post-process gather DoF filter (our reading of the paper's adapted         */
+/* post-process plus its CoC-radius rejection rule).                         */
+/*  c_p = signed CoC (px), r_p = |c_p| / 2.                                   */
+/*  R(p) = min(R_cap, max of r over the tiles within ceil(R_cap / tile)      */
+/*         tiles (Chebyshev) of p's tile).                                    */
+/*  taps k = 1..N: u_k = sqrt((k - 0.5)/N) (cos k g, sin k g), g = pi(3-sqrt5)*/
+/*  q_k = pixel centre + R u_k, d_k = R |u_k|; bilinear fetch of colour and  */
+/*  signed CoC (texel centres at +0.5, clamp to edge).                        */
+/*  background clamp t = clamp((c_q - c_p) / bg_ramp, 0, 1),                 */
+/*  r_eff = r_q - t max(0, r_q - r_p), a = clamp(r_eff - d_k + 0.5, 0, 1),   */
+/*  w_k = a (R^2 / N) / max(r_q, 0.5)^2, centre w_0 = 1 / max(r_p, 0.5)^2.   */
+/*  C_pp = (w_0 C_p + sum w_k C_q) / (w_0 + sum w_k).                        */
+/* pp[4] = n_taps, tile, r_cap, bg_ramp_px.  Out for listed pixels.           */
+/* ------------------------------------------------------------------------- */
+static void bilerp(const double* img, int W, int H, double fx, double fy, double* o, int nch, size_t plane) {
+  double gx = fx - 0.5, gy = fy - 0.5;
+  double x0f = floor(gx), y0f = floor(gy);
+  double ax = gx - x0f, ay = gy - y0f;
+  int x0 = (int)x0f, y0 = (int)y0f;
+  int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+  int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+  for (int c = 0; c < nch; ++c) {
+    const double* b = img + (size_t)c * plane;
+    double v00 = b[(size_t)ya * W + xa], v10 = b[(size_t)ya * W + xb];
+    double v01 = b[(size_t)yb * W + xa], v11 = b[(size_t)yb * W + xb];
+    o[c] = (1 - ay) * ((1 - ax) * v00 + ax * v10) + ay * ((1 - ax) * v01 + ax * v11);
+  }
+}
+
+void or_pp_radius(int W, int H, const double* cimg, double r_cap, int tile, double* Rout) {
+  int TW = (W + tile - 1) / tile, TH = (H + tile - 1) / tile;
+  double* rt = (double*)calloc((size_t)TW * TH, sizeof(double));
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      double r = 0.5 * fabs(cimg[(size_t)y * W + x]);
+      size_t t = (size_t)(y / tile) * TW + x / tile;
+      if (r > rt[t]) rt[t] = r;
+    }
+  int K = (int)ceil(r_cap / tile);
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      int tx = x / tile, ty = y / tile;
+      double m = 0.0;
+      for (int dy = -K; dy <= K; ++dy)
+        for (int dx = -K; dx <= K; ++dx) {
+          int yy = ty + dy, xx = tx + dx;
+          if (yy < 0 || yy >= TH || xx < 0 || xx >= TW) continue;
+          m = maxd(m, rt[(size_t)yy * TW + xx]);
+        }
+      Rout[(size_t)y * W + x] = mind(r_cap, m);
+    }
+  free(rt);
+}
+
+void or_postfilter(const double* cam, int W, int H, const double* lens, const double* color, const double* z,
+                   const double* pp, const int64_t* pix, int64_t n, double* out) {
+  cam_t k = mk_cam(cam, W, H);
+  size_t N = (size_t)W * H;
+  int NT = (int)pp[0], tile = (int)pp[1];
+  double r_cap = pp[2], ramp = pp[3];
+  double* img = (double*)malloc(sizeof(double) * 4 * N); /* rgb + signed CoC */
+  double* R = (double*)malloc(sizeof(double) * N);
+  for (size_t p = 0; p < N; ++p) {
+    for (int c = 0; c < 3; ++c) img[(size_t)c * N + p] = color[(size_t)c * N + p];
+    img[3 * N + p] = coc_px(&k, lens, z[p]);
+  }
+  or_pp_radius(W, H, img + 3 * N, r_cap, tile, R);
+  double g = OR_PI * (3.0 - sqrt(5.0));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t p = pix ? pix[i] : i;
+    int x = (int)(p % W), y = (int)(p / W);
+    double cp = img[3 * N + p], rp = 0.5 * fabs(cp);
+    double Rp = R[p];
+    double w0 = 1.0 / (maxd(rp, 0.5) * maxd(rp, 0.5));
+    double acc[3], wsum = w0;
+    for (int c = 0; c < 3; ++c) acc[c] = w0 * img[(size_t)c * N + p];
+    for (int kk = 1; kk <= NT; ++kk) {
+      double rad = sqrt((kk - 0.5) / NT);
+      double ux = rad * cos(kk * g), uy = rad * sin(kk * g);
+      double qx = x + 0.5 + Rp * ux, qy = y + 0.5 + Rp * uy;
+      double smp[4];
+      bilerp(img, W, H, qx, qy, smp, 4, N);
+      double dk = Rp * rad;
+      double cq = smp[3], rq = 0.5 * fabs(cq);
+      double t = clampd((cq - cp) / ramp, 0.0, 1.0);
+      double reff = rq - t * maxd(0.0, rq - rp);
+      double a = clampd(reff - dk + 0.5, 0.0, 1.0);
+      double w = a * (Rp * Rp / NT) / (maxd(rq, 0.5) * maxd(rq, 0.5));
+      for (int c = 0; c < 3; ++c) acc[c] += w * smp[c];
+      wsum += w;
+    }
+    for (int c = 0; c < 3; ++c) out[(size_t)c * n + i] = acc[c] / wsum;
+  }
+  free(img); free(R);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Composite (paper's Composite section; our readings of its thresholds).     */
+/*  phi = clamp(|c_p| - sqrt 2, 0, 1): out-of-focus weight (focus zone is    */
+/*        |c| < sqrt 2 with a 1-px ramp above it);                            */
+/*  nu  = clamp(0.5 - c_p / (2 sqrt 2), 0, 1): near (1) / far (0);            */
+/*  C_rt = h C_tn + (1 - h) C_tf;                                             */
+/*  rho = [s > 0] (1 - spec), spec = 0 for Lambertian scenes;                 */
+/*  beta = [s > 0] clamp(1 - h / h_t, 0, 1);                                  */
+/*  C_oof = nu (rho C_rt + (1 - rho) C_pp) + (1 - nu)(beta C_rt + (1-beta)C_pp)*/
+/*  out = (1 - phi) C_r + phi C_oof;  rt_override: out = C_rt where s > 0.   */
+/* ------------------------------------------------------------------------- */
+void or_composite(const double* cam, int W, int H, const double* lens,
+                  const double* color, const double* cpp, const double* z, const int* spp,
+                  const double* c_near, const double* c_far, const double* hit,
+                  double h_t, int rt_override, double* out) {
+  cam_t k = mk_cam(cam, W, H);
+  size_t N = (size_t)W * H;
+  for (size_t p = 0; p < N; ++p) {
+    double c = coc_px(&k, lens, z[p]);
+    double phi = clampd(fabs(c) - OR_SQRT2, 0.0, 1.0);
+    double nu = clampd(0.5 - c / (2.0 * OR_SQRT2), 0.0, 1.0);
+    double h = hit[p];
+    int traced = spp[p] > 0;
+    double rho = traced ? 1.0 : 0.0;
+    double beta = traced ? clampd(1.0 - h / h_t, 0.0, 1.0) : 0.0;
+    for (int q = 0; q < 3; ++q) {
+      double crt = h * c_near[(size_t)q * N + p] + (1.0 - h) * c_far[(size_t)q * N + p];
+      double cp = cpp[(size_t)q * N + p];
+      double oof = nu * (rho * crt + (1.0 - rho) * cp) + (1.0 - nu) * (beta * crt + (1.0 - beta) * cp);
+      double o = (1.0 - phi) * color[(size_t)q * N + p] + phi * oof;
+      if (rt_override && traced) o = crt;
+      out[(size_t)q * N + p] = o;
+    }
+  }
+}
