@@ -1,0 +1,301 @@
+/*
+ * hdof.h -- C ABI of the MI355X (gfx950) hybrid depth-of-field hot path.
+ *
+ * Method: Tan, Chua, Biette, Bhojan, "Hybrid DoF: Ray-Traced and
+ * Post-Processed Hybrid Depth of Field Effect for Real-Time Rendering"
+ * (SIGGRAPH 2020 posters).  One frame runs, in the paper's order:
+ *   G-buffer with a sharp image (Design)                     -> hdof_gbuffer
+ *   adaptive ray mask: Gaussian, Sobel on normal and depth,
+ *   temporally accumulated luminance variance (Ray Trace)    -> hdof_ray_mask
+ *   thin-lens distributed ray tracing of the masked pixels,
+ *   near/far split and hit ratio (Ray Trace)                 -> hdof_trace_thin_lens
+ *   variance history update (Ray Trace)                      -> hdof_variance_update
+ *   post-process gather filter (Design; rejection rule from
+ *   Reconstruction)                                          -> hdof_postfilter
+ *   near/far composite (Composite)                           -> hdof_composite
+ * and hdof_frame chains all of them.  Scene acceleration (the paper relies on
+ * hardware BVHs) is hdof_build_bvh.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named d_* are DEVICE pointers on the context's GPU, owned by
+ *    the caller, contiguous.  Images are planar float32 [C][H][W] in
+ *    row-major pixel order (pixel (x, y) at y*W + x, y pointing down).
+ *  - Every call only enqueues work on `stream` (a hipStream_t; NULL = the
+ *    null stream) and returns; results are ready when the stream is.
+ *    No call synchronises the host except hdof_create, hdof_destroy,
+ *    hdof_scene_destroy, hdof_scene_stats, hdof_history_reset and hdof_sync.
+ *  - Arguments are validated before anything is enqueued; a failing call
+ *    enqueues nothing and returns a status; hdof_last_error() then holds a
+ *    message for the calling thread.  Nothing throws across this ABI.
+ *  - Faults found on the device (traversal stack overflow) set a flag that
+ *    hdof_sync reports as HDOF_ERR_CAPACITY.
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Camera and lens scalars are float32, so a reference implementation in
+ *    double precision can widen exactly the same values.
+ */
+#ifndef HDOF_H
+#define HDOF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HDOF_OK = 0,
+  HDOF_ERR_INVALID_ARG = 1, /* a pointer, size or parameter out of range      */
+  HDOF_ERR_UNSUPPORTED = 2, /* device is not gfx950                            */
+  HDOF_ERR_OOM = 3,         /* device allocation of library scratch failed     */
+  HDOF_ERR_CAPACITY = 4,    /* a device-side limit was hit (see hdof_sync)     */
+  HDOF_ERR_HIP = 5          /* a HIP runtime call failed                       */
+} hdof_status;
+
+typedef struct hdof_ctx hdof_ctx;     /* device, scratch, variance history   */
+typedef struct hdof_scene hdof_scene; /* BVH + triangles + albedo on device  */
+typedef void* hdof_stream;            /* hipStream_t                          */
+
+/* Pinhole frame of the thin-lens camera (paper, Design: thin lens model).
+ * right/up/fwd orthonormal; the ray through the centre of pixel (x, y) has
+ * direction v = fwd + sx right + sy up with
+ *   sx = (2 (x + 0.5) / width - 1) tan_half_fov_x,
+ *   sy = (1 - 2 (y + 0.5) / height) tan_half_fov_x height / width. */
+typedef struct {
+  float eye[3], right[3], up[3], fwd[3];
+  float tan_half_fov_x;
+  int32_t width, height;
+} hdof_camera;
+
+/* Thin lens: focal length f (m), aperture DIAMETER A = f / N (m; 0 = pinhole),
+ * focus distance S1 (m, axial, > f).  Signed circle of confusion of axial
+ * depth z, in pixels: c(z) = A (1/S1 - 1/z) width / (2 tan_half_fov_x);
+ * negative = near field (in front of the focus plane), positive = far. */
+typedef struct {
+  float focal_length, aperture, focus_distance;
+} hdof_lens;
+
+/* One point light (position, rgb intensity) and an rgb ambient term for the
+ * two-sided Lambertian shading of both the G-buffer and the traced rays. */
+typedef struct {
+  float pos[3], intensity[3], ambient[3];
+} hdof_light;
+
+/* Adaptive ray mask (paper, Ray Trace).  sigma in (0, 2]: Gaussian on depth
+ * and normal before the 3x3 Sobel; tau_*: score normalisers (> 0);
+ * var_alpha in [0, 1]: EMA weight of the luminance moments; spp_max in
+ * [1, 255]; tile in {1, 2, 4, 8, 16}: mask tile edge in pixels (tile max);
+ * dilate in [0, 8]: tile dilation radius. */
+typedef struct {
+  float sigma, tau_depth, tau_normal, tau_var, var_alpha;
+  int32_t spp_max, tile, dilate;
+} hdof_mask_params;
+
+/* Post-process gather filter.  n_taps in [1, 256]; tile in {4, 8, 16}:
+ * CoC tile edge in pixels; r_cap in [0, 256]: largest gather radius (px);
+ * bg_ramp_px > 0: width of the background clamp ramp in CoC pixels. */
+typedef struct {
+  int32_t n_taps, tile;
+  float r_cap, bg_ramp_px;
+} hdof_pp_params;
+
+/* Composite.  h_t > 0: hit ratio below which far pixels blend towards the
+ * ray-traced colour; rt_override != 0: output the ray-traced colour wherever
+ * a pixel was traced (full ray-traced reference mode). */
+typedef struct {
+  float h_t;
+  int32_t rt_override;
+} hdof_composite_params;
+
+typedef struct {
+  hdof_mask_params mask;
+  hdof_pp_params pp;
+  hdof_composite_params comp;
+} hdof_frame_params;
+
+/* G-buffer planes: depth [H][W] (axial, 1e4 on a miss), normal [3][H][W]
+ * (face normal facing the viewer; 0 on a miss), albedo [3][H][W], color
+ * [3][H][W] (shaded sharp image C_r), tri_id [H][W] (input triangle index,
+ * -1 on a miss). */
+typedef struct {
+  float *depth, *normal, *albedo, *color;
+  int32_t* tri_id;
+} hdof_gbuffer_bufs;
+
+/* Per-pixel ray-trace results: c_near, c_far [3][H][W] (near- and far-field
+ * weighted mean colours), hit_ratio [H][W] (near weight / rays), lum_m1,
+ * lum_m2 [H][W] (mean luminance and mean squared luminance of the rays).
+ * All zero where no ray was traced. */
+typedef struct {
+  float *c_near, *c_far, *hit_ratio, *lum_m1, *lum_m2;
+} hdof_rt_bufs;
+
+/* Optional caller-owned intermediates of hdof_frame.  A NULL member makes the
+ * frame use library scratch for that buffer. */
+typedef struct {
+  hdof_gbuffer_bufs gb;
+  uint8_t* spp;      /* [H][W] */
+  int32_t* offsets;  /* [H][W] */
+  int32_t* total;    /* [1] */
+  hdof_rt_bufs rt;
+  float* pp;         /* [3][H][W] */
+} hdof_frame_bufs;
+
+typedef struct {
+  int32_t n_tris, n_nodes, max_depth, leaf_size;
+  int64_t device_bytes;
+} hdof_scene_info;
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (must be gfx950, else
+ * HDOF_ERR_UNSUPPORTED).  Makes `device` current on the calling thread. */
+hdof_status hdof_create(int device, hdof_ctx** out);
+/* Synchronises the device, then frees all library scratch. NULL is a no-op. */
+void hdof_destroy(hdof_ctx* ctx);
+const char* hdof_status_str(hdof_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* hdof_last_error(void);
+/* Waits for `stream`, then reports and clears device-side flags
+ * (HDOF_ERR_CAPACITY after a traversal stack overflow). */
+hdof_status hdof_sync(hdof_ctx* ctx, hdof_stream stream);
+
+/* ---------------------------------------------------------------------- */
+/* Scene (acceleration structure; the paper uses the driver's hardware BVH) */
+/* ---------------------------------------------------------------------- */
+
+/* Build a linear BVH (Morton order, Karras-style hierarchy, bottom-up refit)
+ * over n_tris triangles.  d_verts: n_tris x 9 floats (v0.xyz v1.xyz v2.xyz);
+ * d_albedo: n_tris x 3 floats.  The inputs are read on `stream` and may be
+ * freed once the stream has passed this call.  n_tris in [1, 2^26].
+ * *out is owned by the caller and freed with hdof_scene_destroy. */
+hdof_status hdof_build_bvh(hdof_ctx* ctx, const float* d_verts, const float* d_albedo,
+                           int32_t n_tris, hdof_scene** out, hdof_stream stream);
+/* Synchronises the device, then frees the scene.  NULL is a no-op. */
+void hdof_scene_destroy(hdof_scene* scene);
+/* Synchronises the device and reports node count, tree depth and bytes. */
+hdof_status hdof_scene_stats(hdof_scene* scene, hdof_scene_info* out);
+
+/* ---------------------------------------------------------------------- */
+/* Hot-path stages                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* G-buffer (paper, Design): one pinhole ray per pixel centre (lens offset 0),
+ * closest hit (smallest t > 0, ties to the lowest triangle index), face
+ * normal, albedo and two-sided Lambertian colour (no shadow rays).  All five
+ * planes of `out` must be non-NULL. */
+hdof_status hdof_gbuffer(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
+                         const hdof_lens* lens, const hdof_light* light,
+                         hdof_gbuffer_bufs out, hdof_stream stream);
+
+/* Adaptive ray mask (paper, Ray Trace).  Reads in->depth and in->normal.
+ * Score m = max(g_z / tau_depth, g_n / tau_normal, V / tau_var), where g_z and
+ * g_n are Sobel magnitudes of the Gaussian-blurred depth (relative to depth)
+ * and normal, and V the variance of the reprojected luminance history
+ * (+inf where the history is new, 0 without history).  Per-pixel count
+ * min(spp_max, ceil(m)) for m >= 1, else 0; tile max; dilation over tiles.
+ * Writes d_spp [H][W], d_offsets [H][W] (exclusive prefix sum of d_spp in
+ * pixel order) and d_total [1].  prev == NULL: no history (first frame or a
+ * camera cut); otherwise the context's history (written by the previous
+ * hdof_variance_update at prev's resolution) is reprojected into the current
+ * frame and kept for the next hdof_variance_update. */
+hdof_status hdof_ray_mask(hdof_ctx* ctx, const hdof_gbuffer_bufs* in, const hdof_camera* cam,
+                          const hdof_camera* prev, const hdof_lens* lens,
+                          const hdof_mask_params* params, uint8_t* d_spp, int32_t* d_offsets,
+                          int32_t* d_total, hdof_stream stream);
+
+/* Thin-lens distributed ray trace of the masked pixels (paper, Ray Trace).
+ * Sample j of pixel p draws Philox4x64-10 with counter (p, j, view, 0) and
+ * key (seed, frame); the top 24 bits of words 0 and 1 give u0, u1; lens point
+ * (A/2) sqrt(u0) (cos 2 pi u1, sin 2 pi u1) in the right/up plane; the ray
+ * aims through the pixel's focus-plane point.  Per pixel over its d_spp[p]
+ * rays: near weight w = clamp(0.5 - c(z)/(2 sqrt 2), 0, 1) of each hit depth z,
+ * c_near / c_far = w- and (1-w)-weighted mean colours, hit_ratio = sum w / s,
+ * luminance moments.  d_offsets must be the exclusive prefix sum of d_spp and
+ * *d_total its sum (as hdof_ray_mask writes them); d_total stays on the
+ * device.  Optional debug outputs per queue entry (index d_offsets[p] + j):
+ * d_ray_tri_id (hit triangle, -1 on miss) and d_ray_depth (axial depth);
+ * each needs W*H*spp_max entries. */
+hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
+                                 const hdof_lens* lens, const hdof_light* light, int32_t spp_max,
+                                 const uint8_t* d_spp, const int32_t* d_offsets,
+                                 const int32_t* d_total, uint32_t seed, uint32_t frame,
+                                 uint32_t view, hdof_rt_bufs out, int32_t* d_ray_tri_id,
+                                 float* d_ray_depth, hdof_stream stream);
+
+/* Variance history update (paper, Ray Trace: temporally accumulated variance).
+ * Where traced: EMA with weight params->var_alpha over the reprojected
+ * history, or a restart flagged "new" where no history was valid; where not
+ * traced: the reprojected history is carried.  Stores d_depth as the history
+ * depth for the next frame's reprojection depth test.  Must follow the
+ * hdof_ray_mask call of the same frame. */
+hdof_status hdof_variance_update(hdof_ctx* ctx, const hdof_camera* cam,
+                                 const hdof_mask_params* params, const uint8_t* d_spp,
+                                 const float* d_depth, const float* d_lum_m1,
+                                 const float* d_lum_m2, hdof_stream stream);
+
+/* Replace / read / clear the context's variance history (width x height;
+ * flags bit0 = valid, bit1 = new).  Load/save enqueue copies on `stream`. */
+hdof_status hdof_history_load(hdof_ctx* ctx, int32_t width, int32_t height, const float* d_lum_m1,
+                              const float* d_lum_m2, const uint8_t* d_flags,
+                              const float* d_depth, hdof_stream stream);
+hdof_status hdof_history_save(hdof_ctx* ctx, float* d_lum_m1, float* d_lum_m2, uint8_t* d_flags,
+                              float* d_depth, hdof_stream stream);
+hdof_status hdof_history_reset(hdof_ctx* ctx);
+
+/* Post-process gather DoF filter (paper, Design: adapted post-process; the
+ * CoC-radius rejection of Reconstruction).  Gather radius = min(r_cap, max
+ * CoC radius over the tiles within ceil(r_cap / tile) tiles); n_taps
+ * golden-angle taps u_k = sqrt((k - 0.5)/n) (cos k g, sin k g),
+ * g = pi (3 - sqrt 5); bilinear colour + signed CoC; a tap at distance d
+ * counts with clamp(r_eff - d + 0.5, 0, 1), r_eff its CoC radius clamped to
+ * the centre's when it lies behind; weights (R^2/n) / max(r, 0.5)^2, centre
+ * 1 / max(r_p, 0.5)^2.  d_color [3][H][W], d_depth [H][W] -> d_out [3][H][W]
+ * (must not alias d_color). */
+hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                            const hdof_camera* cam, const hdof_lens* lens,
+                            const hdof_pp_params* params, float* d_out, hdof_stream stream);
+
+/* Composite (paper, Composite).  phi = clamp(|c| - sqrt 2, 0, 1) blends the
+ * sharp colour (focus zone |c| < sqrt 2) with the out-of-focus colour; near
+ * field: ray-traced colour where traced, else post-process; far field:
+ * beta = clamp(1 - h / h_t, 0, 1) of ray-traced over post-process where
+ * traced.  C_rt = h c_near + (1 - h) c_far.  d_out may alias d_pp. */
+hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_pp,
+                           const float* d_depth, const uint8_t* d_spp, hdof_rt_bufs rt,
+                           const hdof_camera* cam, const hdof_lens* lens,
+                           const hdof_composite_params* params, float* d_out, hdof_stream stream);
+
+/* Whole frame: G-buffer -> mask (reprojecting the history when prev != NULL)
+ * -> trace -> variance update -> post-process -> composite.  d_out
+ * [3][H][W].  `keep` (nullable) supplies caller buffers for intermediates. */
+hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
+                       const hdof_camera* prev, const hdof_lens* lens, const hdof_light* light,
+                       const hdof_frame_params* params, uint32_t seed, uint32_t frame,
+                       uint32_t view, float* d_out, const hdof_frame_bufs* keep,
+                       hdof_stream stream);
+
+/* ---------------------------------------------------------------------- */
+/* Stage timing                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Stages hdof_frame brackets with HIP events while profiling is on, in
+ * order: G-buffer, ray mask, queue build, thin-lens trace kernel, per-pixel
+ * reduction, variance update, post-filter preparation (pack, tile radius,
+ * taps), post-filter gather, composite. */
+#define HDOF_PROFILE_STAGES 9
+
+/* Start recording stage events in every following hdof_frame call (events
+ * are recorded on the frame's stream; the host is not synchronised). */
+hdof_status hdof_profile_begin(hdof_ctx* ctx);
+/* Synchronise, stop recording and return the mean duration in milliseconds
+ * of each stage over the recorded frames (ms_out[HDOF_PROFILE_STAGES]) and
+ * the number of frames (*n_frames, may be NULL). */
+hdof_status hdof_profile_end(hdof_ctx* ctx, float* ms_out, int32_t* n_frames);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDOF_H */

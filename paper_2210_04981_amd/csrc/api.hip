@@ -1,0 +1,537 @@
+// api.hip -- the C ABI declared in include/hdof.h: argument validation,
+// context and scene lifetimes, scratch management, stage sequencing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "hdof_internal.h"
+
+static thread_local char g_err[512] = "";
+
+hdof_status hdof_set_error(hdof_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+hdof_status hdof_ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (b.bytes >= bytes) return HDOF_OK;
+  if (b.p) {
+    // the old buffer may still be read by work in flight
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hdof_set_error(HDOF_ERR_HIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;  // some slack so small growth does not reallocate
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return hdof_set_error(HDOF_ERR_OOM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+  }
+  b.bytes = want;
+  return HDOF_OK;
+}
+
+static void buf_free(Buf& b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+#define REQUIRE(cond, ...)                                      \
+  do {                                                          \
+    if (!(cond)) return hdof_set_error(HDOF_ERR_INVALID_ARG, __VA_ARGS__); \
+  } while (0)
+
+static bool finite3(const float* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+static hdof_status check_camera(const hdof_camera* c, const char* what) {
+  REQUIRE(c, "%s camera is NULL", what);
+  REQUIRE(c->width > 0 && c->height > 0 && c->width <= 16384 && c->height <= 16384,
+          "%s camera size %dx%d outside [1, 16384]", what, c->width, c->height);
+  REQUIRE(isfinite(c->tan_half_fov_x) && c->tan_half_fov_x > 0.0f && c->tan_half_fov_x < 1e4f,
+          "%s camera tan_half_fov_x must be finite and > 0", what);
+  REQUIRE(finite3(c->eye) && finite3(c->right) && finite3(c->up) && finite3(c->fwd),
+          "%s camera vectors must be finite", what);
+  return HDOF_OK;
+}
+
+static hdof_status check_lens(const hdof_lens* l) {
+  REQUIRE(l, "lens is NULL");
+  REQUIRE(isfinite(l->focal_length) && l->focal_length > 0.0f, "focal_length must be > 0");
+  REQUIRE(isfinite(l->aperture) && l->aperture >= 0.0f, "aperture must be >= 0");
+  REQUIRE(isfinite(l->focus_distance) && l->focus_distance > l->focal_length,
+          "focus_distance (S1) must exceed the focal length");
+  return HDOF_OK;
+}
+
+static hdof_status check_light(const hdof_light* l) {
+  REQUIRE(l, "light is NULL");
+  REQUIRE(finite3(l->pos) && finite3(l->intensity) && finite3(l->ambient), "light values must be finite");
+  return HDOF_OK;
+}
+
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+static hdof_status check_mask(const hdof_mask_params* m) {
+  REQUIRE(m, "mask params are NULL");
+  REQUIRE(isfinite(m->sigma) && m->sigma > 0.0f && m->sigma <= 2.0f, "mask sigma must be in (0, 2]");
+  REQUIRE(m->tau_depth > 0.0f && m->tau_normal > 0.0f && m->tau_var > 0.0f && isfinite(m->tau_depth) &&
+              isfinite(m->tau_normal) && isfinite(m->tau_var),
+          "mask thresholds must be finite and > 0");
+  REQUIRE(m->var_alpha >= 0.0f && m->var_alpha <= 1.0f, "var_alpha must be in [0, 1]");
+  REQUIRE(m->spp_max >= 1 && m->spp_max <= 255, "spp_max must be in [1, 255]");
+  REQUIRE(pow2_in(m->tile, 1, 16), "mask tile must be 1, 2, 4, 8 or 16");
+  REQUIRE(m->dilate >= 0 && m->dilate <= 8, "mask dilate must be in [0, 8]");
+  return HDOF_OK;
+}
+
+static hdof_status check_pp(const hdof_pp_params* p) {
+  REQUIRE(p, "post-filter params are NULL");
+  REQUIRE(p->n_taps >= 1 && p->n_taps <= 256, "n_taps must be in [1, 256]");
+  REQUIRE(pow2_in(p->tile, 4, 16), "post-filter tile must be 4, 8 or 16");
+  REQUIRE(isfinite(p->r_cap) && p->r_cap >= 0.0f && p->r_cap <= 256.0f, "r_cap must be in [0, 256]");
+  REQUIRE(isfinite(p->bg_ramp_px) && p->bg_ramp_px > 0.0f, "bg_ramp_px must be > 0");
+  return HDOF_OK;
+}
+
+static hdof_status check_comp(const hdof_composite_params* c) {
+  REQUIRE(c, "composite params are NULL");
+  REQUIRE(isfinite(c->h_t) && c->h_t > 0.0f, "h_t must be > 0");
+  return HDOF_OK;
+}
+
+#define TRY(x)                        \
+  do {                                \
+    hdof_status s_ = (x);             \
+    if (s_ != HDOF_OK) return s_;     \
+  } while (0)
+
+static hdof_status check_ctx(hdof_ctx* ctx) {
+  REQUIRE(ctx, "context is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hdof_set_error(HDOF_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+  return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" const char* hdof_status_str(hdof_status s) {
+  switch (s) {
+    case HDOF_OK: return "HDOF_OK";
+    case HDOF_ERR_INVALID_ARG: return "HDOF_ERR_INVALID_ARG";
+    case HDOF_ERR_UNSUPPORTED: return "HDOF_ERR_UNSUPPORTED";
+    case HDOF_ERR_OOM: return "HDOF_ERR_OOM";
+    case HDOF_ERR_CAPACITY: return "HDOF_ERR_CAPACITY";
+    case HDOF_ERR_HIP: return "HDOF_ERR_HIP";
+  }
+  return "HDOF_ERR_UNKNOWN";
+}
+
+extern "C" const char* hdof_last_error(void) { return g_err; }
+
+extern "C" hdof_status hdof_create(int device, hdof_ctx** out) {
+  REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return hdof_set_error(HDOF_ERR_UNSUPPORTED, "no HIP device available");
+  REQUIRE(device >= 0 && device < n, "device %d out of range [0, %d)", device, n);
+  hipDeviceProp_t prop;
+  HDOF_HIP(hipGetDeviceProperties(&prop, device));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "device %d is %s, this library is built for gfx950", device,
+                          prop.gcnArchName);
+  HDOF_HIP(hipSetDevice(device));
+  hdof_ctx* c = new hdof_ctx();
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  e = hipMalloc(&c->d_flags, sizeof(int));
+  if (e != hipSuccess) {
+    delete c;
+    return hdof_set_error(HDOF_ERR_OOM, "hipMalloc(flags): %s", hipGetErrorString(e));
+  }
+  e = hipMemset(c->d_flags, 0, sizeof(int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    hipFree(c->d_flags);
+    delete c;
+    return hdof_set_error(HDOF_ERR_HIP, "init: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return HDOF_OK;
+}
+
+extern "C" void hdof_destroy(hdof_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  Buf* all[] = {&ctx->queue, &ctx->ray_col, &ctx->ray_z, &ctx->work_counter, &ctx->mask_tile,
+                &ctx->mask_tile_dil, &ctx->mask_xpref, &ctx->mask_rowsum, &ctx->mask_ybase,
+                &ctx->pp_pack, &ctx->pp_tile, &ctx->pp_rad, &ctx->pp_taps, &ctx->hist_m1,
+                &ctx->hist_m2, &ctx->hist_flags, &ctx->hist_z, &ctx->rep_m1, &ctx->rep_m2,
+                &ctx->rep_flags, &ctx->f_depth, &ctx->f_normal, &ctx->f_albedo, &ctx->f_color,
+                &ctx->f_triid, &ctx->f_spp, &ctx->f_offsets, &ctx->f_total, &ctx->f_cn, &ctx->f_cf,
+                &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp};
+  for (Buf* b : all) buf_free(*b);
+  for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
+  if (ctx->d_flags) hipFree(ctx->d_flags);
+  delete ctx;
+}
+
+extern "C" hdof_status hdof_sync(hdof_ctx* ctx, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  HDOF_HIP(hipStreamSynchronize((hipStream_t)stream));
+  int f = 0;
+  HDOF_HIP(hipMemcpy(&f, ctx->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+  if (f) {
+    HDOF_HIP(hipMemset(ctx->d_flags, 0, sizeof(int)));
+    HDOF_HIP(hipDeviceSynchronize());
+    if (f & HDOF_FLAG_STACK_OVERFLOW)
+      return hdof_set_error(HDOF_ERR_CAPACITY, "traversal stack overflow (tree deeper than %d)",
+                            HDOF_LDS_STACK + HDOF_SPILL_STACK);
+    return hdof_set_error(HDOF_ERR_CAPACITY, "ray total exceeded the queue capacity (spp above spp_max)");
+  }
+  return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scene
+// ---------------------------------------------------------------------------
+extern "C" hdof_status hdof_build_bvh(hdof_ctx* ctx, const float* d_verts, const float* d_albedo,
+                                      int32_t n_tris, hdof_scene** out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  REQUIRE(d_verts && d_albedo, "vertex and albedo pointers must be non-NULL");
+  REQUIRE(n_tris >= 1 && n_tris <= (1 << 26), "n_tris %d outside [1, 2^26]", n_tris);
+  hdof_scene* sc = new hdof_scene();
+  sc->ctx = ctx;
+  sc->n_tris = n_tris;
+  hdof_status s = launch_bvh_build(ctx, d_verts, d_albedo, n_tris, sc, (hipStream_t)stream);
+  if (s != HDOF_OK) {
+    hdof_scene_destroy(sc);
+    return s;
+  }
+  *out = sc;
+  return HDOF_OK;
+}
+
+extern "C" void hdof_scene_destroy(hdof_scene* sc) {
+  if (!sc) return;
+  hipSetDevice(sc->ctx->device);
+  hipDeviceSynchronize();
+  if (sc->nodes) hipFree(sc->nodes);
+  if (sc->tris) hipFree(sc->tris);
+  if (sc->albedo) hipFree(sc->albedo);
+  if (sc->depth_out) hipFree(sc->depth_out);
+  delete sc;
+}
+
+extern "C" hdof_status hdof_scene_stats(hdof_scene* sc, hdof_scene_info* out) {
+  REQUIRE(sc && out, "scene and out must be non-NULL");
+  TRY(check_ctx(sc->ctx));
+  HDOF_HIP(hipDeviceSynchronize());
+  int d = 0;
+  HDOF_HIP(hipMemcpy(&d, sc->depth_out, sizeof(int), hipMemcpyDeviceToHost));
+  out->n_tris = sc->n_tris;
+  out->n_nodes = sc->n_nodes;
+  out->max_depth = d;
+  out->leaf_size = 0;
+  out->device_bytes = sc->bytes;
+  return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stages
+// ---------------------------------------------------------------------------
+static hdof_status check_gb(const hdof_gbuffer_bufs* b) {
+  REQUIRE(b && b->depth && b->normal && b->albedo && b->color && b->tri_id,
+          "all G-buffer planes must be non-NULL");
+  return HDOF_OK;
+}
+
+static hdof_status check_rt(const hdof_rt_bufs* b) {
+  REQUIRE(b->c_near && b->c_far && b->hit_ratio && b->lum_m1 && b->lum_m2,
+          "all ray-trace result planes must be non-NULL");
+  return HDOF_OK;
+}
+
+static hdof_status check_capacity(const hdof_camera* cam, int spp_max) {
+  REQUIRE((int64_t)cam->width * cam->height * spp_max < ((int64_t)1 << 31),
+          "width * height * spp_max must stay below 2^31");
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_gbuffer(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
+                                    const hdof_lens* lens, const hdof_light* light,
+                                    hdof_gbuffer_bufs out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(scene, "scene is NULL");
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_light(light));
+  TRY(check_gb(&out));
+  CamK k = make_camk(cam);
+  return launch_gbuffer(ctx, scene, k, make_lensk(lens, k), make_lightk(light), out, (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_ray_mask(hdof_ctx* ctx, const hdof_gbuffer_bufs* in, const hdof_camera* cam,
+                                     const hdof_camera* prev, const hdof_lens* lens,
+                                     const hdof_mask_params* params, uint8_t* d_spp, int32_t* d_offsets,
+                                     int32_t* d_total, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(in && in->depth && in->normal, "depth and normal planes must be non-NULL");
+  TRY(check_camera(cam, "current"));
+  if (prev) TRY(check_camera(prev, "previous"));
+  TRY(check_lens(lens));
+  TRY(check_mask(params));
+  TRY(check_capacity(cam, params->spp_max));
+  REQUIRE(d_spp && d_offsets && d_total, "spp, offsets and total must be non-NULL");
+  CamK k = make_camk(cam);
+  CamK pk;
+  if (prev) pk = make_camk(prev);
+  return launch_mask(ctx, in->depth, in->normal, k, prev ? &pk : nullptr, *params, d_spp, d_offsets, d_total,
+                     (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
+                                            const hdof_lens* lens, const hdof_light* light, int32_t spp_max,
+                                            const uint8_t* d_spp, const int32_t* d_offsets,
+                                            const int32_t* d_total, uint32_t seed, uint32_t frame,
+                                            uint32_t view, hdof_rt_bufs out, int32_t* d_ray_tri_id,
+                                            float* d_ray_depth, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(scene, "scene is NULL");
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_light(light));
+  REQUIRE(spp_max >= 1 && spp_max <= 255, "spp_max must be in [1, 255]");
+  TRY(check_capacity(cam, spp_max));
+  REQUIRE(d_spp && d_offsets && d_total, "spp, offsets and total must be non-NULL");
+  TRY(check_rt(&out));
+  CamK k = make_camk(cam);
+  return launch_trace(ctx, scene, k, make_lensk(lens, k), make_lightk(light), spp_max, d_spp, d_offsets,
+                      d_total, seed, frame, view, out, d_ray_tri_id, d_ray_depth, (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_variance_update(hdof_ctx* ctx, const hdof_camera* cam,
+                                            const hdof_mask_params* params, const uint8_t* d_spp,
+                                            const float* d_depth, const float* d_lum_m1,
+                                            const float* d_lum_m2, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_camera(cam, "current"));
+  TRY(check_mask(params));
+  REQUIRE(d_spp && d_depth && d_lum_m1 && d_lum_m2, "spp, depth and moment planes must be non-NULL");
+  CamK k = make_camk(cam);
+  return launch_var_update(ctx, k, params->var_alpha, d_spp, d_depth, d_lum_m1, d_lum_m2, (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_history_load(hdof_ctx* ctx, int32_t width, int32_t height, const float* d_lum_m1,
+                                         const float* d_lum_m2, const uint8_t* d_flags,
+                                         const float* d_depth, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(width > 0 && height > 0 && width <= 16384 && height <= 16384, "history size out of range");
+  REQUIRE(d_lum_m1 && d_lum_m2 && d_flags && d_depth, "history planes must be non-NULL");
+  size_t N = (size_t)width * height;
+  TRY(hdof_ensure(ctx->hist_m1, 4 * N));
+  TRY(hdof_ensure(ctx->hist_m2, 4 * N));
+  TRY(hdof_ensure(ctx->hist_flags, N));
+  TRY(hdof_ensure(ctx->hist_z, 4 * N));
+  hipStream_t st = (hipStream_t)stream;
+  HDOF_HIP(hipMemcpyAsync(ctx->hist_m1.p, d_lum_m1, 4 * N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(ctx->hist_m2.p, d_lum_m2, 4 * N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(ctx->hist_flags.p, d_flags, N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(ctx->hist_z.p, d_depth, 4 * N, hipMemcpyDeviceToDevice, st));
+  ctx->hist_w = width;
+  ctx->hist_h = height;
+  ctx->hist_any = true;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_history_save(hdof_ctx* ctx, float* d_lum_m1, float* d_lum_m2, uint8_t* d_flags,
+                                         float* d_depth, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(ctx->hist_any, "the context holds no history");
+  REQUIRE(d_lum_m1 && d_lum_m2 && d_flags && d_depth, "history planes must be non-NULL");
+  size_t N = (size_t)ctx->hist_w * ctx->hist_h;
+  hipStream_t st = (hipStream_t)stream;
+  HDOF_HIP(hipMemcpyAsync(d_lum_m1, ctx->hist_m1.p, 4 * N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(d_lum_m2, ctx->hist_m2.p, 4 * N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(d_flags, ctx->hist_flags.p, N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(d_depth, ctx->hist_z.p, 4 * N, hipMemcpyDeviceToDevice, st));
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_history_reset(hdof_ctx* ctx) {
+  TRY(check_ctx(ctx));
+  HDOF_HIP(hipDeviceSynchronize());
+  ctx->hist_any = false;
+  ctx->hist_w = ctx->hist_h = 0;
+  ctx->rep_valid = false;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                                       const hdof_camera* cam, const hdof_lens* lens,
+                                       const hdof_pp_params* params, float* d_out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(d_color && d_depth && d_out, "color, depth and out must be non-NULL");
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_pp(params));
+  CamK k = make_camk(cam);
+  return launch_postfilter(ctx, d_color, d_depth, k, make_lensk(lens, k), *params, d_out, (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_pp,
+                                      const float* d_depth, const uint8_t* d_spp, hdof_rt_bufs rt,
+                                      const hdof_camera* cam, const hdof_lens* lens,
+                                      const hdof_composite_params* params, float* d_out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(d_color && d_pp && d_depth && d_spp && d_out, "color, pp, depth, spp and out must be non-NULL");
+  TRY(check_rt(&rt));
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_comp(params));
+  CamK k = make_camk(cam);
+  return launch_composite(ctx, d_color, d_pp, d_depth, d_spp, rt, k, make_lensk(lens, k), *params, d_out,
+                          (hipStream_t)stream);
+}
+
+template <typename T>
+static hdof_status pick_buf(T* user, Buf& scratch, size_t bytes, T** out) {
+  if (user) {
+    *out = user;
+    return HDOF_OK;
+  }
+  TRY(hdof_ensure(scratch, bytes));
+  *out = (T*)scratch.p;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
+                                  const hdof_camera* prev, const hdof_lens* lens, const hdof_light* light,
+                                  const hdof_frame_params* params, uint32_t seed, uint32_t frame,
+                                  uint32_t view, float* d_out, const hdof_frame_bufs* keep,
+                                  hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(scene, "scene is NULL");
+  TRY(check_camera(cam, "current"));
+  if (prev) TRY(check_camera(prev, "previous"));
+  TRY(check_lens(lens));
+  TRY(check_light(light));
+  REQUIRE(params, "frame params are NULL");
+  TRY(check_mask(&params->mask));
+  TRY(check_pp(&params->pp));
+  TRY(check_comp(&params->comp));
+  TRY(check_capacity(cam, params->mask.spp_max));
+  REQUIRE(d_out, "out is NULL");
+  hdof_frame_bufs z;
+  memset(&z, 0, sizeof z);
+  const hdof_frame_bufs& u = keep ? *keep : z;
+  const size_t N = (size_t)cam->width * cam->height;
+  hdof_gbuffer_bufs gb;
+  hdof_rt_bufs rt;
+  uint8_t* spp;
+  int32_t *offs, *total;
+  float* pp;
+  TRY(pick_buf(u.gb.depth, ctx->f_depth, 4 * N, &gb.depth));
+  TRY(pick_buf(u.gb.normal, ctx->f_normal, 12 * N, &gb.normal));
+  TRY(pick_buf(u.gb.albedo, ctx->f_albedo, 12 * N, &gb.albedo));
+  TRY(pick_buf(u.gb.color, ctx->f_color, 12 * N, &gb.color));
+  TRY(pick_buf(u.gb.tri_id, ctx->f_triid, 4 * N, &gb.tri_id));
+  TRY(pick_buf(u.spp, ctx->f_spp, N, &spp));
+  TRY(pick_buf(u.offsets, ctx->f_offsets, 4 * N, &offs));
+  TRY(pick_buf(u.total, ctx->f_total, 4, &total));
+  TRY(pick_buf(u.rt.c_near, ctx->f_cn, 12 * N, &rt.c_near));
+  TRY(pick_buf(u.rt.c_far, ctx->f_cf, 12 * N, &rt.c_far));
+  TRY(pick_buf(u.rt.hit_ratio, ctx->f_h, 4 * N, &rt.hit_ratio));
+  TRY(pick_buf(u.rt.lum_m1, ctx->f_m1, 4 * N, &rt.lum_m1));
+  TRY(pick_buf(u.rt.lum_m2, ctx->f_m2, 4 * N, &rt.lum_m2));
+  TRY(pick_buf(u.pp, ctx->f_pp, 12 * N, &pp));
+  hipStream_t st = (hipStream_t)stream;
+  CamK k = make_camk(cam);
+  LensK l = make_lensk(lens, k);
+  LightK li = make_lightk(light);
+  CamK pk;
+  if (prev) pk = make_camk(prev);
+  // reserve every scratch buffer before the first launch so no reallocation
+  // (and its device synchronisation) happens between profiled stages
+  const size_t cap = N * (size_t)params->mask.spp_max;
+  TRY(hdof_ensure(ctx->queue, sizeof(int) * cap));
+  TRY(hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap));
+  TRY(hdof_ensure(ctx->ray_z, sizeof(float) * cap));
+  ctx->prof_in_frame = true;
+  hdof_prof_mark(ctx, 0, st);
+  hdof_status s = launch_gbuffer(ctx, scene, k, l, li, gb, st);
+  hdof_prof_mark(ctx, 1, st);
+  if (s == HDOF_OK)
+    s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st);
+  hdof_prof_mark(ctx, 2, st);
+  if (s == HDOF_OK)
+    s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt,
+                     nullptr, nullptr, st);  // marks 3, 4, 5
+  if (s == HDOF_OK) s = launch_var_update(ctx, k, params->mask.var_alpha, spp, gb.depth, rt.lum_m1, rt.lum_m2, st);
+  hdof_prof_mark(ctx, 6, st);
+  if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st);  // mark 7
+  hdof_prof_mark(ctx, 8, st);
+  if (s == HDOF_OK) s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st);
+  hdof_prof_mark(ctx, 9, st);
+  ctx->prof_in_frame = false;
+  if (s == HDOF_OK && ctx->prof_on) ctx->prof_frames++;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// stage profiling
+// ---------------------------------------------------------------------------
+void hdof_prof_mark(hdof_ctx* ctx, int i, hipStream_t st) {
+  if (!ctx->prof_on || !ctx->prof_in_frame) return;
+  size_t idx = (size_t)ctx->prof_frames * (HDOF_PROFILE_STAGES + 1) + i;
+  while (ctx->prof_events.size() <= idx) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    ctx->prof_events.push_back(e);
+  }
+  (void)hipEventRecord(ctx->prof_events[idx], st);
+}
+
+extern "C" hdof_status hdof_profile_begin(hdof_ctx* ctx) {
+  TRY(check_ctx(ctx));
+  ctx->prof_on = true;
+  ctx->prof_frames = 0;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_profile_end(hdof_ctx* ctx, float* ms_out, int32_t* n_frames) {
+  TRY(check_ctx(ctx));
+  REQUIRE(ms_out, "ms_out is NULL");
+  HDOF_HIP(hipDeviceSynchronize());
+  const int S = HDOF_PROFILE_STAGES;
+  for (int i = 0; i < S; ++i) ms_out[i] = 0.0f;
+  for (int f = 0; f < ctx->prof_frames; ++f)
+    for (int i = 0; i < S; ++i) {
+      float ms = 0.0f;
+      HDOF_HIP(hipEventElapsedTime(&ms, ctx->prof_events[(size_t)f * (S + 1) + i],
+                                   ctx->prof_events[(size_t)f * (S + 1) + i + 1]));
+      ms_out[i] += ms;
+    }
+  if (ctx->prof_frames > 0)
+    for (int i = 0; i < S; ++i) ms_out[i] /= (float)ctx->prof_frames;
+  if (n_frames) *n_frames = ctx->prof_frames;
+  ctx->prof_on = false;
+  ctx->prof_frames = 0;
+  return HDOF_OK;
+}

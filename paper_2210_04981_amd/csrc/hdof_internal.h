@@ -1,0 +1,225 @@
+// hdof_internal.h -- device helpers and library-internal types of the
+// gfx950 hybrid depth-of-field path.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/hdof.h"
+
+#define HDOF_ZMAX 1.0e4f
+#define HDOF_SQRT2 1.41421356237309505f
+#define HDOF_PI 3.14159265358979324f
+
+// traversal stack: this many entries per lane live in LDS, the rest spill to
+// a small private array; beyond both the ray sets the overflow flag.
+#define HDOF_LDS_STACK 20
+#define HDOF_SPILL_STACK 44
+#define HDOF_TRACE_BLOCK 128
+
+// device flag bits (ctx->d_flags)
+#define HDOF_FLAG_STACK_OVERFLOW 1
+#define HDOF_FLAG_CAPACITY 2
+
+// history flag bits
+#define HDOF_HIST_VALID 1
+#define HDOF_HIST_NEW 2
+
+// leaf child encoding: bit 31 set, bits 27..30 = count - 1, bits 0..26 = first
+#define HDOF_LEAF_BIT 0x80000000u
+#define HDOF_LEAF_FIRST_MASK 0x07FFFFFFu
+
+struct hdof_scene {
+  hdof_ctx* ctx;
+  int32_t n_tris;
+  int32_t n_nodes;
+  float4* nodes;   // 4 float4 per node: child boxes x/y (2), z (1), children (1)
+  float4* tris;    // 3 float4 per triangle in leaf order; .w of the first = input index
+  float* albedo;   // 3 floats per triangle, input order
+  int32_t* depth_out;  // [1] tree depth (computed at build)
+  int64_t bytes;
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct hdof_ctx {
+  int device = 0;
+  int n_cu = 0;
+  int* d_flags = nullptr;  // device-side fault flags
+  // trace scratch
+  Buf queue, ray_col, ray_z, work_counter;
+  // mask scratch
+  Buf mask_tile, mask_tile_dil, mask_xpref, mask_rowsum, mask_ybase;
+  // post-filter scratch
+  Buf pp_pack, pp_tile, pp_rad, pp_taps;
+  // variance history (previous frame) and its reprojection into this frame
+  int hist_w = 0, hist_h = 0;
+  bool hist_any = false;
+  Buf hist_m1, hist_m2, hist_flags, hist_z;
+  int rep_w = 0, rep_h = 0;
+  bool rep_valid = false;
+  Buf rep_m1, rep_m2, rep_flags;
+  // frame intermediates when the caller keeps none
+  Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
+  Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
+  // stage profiling: HDOF_PROFILE_STAGES + 1 events per profiled frame
+  bool prof_on = false, prof_in_frame = false;
+  int prof_frames = 0;
+  std::vector<hipEvent_t> prof_events;
+};
+
+// record stage boundary `i` of the current profiled frame (no-op when off)
+void hdof_prof_mark(hdof_ctx* ctx, int i, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// host-side helpers (api.hip)
+// ---------------------------------------------------------------------------
+hdof_status hdof_set_error(hdof_status s, const char* fmt, ...);
+hdof_status hdof_ensure(Buf& b, size_t bytes);
+#define HDOF_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return hdof_set_error(HDOF_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// small vector math (float3 with explicit fma order)
+// ---------------------------------------------------------------------------
+struct V3 {
+  float x, y, z;
+};
+__host__ __device__ inline V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__host__ __device__ inline V3 v3(const float* p) { return V3{p[0], p[1], p[2]}; }
+__device__ inline V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline V3 operator*(float s, V3 a) { return V3{s * a.x, s * a.y, s * a.z}; }
+__device__ inline float dot3(V3 a, V3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ inline V3 cross3(V3 a, V3 b) {
+  return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ inline float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+__device__ inline float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// camera constants gathered once per launch
+struct CamK {
+  V3 e, r, u, w;
+  float tx, ty, spx;
+  int W, H;
+};
+inline CamK make_camk(const hdof_camera* c) {
+  CamK k;
+  k.e = v3(c->eye);
+  k.r = v3(c->right);
+  k.u = v3(c->up);
+  k.w = v3(c->fwd);
+  k.tx = c->tan_half_fov_x;
+  k.ty = (float)((double)c->tan_half_fov_x * c->height / c->width);
+  k.spx = (float)((double)c->width / (2.0 * c->tan_half_fov_x));
+  k.W = c->width;
+  k.H = c->height;
+  return k;
+}
+
+// pinhole direction through the centre of pixel (x, y), unit forward part
+__device__ inline V3 pixel_dir(const CamK& k, int x, int y) {
+  float sx = ((float)(2 * x + 1) / (float)k.W - 1.0f) * k.tx;
+  float sy = (1.0f - (float)(2 * y + 1) / (float)k.H) * k.ty;
+  return V3{fmaf(sy, k.u.x, fmaf(sx, k.r.x, k.w.x)), fmaf(sy, k.u.y, fmaf(sx, k.r.y, k.w.y)),
+            fmaf(sy, k.u.z, fmaf(sx, k.r.z, k.w.z))};
+}
+
+// signed CoC diameter in pixels: A (1/S1 - 1/z) s_px
+struct LensK {
+  float f, A, S1, invS1, coc_scale;  // coc_scale = A * s_px
+};
+inline LensK make_lensk(const hdof_lens* l, const CamK& k) {
+  LensK q;
+  q.f = l->focal_length;
+  q.A = l->aperture;
+  q.S1 = l->focus_distance;
+  q.invS1 = 1.0f / l->focus_distance;
+  q.coc_scale = l->aperture * k.spx;
+  return q;
+}
+__device__ inline float coc_px(const LensK& l, float z) { return l.coc_scale * (l.invS1 - 1.0f / z); }
+
+struct LightK {
+  V3 p, I, ka;
+};
+inline LightK make_lightk(const hdof_light* l) {
+  LightK q;
+  q.p = v3(l->pos);
+  q.I = v3(l->intensity);
+  q.ka = v3(l->ambient);
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): 10 rounds of two 64x64 -> 128-bit
+// multiplies, key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                     uint64_t k1, uint64_t& o0, uint64_t& o1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  o0 = c0;
+  o1 = c1;
+}
+
+// thin-lens ray for sample j of pixel (x, y); pinhole when A == 0
+__device__ inline void lens_ray(const CamK& k, const LensK& l, int x, int y, uint32_t j, uint32_t view,
+                                uint32_t seed, uint32_t frame, V3& O, V3& D) {
+  V3 v = pixel_dir(k, x, y);
+  uint64_t w0, w1;
+  philox4x64_10((uint64_t)y * (uint64_t)k.W + (uint64_t)x, j, view, 0, seed, frame, w0, w1);
+  float u0 = (float)(uint32_t)(w0 >> 40) * (1.0f / 16777216.0f);
+  float u1 = (float)(uint32_t)(w1 >> 40) * (1.0f / 16777216.0f);
+  float rho = 0.5f * l.A * sqrtf(u0);
+  float s, c;
+  sincospif(2.0f * u1, &s, &c);
+  float lx = rho * c, ly = rho * s;
+  V3 lv = V3{fmaf(ly, k.u.x, lx * k.r.x), fmaf(ly, k.u.y, lx * k.r.y), fmaf(ly, k.u.z, lx * k.r.z)};
+  O = k.e + lv;
+  D = V3{fmaf(l.S1, v.x, -lv.x), fmaf(l.S1, v.y, -lv.y), fmaf(l.S1, v.z, -lv.z)};
+}
+
+// ---------------------------------------------------------------------------
+// launchers (one per translation unit)
+// ---------------------------------------------------------------------------
+hdof_status launch_bvh_build(hdof_ctx* ctx, const float* verts, const float* albedo, int n,
+                             hdof_scene* sc, hipStream_t st);
+hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
+                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st);
+hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
+                         const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
+                         const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
+                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, hipStream_t st);
+hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
+                        const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
+                        int32_t* total, hipStream_t st);
+hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
+                              const float* depth, const float* m1, const float* m2, hipStream_t st);
+hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
+                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st);
+hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
+                             const uint8_t* spp, hdof_rt_bufs rt, const CamK& k, const LensK& l,
+                             const hdof_composite_params& cp, float* out, hipStream_t st);

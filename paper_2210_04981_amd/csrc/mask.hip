@@ -1,0 +1,347 @@
+// mask.hip -- adaptive ray mask and temporally accumulated luminance variance.
+//
+// k_mask_score: one block per 16x16 pixel tile.  The tile plus an apron of
+// (Gaussian radius + 1) pixels of depth and normal is staged in LDS with
+// clamp-to-edge, blurred separably (x then y), Sobel-filtered, scored, and
+// the per-pixel count reduced to the mask-tile maxima (mask tiles divide 16,
+// so no mask tile straddles a block).  The variance history is reprojected
+// in the same pass when a previous camera is given.
+// k_mask_rows / k_mask_rowscan / k_mask_write: per-pixel counts are constant
+// over a mask tile, so the row-major exclusive scan over pixels reduces to a
+// scan over tile rows; the device-side total is written last.
+#include "hdof_internal.h"
+
+#define MT 16          // pixels per block edge
+#define MAX_GR 6       // max Gaussian radius (sigma <= 2)
+#define MAX_AP (MAX_GR + 1)
+#define MAX_IN (MT + 2 * MAX_AP)
+#define BL (MT + 2)    // blurred region edge (Sobel apron 1)
+
+namespace {
+
+struct MaskK {
+  float taps[2 * MAX_GR + 1];
+  int gr;
+  float inv_tz, inv_tn, inv_tv;
+  int spp_max, tile, dilate;
+};
+
+struct HistIn {
+  const float* m1;
+  const float* m2;
+  const uint8_t* flags;
+  const float* z;
+  int PW, PH;
+  int valid;  // 0: no history (first frame, camera cut, size change)
+  CamK pk;
+};
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ depth,
+                                                    const float* __restrict__ normal, CamK k, MaskK mk,
+                                                    HistIn hi, float* __restrict__ rep_m1,
+                                                    float* __restrict__ rep_m2,
+                                                    uint8_t* __restrict__ rep_flags,
+                                                    int* __restrict__ tile_max) {
+  __shared__ float in[4][MAX_IN][MAX_IN];
+  __shared__ float xb[4][MAX_IN][BL];
+  __shared__ float yb[4][BL][BL];
+  __shared__ int sr[MT][MT];
+  const int W = k.W, H = k.H;
+  const size_t N = (size_t)W * H;
+  const int x0 = blockIdx.x * MT, y0 = blockIdx.y * MT;
+  const int tid = threadIdx.x;
+  const int gr = mk.gr, ap = gr + 1, nin = MT + 2 * ap;
+  // stage depth (clamped to zmax) and normal with clamp-to-edge
+  for (int i = tid; i < nin * nin; i += 256) {
+    int ly = i / nin, lx = i - ly * nin;
+    int gx = clampi(x0 - ap + lx, 0, W - 1), gy = clampi(y0 - ap + ly, 0, H - 1);
+    size_t p = (size_t)gy * W + gx;
+    in[0][ly][lx] = fminf(depth[p], HDOF_ZMAX);
+    in[1][ly][lx] = normal[p];
+    in[2][ly][lx] = normal[N + p];
+    in[3][ly][lx] = normal[2 * N + p];
+  }
+  __syncthreads();
+  // x pass on every staged row, for the 18 columns the Sobel needs; a column
+  // outside the image takes the value of the clamped column
+  for (int i = tid; i < 4 * nin * BL; i += 256) {
+    int c = i / (nin * BL), rem = i - c * nin * BL;
+    int ly = rem / BL, ox = rem - ly * BL;
+    int gxc = clampi(x0 - 1 + ox, 0, W - 1);
+    int lx0 = gxc - (x0 - ap) - gr;
+    float acc = 0.0f;
+    for (int t = 0; t <= 2 * gr; ++t) acc = fmaf(mk.taps[t], in[c][ly][lx0 + t], acc);
+    xb[c][ly][ox] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < 4 * BL * BL; i += 256) {
+    int c = i / (BL * BL), rem = i - c * BL * BL;
+    int oy = rem / BL, ox = rem - oy * BL;
+    int gyc = clampi(y0 - 1 + oy, 0, H - 1);
+    int ly0 = gyc - (y0 - ap) - gr;
+    float acc = 0.0f;
+    for (int t = 0; t <= 2 * gr; ++t) acc = fmaf(mk.taps[t], xb[c][ly0 + t][ox], acc);
+    yb[c][oy][ox] = acc;
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  const int x = x0 + tx, y = y0 + ty;
+  int s_raw = 0;
+  if (x < W && y < H) {
+    float gsq[4];
+    for (int c = 0; c < 4; ++c) {
+      // yb index = local + 1
+#define YB(dx, dy) yb[c][ty + 1 + (dy)][tx + 1 + (dx)]
+      float gx = (YB(1, -1) - YB(-1, -1)) + 2.0f * (YB(1, 0) - YB(-1, 0)) + (YB(1, 1) - YB(-1, 1));
+      float gy = (YB(-1, 1) - YB(-1, -1)) + 2.0f * (YB(0, 1) - YB(0, -1)) + (YB(1, 1) - YB(1, -1));
+#undef YB
+      gsq[c] = fmaf(gx, gx, gy * gy);
+    }
+    float zb = yb[0][ty + 1][tx + 1];
+    float gz = sqrtf(gsq[0]) / (8.0f * fmaxf(zb, 1e-3f));
+    float gn = sqrtf(gsq[1] + gsq[2] + gsq[3]) * 0.125f;
+    // reprojected variance
+    const size_t p = (size_t)y * W + x;
+    float V = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    uint8_t fl = 0;
+    if (hi.valid) {
+      float z = depth[p];
+      V3 v = pixel_dir(k, x, y);
+      V3 X = V3{fmaf(z, v.x, k.e.x), fmaf(z, v.y, k.e.y), fmaf(z, v.z, k.e.z)};
+      V3 d = X - hi.pk.e;
+      float zc = dot3(d, hi.pk.w);
+      if (zc > 0.0f) {
+        float sxp = dot3(d, hi.pk.r) / zc, syp = dot3(d, hi.pk.u) / zc;
+        float fx = (sxp / hi.pk.tx + 1.0f) * 0.5f * (float)hi.PW;
+        float fy = (1.0f - syp / hi.pk.ty) * 0.5f * (float)hi.PH;
+        float px = floorf(fx), py = floorf(fy);
+        if (px >= 0.0f && px < (float)hi.PW && py >= 0.0f && py < (float)hi.PH) {
+          size_t q = (size_t)py * hi.PW + (size_t)px;
+          uint8_t pf = hi.flags[q];
+          if (pf & HDOF_HIST_VALID) {
+            float rel = fabsf(hi.z[q] - zc) / zc;
+            if (rel <= 0.01f) {
+              a1 = hi.m1[q];
+              a2 = hi.m2[q];
+              fl = pf;
+            }
+          }
+        }
+      }
+      if (fl & HDOF_HIST_VALID) V = (fl & HDOF_HIST_NEW) ? INFINITY : fmaxf(0.0f, fmaf(-a1, a1, a2));
+    }
+    rep_m1[p] = a1;
+    rep_m2[p] = a2;
+    rep_flags[p] = fl;
+    float m = fmaxf(gz * mk.inv_tz, fmaxf(gn * mk.inv_tn, V * mk.inv_tv));
+    if (m >= 1.0f) s_raw = (int)ceilf(fminf(m, (float)mk.spp_max));
+  }
+  sr[ty][tx] = s_raw;
+  __syncthreads();
+  const int t = mk.tile;
+  if ((tx % t) == 0 && (ty % t) == 0 && x < W && y < H) {
+    int mx = 0;
+    for (int dy = 0; dy < t; ++dy)
+      for (int dx = 0; dx < t; ++dx) mx = max(mx, sr[ty + dy][tx + dx]);
+    const int TW = (W + t - 1) / t;
+    tile_max[(y / t) * TW + x / t] = mx;
+  }
+}
+
+// per tile row: dilated tile values, x-prefix of (value * tile width), row sum
+__global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_max, int W, int H,
+                                                   int t, int dil, int* __restrict__ tile_dil,
+                                                   int* __restrict__ xpref, int* __restrict__ rowsum,
+                                                   int* __restrict__ rowtot) {
+  __shared__ int part[256];
+  const int TW = (W + t - 1) / t, TH = (H + t - 1) / t;
+  const int ty = blockIdx.x, tid = threadIdx.x;
+  const int chunk = (TW + 255) / 256;
+  const int lo = tid * chunk, hi = min(TW, lo + chunk);
+  int local = 0;
+  for (int tx = lo; tx < hi; ++tx) {
+    int m = 0;
+    for (int dy = -dil; dy <= dil; ++dy) {
+      int yy = ty + dy;
+      if (yy < 0 || yy >= TH) continue;
+      for (int dx = -dil; dx <= dil; ++dx) {
+        int xx = tx + dx;
+        if (xx < 0 || xx >= TW) continue;
+        m = max(m, tile_max[yy * TW + xx]);
+      }
+    }
+    tile_dil[ty * TW + tx] = m;
+    local += m * min(t, W - tx * t);
+  }
+  part[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - local;
+  for (int tx = lo; tx < hi; ++tx) {
+    xpref[ty * TW + tx] = run;
+    run += tile_dil[ty * TW + tx] * min(t, W - tx * t);
+  }
+  if (tid == 255) {
+    rowsum[ty] = part[255];
+    rowtot[ty] = part[255] * min(t, H - ty * t);
+  }
+}
+
+// exclusive scan over tile rows (one block), total to the caller's buffer
+__global__ void k_mask_rowscan(const int* __restrict__ rowtot, int TH, int* __restrict__ ybase,
+                               int* __restrict__ total) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (TH + 1023) / 1024;
+  const int lo = tid * chunk, hi = min(TH, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += rowtot[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;
+  for (int i = lo; i < hi; ++i) {
+    ybase[i] = run;
+    run += rowtot[i];
+  }
+  if (tid == 1023) *total = part[1023];
+}
+
+__global__ void k_mask_write(int W, int H, int t, const int* __restrict__ tile_dil,
+                             const int* __restrict__ xpref, const int* __restrict__ rowsum,
+                             const int* __restrict__ ybase, uint8_t* __restrict__ spp,
+                             int* __restrict__ offsets) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= W) return;
+  const int TW = (W + t - 1) / t;
+  int tx = x / t, ty = y / t;
+  int S = tile_dil[ty * TW + tx];
+  size_t p = (size_t)y * W + x;
+  spp[p] = (uint8_t)S;
+  offsets[p] = ybase[ty] + (y - ty * t) * rowsum[ty] + xpref[ty * TW + tx] + (x - tx * t) * S;
+}
+
+// history update after the trace
+__global__ void k_var_update(int N, float alpha, const uint8_t* __restrict__ spp,
+                             const float* __restrict__ depth, const float* __restrict__ ybar,
+                             const float* __restrict__ y2bar, const float* __restrict__ rm1,
+                             const float* __restrict__ rm2, const uint8_t* __restrict__ rfl,
+                             float* __restrict__ m1, float* __restrict__ m2, uint8_t* __restrict__ fl,
+                             float* __restrict__ hz) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  float a1 = rm1[p], a2 = rm2[p];
+  uint8_t f = rfl[p];
+  if (spp[p] > 0) {
+    if (f & HDOF_HIST_VALID) {
+      a1 = fmaf(alpha, ybar[p], (1.0f - alpha) * a1);
+      a2 = fmaf(alpha, y2bar[p], (1.0f - alpha) * a2);
+      f = HDOF_HIST_VALID;
+    } else {
+      a1 = ybar[p];
+      a2 = y2bar[p];
+      f = HDOF_HIST_VALID | HDOF_HIST_NEW;
+    }
+  }
+  m1[p] = a1;
+  m2[p] = a2;
+  fl[p] = f;
+  hz[p] = depth[p];
+}
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
+                        const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
+                        int32_t* total, hipStream_t st) {
+  const int W = k.W, H = k.H, t = mp.tile;
+  const size_t N = (size_t)W * H;
+  const int TW = cdiv(W, t), TH = cdiv(H, t);
+  MaskK mk;
+  // Gaussian taps exp(-i^2 / 2 sigma^2), radius floor(3 sigma + 0.5), normalised
+  int gr = (int)floor(3.0 * mp.sigma + 0.5);
+  double tw[2 * MAX_GR + 1], sum = 0.0;
+  for (int i = -gr; i <= gr; ++i) sum += (tw[i + gr] = exp(-(double)(i * i) / (2.0 * mp.sigma * mp.sigma)));
+  for (int i = 0; i <= 2 * gr; ++i) mk.taps[i] = (float)(tw[i] / sum);
+  mk.gr = gr;
+  mk.inv_tz = 1.0f / mp.tau_depth;
+  mk.inv_tn = 1.0f / mp.tau_normal;
+  mk.inv_tv = 1.0f / mp.tau_var;
+  mk.spp_max = mp.spp_max;
+  mk.tile = t;
+  mk.dilate = mp.dilate;
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->mask_tile, sizeof(int) * (size_t)TW * TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_tile_dil, sizeof(int) * (size_t)TW * TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_xpref, sizeof(int) * (size_t)TW * TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_rowsum, sizeof(int) * 2 * (size_t)TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_ybase, sizeof(int) * (size_t)TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->rep_m1, sizeof(float) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->rep_m2, sizeof(float) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->rep_flags, N)) != HDOF_OK) return s;
+  HistIn hi{};
+  hi.valid = 0;
+  if (prev && ctx->hist_any && ctx->hist_w == prev->W && ctx->hist_h == prev->H) {
+    hi.valid = 1;
+    hi.m1 = (const float*)ctx->hist_m1.p;
+    hi.m2 = (const float*)ctx->hist_m2.p;
+    hi.flags = (const uint8_t*)ctx->hist_flags.p;
+    hi.z = (const float*)ctx->hist_z.p;
+    hi.PW = prev->W;
+    hi.PH = prev->H;
+    hi.pk = *prev;
+  }
+  ctx->rep_w = W;
+  ctx->rep_h = H;
+  ctx->rep_valid = true;
+  int* rowsum = (int*)ctx->mask_rowsum.p;
+  int* rowtot = rowsum + TH;
+  hipLaunchKernelGGL(k_mask_score, dim3(cdiv(W, MT), cdiv(H, MT)), dim3(256), 0, st, depth, normal, k, mk,
+                     hi, (float*)ctx->rep_m1.p, (float*)ctx->rep_m2.p, (uint8_t*)ctx->rep_flags.p,
+                     (int*)ctx->mask_tile.p);
+  hipLaunchKernelGGL(k_mask_rows, dim3(TH), dim3(256), 0, st, (const int*)ctx->mask_tile.p, W, H, t,
+                     mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot);
+  hipLaunchKernelGGL(k_mask_rowscan, dim3(1), dim3(1024), 0, st, (const int*)rowtot, TH,
+                     (int*)ctx->mask_ybase.p, total);
+  hipLaunchKernelGGL(k_mask_write, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t,
+                     (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p,
+                     (const int*)rowsum, (const int*)ctx->mask_ybase.p, spp, offsets);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
+                              const float* depth, const float* m1, const float* m2, hipStream_t st) {
+  const size_t N = (size_t)k.W * k.H;
+  hdof_status s;
+  if (!ctx->rep_valid || ctx->rep_w != k.W || ctx->rep_h != k.H)
+    return hdof_set_error(HDOF_ERR_INVALID_ARG,
+                          "variance update without a ray mask of the same frame size");
+  if ((s = hdof_ensure(ctx->hist_m1, sizeof(float) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->hist_m2, sizeof(float) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->hist_flags, N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->hist_z, sizeof(float) * N)) != HDOF_OK) return s;
+  hipLaunchKernelGGL(k_var_update, dim3(cdiv((long)N, 256)), dim3(256), 0, st, (int)N, alpha, spp, depth,
+                     m1, m2, (const float*)ctx->rep_m1.p, (const float*)ctx->rep_m2.p,
+                     (const uint8_t*)ctx->rep_flags.p, (float*)ctx->hist_m1.p, (float*)ctx->hist_m2.p,
+                     (uint8_t*)ctx->hist_flags.p, (float*)ctx->hist_z.p);
+  HDOF_HIP(hipGetLastError());
+  ctx->hist_w = k.W;
+  ctx->hist_h = k.H;
+  ctx->hist_any = true;
+  return HDOF_OK;
+}

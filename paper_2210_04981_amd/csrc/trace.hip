@@ -1,0 +1,394 @@
+// trace.hip -- BVH traversal, G-buffer and thin-lens distributed ray trace.
+//
+// Traversal: per-lane stack whose first HDOF_LDS_STACK entries live in LDS
+// (entry i of lane t at stk[i * BLOCK + t], so a wave's pushes hit 64
+// distinct banks) and the rest in a short private spill array; both children
+// of a node are box-tested from one 64-byte node record, leaves are tested
+// in the same step, the nearer internal child is visited first.
+// Triangles: watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013),
+// ties broken towards the lowest input triangle index.
+//
+// G-buffer: 16x16-pixel blocks, each wave a 16x4 strip (coherent primary
+// rays); blocks remapped so each XCD works on a contiguous band of the image
+// and keeps its part of the BVH in its own L2.
+// Thin-lens trace: queue of (pixel, sample) entries built from the mask's
+// counts and offsets; a persistent grid pops 64 entries per wave from a
+// device counter, so the host never reads the ray count; results per entry,
+// then a per-pixel reduction in fixed sample order (deterministic).
+#include "hdof_internal.h"
+
+namespace {
+
+struct Ray {
+  V3 O, D;
+  V3 inv, oinv;            // 1/D and -O/D for the slab test
+  int kx, ky, kz;          // watertight axis permutation
+  float Sx, Sy, Sz;        // shear constants
+  float Ox, Oy, Oz;        // origin in permuted order
+};
+
+__device__ inline float safe_inv(float d) {
+  float a = fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d);
+  return 1.0f / a;
+}
+
+__device__ inline Ray make_ray(V3 O, V3 D) {
+  Ray r;
+  r.O = O;
+  r.D = D;
+  r.inv = V3{safe_inv(D.x), safe_inv(D.y), safe_inv(D.z)};
+  r.oinv = V3{-O.x * r.inv.x, -O.y * r.inv.y, -O.z * r.inv.z};
+  float ax = fabsf(D.x), ay = fabsf(D.y), az = fabsf(D.z);
+  int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  float dz = comp(D, kz);
+  if (dz < 0.0f) {
+    int t = kx;
+    kx = ky;
+    ky = t;
+  }
+  r.kx = kx;
+  r.ky = ky;
+  r.kz = kz;
+  r.Sx = comp(D, kx) / dz;
+  r.Sy = comp(D, ky) / dz;
+  r.Sz = 1.0f / dz;
+  r.Ox = comp(O, kx);
+  r.Oy = comp(O, ky);
+  r.Oz = comp(O, kz);
+  return r;
+}
+
+__device__ inline float pick(float4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+// slab test of one child box against [0, tmax]; conservative by 2 gamma(3)
+__device__ inline bool box_hit(const Ray& r, float lox, float hix, float loy, float hiy, float loz,
+                               float hiz, float tmax, float& tnear) {
+  float tx0 = fmaf(lox, r.inv.x, r.oinv.x), tx1 = fmaf(hix, r.inv.x, r.oinv.x);
+  float ty0 = fmaf(loy, r.inv.y, r.oinv.y), ty1 = fmaf(hiy, r.inv.y, r.oinv.y);
+  float tz0 = fmaf(loz, r.inv.z, r.oinv.z), tz1 = fmaf(hiz, r.inv.z, r.oinv.z);
+  float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  float tmx = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+  tnear = tmin;
+  return tmin <= tmx * 1.0000004f;
+}
+
+struct Best {
+  float t;
+  int tri;   // leaf-order index, -1 = none
+  int id;    // input index
+};
+
+// Woop-Benthin-Wald watertight test; updates best on a closer (or tied,
+// lower input index) hit with t > 0.
+__device__ inline void tri_test(const Ray& r, const float4* __restrict__ tris, int i, Best& b) {
+  float4 a = tris[3 * i], q = tris[3 * i + 1], c = tris[3 * i + 2];
+  float Akx = pick(a, r.kx) - r.Ox, Aky = pick(a, r.ky) - r.Oy, Akz = pick(a, r.kz) - r.Oz;
+  float Bkx = pick(q, r.kx) - r.Ox, Bky = pick(q, r.ky) - r.Oy, Bkz = pick(q, r.kz) - r.Oz;
+  float Ckx = pick(c, r.kx) - r.Ox, Cky = pick(c, r.ky) - r.Oy, Ckz = pick(c, r.kz) - r.Oz;
+  float Ax = fmaf(-r.Sx, Akz, Akx), Ay = fmaf(-r.Sy, Akz, Aky);
+  float Bx = fmaf(-r.Sx, Bkz, Bkx), By = fmaf(-r.Sy, Bkz, Bky);
+  float Cx = fmaf(-r.Sx, Ckz, Ckx), Cy = fmaf(-r.Sy, Ckz, Cky);
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+    V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+    W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+  }
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return;
+  float det = U + V + W;
+  if (det == 0.0f) return;
+  float T = U * (r.Sz * Akz) + V * (r.Sz * Bkz) + W * (r.Sz * Ckz);
+  float t = T / det;
+  if (!(t > 0.0f)) return;
+  int id = __float_as_int(a.w);
+  if (t < b.t || (t == b.t && id < b.id)) {
+    b.t = t;
+    b.tri = i;
+    b.id = id;
+  }
+}
+
+__device__ inline void test_leaf(const Ray& r, const float4* __restrict__ tris, unsigned code, Best& b) {
+  int first = (int)(code & HDOF_LEAF_FIRST_MASK);
+  int cnt = (int)((code >> 27) & 0xF) + 1;
+  for (int k = 0; k < cnt; ++k) tri_test(r, tris, first + k, b);
+}
+
+// Each internal node is entered at most once per ray, so more than n_nodes
+// steps means a malformed tree: the ray stops and raises the device flag
+// instead of looping.
+template <int BLOCK>
+__device__ inline Best traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                int n_nodes, const Ray& r, int* __restrict__ stk, int* __restrict__ flags) {
+  Best b{INFINITY, -1, 0x7fffffff};
+  int spill[HDOF_SPILL_STACK];
+  int sp = 0;
+  unsigned cur = 0;  // root (internal)
+  for (int steps = 0;; ++steps) {
+    if (steps > n_nodes) {
+      atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+      break;
+    }
+    const float4* nd = nodes + 4 * (size_t)cur;
+    float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+    float t0, t1;
+    bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0);
+    bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1);
+    unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
+    if (h0 && (c0 & HDOF_LEAF_BIT)) {
+      test_leaf(r, tris, c0, b);
+      h0 = false;
+    }
+    if (h1 && (c1 & HDOF_LEAF_BIT)) {
+      test_leaf(r, tris, c1, b);
+      h1 = false;
+    }
+    if (h0 && h1) {
+      unsigned nearc = t0 <= t1 ? c0 : c1;
+      unsigned farc = t0 <= t1 ? c1 : c0;
+      if (sp < HDOF_LDS_STACK) {
+        stk[sp * BLOCK] = (int)farc;
+        ++sp;
+      } else if (sp < HDOF_LDS_STACK + HDOF_SPILL_STACK) {
+        spill[sp - HDOF_LDS_STACK] = (int)farc;
+        ++sp;
+      } else {
+        atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+      }
+      cur = nearc;
+    } else if (h0) {
+      cur = c0;
+    } else if (h1) {
+      cur = c1;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      cur = (unsigned)(sp < HDOF_LDS_STACK ? stk[sp * BLOCK] : spill[sp - HDOF_LDS_STACK]);
+    }
+  }
+  return b;
+}
+
+// Two-sided Lambertian face normal + point light, no shadow ray.
+__device__ inline void shade(const float4* __restrict__ tris, const float* __restrict__ albedo,
+                             const LightK& li, const Ray& r, const Best& b, V3& L, V3& n, V3& alb) {
+  float4 a = tris[3 * b.tri], q = tris[3 * b.tri + 1], c = tris[3 * b.tri + 2];
+  V3 e1 = V3{q.x - a.x, q.y - a.y, q.z - a.z};
+  V3 e2 = V3{c.x - a.x, c.y - a.y, c.z - a.z};
+  V3 nn = cross3(e1, e2);
+  float il = rsqrtf(dot3(nn, nn));
+  nn = il * nn;
+  if (dot3(nn, r.D) > 0.0f) nn = V3{-nn.x, -nn.y, -nn.z};
+  V3 P = V3{fmaf(b.t, r.D.x, r.O.x), fmaf(b.t, r.D.y, r.O.y), fmaf(b.t, r.D.z, r.O.z)};
+  V3 l = li.p - P;
+  float d2 = dot3(l, l);
+  float cosv = d2 > 0.0f ? dot3(nn, l) * rsqrtf(d2) : 0.0f;
+  float irr = fmaxf(0.0f, cosv) / fmaxf(d2, 1e-4f);
+  const float* al = albedo + 3 * (size_t)b.id;
+  alb = V3{al[0], al[1], al[2]};
+  L = V3{alb.x * fmaf(li.I.x, irr, li.ka.x), alb.y * fmaf(li.I.y, irr, li.ka.y),
+         alb.z * fmaf(li.I.z, irr, li.ka.z)};
+  n = nn;
+}
+
+// logical block index so that XCD x (blocks dispatched round-robin over 8
+// XCDs) processes one contiguous range of logical blocks
+__device__ inline int xcd_block(int b, int nb) {
+  int per = nb >> 3, rem = nb & 7;
+  int x = b & 7, i = b >> 3;
+  return x * per + min(x, rem) + i;
+}
+
+__global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ nodes,
+                                                 const float4* __restrict__ tris, int n_nodes,
+                                                 const float* __restrict__ albedo, CamK k, LensK l,
+                                                 LightK li, float* __restrict__ depth,
+                                                 float* __restrict__ normal, float* __restrict__ alb_out,
+                                                 float* __restrict__ color, int* __restrict__ tri_id,
+                                                 int* __restrict__ flags) {
+  __shared__ int stk[HDOF_LDS_STACK * 256];
+  const int bx_n = (k.W + 15) >> 4, by_n = (k.H + 15) >> 4;
+  const int lb = xcd_block(blockIdx.x, bx_n * by_n);
+  const int bx = lb % bx_n, by = lb / bx_n;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int x = bx * 16 + (lane & 15), y = by * 16 + wave * 4 + (lane >> 4);
+  if (x >= k.W || y >= k.H) return;
+  V3 v = pixel_dir(k, x, y);
+  Ray r = make_ray(k.e, V3{l.S1 * v.x, l.S1 * v.y, l.S1 * v.z});
+  Best b = traverse<256>(nodes, tris, n_nodes, r, stk + t, flags);
+  const size_t N = (size_t)k.W * k.H, p = (size_t)y * k.W + x;
+  if (b.tri >= 0) {
+    V3 L, n, a;
+    shade(tris, albedo, li, r, b, L, n, a);
+    depth[p] = b.t * l.S1;
+    normal[p] = n.x;
+    normal[N + p] = n.y;
+    normal[2 * N + p] = n.z;
+    alb_out[p] = a.x;
+    alb_out[N + p] = a.y;
+    alb_out[2 * N + p] = a.z;
+    color[p] = L.x;
+    color[N + p] = L.y;
+    color[2 * N + p] = L.z;
+    tri_id[p] = b.id;
+  } else {
+    depth[p] = HDOF_ZMAX;
+    for (int c = 0; c < 3; ++c) {
+      normal[c * N + p] = 0.0f;
+      alb_out[c * N + p] = 0.0f;
+      color[c * N + p] = 0.0f;
+    }
+    tri_id[p] = -1;
+  }
+}
+
+// queue entries: pixel index repeated spp times at its offset; also resets
+// the persistent trace's work counter (same stream, runs before the trace)
+// (entries outside [0, cap) are dropped: inconsistent offsets never write out
+// of bounds)
+__global__ void k_queue_fill(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
+                             long cap, int* __restrict__ queue, int* __restrict__ counter) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) *counter = 0;
+  if (p >= N) return;
+  int s = spp[p];
+  long o = offsets[p];
+  for (int j = 0; j < s; ++j)
+    if (o + j >= 0 && o + j < cap) queue[o + j] = p;
+}
+
+__global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
+    const float4* __restrict__ nodes, const float4* __restrict__ tris, int n_nodes,
+    const float* __restrict__ albedo, CamK k, LensK l, LightK li, const int* __restrict__ queue, const int* __restrict__ offsets,
+    const int* __restrict__ total_p, int* __restrict__ counter, uint32_t seed, uint32_t frame,
+    uint32_t view, float* __restrict__ ray_col, float* __restrict__ ray_z, int* __restrict__ ray_id,
+    size_t cap, int* __restrict__ flags) {
+  __shared__ int stk[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
+  const int t = threadIdx.x, lane = t & 63;
+  const int N = k.W * k.H;
+  int total = *total_p;
+  if (total < 0) total = 0;
+  if ((size_t)total > cap) {
+    if (blockIdx.x == 0 && t == 0) atomicOr(flags, HDOF_FLAG_CAPACITY);
+    total = (int)cap;
+  }
+  for (;;) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(counter, 64);
+    base = __shfl(base, 0);
+    if (base >= total) break;
+    int e = base + lane;
+    int p = e < total ? queue[e] : -1;
+    if (p >= 0 && p < N) {
+      int j = e - offsets[p];
+      int x = p % k.W, y = p / k.W;
+      V3 O, D;
+      lens_ray(k, l, x, y, (uint32_t)j, view, seed, frame, O, D);
+      Ray r = make_ray(O, D);
+      Best b = traverse<HDOF_TRACE_BLOCK>(nodes, tris, n_nodes, r, stk + t, flags);
+      float z = HDOF_ZMAX;
+      V3 L = V3{0.0f, 0.0f, 0.0f};
+      if (b.tri >= 0) {
+        V3 n, a;
+        shade(tris, albedo, li, r, b, L, n, a);
+        z = b.t * l.S1;
+      }
+      ray_col[e] = L.x;
+      ray_col[cap + e] = L.y;
+      ray_col[2 * cap + e] = L.z;
+      ray_z[e] = z;
+      if (ray_id) ray_id[e] = b.tri >= 0 ? b.id : -1;
+    }
+  }
+}
+
+// per-pixel near/far split, hit ratio and luminance moments, fixed order
+__global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
+                            const float* __restrict__ ray_col, const float* __restrict__ ray_z, size_t cap,
+                            LensK l, float* __restrict__ cn, float* __restrict__ cf, float* __restrict__ h,
+                            float* __restrict__ m1, float* __restrict__ m2) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  int s = spp[p];
+  float Nw = 0.f, Fw = 0.f, snr = 0.f, sng = 0.f, snb = 0.f, sfr = 0.f, sfg = 0.f, sfb = 0.f, sy = 0.f, sy2 = 0.f;
+  long o = offsets[p];
+  if (o < 0 || o + s > (long)cap) s = 0;  // inconsistent offsets: nothing was traced here
+  if (s > 0) {
+    for (int j = 0; j < s; ++j) {
+      int e = o + j;
+      float R = ray_col[e], G = ray_col[cap + e], B = ray_col[2 * cap + e];
+      float c = coc_px(l, ray_z[e]);
+      float w = clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
+      float wf = 1.0f - w;
+      Nw += w;
+      Fw += wf;
+      snr = fmaf(w, R, snr);
+      sng = fmaf(w, G, sng);
+      snb = fmaf(w, B, snb);
+      sfr = fmaf(wf, R, sfr);
+      sfg = fmaf(wf, G, sfg);
+      sfb = fmaf(wf, B, sfb);
+      float Y = fmaf(0.2126f, R, fmaf(0.7152f, G, 0.0722f * B));
+      sy += Y;
+      sy2 = fmaf(Y, Y, sy2);
+    }
+  }
+  const float in_ = Nw > 0.f ? 1.0f / Nw : 0.f, if_ = Fw > 0.f ? 1.0f / Fw : 0.f;
+  const float is = s > 0 ? 1.0f / (float)s : 0.f;
+  cn[p] = snr * in_;
+  cn[N + p] = sng * in_;
+  cn[2 * (size_t)N + p] = snb * in_;
+  cf[p] = sfr * if_;
+  cf[N + p] = sfg * if_;
+  cf[2 * (size_t)N + p] = sfb * if_;
+  h[p] = Nw * is;
+  m1[p] = sy * is;
+  m2[p] = sy2 * is;
+}
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
+                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st) {
+  int nb = cdiv(k.W, 16) * cdiv(k.H, 16);
+  hipLaunchKernelGGL(k_gbuffer, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo, k, l, li,
+                     out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
+                         const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
+                         const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
+                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, hipStream_t st) {
+  const int N = k.W * k.H;
+  const size_t cap = (size_t)N * (size_t)spp_max;
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->queue, sizeof(int) * cap)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap)) != HDOF_OK) return s;
+  if (!ray_depth && (s = hdof_ensure(ctx->ray_z, sizeof(float) * cap)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->work_counter, sizeof(int) * 64)) != HDOF_OK) return s;
+  float* rz = ray_depth ? ray_depth : (float*)ctx->ray_z.p;
+  int* counter = (int*)ctx->work_counter.p;
+  hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (long)cap,
+                     (int*)ctx->queue.p, counter);
+  hdof_prof_mark(ctx, 3, st);
+  // persistent grid: enough resident waves to cover every CU several times
+  int grid = ctx->n_cu * 8;
+  hipLaunchKernelGGL(k_trace, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                     k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
+                     (float*)ctx->ray_col.p, rz, ray_id, cap, ctx->d_flags);
+  hdof_prof_mark(ctx, 4, st);
+  hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
+                     (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near, out.c_far,
+                     out.hit_ratio, out.lum_m1, out.lum_m2);
+  hdof_prof_mark(ctx, 5, st);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}

@@ -1,0 +1,484 @@
+"""Thin Python binding of libhdof.so (the C ABI in include/hdof.h).
+
+Argument marshalling only: every step of the hybrid depth-of-field path runs
+in the library's HIP kernels.  PyTorch supplies device memory (tensors are
+passed as raw ``data_ptr()`` values) and the stream (torch's current stream
+unless one is given).  Each wrapper checks tensor device, dtype, contiguity
+and size against what the kernels assume before anything is enqueued, and
+raises ``HdofError`` on a non-OK status.  There is no fallback: if the
+library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdof.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2210_04981_amd.build` "
+                      "(hipcc, gfx950).  There is no fallback path.")
+
+_lib = C.CDLL(LIB_PATH)
+
+F3 = C.c_float * 3
+
+
+class Camera(C.Structure):
+    _fields_ = [("eye", F3), ("right", F3), ("up", F3), ("fwd", F3),
+                ("tan_half_fov_x", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class Lens(C.Structure):
+    _fields_ = [("focal_length", C.c_float), ("aperture", C.c_float), ("focus_distance", C.c_float)]
+
+
+class Light(C.Structure):
+    _fields_ = [("pos", F3), ("intensity", F3), ("ambient", F3)]
+
+
+class MaskParams(C.Structure):
+    _fields_ = [("sigma", C.c_float), ("tau_depth", C.c_float), ("tau_normal", C.c_float),
+                ("tau_var", C.c_float), ("var_alpha", C.c_float), ("spp_max", C.c_int32),
+                ("tile", C.c_int32), ("dilate", C.c_int32)]
+
+
+class PPParams(C.Structure):
+    _fields_ = [("n_taps", C.c_int32), ("tile", C.c_int32), ("r_cap", C.c_float),
+                ("bg_ramp_px", C.c_float)]
+
+
+class CompositeParams(C.Structure):
+    _fields_ = [("h_t", C.c_float), ("rt_override", C.c_int32)]
+
+
+class FrameParams(C.Structure):
+    _fields_ = [("mask", MaskParams), ("pp", PPParams), ("comp", CompositeParams)]
+
+
+P = C.c_void_p
+
+
+class GBufferBufs(C.Structure):
+    _fields_ = [("depth", P), ("normal", P), ("albedo", P), ("color", P), ("tri_id", P)]
+
+
+class RTBufs(C.Structure):
+    _fields_ = [("c_near", P), ("c_far", P), ("hit_ratio", P), ("lum_m1", P), ("lum_m2", P)]
+
+
+class FrameBufs(C.Structure):
+    _fields_ = [("gb", GBufferBufs), ("spp", P), ("offsets", P), ("total", P), ("rt", RTBufs),
+                ("pp", P)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_tris", C.c_int32), ("n_nodes", C.c_int32), ("max_depth", C.c_int32),
+                ("leaf_size", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+_S = C.c_int
+_u32, _i32 = C.c_uint32, C.c_int32
+_PROTOS = {
+    "hdof_create": (_S, [C.c_int, C.POINTER(P)]),
+    "hdof_destroy": (None, [P]),
+    "hdof_status_str": (C.c_char_p, [_S]),
+    "hdof_last_error": (C.c_char_p, []),
+    "hdof_sync": (_S, [P, P]),
+    "hdof_build_bvh": (_S, [P, P, P, _i32, C.POINTER(P), P]),
+    "hdof_scene_destroy": (None, [P]),
+    "hdof_scene_stats": (_S, [P, C.POINTER(SceneInfo)]),
+    "hdof_gbuffer": (_S, [P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(Light), GBufferBufs, P]),
+    "hdof_ray_mask": (_S, [P, C.POINTER(GBufferBufs), C.POINTER(Camera), C.POINTER(Camera),
+                           C.POINTER(Lens), C.POINTER(MaskParams), P, P, P, P]),
+    "hdof_trace_thin_lens": (_S, [P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(Light), _i32,
+                                  P, P, P, _u32, _u32, _u32, RTBufs, P, P, P]),
+    "hdof_variance_update": (_S, [P, C.POINTER(Camera), C.POINTER(MaskParams), P, P, P, P, P]),
+    "hdof_history_load": (_S, [P, _i32, _i32, P, P, P, P, P]),
+    "hdof_history_save": (_S, [P, P, P, P, P, P]),
+    "hdof_history_reset": (_S, [P]),
+    "hdof_postfilter": (_S, [P, P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(PPParams), P, P]),
+    "hdof_composite": (_S, [P, P, P, P, P, RTBufs, C.POINTER(Camera), C.POINTER(Lens),
+                            C.POINTER(CompositeParams), P, P]),
+    "hdof_frame": (_S, [P, P, C.POINTER(Camera), C.POINTER(Camera), C.POINTER(Lens), C.POINTER(Light),
+                        C.POINTER(FrameParams), _u32, _u32, _u32, P, C.POINTER(FrameBufs), P]),
+    "hdof_profile_begin": (_S, [P]),
+    "hdof_profile_end": (_S, [P, C.POINTER(C.c_float), C.POINTER(_i32)]),
+}
+
+PROFILE_STAGES = ("gbuffer", "ray_mask", "queue_fill", "trace", "rt_reduce", "var_update", "pp_prep",
+                  "pp_gather", "composite")
+for _name, (_res, _args) in _PROTOS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_PROTOS)
+
+
+class HdofError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.hdof_last_error().decode()
+        super().__init__(f"{where}: {_lib.hdof_status_str(status).decode()}: {msg}")
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise HdofError(status, where)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t: torch.Tensor | None, dtype, numel: int | None, name: str) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name}: expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs at least {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def camera(eye, right, up, fwd, tan_half_fov_x, width, height) -> Camera:
+    return Camera(F3(*eye), F3(*right), F3(*up), F3(*fwd), float(tan_half_fov_x), int(width), int(height))
+
+
+def lens(focal_length, aperture, focus_distance) -> Lens:
+    return Lens(float(focal_length), float(aperture), float(focus_distance))
+
+
+def light(pos, intensity, ambient) -> Light:
+    return Light(F3(*pos), F3(*intensity), F3(*ambient))
+
+
+def mask_params(sigma=1.0, tau_depth=0.05, tau_normal=0.1, tau_var=0.01, var_alpha=0.2, spp_max=8,
+                tile=8, dilate=1) -> MaskParams:
+    return MaskParams(sigma, tau_depth, tau_normal, tau_var, var_alpha, spp_max, tile, dilate)
+
+
+def pp_params(n_taps=48, tile=16, r_cap=64.0, bg_ramp_px=1.0) -> PPParams:
+    return PPParams(n_taps, tile, r_cap, bg_ramp_px)
+
+
+def composite_params(h_t=0.5, rt_override=0) -> CompositeParams:
+    return CompositeParams(h_t, rt_override)
+
+
+# ----------------------------------------------------------------------------
+# context and scene
+# ----------------------------------------------------------------------------
+
+class Context:
+    """Owns an hdof_ctx (device, scratch, variance history)."""
+
+    def __init__(self, device: int = 0):
+        h = P()
+        _check(_lib.hdof_create(int(device), C.byref(h)), "hdof_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib.hdof_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self, stream=None):
+        _check(_lib.hdof_sync(self.handle, _stream(stream)), "hdof_sync")
+
+
+class Scene:
+    """Owns an hdof_scene (BVH + triangles + albedo on the device)."""
+
+    def __init__(self, handle, ctx: Context, n_tris: int):
+        self.handle = handle
+        self.ctx = ctx
+        self.n_tris = n_tris
+
+    def stats(self) -> dict:
+        s = SceneInfo()
+        _check(_lib.hdof_scene_stats(self.handle, C.byref(s)), "hdof_scene_stats")
+        return dict(n_tris=s.n_tris, n_nodes=s.n_nodes, max_depth=s.max_depth,
+                    device_bytes=s.device_bytes)
+
+    def close(self):
+        if self.handle:
+            _lib.hdof_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hdof_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def hdof_build_bvh(ctx: Context, verts: torch.Tensor, albedo: torch.Tensor, stream=None) -> Scene:
+    n = verts.shape[0]
+    pv = _ptr(verts, torch.float32, 9 * n, "verts")
+    pa = _ptr(albedo, torch.float32, 3 * n, "albedo")
+    if verts.numel() != 9 * n or albedo.numel() != 3 * n:
+        raise ValueError("verts must be (n, 9) and albedo (n, 3)")
+    h = P()
+    _check(_lib.hdof_build_bvh(ctx.handle, pv, pa, int(n), C.byref(h), _stream(stream)), "hdof_build_bvh")
+    return Scene(h, ctx, n)
+
+
+# ----------------------------------------------------------------------------
+# stages
+# ----------------------------------------------------------------------------
+
+@dataclass
+class GBuffer:
+    depth: torch.Tensor
+    normal: torch.Tensor
+    albedo: torch.Tensor
+    color: torch.Tensor
+    tri_id: torch.Tensor
+
+    @staticmethod
+    def empty(H: int, W: int, device="cuda") -> "GBuffer":
+        f = dict(dtype=torch.float32, device=device)
+        return GBuffer(torch.empty(H, W, **f), torch.empty(3, H, W, **f), torch.empty(3, H, W, **f),
+                       torch.empty(3, H, W, **f), torch.empty(H, W, dtype=torch.int32, device=device))
+
+    def bufs(self) -> GBufferBufs:
+        n = self.depth.numel()
+        return GBufferBufs(_ptr(self.depth, torch.float32, n, "depth"),
+                           _ptr(self.normal, torch.float32, 3 * n, "normal"),
+                           _ptr(self.albedo, torch.float32, 3 * n, "albedo"),
+                           _ptr(self.color, torch.float32, 3 * n, "color"),
+                           _ptr(self.tri_id, torch.int32, n, "tri_id"))
+
+
+@dataclass
+class RTResult:
+    c_near: torch.Tensor
+    c_far: torch.Tensor
+    hit_ratio: torch.Tensor
+    lum_m1: torch.Tensor
+    lum_m2: torch.Tensor
+
+    @staticmethod
+    def empty(H: int, W: int, device="cuda") -> "RTResult":
+        f = dict(dtype=torch.float32, device=device)
+        return RTResult(torch.empty(3, H, W, **f), torch.empty(3, H, W, **f), torch.empty(H, W, **f),
+                        torch.empty(H, W, **f), torch.empty(H, W, **f))
+
+    def bufs(self, n: int) -> RTBufs:
+        return RTBufs(_ptr(self.c_near, torch.float32, 3 * n, "c_near"),
+                      _ptr(self.c_far, torch.float32, 3 * n, "c_far"),
+                      _ptr(self.hit_ratio, torch.float32, n, "hit_ratio"),
+                      _ptr(self.lum_m1, torch.float32, n, "lum_m1"),
+                      _ptr(self.lum_m2, torch.float32, n, "lum_m2"))
+
+
+def _npx(cam: Camera) -> int:
+    return int(cam.width) * int(cam.height)
+
+
+def hdof_gbuffer(ctx: Context, scene: Scene, cam: Camera, lns: Lens, lit: Light, out: GBuffer | None = None,
+                 stream=None) -> GBuffer:
+    if out is None:
+        out = GBuffer.empty(cam.height, cam.width)
+    if out.depth.numel() < _npx(cam):
+        raise ValueError("G-buffer smaller than the camera image")
+    _check(_lib.hdof_gbuffer(ctx.handle, scene.handle, C.byref(cam), C.byref(lns), C.byref(lit), out.bufs(),
+                             _stream(stream)), "hdof_gbuffer")
+    return out
+
+
+def hdof_ray_mask(ctx: Context, depth: torch.Tensor, normal: torch.Tensor, cam: Camera, prev: Camera | None,
+                  lns: Lens, mp: MaskParams, spp=None, offsets=None, total=None, stream=None):
+    n = _npx(cam)
+    dev = depth.device
+    spp = torch.empty(cam.height, cam.width, dtype=torch.uint8, device=dev) if spp is None else spp
+    offsets = torch.empty(cam.height, cam.width, dtype=torch.int32, device=dev) if offsets is None else offsets
+    total = torch.empty(1, dtype=torch.int32, device=dev) if total is None else total
+    gb = GBufferBufs(_ptr(depth, torch.float32, n, "depth"), _ptr(normal, torch.float32, 3 * n, "normal"),
+                     None, None, None)
+    _check(_lib.hdof_ray_mask(ctx.handle, C.byref(gb), C.byref(cam), C.byref(prev) if prev is not None else None,
+                              C.byref(lns), C.byref(mp), _ptr(spp, torch.uint8, n, "spp"),
+                              _ptr(offsets, torch.int32, n, "offsets"), _ptr(total, torch.int32, 1, "total"),
+                              _stream(stream)), "hdof_ray_mask")
+    return spp, offsets, total
+
+
+def hdof_trace_thin_lens(ctx: Context, scene: Scene, cam: Camera, lns: Lens, lit: Light, spp_max: int,
+                         spp: torch.Tensor, offsets: torch.Tensor, total: torch.Tensor, seed=0, frame=0, view=0,
+                         out: RTResult | None = None, ray_tri_id: torch.Tensor | None = None,
+                         ray_depth: torch.Tensor | None = None, stream=None) -> RTResult:
+    n = _npx(cam)
+    out = RTResult.empty(cam.height, cam.width) if out is None else out
+    cap = n * int(spp_max)
+    _check(_lib.hdof_trace_thin_lens(ctx.handle, scene.handle, C.byref(cam), C.byref(lns), C.byref(lit),
+                                     int(spp_max), _ptr(spp, torch.uint8, n, "spp"),
+                                     _ptr(offsets, torch.int32, n, "offsets"), _ptr(total, torch.int32, 1, "total"),
+                                     int(seed), int(frame), int(view), out.bufs(n),
+                                     _ptr(ray_tri_id, torch.int32, cap, "ray_tri_id"),
+                                     _ptr(ray_depth, torch.float32, cap, "ray_depth"), _stream(stream)),
+           "hdof_trace_thin_lens")
+    return out
+
+
+def hdof_variance_update(ctx: Context, cam: Camera, mp: MaskParams, spp, depth, lum_m1, lum_m2, stream=None):
+    n = _npx(cam)
+    _check(_lib.hdof_variance_update(ctx.handle, C.byref(cam), C.byref(mp), _ptr(spp, torch.uint8, n, "spp"),
+                                     _ptr(depth, torch.float32, n, "depth"),
+                                     _ptr(lum_m1, torch.float32, n, "lum_m1"),
+                                     _ptr(lum_m2, torch.float32, n, "lum_m2"), _stream(stream)),
+           "hdof_variance_update")
+
+
+def hdof_history_load(ctx: Context, lum_m1, lum_m2, flags, depth, stream=None):
+    H, W = depth.shape
+    n = H * W
+    _check(_lib.hdof_history_load(ctx.handle, W, H, _ptr(lum_m1, torch.float32, n, "lum_m1"),
+                                  _ptr(lum_m2, torch.float32, n, "lum_m2"), _ptr(flags, torch.uint8, n, "flags"),
+                                  _ptr(depth, torch.float32, n, "depth"), _stream(stream)), "hdof_history_load")
+
+
+def hdof_history_save(ctx: Context, H: int, W: int, stream=None) -> dict:
+    f = dict(dtype=torch.float32, device="cuda")
+    out = dict(lum_m1=torch.empty(H, W, **f), lum_m2=torch.empty(H, W, **f),
+               flags=torch.empty(H, W, dtype=torch.uint8, device="cuda"), depth=torch.empty(H, W, **f))
+    _check(_lib.hdof_history_save(ctx.handle, out["lum_m1"].data_ptr(), out["lum_m2"].data_ptr(),
+                                  out["flags"].data_ptr(), out["depth"].data_ptr(), _stream(stream)),
+           "hdof_history_save")
+    return out
+
+
+def hdof_history_reset(ctx: Context):
+    _check(_lib.hdof_history_reset(ctx.handle), "hdof_history_reset")
+
+
+def hdof_postfilter(ctx: Context, color, depth, cam: Camera, lns: Lens, pp: PPParams, out=None, stream=None):
+    n = _npx(cam)
+    out = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device=color.device) if out is None else out
+    _check(_lib.hdof_postfilter(ctx.handle, _ptr(color, torch.float32, 3 * n, "color"),
+                                _ptr(depth, torch.float32, n, "depth"), C.byref(cam), C.byref(lns), C.byref(pp),
+                                _ptr(out, torch.float32, 3 * n, "out"), _stream(stream)), "hdof_postfilter")
+    return out
+
+
+def hdof_composite(ctx: Context, color, pp_col, depth, spp, rt: RTResult, cam: Camera, lns: Lens,
+                   cp: CompositeParams, out=None, stream=None):
+    n = _npx(cam)
+    out = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device=color.device) if out is None else out
+    _check(_lib.hdof_composite(ctx.handle, _ptr(color, torch.float32, 3 * n, "color"),
+                               _ptr(pp_col, torch.float32, 3 * n, "pp"), _ptr(depth, torch.float32, n, "depth"),
+                               _ptr(spp, torch.uint8, n, "spp"), rt.bufs(n), C.byref(cam), C.byref(lns),
+                               C.byref(cp), _ptr(out, torch.float32, 3 * n, "out"), _stream(stream)),
+           "hdof_composite")
+    return out
+
+
+@dataclass
+class FrameKeep:
+    """Caller-owned intermediates of hdof_frame (all optional)."""
+    gb: GBuffer | None = None
+    spp: torch.Tensor | None = None
+    offsets: torch.Tensor | None = None
+    total: torch.Tensor | None = None
+    rt: RTResult | None = None
+    pp: torch.Tensor | None = None
+
+    @staticmethod
+    def empty(H: int, W: int, device="cuda") -> "FrameKeep":
+        return FrameKeep(GBuffer.empty(H, W, device), torch.empty(H, W, dtype=torch.uint8, device=device),
+                         torch.empty(H, W, dtype=torch.int32, device=device),
+                         torch.empty(1, dtype=torch.int32, device=device), RTResult.empty(H, W, device),
+                         torch.empty(3, H, W, dtype=torch.float32, device=device))
+
+    def bufs(self, n: int) -> FrameBufs:
+        fb = FrameBufs()
+        if self.gb is not None:
+            fb.gb = self.gb.bufs()
+        if self.rt is not None:
+            fb.rt = self.rt.bufs(n)
+        fb.spp = _ptr(self.spp, torch.uint8, n, "spp")
+        fb.offsets = _ptr(self.offsets, torch.int32, n, "offsets")
+        fb.total = _ptr(self.total, torch.int32, 1, "total")
+        fb.pp = _ptr(self.pp, torch.float32, 3 * n, "pp")
+        return fb
+
+
+def hdof_frame(ctx: Context, scene: Scene, cam: Camera, prev: Camera | None, lns: Lens, lit: Light,
+               params: FrameParams, seed=0, frame=0, view=0, out=None, keep: FrameKeep | None = None,
+               stream=None):
+    n = _npx(cam)
+    out = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device="cuda") if out is None else out
+    fb = keep.bufs(n) if keep is not None else None
+    _check(_lib.hdof_frame(ctx.handle, scene.handle, C.byref(cam), C.byref(prev) if prev is not None else None,
+                           C.byref(lns), C.byref(lit), C.byref(params), int(seed), int(frame), int(view),
+                           _ptr(out, torch.float32, 3 * n, "out"), C.byref(fb) if fb is not None else None,
+                           _stream(stream)), "hdof_frame")
+    return out
+
+
+# ----------------------------------------------------------------------------
+# duck-typed constructors (objects with the same field names)
+# ----------------------------------------------------------------------------
+
+def camera_of(c) -> Camera:
+    return camera(c.eye, c.right, c.up, c.fwd, c.tan_half_fov_x, c.width, c.height)
+
+
+def lens_of(l) -> Lens:
+    return lens(l.focal_length, l.aperture, l.focus_distance)
+
+
+def light_of(l) -> Light:
+    return light(l.pos, l.intensity, l.ambient)
+
+
+def mask_params_of(m) -> MaskParams:
+    return mask_params(m.sigma, m.tau_depth, m.tau_normal, m.tau_var, m.var_alpha, m.spp_max, m.tile, m.dilate)
+
+
+def pp_params_of(p) -> PPParams:
+    return pp_params(p.n_taps, p.tile, p.r_cap, p.bg_ramp_px)
+
+
+def composite_params_of(c) -> CompositeParams:
+    return composite_params(c.h_t, c.rt_override)
+
+
+def frame_params_of(cfg) -> FrameParams:
+    return FrameParams(mask_params_of(cfg.mask), pp_params_of(cfg.pp), composite_params_of(cfg.comp))
+
+
+def hdof_profile_begin(ctx: Context) -> None:
+    _check(_lib.hdof_profile_begin(ctx.handle), "hdof_profile_begin")
+
+
+def hdof_profile_end(ctx: Context) -> tuple[dict, int]:
+    """Mean ms per stage over the frames recorded since hdof_profile_begin."""
+    ms = (C.c_float * len(PROFILE_STAGES))()
+    n = C.c_int32(0)
+    _check(_lib.hdof_profile_end(ctx.handle, ms, C.byref(n)), "hdof_profile_end")
+    return {k: float(v) for k, v in zip(PROFILE_STAGES, ms)}, int(n.value)

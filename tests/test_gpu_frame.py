@@ -1,0 +1,174 @@
+"""GPU whole-frame parity and invariants through hdof_frame.
+
+End to end, a G-buffer hit that legitimately differs (oracle-flagged edge)
+changes the stages downstream of it; the comparison therefore excludes the
+footprint of pixels whose GPU and oracle inputs actually differ, after
+checking that each such difference is one the oracle flagged.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen as sg
+from gpu_common import DEV, chebyshev_dilate, excl_cumsum, f32, print_case, tile_footprint, to_dev, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+COL_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def hd():
+    from paper_2210_04981_amd import hdof
+    return hdof
+
+
+@pytest.fixture(scope="module")
+def ctx(hd):
+    c = hd.Context(0)
+    yield c
+    c.close()
+
+
+def run_frame(hd, ctx, sc, cfg, prev=None, frame=0, view=0):
+    H, W = cfg.camera.height, cfg.camera.width
+    keep = hd.FrameKeep.empty(H, W)
+    out = hd.hdof_frame(ctx, sc, hd.camera_of(cfg.camera), hd.camera_of(prev) if prev is not None else None,
+                        hd.lens_of(cfg.lens), hd.light_of(cfg.light), hd.frame_params_of(cfg), seed=cfg.seed,
+                        frame=frame, view=view, keep=keep)
+    torch.cuda.synchronize()
+    ctx.sync()
+    g = dict(out=out.cpu().numpy().astype(np.float64), spp=keep.spp.cpu().numpy().astype(np.int64),
+             offsets=keep.offsets.cpu().numpy().astype(np.int64), total=int(keep.total.item()),
+             tri_id=keep.gb.tri_id.cpu().numpy(), color=keep.gb.color.cpu().numpy().astype(np.float64),
+             depth=keep.gb.depth.cpu().numpy().astype(np.float64), pp=keep.pp.cpu().numpy().astype(np.float64))
+    for k in ("c_near", "c_far", "hit_ratio", "lum_m1", "lum_m2"):
+        g[k] = getattr(keep.rt, k).cpu().numpy().astype(np.float64)
+    return g
+
+
+def compare_frame(g, ref, cfg):
+    gb = ref["gbuffer"]
+    H, W = gb["depth"].shape
+    # 1. G-buffer: differences only where the oracle flags them
+    diff_gb = g["tri_id"] != gb["tri_id"]
+    assert not (diff_gb & (gb["amb"] == 0)).any()
+    same = ~diff_gb
+    assert np.max(np.abs(g["color"] - gb["color"])[:, same], initial=0) < COL_TOL
+    # 2. mask, outside the stencil + tile footprint of differing G-buffer pixels
+    mp = cfg.mask
+    gr = int(math.floor(3 * mp.sigma + 0.5))
+    foot_mask = tile_footprint(chebyshev_dilate(diff_gb, gr + 1), mp.tile, mp.dilate)
+    lo, hi = ref["mask"]["spp_lo"], ref["mask"]["spp_hi"]
+    s = g["spp"]
+    ok = ~foot_mask
+    assert np.all((s >= lo) & (s <= hi) | foot_mask)
+    assert np.array_equal(g["offsets"], excl_cumsum(s)) and g["total"] == s.sum()
+    # 3. trace: pixels with equal counts and unambiguous rays trace the same rays
+    rt = ref["rt"]
+    tr_ok = (s == ref["spp"]) & (rt["px_amb"] == 0)
+    h = g["hit_ratio"]
+    assert np.max(np.abs(h - rt["hit_ratio"])[tr_ok], initial=0) < 1e-4
+    crt_g = h * g["c_near"] + (1 - h) * g["c_far"]
+    crt_r = rt["hit_ratio"] * rt["c_near"] + (1 - rt["hit_ratio"]) * rt["c_far"]
+    assert np.max(np.abs(crt_g - crt_r)[:, tr_ok], initial=0) < COL_TOL
+    # 4. post-filter outside the gather footprint of differing G-buffer pixels
+    pp = cfg.pp
+    K = math.ceil(pp.r_cap / pp.tile)
+    foot_pp = chebyshev_dilate(diff_gb, int(pp.r_cap) + 2) | tile_footprint(diff_gb, pp.tile, K)
+    assert np.max(np.abs(g["pp"] - ref["pp"])[:, ~foot_pp], initial=0) < COL_TOL
+    # 5. composite where every input agrees
+    comp_ok = same & ~foot_pp & tr_ok
+    assert np.max(np.abs(g["out"] - ref["out"])[:, comp_ok], initial=0) < COL_TOL
+    return dict(diff_gb=int(diff_gb.sum()), compared=float(comp_ok.mean()))
+
+
+@pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_320x180"])
+def test_frame_matches_oracle(hd, ctx, which):
+    print_case(f"frame {which}")
+    if which == "room_320x180":
+        scene, cfg = sg.living_room_scene(0), sg.config_1080p(320, 180)
+    else:
+        scene = sg.tiny_scene(0)
+        cfg = sg.config_tiny() if which == "tiny" else sg.config_tiny(aperture_override=0.2)
+    sc = upload_scene(hd, ctx, scene)
+    hd.hdof_history_reset(ctx)
+    g = run_frame(hd, ctx, sc, cfg)
+    ref = oracle.frame(oracle.Scene(scene.verts, scene.albedo), cfg)
+    info = compare_frame(g, ref, cfg)
+    assert info["compared"] > 0.5, info
+    sc.close()
+
+
+def test_zero_aperture_frame_is_gbuffer_bitwise(hd, ctx):
+    print_case("invariant A=0")
+    scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.0)
+    cfg.mask.tile, cfg.mask.dilate = 1, 0
+    sc = upload_scene(hd, ctx, scene)
+    g = run_frame(hd, ctx, sc, cfg)
+    assert g["total"] > 0
+    assert np.array_equal(g["out"], g["color"])
+    traced = g["spp"] > 0
+    crt = g["hit_ratio"] * g["c_near"] + (1 - g["hit_ratio"]) * g["c_far"]
+    # every lens ray is the pinhole ray: same hit, same colour (up to the
+    # fp32 near/far weighting, exact when all weights are 0 or 1)
+    assert np.max(np.abs(crt - g["color"])[:, traced]) < 1e-6
+    sc.close()
+
+
+def test_full_mask_override_is_full_rt(hd, ctx):
+    """tau -> tiny makes every pixel traced at spp_max; with rt_override the
+    frame equals the ray-traced colour everywhere (full ray-traced mode)."""
+    print_case("invariant full mask + override")
+    scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.2)
+    cfg.mask.tau_depth = cfg.mask.tau_normal = 1e-12
+    cfg.mask.tile, cfg.mask.dilate = 16, 8   # one tile with any edge covers the image
+    cfg.comp.rt_override = 1
+    sc = upload_scene(hd, ctx, scene)
+    g = run_frame(hd, ctx, sc, cfg)
+    assert np.all(g["spp"] == cfg.mask.spp_max)
+    crt = (g["hit_ratio"] * g["c_near"] + (1 - g["hit_ratio"]) * g["c_far"]).astype(np.float32)
+    assert np.array_equal(g["out"].astype(np.float32), crt)
+    ref = oracle.frame(oracle.Scene(scene.verts, scene.albedo), cfg, rt_full_spp=cfg.mask.spp_max)
+    ok = ref["rt"]["px_amb"] == 0
+    assert np.max(np.abs(g["out"] - ref["out"])[:, ok]) < COL_TOL
+    sc.close()
+
+
+def test_trace_independent_of_other_pixels(hd, ctx):
+    """A pixel's traced result depends only on its own count: halving every
+    other pixel's count leaves it bitwise unchanged."""
+    print_case("invariant per-pixel independence")
+    scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.2)
+    sc = upload_scene(hd, ctx, scene)
+    H = W = 64
+    rng = np.random.default_rng(1)
+    s1 = rng.integers(1, 5, (H, W)).astype(np.int32)
+    s2 = s1.copy()
+    s2[::2] = rng.integers(0, 5, (H // 2, W))
+    res = []
+    for s in (s1, s2):
+        out = hd.hdof_trace_thin_lens(ctx, sc, hd.camera_of(cfg.camera), hd.lens_of(cfg.lens),
+                                      hd.light_of(cfg.light), 4, to_dev(s.astype(np.uint8)),
+                                      to_dev(excl_cumsum(s).astype(np.int32)),
+                                      to_dev(np.array([s.sum()], np.int32)), seed=5)
+        torch.cuda.synchronize()
+        res.append(out.c_near.cpu().numpy())
+    keep = np.ones((H, W), bool)
+    keep[::2] = False
+    assert np.array_equal(res[0][:, keep], res[1][:, keep])
+    sc.close()
+
+
+def test_run_to_run_deterministic(hd, ctx):
+    print_case("invariant determinism")
+    scene, cfg = sg.living_room_scene(0), sg.config_1080p(256, 144)
+    sc = upload_scene(hd, ctx, scene)
+    a = run_frame(hd, ctx, sc, cfg)
+    b = run_frame(hd, ctx, sc, cfg)
+    for k in ("out", "spp", "c_near", "pp"):
+        assert np.array_equal(a[k], b[k]), k
+    sc.close()
