@@ -2,7 +2,7 @@
 GPU stage and the oracle receive the same float32 inputs, produced by the
 oracle or by scenegen, never by the GPU).
 
-Bars (the benchmark spec): hit triangle ids and per-pixel ray counts identical
+Bars: hit triangle ids and per-pixel ray counts identical
 except where the oracle flags an edge / tie / threshold ambiguity within
 1e-5; linear colour within 1e-3 absolute.
 """
