@@ -97,6 +97,12 @@ def main():
     ms_per_step = gpu_ms / args.steps
     fps = 1000.0 / ms_per_step
 
+    # one extra frame with the counting traversal variants: node visits and
+    # triangle tests per ray (not part of the timed region)
+    hdof.hdof_counters_begin(ctx)
+    step(args.warmup + args.steps)
+    work = hdof.hdof_counters_end(ctx)
+
     spp = keep.spp.cpu().numpy()
     rays = int(keep.total.item())
     coverage = float((spp > 0).mean())
@@ -106,7 +112,11 @@ def main():
 
     # dominant kernel and its roofline
     dom = max(stage_ms, key=stage_ms.get)
-    roofline = roofline_for(dom, stage_ms[dom], N, rays)
+    per_ray = {
+        "gbuffer": (work["gbuffer_visits"] / max(work["gbuffer_rays"], 1), work["gbuffer_tests"] / max(work["gbuffer_rays"], 1)),
+        "trace": (work["trace_visits"] / max(work["trace_rays"], 1), work["trace_tests"] / max(work["trace_rays"], 1)),
+    }
+    roofline = roofline_for(dom, stage_ms[dom], N, rays, per_ray)
 
     res = {
         "metric": METRIC,
@@ -133,6 +143,7 @@ def main():
         "frame_traced_mrays_per_s": round(rays * fps / 1e6, 2),
         "mask_coverage": round(coverage, 4),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "traversal_per_ray": {k: {"node_visits": round(v[0], 2), "tri_tests": round(v[1], 2)} for k, v in per_ray.items()},
         "profiled_frames": nf,
         "bvh": {"build_ms_host_timed": round(bvh_ms, 2), **stats},
         "roofline": roofline,
@@ -154,10 +165,17 @@ HBM_BYTES_PER_PX = {
 }
 
 
-def roofline_for(stage, ms, n_px, rays):
+# algorithmic lane-ops per unit of work: one BVH node step
+# (two slab tests), one watertight triangle test, the per-ray setup and
+# shading, a Philox4x64-10 block, one post-filter tap
+OPS_NODE, OPS_TRI, OPS_RAY, OPS_PHILOX, OPS_TAP = 38, 45, 150, 250, 34
+
+
+def roofline_for(stage, ms, n_px, rays, per_ray):
     """Roofline entry of the dominant stage.  Traversal and gather stages are
     reported against the VALU peak with their algorithmic lane-op counts per
-    unit; streaming stages against HBM with algorithmic bytes per pixel."""
+    unit (node visits and triangle tests measured by the counting pass);
+    streaming stages against HBM with algorithmic bytes per pixel."""
     sec = ms * 1e-3
     if stage in HBM_BYTES_PER_PX:
         b = HBM_BYTES_PER_PX[stage] * n_px
@@ -165,11 +183,13 @@ def roofline_for(stage, ms, n_px, rays):
         return {"kernel": stage, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
     if stage == "pp_gather":
-        ops = n_px * 48 * 60      # lane-ops per tap (bilinear of 4 float4 + weights), see the design doc
+        ops = n_px * 48 * OPS_TAP
     elif stage == "gbuffer":
-        ops = n_px * 1500         # lane-ops per primary ray (traversal + watertight tests + shading)
+        v, t = per_ray["gbuffer"]
+        ops = n_px * (v * OPS_NODE + t * OPS_TRI + OPS_RAY)
     else:
-        ops = max(rays, 1) * 1900  # per thin-lens ray (Philox + traversal + tests + shading)
+        v, t = per_ray["trace"]
+        ops = max(rays, 1) * (v * OPS_NODE + t * OPS_TRI + OPS_RAY + OPS_PHILOX)
     ach = ops / sec / 1e12
     return {"kernel": stage, "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tlane-op/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": None}

@@ -294,6 +294,15 @@ hdof_status hdof_profile_begin(hdof_ctx* ctx);
  * the number of frames (*n_frames, may be NULL). */
 hdof_status hdof_profile_end(hdof_ctx* ctx, float* ms_out, int32_t* n_frames);
 
+/* Traversal work counters.  Between begin and end, hdof_gbuffer,
+ * hdof_trace_thin_lens and hdof_frame run variants of their traversal
+ * kernels that count, per ray, the BVH nodes entered and the triangles
+ * tested (slower; for measurement only).  end synchronises and writes
+ * out[6] = {G-buffer rays, node visits, triangle tests, thin-lens rays,
+ * node visits, triangle tests}. */
+hdof_status hdof_counters_begin(hdof_ctx* ctx);
+hdof_status hdof_counters_end(hdof_ctx* ctx, int64_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -162,7 +162,14 @@ extern "C" hdof_status hdof_create(int device, hdof_ctx** out) {
     delete c;
     return hdof_set_error(HDOF_ERR_OOM, "hipMalloc(flags): %s", hipGetErrorString(e));
   }
-  e = hipMemset(c->d_flags, 0, sizeof(int));
+  e = hipMalloc(&c->d_counters, 6 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    hipFree(c->d_flags);
+    delete c;
+    return hdof_set_error(HDOF_ERR_OOM, "hipMalloc(counters): %s", hipGetErrorString(e));
+  }
+  e = hipMemset(c->d_counters, 0, 6 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     hipFree(c->d_flags);
@@ -187,6 +194,7 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
   if (ctx->d_flags) hipFree(ctx->d_flags);
+  if (ctx->d_counters) hipFree(ctx->d_counters);
   delete ctx;
 }
 
@@ -533,5 +541,28 @@ extern "C" hdof_status hdof_profile_end(hdof_ctx* ctx, float* ms_out, int32_t* n
   if (n_frames) *n_frames = ctx->prof_frames;
   ctx->prof_on = false;
   ctx->prof_frames = 0;
+  return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// traversal work counters
+// ---------------------------------------------------------------------------
+extern "C" hdof_status hdof_counters_begin(hdof_ctx* ctx) {
+  TRY(check_ctx(ctx));
+  HDOF_HIP(hipDeviceSynchronize());
+  HDOF_HIP(hipMemset(ctx->d_counters, 0, 6 * sizeof(unsigned long long)));
+  HDOF_HIP(hipDeviceSynchronize());
+  ctx->count_on = true;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_counters_end(hdof_ctx* ctx, int64_t* out) {
+  TRY(check_ctx(ctx));
+  REQUIRE(out, "out is NULL");
+  HDOF_HIP(hipDeviceSynchronize());
+  unsigned long long c[6];
+  HDOF_HIP(hipMemcpy(c, ctx->d_counters, sizeof c, hipMemcpyDeviceToHost));
+  for (int i = 0; i < 6; ++i) out[i] = (int64_t)c[i];
+  ctx->count_on = false;
   return HDOF_OK;
 }

@@ -57,6 +57,7 @@ struct hdof_ctx {
   Buf mask_tile, mask_tile_dil, mask_xpref, mask_rowsum, mask_ybase;
   // post-filter scratch
   Buf pp_pack, pp_tile, pp_rad, pp_taps;
+  int pp_taps_n = 0;  // tap count the table currently holds
   // variance history (previous frame) and its reprojection into this frame
   int hist_w = 0, hist_h = 0;
   bool hist_any = false;
@@ -67,6 +68,9 @@ struct hdof_ctx {
   // frame intermediates when the caller keeps none
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
+  // traversal work counters (rays, node visits, triangle tests) x (G-buffer, trace)
+  bool count_on = false;
+  unsigned long long* d_counters = nullptr;
   // stage profiling: HDOF_PROFILE_STAGES + 1 events per profiled frame
   bool prof_on = false, prof_in_frame = false;
   int prof_frames = 0;

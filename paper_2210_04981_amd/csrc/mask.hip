@@ -38,70 +38,82 @@ struct HistIn {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+template <int GR>
 __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ depth,
                                                     const float* __restrict__ normal, CamK k, MaskK mk,
                                                     HistIn hi, float* __restrict__ rep_m1,
                                                     float* __restrict__ rep_m2,
                                                     uint8_t* __restrict__ rep_flags,
                                                     int* __restrict__ tile_max) {
-  __shared__ float in[4][MAX_IN][MAX_IN];
-  __shared__ float xb[4][MAX_IN][BL];
-  __shared__ float yb[4][BL][BL];
+  // (depth, nx, ny, nz) of one pixel per float4; all extents compile-time
+  constexpr int AP = GR + 1, NIN = MT + 2 * AP;
+  __shared__ float4 in[NIN][NIN];
+  __shared__ float4 xb[NIN][BL];
+  __shared__ float4 yb[BL][BL];
   __shared__ int sr[MT][MT];
   const int W = k.W, H = k.H;
   const size_t N = (size_t)W * H;
   const int x0 = blockIdx.x * MT, y0 = blockIdx.y * MT;
   const int tid = threadIdx.x;
-  const int gr = mk.gr, ap = gr + 1, nin = MT + 2 * ap;
   // stage depth (clamped to zmax) and normal with clamp-to-edge
-  for (int i = tid; i < nin * nin; i += 256) {
-    int ly = i / nin, lx = i - ly * nin;
-    int gx = clampi(x0 - ap + lx, 0, W - 1), gy = clampi(y0 - ap + ly, 0, H - 1);
-    size_t p = (size_t)gy * W + gx;
-    in[0][ly][lx] = fminf(depth[p], HDOF_ZMAX);
-    in[1][ly][lx] = normal[p];
-    in[2][ly][lx] = normal[N + p];
-    in[3][ly][lx] = normal[2 * N + p];
+  for (int i = tid; i < NIN * NIN; i += 256) {
+    const int ly = i / NIN, lx = i - ly * NIN;
+    const int gx = clampi(x0 - AP + lx, 0, W - 1), gy = clampi(y0 - AP + ly, 0, H - 1);
+    const size_t p = (size_t)gy * W + gx;
+    in[ly][lx] = make_float4(fminf(depth[p], HDOF_ZMAX), normal[p], normal[N + p], normal[2 * N + p]);
   }
   __syncthreads();
-  // x pass on every staged row, for the 18 columns the Sobel needs; a column
+  // x pass on every staged row for the 18 columns the Sobel needs; a column
   // outside the image takes the value of the clamped column
-  for (int i = tid; i < 4 * nin * BL; i += 256) {
-    int c = i / (nin * BL), rem = i - c * nin * BL;
-    int ly = rem / BL, ox = rem - ly * BL;
-    int gxc = clampi(x0 - 1 + ox, 0, W - 1);
-    int lx0 = gxc - (x0 - ap) - gr;
-    float acc = 0.0f;
-    for (int t = 0; t <= 2 * gr; ++t) acc = fmaf(mk.taps[t], in[c][ly][lx0 + t], acc);
-    xb[c][ly][ox] = acc;
+  for (int i = tid; i < NIN * BL; i += 256) {
+    const int ly = i / BL, ox = i - ly * BL;
+    const int lx0 = clampi(x0 - 1 + ox, 0, W - 1) - x0 + 1;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t <= 2 * GR; ++t) {
+      const float4 v = in[ly][lx0 + t];
+      const float w = mk.taps[t];
+      a.x = fmaf(w, v.x, a.x);
+      a.y = fmaf(w, v.y, a.y);
+      a.z = fmaf(w, v.z, a.z);
+      a.w = fmaf(w, v.w, a.w);
+    }
+    xb[ly][ox] = a;
   }
   __syncthreads();
-  for (int i = tid; i < 4 * BL * BL; i += 256) {
-    int c = i / (BL * BL), rem = i - c * BL * BL;
-    int oy = rem / BL, ox = rem - oy * BL;
-    int gyc = clampi(y0 - 1 + oy, 0, H - 1);
-    int ly0 = gyc - (y0 - ap) - gr;
-    float acc = 0.0f;
-    for (int t = 0; t <= 2 * gr; ++t) acc = fmaf(mk.taps[t], xb[c][ly0 + t][ox], acc);
-    yb[c][oy][ox] = acc;
+  for (int i = tid; i < BL * BL; i += 256) {
+    const int oy = i / BL, ox = i - oy * BL;
+    const int ly0 = clampi(y0 - 1 + oy, 0, H - 1) - y0 + 1;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t <= 2 * GR; ++t) {
+      const float4 v = xb[ly0 + t][ox];
+      const float w = mk.taps[t];
+      a.x = fmaf(w, v.x, a.x);
+      a.y = fmaf(w, v.y, a.y);
+      a.z = fmaf(w, v.z, a.z);
+      a.w = fmaf(w, v.w, a.w);
+    }
+    yb[oy][ox] = a;
   }
   __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
   const int x = x0 + tx, y = y0 + ty;
   int s_raw = 0;
   if (x < W && y < H) {
-    float gsq[4];
-    for (int c = 0; c < 4; ++c) {
-      // yb index = local + 1
-#define YB(dx, dy) yb[c][ty + 1 + (dy)][tx + 1 + (dx)]
-      float gx = (YB(1, -1) - YB(-1, -1)) + 2.0f * (YB(1, 0) - YB(-1, 0)) + (YB(1, 1) - YB(-1, 1));
-      float gy = (YB(-1, 1) - YB(-1, -1)) + 2.0f * (YB(0, 1) - YB(0, -1)) + (YB(1, 1) - YB(1, -1));
-#undef YB
-      gsq[c] = fmaf(gx, gx, gy * gy);
-    }
-    float zb = yb[0][ty + 1][tx + 1];
-    float gz = sqrtf(gsq[0]) / (8.0f * fmaxf(zb, 1e-3f));
-    float gn = sqrtf(gsq[1] + gsq[2] + gsq[3]) * 0.125f;
+    // Sobel: yb index = local + 1
+    const float4 a00 = yb[ty][tx], a10 = yb[ty][tx + 1], a20 = yb[ty][tx + 2];
+    const float4 a01 = yb[ty + 1][tx], a21 = yb[ty + 1][tx + 2];
+    const float4 a02 = yb[ty + 2][tx], a12 = yb[ty + 2][tx + 1], a22 = yb[ty + 2][tx + 2];
+    const float zb = yb[ty + 1][tx + 1].x;
+#define SOBEL(c)                                                                      \
+  const float gx_##c = (a20.c - a00.c) + 2.0f * (a21.c - a01.c) + (a22.c - a02.c);    \
+  const float gy_##c = (a02.c - a00.c) + 2.0f * (a12.c - a10.c) + (a22.c - a20.c);    \
+  const float g2_##c = fmaf(gx_##c, gx_##c, gy_##c * gy_##c);
+    SOBEL(x) SOBEL(y) SOBEL(z) SOBEL(w)
+#undef SOBEL
+    const float gz = sqrtf(g2_x) / (8.0f * fmaxf(zb, 1e-3f));
+    const float gn = sqrtf(g2_y + g2_z + g2_w) * 0.125f;
     // reprojected variance
     const size_t p = (size_t)y * W + x;
     float V = 0.0f, a1 = 0.0f, a2 = 0.0f;
@@ -310,9 +322,20 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   ctx->rep_valid = true;
   int* rowsum = (int*)ctx->mask_rowsum.p;
   int* rowtot = rowsum + TH;
-  hipLaunchKernelGGL(k_mask_score, dim3(cdiv(W, MT), cdiv(H, MT)), dim3(256), 0, st, depth, normal, k, mk,
-                     hi, (float*)ctx->rep_m1.p, (float*)ctx->rep_m2.p, (uint8_t*)ctx->rep_flags.p,
-                     (int*)ctx->mask_tile.p);
+  {
+    const dim3 g(cdiv(W, MT), cdiv(H, MT)), b(256);
+    float* r1 = (float*)ctx->rep_m1.p;
+    float* r2 = (float*)ctx->rep_m2.p;
+    uint8_t* rf = (uint8_t*)ctx->rep_flags.p;
+    int* tm = (int*)ctx->mask_tile.p;
+    switch (gr) {
+#define CASE(R) \
+  case R: hipLaunchKernelGGL(k_mask_score<R>, g, b, 0, st, depth, normal, k, mk, hi, r1, r2, rf, tm); break;
+      CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+      default: return hdof_set_error(HDOF_ERR_INVALID_ARG, "Gaussian radius %d above %d", gr, MAX_GR);
+    }
+  }
   hipLaunchKernelGGL(k_mask_rows, dim3(TH), dim3(256), 0, st, (const int*)ctx->mask_tile.p, W, H, t,
                      mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot);
   hipLaunchKernelGGL(k_mask_rowscan, dim3(1), dim3(1024), 0, st, (const int*)rowtot, TH,

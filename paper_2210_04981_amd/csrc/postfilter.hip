@@ -14,6 +14,8 @@
 
 namespace {
 
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 __global__ __launch_bounds__(256) void k_pp_pack(const float* __restrict__ color,
                                                  const float* __restrict__ depth, CamK k, LensK l,
                                                  int tile, float4* __restrict__ pack,
@@ -68,19 +70,25 @@ __global__ void k_pp_dilate(const float* __restrict__ tile_r, int TW, int TH, in
   rad[ty * TW + tx] = fminf(r_cap, m);
 }
 
-__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// UNI: the post-filter tile equals the 16x16 block, so the gather radius and
+// with it every tap's integer offset and bilinear weights are uniform over
+// the block (computed once per tap in scalar registers); only the four
+// texel loads and the per-tap weight are per lane.  Blocks whose reach stays
+// inside the image skip the clamp-to-edge.
+template <bool UNI>
 __global__ __launch_bounds__(256) void k_pp_gather(const float4* __restrict__ pack,
                                                    const float* __restrict__ rad,
                                                    const float4* __restrict__ taps, int n_taps,
                                                    int W, int H, int tile, float inv_ramp,
                                                    float* __restrict__ out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int x = blockIdx.x * 16 + (lane & 15), y = blockIdx.y * 16 + wave * 4 + (lane >> 4);
+  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  const int x = x0 + (lane & 15), y = y0 + wave * 4 + (lane >> 4);
   if (x >= W || y >= H) return;
   const size_t N = (size_t)W * H, p = (size_t)y * W + x;
   const int TW = (W + tile - 1) / tile;
-  const float R = rad[(y / tile) * TW + x / tile];
+  const float R = UNI ? rad[blockIdx.y * TW + blockIdx.x] : rad[(y / tile) * TW + x / tile];
   const float4 cp4 = pack[p];
   const float cp = cp4.w, rp = 0.5f * fabsf(cp);
   const float rp5 = fmaxf(rp, 0.5f);
@@ -88,28 +96,37 @@ __global__ __launch_bounds__(256) void k_pp_gather(const float4* __restrict__ pa
   float ar = w0 * cp4.x, ag = w0 * cp4.y, ab = w0 * cp4.z, ws = w0;
   if (R > 0.0f) {
     const float area = R * R / (float)n_taps;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const int reach = (int)ceilf(R) + 1;
+    const bool interior = UNI && x0 - reach >= 0 && x0 + 15 + reach < W && y0 - reach >= 0 && y0 + 15 + reach < H;
     for (int kk = 0; kk < n_taps; ++kk) {
       const float4 u = taps[kk];  // (ux, uy, |u|, 0)
-      float gx = fmaf(R, u.x, px) - 0.5f, gy = fmaf(R, u.y, py) - 0.5f;
-      float fx0 = floorf(gx), fy0 = floorf(gy);
-      float ax = gx - fx0, ay = gy - fy0;
-      int ix = (int)fx0, iy = (int)fy0;
-      int xa = clampi(ix, 0, W - 1), xb = clampi(ix + 1, 0, W - 1);
-      int ya = clampi(iy, 0, H - 1), yb = clampi(iy + 1, 0, H - 1);
-      float4 v00 = pack[(size_t)ya * W + xa], v10 = pack[(size_t)ya * W + xb];
-      float4 v01 = pack[(size_t)yb * W + xa], v11 = pack[(size_t)yb * W + xb];
-      float bx = 1.0f - ax, by = 1.0f - ay;
-      float sr = by * (bx * v00.x + ax * v10.x) + ay * (bx * v01.x + ax * v11.x);
-      float sg = by * (bx * v00.y + ax * v10.y) + ay * (bx * v01.y + ax * v11.y);
-      float sb = by * (bx * v00.z + ax * v10.z) + ay * (bx * v01.z + ax * v11.z);
-      float cq = by * (bx * v00.w + ax * v10.w) + ay * (bx * v01.w + ax * v11.w);
-      float rq = 0.5f * fabsf(cq);
-      float tk = clamp01((cq - cp) * inv_ramp);
-      float reff = rq - tk * fmaxf(0.0f, rq - rp);
-      float a = clamp01(reff - R * u.z + 0.5f);
-      float rq5 = fmaxf(rq, 0.5f);
-      float w = a * area / (rq5 * rq5);
+      // tap position relative to this pixel's texel grid: x + R u.x (the
+      // +0.5 pixel centre and the -0.5 texel centre cancel)
+      const float ox = R * u.x, oy = R * u.y;
+      const float fx = floorf(ox), fy = floorf(oy);
+      const float ax = ox - fx, ay = oy - fy;
+      int xa = x + (int)fx, ya = y + (int)fy;
+      int xb = xa + 1, yb = ya + 1;
+      if (!interior) {
+        xa = clampi(xa, 0, W - 1);
+        xb = clampi(xb, 0, W - 1);
+        ya = clampi(ya, 0, H - 1);
+        yb = clampi(yb, 0, H - 1);
+      }
+      const float4 v00 = pack[(size_t)ya * W + xa], v10 = pack[(size_t)ya * W + xb];
+      const float4 v01 = pack[(size_t)yb * W + xa], v11 = pack[(size_t)yb * W + xb];
+      const float bx = 1.0f - ax, by = 1.0f - ay;
+      const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
+      const float sr = fmaf(w11, v11.x, fmaf(w01, v01.x, fmaf(w10, v10.x, w00 * v00.x)));
+      const float sg = fmaf(w11, v11.y, fmaf(w01, v01.y, fmaf(w10, v10.y, w00 * v00.y)));
+      const float sb = fmaf(w11, v11.z, fmaf(w01, v01.z, fmaf(w10, v10.z, w00 * v00.z)));
+      const float cq = fmaf(w11, v11.w, fmaf(w01, v01.w, fmaf(w10, v10.w, w00 * v00.w)));
+      const float rq = 0.5f * fabsf(cq);
+      const float tk = clamp01((cq - cp) * inv_ramp);
+      const float reff = rq - tk * fmaxf(0.0f, rq - rp);
+      const float a = clamp01(reff + (0.5f - R * u.z));
+      const float rq5 = fmaxf(rq, 0.5f);
+      const float w = a * area * __frcp_rn(rq5 * rq5);
       ar = fmaf(w, sr, ar);
       ag = fmaf(w, sg, ag);
       ab = fmaf(w, sb, ab);
@@ -162,15 +179,23 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
   if ((s = hdof_ensure(ctx->pp_tile, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_rad, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
-  hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
+  if (ctx->pp_taps_n != pp.n_taps) {  // the table depends on the tap count only
+    hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
+    ctx->pp_taps_n = pp.n_taps;
+  }
   hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
                      (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
   hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p, TW,
                      TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
   hdof_prof_mark(ctx, 7, st);
-  hipLaunchKernelGGL(k_pp_gather, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
-                     (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
-                     (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
+  if (t == 16)
+    hipLaunchKernelGGL(k_pp_gather<true>, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
+                       (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
+                       (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
+  else
+    hipLaunchKernelGGL(k_pp_gather<false>, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
+                       (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
+                       (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

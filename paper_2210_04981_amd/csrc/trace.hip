@@ -121,9 +121,14 @@ __device__ inline void test_leaf(const Ray& r, const float4* __restrict__ tris, 
 // Each internal node is entered at most once per ray, so more than n_nodes
 // steps means a malformed tree: the ray stops and raises the device flag
 // instead of looping.
-template <int BLOCK>
+struct Work {
+  int visits, tests;
+};
+
+template <int BLOCK, bool COUNT>
 __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                int n_nodes, const Ray& r, int* __restrict__ stk, int* __restrict__ flags) {
+                                int n_nodes, const Ray& r, int* __restrict__ stk, int* __restrict__ flags,
+                                Work& wk) {
   Best b{INFINITY, -1, 0x7fffffff};
   int spill[HDOF_SPILL_STACK];
   int sp = 0;
@@ -133,6 +138,7 @@ __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* 
       atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
       break;
     }
+    if (COUNT) wk.visits++;
     const float4* nd = nodes + 4 * (size_t)cur;
     float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
     float t0, t1;
@@ -141,10 +147,12 @@ __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* 
     unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
     if (h0 && (c0 & HDOF_LEAF_BIT)) {
       test_leaf(r, tris, c0, b);
+      if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
       h0 = false;
     }
     if (h1 && (c1 & HDOF_LEAF_BIT)) {
       test_leaf(r, tris, c1, b);
+      if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
       h1 = false;
     }
     if (h0 && h1) {
@@ -203,13 +211,15 @@ __device__ inline int xcd_block(int b, int nb) {
   return x * per + min(x, rem) + i;
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ nodes,
                                                  const float4* __restrict__ tris, int n_nodes,
                                                  const float* __restrict__ albedo, CamK k, LensK l,
                                                  LightK li, float* __restrict__ depth,
                                                  float* __restrict__ normal, float* __restrict__ alb_out,
                                                  float* __restrict__ color, int* __restrict__ tri_id,
-                                                 int* __restrict__ flags) {
+                                                 int* __restrict__ flags,
+                                                 unsigned long long* __restrict__ counters) {
   __shared__ int stk[HDOF_LDS_STACK * 256];
   const int bx_n = (k.W + 15) >> 4, by_n = (k.H + 15) >> 4;
   const int lb = xcd_block(blockIdx.x, bx_n * by_n);
@@ -219,7 +229,13 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
   if (x >= k.W || y >= k.H) return;
   V3 v = pixel_dir(k, x, y);
   Ray r = make_ray(k.e, V3{l.S1 * v.x, l.S1 * v.y, l.S1 * v.z});
-  Best b = traverse<256>(nodes, tris, n_nodes, r, stk + t, flags);
+  Work wk{0, 0};
+  Best b = traverse<256, COUNT>(nodes, tris, n_nodes, r, stk + t, flags, wk);
+  if (COUNT) {
+    atomicAdd(&counters[0], 1ull);
+    atomicAdd(&counters[1], (unsigned long long)wk.visits);
+    atomicAdd(&counters[2], (unsigned long long)wk.tests);
+  }
   const size_t N = (size_t)k.W * k.H, p = (size_t)y * k.W + x;
   if (b.tri >= 0) {
     V3 L, n, a;
@@ -261,12 +277,13 @@ __global__ void k_queue_fill(const uint8_t* __restrict__ spp, const int* __restr
     if (o + j >= 0 && o + j < cap) queue[o + j] = p;
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
     const float4* __restrict__ nodes, const float4* __restrict__ tris, int n_nodes,
     const float* __restrict__ albedo, CamK k, LensK l, LightK li, const int* __restrict__ queue, const int* __restrict__ offsets,
     const int* __restrict__ total_p, int* __restrict__ counter, uint32_t seed, uint32_t frame,
     uint32_t view, float* __restrict__ ray_col, float* __restrict__ ray_z, int* __restrict__ ray_id,
-    size_t cap, int* __restrict__ flags) {
+    size_t cap, int* __restrict__ flags, unsigned long long* __restrict__ counters) {
   __shared__ int stk[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
   const int t = threadIdx.x, lane = t & 63;
   const int N = k.W * k.H;
@@ -289,7 +306,13 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
       V3 O, D;
       lens_ray(k, l, x, y, (uint32_t)j, view, seed, frame, O, D);
       Ray r = make_ray(O, D);
-      Best b = traverse<HDOF_TRACE_BLOCK>(nodes, tris, n_nodes, r, stk + t, flags);
+      Work wk{0, 0};
+      Best b = traverse<HDOF_TRACE_BLOCK, COUNT>(nodes, tris, n_nodes, r, stk + t, flags, wk);
+      if (COUNT) {
+        atomicAdd(&counters[3], 1ull);
+        atomicAdd(&counters[4], (unsigned long long)wk.visits);
+        atomicAdd(&counters[5], (unsigned long long)wk.tests);
+      }
       float z = HDOF_ZMAX;
       V3 L = V3{0.0f, 0.0f, 0.0f};
       if (b.tri >= 0) {
@@ -357,8 +380,14 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                            const LightK& li, hdof_gbuffer_bufs out, hipStream_t st) {
   int nb = cdiv(k.W, 16) * cdiv(k.H, 16);
-  hipLaunchKernelGGL(k_gbuffer, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo, k, l, li,
-                     out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags);
+  if (ctx->count_on)
+    hipLaunchKernelGGL(k_gbuffer<true>, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                       k, l, li, out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags,
+                       ctx->d_counters);
+  else
+    hipLaunchKernelGGL(k_gbuffer<false>, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                       k, l, li, out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags,
+                       ctx->d_counters);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
@@ -381,9 +410,14 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
   hdof_prof_mark(ctx, 3, st);
   // persistent grid: enough resident waves to cover every CU several times
   int grid = ctx->n_cu * 8;
-  hipLaunchKernelGGL(k_trace, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
-                     k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
-                     (float*)ctx->ray_col.p, rz, ray_id, cap, ctx->d_flags);
+  if (ctx->count_on)
+    hipLaunchKernelGGL(k_trace<true>, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                       k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
+                       (float*)ctx->ray_col.p, rz, ray_id, cap, ctx->d_flags, ctx->d_counters);
+  else
+    hipLaunchKernelGGL(k_trace<false>, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                       k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
+                       (float*)ctx->ray_col.p, rz, ray_id, cap, ctx->d_flags, ctx->d_counters);
   hdof_prof_mark(ctx, 4, st);
   hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
                      (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near, out.c_far,

@@ -108,6 +108,8 @@ _PROTOS = {
                         C.POINTER(FrameParams), _u32, _u32, _u32, P, C.POINTER(FrameBufs), P]),
     "hdof_profile_begin": (_S, [P]),
     "hdof_profile_end": (_S, [P, C.POINTER(C.c_float), C.POINTER(_i32)]),
+    "hdof_counters_begin": (_S, [P]),
+    "hdof_counters_end": (_S, [P, C.POINTER(C.c_int64)]),
 }
 
 PROFILE_STAGES = ("gbuffer", "ray_mask", "queue_fill", "trace", "rt_reduce", "var_update", "pp_prep",
@@ -482,3 +484,15 @@ def hdof_profile_end(ctx: Context) -> tuple[dict, int]:
     n = C.c_int32(0)
     _check(_lib.hdof_profile_end(ctx.handle, ms, C.byref(n)), "hdof_profile_end")
     return {k: float(v) for k, v in zip(PROFILE_STAGES, ms)}, int(n.value)
+
+
+def hdof_counters_begin(ctx: Context) -> None:
+    _check(_lib.hdof_counters_begin(ctx.handle), "hdof_counters_begin")
+
+
+def hdof_counters_end(ctx: Context) -> dict:
+    """Traversal work since hdof_counters_begin: rays, node visits, triangle tests."""
+    c = (C.c_int64 * 6)()
+    _check(_lib.hdof_counters_end(ctx.handle, c), "hdof_counters_end")
+    return dict(gbuffer_rays=c[0], gbuffer_visits=c[1], gbuffer_tests=c[2],
+                trace_rays=c[3], trace_visits=c[4], trace_tests=c[5])
