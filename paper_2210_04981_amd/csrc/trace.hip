@@ -409,7 +409,7 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
                      (int*)ctx->queue.p, counter);
   hdof_prof_mark(ctx, 3, st);
   // persistent grid: enough resident waves to cover every CU several times
-  int grid = ctx->n_cu * 8;
+  int grid = ctx->n_cu * 12;
   if (ctx->count_on)
     hipLaunchKernelGGL(k_trace<true>, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
                        k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
