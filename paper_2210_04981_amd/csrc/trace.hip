@@ -21,16 +21,20 @@ namespace {
 
 struct Ray {
   V3 O, D;
-  V3 inv, oinv;            // 1/D and -O/D for the slab test
-  int kx, ky, kz;          // watertight axis permutation
-  float Sx, Sy, Sz;        // shear constants
-  float Ox, Oy, Oz;        // origin in permuted order
+  V3 inv, oinv;  // 1/D and -O/D for the slab test
+  // watertight test in the ray's sheared frame (Woop, Benthin, Wald): rows
+  // of the map v -> ((v-O)[kx] - Sx (v-O)[kz], (v-O)[ky] - Sy (v-O)[kz],
+  // Sz (v-O)[kz]) as dense 3-vectors, with the origin term folded in
+  V3 mx, my, mz;
+  float ox, oy, oz;
 };
 
 __device__ inline float safe_inv(float d) {
   float a = fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d);
   return 1.0f / a;
 }
+
+__device__ inline V3 unit(int k) { return V3{k == 0 ? 1.0f : 0.0f, k == 1 ? 1.0f : 0.0f, k == 2 ? 1.0f : 0.0f}; }
 
 __device__ inline Ray make_ray(V3 O, V3 D) {
   Ray r;
@@ -48,19 +52,16 @@ __device__ inline Ray make_ray(V3 O, V3 D) {
     kx = ky;
     ky = t;
   }
-  r.kx = kx;
-  r.ky = ky;
-  r.kz = kz;
-  r.Sx = comp(D, kx) / dz;
-  r.Sy = comp(D, ky) / dz;
-  r.Sz = 1.0f / dz;
-  r.Ox = comp(O, kx);
-  r.Oy = comp(O, ky);
-  r.Oz = comp(O, kz);
+  const float Sx = comp(D, kx) / dz, Sy = comp(D, ky) / dz, Sz = 1.0f / dz;
+  const V3 ex = unit(kx), ey = unit(ky), ez = unit(kz);
+  r.mx = V3{ex.x - Sx * ez.x, ex.y - Sx * ez.y, ex.z - Sx * ez.z};
+  r.my = V3{ey.x - Sy * ez.x, ey.y - Sy * ez.y, ey.z - Sy * ez.z};
+  r.mz = V3{Sz * ez.x, Sz * ez.y, Sz * ez.z};
+  r.ox = dot3(r.mx, O);
+  r.oy = dot3(r.my, O);
+  r.oz = dot3(r.mz, O);
   return r;
 }
-
-__device__ inline float pick(float4 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
 // slab test of one child box against [0, tmax]; conservative by 2 gamma(3)
 __device__ inline bool box_hit(const Ray& r, float lox, float hix, float loy, float hiy, float loz,
@@ -81,15 +82,17 @@ struct Best {
 };
 
 // Woop-Benthin-Wald watertight test; updates best on a closer (or tied,
-// lower input index) hit with t > 0.
+// lower input index) hit with t > 0.  Each vertex is mapped by the ray's
+// shear exactly once per test, so two triangles sharing an edge evaluate
+// the same 2D edge function for it (watertight); the z row is only needed
+// for a triangle the ray passes through.
+__device__ inline float shear(V3 m, float o, float4 v) { return fmaf(m.z, v.z, fmaf(m.y, v.y, m.x * v.x)) - o; }
+
 __device__ inline void tri_test(const Ray& r, const float4* __restrict__ tris, int i, Best& b) {
-  float4 a = tris[3 * i], q = tris[3 * i + 1], c = tris[3 * i + 2];
-  float Akx = pick(a, r.kx) - r.Ox, Aky = pick(a, r.ky) - r.Oy, Akz = pick(a, r.kz) - r.Oz;
-  float Bkx = pick(q, r.kx) - r.Ox, Bky = pick(q, r.ky) - r.Oy, Bkz = pick(q, r.kz) - r.Oz;
-  float Ckx = pick(c, r.kx) - r.Ox, Cky = pick(c, r.ky) - r.Oy, Ckz = pick(c, r.kz) - r.Oz;
-  float Ax = fmaf(-r.Sx, Akz, Akx), Ay = fmaf(-r.Sy, Akz, Aky);
-  float Bx = fmaf(-r.Sx, Bkz, Bkx), By = fmaf(-r.Sy, Bkz, Bky);
-  float Cx = fmaf(-r.Sx, Ckz, Ckx), Cy = fmaf(-r.Sy, Ckz, Cky);
+  const float4 a = tris[3 * i], q = tris[3 * i + 1], c = tris[3 * i + 2];
+  const float Ax = shear(r.mx, r.ox, a), Ay = shear(r.my, r.oy, a);
+  const float Bx = shear(r.mx, r.ox, q), By = shear(r.my, r.oy, q);
+  const float Cx = shear(r.mx, r.ox, c), Cy = shear(r.my, r.oy, c);
   float U = Cx * By - Cy * Bx;
   float V = Ax * Cy - Ay * Cx;
   float W = Bx * Ay - By * Ax;
@@ -99,12 +102,12 @@ __device__ inline void tri_test(const Ray& r, const float4* __restrict__ tris, i
     W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
   }
   if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return;
-  float det = U + V + W;
+  const float det = U + V + W;
   if (det == 0.0f) return;
-  float T = U * (r.Sz * Akz) + V * (r.Sz * Bkz) + W * (r.Sz * Ckz);
-  float t = T / det;
+  const float T = U * shear(r.mz, r.oz, a) + V * shear(r.mz, r.oz, q) + W * shear(r.mz, r.oz, c);
+  const float t = T * __frcp_rn(det);
   if (!(t > 0.0f)) return;
-  int id = __float_as_int(a.w);
+  const int id = __float_as_int(a.w);
   if (t < b.t || (t == b.t && id < b.id)) {
     b.t = t;
     b.tri = i;
@@ -125,60 +128,86 @@ struct Work {
   int visits, tests;
 };
 
+// Traversal state of one ray between steps.
+struct Trav {
+  Best b;
+  unsigned cur;  // internal node to enter next
+  int sp;        // stack depth
+};
+
+__device__ inline void trav_init(Trav& s) {
+  s.b = Best{INFINITY, -1, 0x7fffffff};
+  s.cur = 0;  // root (internal)
+  s.sp = 0;
+}
+
+// One step: enter node s.cur, test both child boxes, test leaf children at
+// once, continue into the nearer internal child and push the farther one,
+// or pop.  Returns true when the stack is empty (traversal finished).
+template <int BLOCK, bool COUNT>
+__device__ inline bool trav_step(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                 const Ray& r, int* __restrict__ stk, int* __restrict__ spill, Trav& s,
+                                 int* __restrict__ flags, Work& wk) {
+  if (COUNT) wk.visits++;
+  const float4* nd = nodes + 4 * (size_t)s.cur;
+  float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+  float t0, t1;
+  bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, s.b.t, t0);
+  bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, s.b.t, t1);
+  unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
+  if (h0 && (c0 & HDOF_LEAF_BIT)) {
+    test_leaf(r, tris, c0, s.b);
+    if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
+    h0 = false;
+  }
+  if (h1 && (c1 & HDOF_LEAF_BIT)) {
+    test_leaf(r, tris, c1, s.b);
+    if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
+    h1 = false;
+  }
+  if (h0 && h1) {
+    unsigned nearc = t0 <= t1 ? c0 : c1;
+    unsigned farc = t0 <= t1 ? c1 : c0;
+    if (s.sp < HDOF_LDS_STACK) {
+      stk[s.sp * BLOCK] = (int)farc;
+      ++s.sp;
+    } else if (s.sp < HDOF_LDS_STACK + HDOF_SPILL_STACK) {
+      spill[s.sp - HDOF_LDS_STACK] = (int)farc;
+      ++s.sp;
+    } else {
+      atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+    }
+    s.cur = nearc;
+  } else if (h0) {
+    s.cur = c0;
+  } else if (h1) {
+    s.cur = c1;
+  } else {
+    if (s.sp == 0) return true;
+    --s.sp;
+    s.cur = (unsigned)(s.sp < HDOF_LDS_STACK ? stk[s.sp * BLOCK] : spill[s.sp - HDOF_LDS_STACK]);
+  }
+  return false;
+}
+
+// Whole traversal of one ray.  Each internal node is entered at most once
+// per ray, so more than n_nodes steps means a malformed tree: the ray stops
+// and raises the device flag instead of looping.
 template <int BLOCK, bool COUNT>
 __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                 int n_nodes, const Ray& r, int* __restrict__ stk, int* __restrict__ flags,
                                 Work& wk) {
-  Best b{INFINITY, -1, 0x7fffffff};
   int spill[HDOF_SPILL_STACK];
-  int sp = 0;
-  unsigned cur = 0;  // root (internal)
+  Trav s;
+  trav_init(s);
   for (int steps = 0;; ++steps) {
     if (steps > n_nodes) {
       atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
       break;
     }
-    if (COUNT) wk.visits++;
-    const float4* nd = nodes + 4 * (size_t)cur;
-    float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-    float t0, t1;
-    bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0);
-    bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1);
-    unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
-    if (h0 && (c0 & HDOF_LEAF_BIT)) {
-      test_leaf(r, tris, c0, b);
-      if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
-      h0 = false;
-    }
-    if (h1 && (c1 & HDOF_LEAF_BIT)) {
-      test_leaf(r, tris, c1, b);
-      if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
-      h1 = false;
-    }
-    if (h0 && h1) {
-      unsigned nearc = t0 <= t1 ? c0 : c1;
-      unsigned farc = t0 <= t1 ? c1 : c0;
-      if (sp < HDOF_LDS_STACK) {
-        stk[sp * BLOCK] = (int)farc;
-        ++sp;
-      } else if (sp < HDOF_LDS_STACK + HDOF_SPILL_STACK) {
-        spill[sp - HDOF_LDS_STACK] = (int)farc;
-        ++sp;
-      } else {
-        atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
-      }
-      cur = nearc;
-    } else if (h0) {
-      cur = c0;
-    } else if (h1) {
-      cur = c1;
-    } else {
-      if (sp == 0) break;
-      --sp;
-      cur = (unsigned)(sp < HDOF_LDS_STACK ? stk[sp * BLOCK] : spill[sp - HDOF_LDS_STACK]);
-    }
+    if (trav_step<BLOCK, COUNT>(nodes, tris, r, stk, spill, s, flags, wk)) break;
   }
-  return b;
+  return s.b;
 }
 
 // Two-sided Lambertian face normal + point light, no shadow ray.
@@ -269,7 +298,7 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
 __global__ void k_queue_fill(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
                              long cap, int* __restrict__ queue, int* __restrict__ counter) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) *counter = 0;
+  if (p < 256) counter[p] = 0;
   if (p >= N) return;
   int s = spp[p];
   long o = offsets[p];
@@ -277,15 +306,36 @@ __global__ void k_queue_fill(const uint8_t* __restrict__ spp, const int* __restr
     if (o + j >= 0 && o + j < cap) queue[o + j] = p;
 }
 
+// Persistent trace with per-lane refill: every lane runs its own ray one
+// node step at a time; when at least HDOF_REFILL lanes of a wave are idle,
+// the wave takes that many entries from the queue with one atomic and hands
+// them to the idle lanes (HDOF_REFILL = 64 is plain batches of 64 rays).
+// The queue is cut into 8 contiguous segments (bands of image rows), one
+// per XCD (blocks are dispatched round-robin over the 8 XCDs): a wave takes
+// work from its own XCD's segment first, so each XCD's L2 holds the part of
+// the BVH its band of rays touches, then moves on to the other segments.
+// Every wave exits once all segments are drained and its lanes are idle.
+#ifndef HDOF_REFILL
+#define HDOF_REFILL 64
+#endif
+#ifndef HDOF_SEGMENTS
+#define HDOF_SEGMENTS 8
+#endif
+#ifndef HDOF_SEG_STRIDE
+#define HDOF_SEG_STRIDE 32  // ints: one 128-byte line per counter (counters sharing a line serialise across XCDs)
+#endif
+
 template <bool COUNT>
 __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
     const float4* __restrict__ nodes, const float4* __restrict__ tris, int n_nodes,
-    const float* __restrict__ albedo, CamK k, LensK l, LightK li, const int* __restrict__ queue, const int* __restrict__ offsets,
-    const int* __restrict__ total_p, int* __restrict__ counter, uint32_t seed, uint32_t frame,
-    uint32_t view, float* __restrict__ ray_col, float* __restrict__ ray_z, int* __restrict__ ray_id,
-    size_t cap, int* __restrict__ flags, unsigned long long* __restrict__ counters) {
-  __shared__ int stk[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
+    const float* __restrict__ albedo, CamK k, LensK l, LightK li, const int* __restrict__ queue,
+    const int* __restrict__ offsets, const int* __restrict__ total_p, int* __restrict__ counter, uint32_t seed,
+    uint32_t frame, uint32_t view, float* __restrict__ ray_col, float* __restrict__ ray_z,
+    int* __restrict__ ray_id, size_t cap, int* __restrict__ flags, unsigned long long* __restrict__ counters) {
+  __shared__ int stk_all[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
+  int spill[HDOF_SPILL_STACK];
   const int t = threadIdx.x, lane = t & 63;
+  int* stk = stk_all + t;
   const int N = k.W * k.H;
   int total = *total_p;
   if (total < 0) total = 0;
@@ -293,38 +343,68 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
     if (blockIdx.x == 0 && t == 0) atomicOr(flags, HDOF_FLAG_CAPACITY);
     total = (int)cap;
   }
+  const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  bool active = false, drained = false;
+  int e = 0, steps = 0;
+  int seg = blockIdx.x % HDOF_SEGMENTS, tried = 0;
+  Ray r;
+  Trav s;
+  Work wk{0, 0};
   for (;;) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(counter, 64);
-    base = __shfl(base, 0);
-    if (base >= total) break;
-    int e = base + lane;
-    int p = e < total ? queue[e] : -1;
-    if (p >= 0 && p < N) {
-      int j = e - offsets[p];
-      int x = p % k.W, y = p / k.W;
-      V3 O, D;
-      lens_ray(k, l, x, y, (uint32_t)j, view, seed, frame, O, D);
-      Ray r = make_ray(O, D);
-      Work wk{0, 0};
-      Best b = traverse<HDOF_TRACE_BLOCK, COUNT>(nodes, tris, n_nodes, r, stk + t, flags, wk);
-      if (COUNT) {
-        atomicAdd(&counters[3], 1ull);
-        atomicAdd(&counters[4], (unsigned long long)wk.visits);
-        atomicAdd(&counters[5], (unsigned long long)wk.tests);
+    const unsigned long long idle = __ballot(!active);
+    const int nidle = __popcll(idle);
+    if (!drained && nidle >= HDOF_REFILL) {
+      const int lo = (int)((long)total * seg / HDOF_SEGMENTS), hi = (int)((long)total * (seg + 1) / HDOF_SEGMENTS);
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&counter[seg * HDOF_SEG_STRIDE], nidle);
+      base = __shfl(base, 0) + lo;
+      if (base + nidle >= hi) {  // this segment is used up: go on to the next one
+        seg = (seg + 1) % HDOF_SEGMENTS;
+        drained = ++tried == HDOF_SEGMENTS;
       }
+      if (!active) {
+        const int ee = base + __popcll(idle & lt_mask);
+        const int p = ee < hi ? queue[ee] : -1;
+        if (p >= 0 && p < N) {
+          V3 O, D;
+          lens_ray(k, l, p % k.W, p / k.W, (uint32_t)(ee - offsets[p]), view, seed, frame, O, D);
+          r = make_ray(O, D);
+          trav_init(s);
+          e = ee;
+          steps = 0;
+          active = true;
+          if (COUNT) wk = Work{0, 0};
+        }
+      }
+    }
+    if (!active) {
+      if (drained) break;  // nothing left to hand out: an idle lane is done
+      continue;
+    }
+    bool done = trav_step<HDOF_TRACE_BLOCK, COUNT>(nodes, tris, r, stk, spill, s, flags, wk);
+    if (++steps > n_nodes) {
+      atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+      done = true;
+    }
+    if (done) {
       float z = HDOF_ZMAX;
       V3 L = V3{0.0f, 0.0f, 0.0f};
-      if (b.tri >= 0) {
+      if (s.b.tri >= 0) {
         V3 n, a;
-        shade(tris, albedo, li, r, b, L, n, a);
-        z = b.t * l.S1;
+        shade(tris, albedo, li, r, s.b, L, n, a);
+        z = s.b.t * l.S1;
       }
       ray_col[e] = L.x;
       ray_col[cap + e] = L.y;
       ray_col[2 * cap + e] = L.z;
       ray_z[e] = z;
-      if (ray_id) ray_id[e] = b.tri >= 0 ? b.id : -1;
+      if (ray_id) ray_id[e] = s.b.tri >= 0 ? s.b.id : -1;
+      if (COUNT) {
+        atomicAdd(&counters[3], 1ull);
+        atomicAdd(&counters[4], (unsigned long long)wk.visits);
+        atomicAdd(&counters[5], (unsigned long long)wk.tests);
+      }
+      active = false;
     }
   }
 }
@@ -402,7 +482,7 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
   if ((s = hdof_ensure(ctx->queue, sizeof(int) * cap)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap)) != HDOF_OK) return s;
   if (!ray_depth && (s = hdof_ensure(ctx->ray_z, sizeof(float) * cap)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->work_counter, sizeof(int) * 64)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->work_counter, sizeof(int) * 256)) != HDOF_OK) return s;
   float* rz = ray_depth ? ray_depth : (float*)ctx->ray_z.p;
   int* counter = (int*)ctx->work_counter.p;
   hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (long)cap,

@@ -18,6 +18,8 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdof.so")
+# a build variant (same ABI, other compile-time tuning) may be named by path
+LIB_PATH = os.environ.get("HDOF_LIBRARY", LIB_PATH)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2210_04981_amd.build` "
