@@ -277,6 +277,56 @@ hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera
                        hdof_stream stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batched form: many views (uneven sizes and lenses) in one frame          */
+/* ---------------------------------------------------------------------- */
+
+#define HDOF_MAX_VIEWS 64
+
+/* One view of a batch: its camera and lens, the random-number key and the
+ * view index that enters the lens-sample counter (so view v of a batch
+ * equals a plain hdof_frame with the same seed, frame and view), and its
+ * caller-owned output [3][H][W]. */
+typedef struct {
+  hdof_camera cam;
+  hdof_lens lens;
+  uint32_t seed, frame, view;
+  float* d_out;
+} hdof_view;
+
+/* Every view's G-buffer, mask, post-filter and composite (one launch each),
+ * one device-side scan of the per-view ray totals, ONE queue over all views
+ * and ONE persistent thin-lens trace launch for the whole batch.  No
+ * variance history (each view is a first frame).  1 <= n_views <=
+ * HDOF_MAX_VIEWS; all views share the scene, light and parameters. */
+hdof_status hdof_frame_batched(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                               const hdof_frame_params* params, int32_t n_views,
+                               const hdof_view* views, hdof_stream stream);
+
+/* The same batch captured once into a HIP graph (all scratch reserved at
+ * creation) and replayed by hdof_batch_launch.  The graph keeps the views,
+ * output pointers and tuning of creation time; the scene and context must
+ * outlive the batch, and one context's batches and frames must not run
+ * concurrently (they share its scratch). */
+typedef struct hdof_batch hdof_batch;
+hdof_status hdof_batch_create(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                              const hdof_frame_params* params, int32_t n_views,
+                              const hdof_view* views, hdof_batch** out);
+hdof_status hdof_batch_launch(hdof_batch* batch, hdof_stream stream);
+/* Synchronises the device, then frees the graph.  NULL is a no-op. */
+void hdof_batch_destroy(hdof_batch* batch);
+
+/* Launch shape of the persistent thin-lens trace (performance only: results
+ * do not depend on it).  blocks_per_cu in [1, 32]; refill in [1, 64]: idle
+ * lanes of a wave that trigger a refill from the queue (64 = batches of 64
+ * rays); segments in [1, 8]: queue segments, one per XCD group.  Defaults
+ * {12, 64, 8}. */
+typedef struct {
+  int32_t blocks_per_cu, refill, segments;
+} hdof_tuning;
+hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* tuning);
+hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
+
+/* ---------------------------------------------------------------------- */
 /* Stage timing                                                             */
 /* ---------------------------------------------------------------------- */
 

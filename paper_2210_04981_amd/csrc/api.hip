@@ -193,6 +193,11 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
+  buf_free(ctx->b_arena);
+  buf_free(ctx->b_views);
+  buf_free(ctx->b_totals);
+  if (ctx->b_views_host) hipHostFree(ctx->b_views_host);
+  if (ctx->b_views_done) hipEventDestroy(ctx->b_views_done);
   if (ctx->d_flags) hipFree(ctx->d_flags);
   if (ctx->d_counters) hipFree(ctx->d_counters);
   delete ctx;
@@ -564,5 +569,266 @@ extern "C" hdof_status hdof_counters_end(hdof_ctx* ctx, int64_t* out) {
   HDOF_HIP(hipMemcpy(c, ctx->d_counters, sizeof c, hipMemcpyDeviceToHost));
   for (int i = 0; i < 6; ++i) out[i] = (int64_t)c[i];
   ctx->count_on = false;
+  return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// trace tuning
+// ---------------------------------------------------------------------------
+extern "C" hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* t) {
+  TRY(check_ctx(ctx));
+  REQUIRE(t, "tuning is NULL");
+  REQUIRE(t->blocks_per_cu >= 1 && t->blocks_per_cu <= 32, "blocks_per_cu must be in [1, 32]");
+  REQUIRE(t->refill >= 1 && t->refill <= 64, "refill must be in [1, 64]");
+  REQUIRE(t->segments >= 1 && t->segments <= 8, "segments must be in [1, 8]");
+  ctx->tune = *t;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* t) {
+  TRY(check_ctx(ctx));
+  REQUIRE(t, "tuning is NULL");
+  *t = ctx->tune;
+  return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+  int n;
+  long npx, max_px;
+  int max_w, max_h;
+  BatchView hv[HDOF_MAX_VIEWS];
+  // byte offsets of each concatenated plane set in the arena
+  size_t o_depth, o_normal, o_albedo, o_color, o_tri, o_spp, o_offs, o_cn, o_cf, o_h, o_m1, o_m2, o_pp, total;
+};
+
+static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                               const hdof_frame_params* params, int32_t n_views, const hdof_view* views,
+                               BatchLayout& L) {
+  TRY(check_ctx(ctx));
+  REQUIRE(scene, "scene is NULL");
+  TRY(check_light(light));
+  REQUIRE(params, "frame params are NULL");
+  TRY(check_mask(&params->mask));
+  TRY(check_pp(&params->pp));
+  TRY(check_comp(&params->comp));
+  REQUIRE(n_views >= 1 && n_views <= HDOF_MAX_VIEWS, "n_views must be in [1, %d]", HDOF_MAX_VIEWS);
+  REQUIRE(views, "views is NULL");
+  L.n = n_views;
+  L.npx = 0;
+  L.max_px = 0;
+  L.max_w = L.max_h = 0;
+  for (int v = 0; v < n_views; ++v) {
+    TRY(check_camera(&views[v].cam, "view"));
+    TRY(check_lens(&views[v].lens));
+    REQUIRE(views[v].d_out, "view %d has no output", v);
+    CamK k = make_camk(&views[v].cam);
+    L.hv[v] = BatchView{k, make_lensk(&views[v].lens, k), views[v].seed, views[v].frame, views[v].view, (int)L.npx};
+    long n = (long)k.W * k.H;
+    L.npx += n;
+    if (n > L.max_px) L.max_px = n;
+    if (k.W > L.max_w) L.max_w = k.W;
+    if (k.H > L.max_h) L.max_h = k.H;
+  }
+  REQUIRE(L.npx * params->mask.spp_max < ((long)1 << 31), "batch pixels * spp_max must stay below 2^31");
+  size_t off = 0;
+  auto carve = [&](size_t per_px) {
+    size_t o = off;
+    off += (per_px * (size_t)L.npx + 255) & ~(size_t)255;
+    return o;
+  };
+  L.o_depth = carve(4);
+  L.o_normal = carve(12);
+  L.o_albedo = carve(12);
+  L.o_color = carve(12);
+  L.o_tri = carve(4);
+  L.o_spp = carve(1);
+  L.o_offs = carve(4);
+  L.o_cn = carve(12);
+  L.o_cf = carve(12);
+  L.o_h = carve(4);
+  L.o_m1 = carve(4);
+  L.o_m2 = carve(4);
+  L.o_pp = carve(12);
+  L.total = off;
+  return HDOF_OK;
+}
+
+// every allocation a batch needs, so that enqueueing it allocates nothing
+static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params, const BatchLayout& L) {
+  TRY(hdof_ensure(ctx->b_arena, L.total));
+  TRY(hdof_ensure(ctx->b_views, batch_view_bytes() * HDOF_MAX_VIEWS));
+  TRY(hdof_ensure(ctx->b_totals, sizeof(int) * (3 * HDOF_MAX_VIEWS + 1)));
+  TRY(reserve_trace(ctx, (size_t)L.npx * params->mask.spp_max, true));
+  // mask scratch for the largest view (tile grids, reprojection planes)
+  const int t = params->mask.tile;
+  const size_t tiles = (size_t)((L.max_w + t - 1) / t + 1) * (size_t)((L.max_h + t - 1) / t + 1);
+  const size_t th = (size_t)(L.max_h + t - 1) / t + 1;
+  TRY(hdof_ensure(ctx->mask_tile, sizeof(int) * tiles));
+  TRY(hdof_ensure(ctx->mask_tile_dil, sizeof(int) * tiles));
+  TRY(hdof_ensure(ctx->mask_xpref, sizeof(int) * tiles));
+  TRY(hdof_ensure(ctx->mask_rowsum, sizeof(int) * 2 * th));
+  TRY(hdof_ensure(ctx->mask_ybase, sizeof(int) * th));
+  TRY(hdof_ensure(ctx->rep_m1, sizeof(float) * L.max_px));
+  TRY(hdof_ensure(ctx->rep_m2, sizeof(float) * L.max_px));
+  TRY(hdof_ensure(ctx->rep_flags, L.max_px));
+  const int pt = params->pp.tile;
+  const size_t ptiles = (size_t)((L.max_w + pt - 1) / pt + 1) * (size_t)((L.max_h + pt - 1) / pt + 1);
+  TRY(hdof_ensure(ctx->pp_pack, 16 * (size_t)L.max_px));
+  TRY(hdof_ensure(ctx->pp_tile, sizeof(float) * ptiles));
+  TRY(hdof_ensure(ctx->pp_rad, sizeof(float) * ptiles));
+  TRY(hdof_ensure(ctx->pp_taps, 16 * 256));
+  return HDOF_OK;
+}
+
+// enqueue one batched frame; `table_host` is pinned memory holding the
+// packed view table (copied to the device as the first operation)
+static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                                 const hdof_frame_params* params, const hdof_view* views, const BatchLayout& L,
+                                 const void* table_host, hipStream_t st) {
+  char* a = (char*)ctx->b_arena.p;
+  int32_t* totals = (int32_t*)ctx->b_totals.p;
+  int32_t* ebase = totals + HDOF_MAX_VIEWS;
+  int32_t* grand = totals + 2 * HDOF_MAX_VIEWS;
+  HDOF_HIP(hipMemcpyAsync(ctx->b_views.p, table_host, batch_view_bytes() * L.n, hipMemcpyHostToDevice, st));
+  LightK li = make_lightk(light);
+  hdof_rt_bufs rt[HDOF_MAX_VIEWS];
+  for (int v = 0; v < L.n; ++v) {
+    const BatchView& bv = L.hv[v];
+    const size_t pb = (size_t)bv.px_base;
+    hdof_gbuffer_bufs gb;
+    gb.depth = (float*)(a + L.o_depth) + pb;
+    gb.normal = (float*)(a + L.o_normal) + 3 * pb;
+    gb.albedo = (float*)(a + L.o_albedo) + 3 * pb;
+    gb.color = (float*)(a + L.o_color) + 3 * pb;
+    gb.tri_id = (int32_t*)(a + L.o_tri) + pb;
+    rt[v].c_near = (float*)(a + L.o_cn) + 3 * pb;
+    rt[v].c_far = (float*)(a + L.o_cf) + 3 * pb;
+    rt[v].hit_ratio = (float*)(a + L.o_h) + pb;
+    rt[v].lum_m1 = (float*)(a + L.o_m1) + pb;
+    rt[v].lum_m2 = (float*)(a + L.o_m2) + pb;
+    TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
+    TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
+                    (int32_t*)(a + L.o_offs) + pb, totals + v, st));
+  }
+  TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
+                           (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,
+                           st));
+  for (int v = 0; v < L.n; ++v) {
+    const BatchView& bv = L.hv[v];
+    const size_t pb = (size_t)bv.px_base;
+    float* color = (float*)(a + L.o_color) + 3 * pb;
+    float* depth = (float*)(a + L.o_depth) + pb;
+    float* pp = (float*)(a + L.o_pp) + 3 * pb;
+    TRY(launch_postfilter(ctx, color, depth, bv.k, bv.l, params->pp, pp, st));
+    TRY(launch_composite(ctx, color, pp, depth, (const uint8_t*)(a + L.o_spp) + pb, rt[v], bv.k, bv.l,
+                         params->comp, views[v].d_out, st));
+  }
+  ctx->rep_valid = false;  // the views' reprojection planes are no frame history
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_frame_batched(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                                          const hdof_frame_params* params, int32_t n_views,
+                                          const hdof_view* views, hdof_stream stream) {
+  static thread_local BatchLayout L;
+  TRY(batch_check(ctx, scene, light, params, n_views, views, L));
+  TRY(batch_reserve(ctx, params, L));
+  hipStream_t st = (hipStream_t)stream;
+  // pinned staging for the view table: wait until the previous batch's copy
+  // has consumed it before overwriting
+  const size_t tb = batch_view_bytes() * HDOF_MAX_VIEWS;
+  if (!ctx->b_views_host) {
+    HDOF_HIP(hipHostMalloc(&ctx->b_views_host, tb, hipHostMallocDefault));
+    ctx->b_views_host_bytes = tb;
+    HDOF_HIP(hipEventCreateWithFlags(&ctx->b_views_done, hipEventDisableTiming));
+  } else {
+    HDOF_HIP(hipEventSynchronize(ctx->b_views_done));
+  }
+  batch_view_pack(L.hv, L.n, ctx->b_views_host);
+  ctx->prof_in_frame = false;
+  TRY(batch_enqueue(ctx, scene, light, params, views, L, ctx->b_views_host, st));
+  HDOF_HIP(hipEventRecord(ctx->b_views_done, st));
+  return HDOF_OK;
+}
+
+// A batch owns a private context (scratch, flags) so that later frames on
+// the caller's context cannot reallocate buffers the graph refers to.
+struct hdof_batch {
+  hdof_ctx* ctx;
+  hipStream_t stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  void* table_host;
+};
+
+extern "C" void hdof_batch_destroy(hdof_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->ctx->device);
+  hipDeviceSynchronize();
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->stream) hipStreamDestroy(b->stream);
+  if (b->table_host) hipHostFree(b->table_host);
+  hdof_destroy(b->ctx);
+  delete b;
+}
+
+extern "C" hdof_status hdof_batch_create(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                                         const hdof_frame_params* params, int32_t n_views,
+                                         const hdof_view* views, hdof_batch** out) {
+  REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  static thread_local BatchLayout L;
+  TRY(batch_check(ctx, scene, light, params, n_views, views, L));
+  hdof_ctx* ictx = nullptr;
+  TRY(hdof_create(ctx->device, &ictx));
+  ictx->tune = ctx->tune;
+  hdof_batch* b = new hdof_batch();
+  b->ctx = ictx;
+  hdof_status s = batch_reserve(ictx, params, L);
+  if (s != HDOF_OK) {
+    hdof_batch_destroy(b);
+    return s;
+  }
+  ctx = ictx;
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc(&b->table_host, batch_view_bytes() * HDOF_MAX_VIEWS, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    hdof_batch_destroy(b);
+    return hdof_set_error(HDOF_ERR_HIP, "batch setup: %s", hipGetErrorString(e));
+  }
+  batch_view_pack(L.hv, L.n, b->table_host);
+  // one eager pass builds anything computed on first use (the tap table)
+  s = batch_enqueue(ctx, scene, light, params, views, L, b->table_host, b->stream);
+  if (s == HDOF_OK && (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+    s = hdof_set_error(HDOF_ERR_HIP, "batch warm-up: %s", hipGetErrorString(e));
+  ctx->pp_taps_n = 0;  // the graph recomputes its own tap table
+  if (s == HDOF_OK) {
+    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) s = hdof_set_error(HDOF_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+  }
+  if (s == HDOF_OK) {
+    hdof_status se = batch_enqueue(ctx, scene, light, params, views, L, b->table_host, b->stream);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+    if (se != HDOF_OK) s = se;
+    else if (e != hipSuccess) s = hdof_set_error(HDOF_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+  }
+  if (s == HDOF_OK && (e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+    s = hdof_set_error(HDOF_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  if (s != HDOF_OK) {
+    hdof_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_batch_launch(hdof_batch* b, hdof_stream stream) {
+  REQUIRE(b, "batch is NULL");
+  TRY(check_ctx(b->ctx));
+  HDOF_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
   return HDOF_OK;
 }

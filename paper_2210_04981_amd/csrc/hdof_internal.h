@@ -18,6 +18,9 @@
 #define HDOF_LDS_STACK 20
 #define HDOF_SPILL_STACK 44
 #define HDOF_TRACE_BLOCK 128
+// ints between the persistent trace's per-segment work counters: one
+// 128-byte line each (counters sharing a line serialise across XCDs)
+#define HDOF_SEG_STRIDE 32
 
 // device flag bits (ctx->d_flags)
 #define HDOF_FLAG_STACK_OVERFLOW 1
@@ -41,6 +44,9 @@ struct hdof_scene {
   int32_t* depth_out;  // [1] tree depth (computed at build)
   int64_t bytes;
 };
+
+// host-side description of one view of a batch
+struct BatchView;
 
 struct Buf {
   void* p = nullptr;
@@ -68,6 +74,13 @@ struct hdof_ctx {
   // frame intermediates when the caller keeps none
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
+  // persistent-trace launch shape (performance only)
+  hdof_tuning tune = {12, 64, 8};
+  // batched form: per-view intermediates, view table (device + pinned host)
+  Buf b_arena, b_views, b_totals;
+  void* b_views_host = nullptr;
+  size_t b_views_host_bytes = 0;
+  hipEvent_t b_views_done = nullptr;
   // traversal work counters (rays, node visits, triangle tests) x (G-buffer, trace)
   bool count_on = false;
   unsigned long long* d_counters = nullptr;
@@ -213,6 +226,19 @@ hdof_status launch_bvh_build(hdof_ctx* ctx, const float* verts, const float* alb
                              hdof_scene* sc, hipStream_t st);
 hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                            const LightK& li, hdof_gbuffer_bufs out, hipStream_t st);
+struct BatchView {
+  CamK k;
+  LensK l;
+  uint32_t seed, frame, view;
+  int px_base;  // first pixel of the view in the batch's concatenated planes
+};
+hdof_status reserve_trace(hdof_ctx* ctx, size_t cap, bool own_depth);
+hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, int spp_max,
+                                 int n_views, const BatchView* hviews, const void* views_dev,
+                                 const uint8_t* spp, const int32_t* offsets, const int32_t* totals,
+                                 int32_t* ebase, int32_t* grand, hdof_rt_bufs* rt, hipStream_t st);
+size_t batch_view_bytes();
+void batch_view_pack(const BatchView* hv, int n, void* out);
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,

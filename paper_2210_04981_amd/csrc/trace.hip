@@ -292,83 +292,127 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
 }
 
 // queue entries: pixel index repeated spp times at its offset; also resets
-// the persistent trace's work counter (same stream, runs before the trace)
-// (entries outside [0, cap) are dropped: inconsistent offsets never write out
-// of bounds)
+// the persistent trace's work counters (same stream, runs before the trace).
+// Batched: offsets are view-local, *ebase is the view's first queue entry
+// and the stored index is the pixel's position in the batch (pxbase + p).
+// Entries outside [0, cap) are dropped: inconsistent offsets never write out
+// of bounds.
 __global__ void k_queue_fill(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
-                             long cap, int* __restrict__ queue, int* __restrict__ counter) {
+                             const int* __restrict__ ebase, int pxbase, long cap, int* __restrict__ queue,
+                             int* __restrict__ counter) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < 256) counter[p] = 0;
+  if (p < 8 * HDOF_SEG_STRIDE) counter[p] = 0;
   if (p >= N) return;
   int s = spp[p];
-  long o = offsets[p];
+  long o = (long)offsets[p] + (ebase ? *ebase : 0);
   for (int j = 0; j < s; ++j)
-    if (o + j >= 0 && o + j < cap) queue[o + j] = p;
+    if (o + j >= 0 && o + j < cap) queue[o + j] = pxbase + p;
 }
 
-// Persistent trace with per-lane refill: every lane runs its own ray one
-// node step at a time; when at least HDOF_REFILL lanes of a wave are idle,
-// the wave takes that many entries from the queue with one atomic and hands
-// them to the idle lanes (HDOF_REFILL = 64 is plain batches of 64 rays).
-// The queue is cut into 8 contiguous segments (bands of image rows), one
-// per XCD (blocks are dispatched round-robin over the 8 XCDs): a wave takes
-// work from its own XCD's segment first, so each XCD's L2 holds the part of
-// the BVH its band of rays touches, then moves on to the other segments.
+// Persistent trace.  Every lane runs its own ray one node step at a time;
+// when at least `refill` lanes of a wave are idle the wave takes that many
+// entries from the queue with one atomic and hands them to the idle lanes
+// (refill = 64: batches of 64 rays).  The queue is cut into `segments`
+// contiguous segments (bands of image rows; whole views in a batch), one
+// per group of XCDs (blocks are dispatched round-robin over the 8 XCDs): a
+// wave takes work from its own segment first, so each XCD's L2 holds the
+// part of the BVH its rays touch, then moves on to the other segments.
 // Every wave exits once all segments are drained and its lanes are idle.
-#ifndef HDOF_REFILL
-#define HDOF_REFILL 64
-#endif
-#ifndef HDOF_SEGMENTS
-#define HDOF_SEGMENTS 8
-#endif
-#ifndef HDOF_SEG_STRIDE
-#define HDOF_SEG_STRIDE 32  // ints: one 128-byte line per counter (counters sharing a line serialise across XCDs)
-#endif
+struct ViewK {
+  CamK k;
+  LensK l;
+  uint32_t seed, frame, view;
+  int px_base;  // first pixel of the view in the batch
+};
 
-template <bool COUNT>
-__global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
-    const float4* __restrict__ nodes, const float4* __restrict__ tris, int n_nodes,
-    const float* __restrict__ albedo, CamK k, LensK l, LightK li, const int* __restrict__ queue,
-    const int* __restrict__ offsets, const int* __restrict__ total_p, int* __restrict__ counter, uint32_t seed,
-    uint32_t frame, uint32_t view, float* __restrict__ ray_col, float* __restrict__ ray_z,
-    int* __restrict__ ray_id, size_t cap, int* __restrict__ flags, unsigned long long* __restrict__ counters) {
+struct TraceArgs {
+  const float4* nodes;
+  const float4* tris;
+  int n_nodes;
+  const float* albedo;
+  LightK li;
+  const int* queue;
+  const int* offsets;
+  const int* total_p;
+  int* counter;
+  float* ray_col;
+  float* ray_z;
+  int* ray_id;
+  size_t cap;
+  int* flags;
+  unsigned long long* counters;
+  int refill, segments;
+  ViewK v0;                // the view of a plain frame
+  const ViewK* views;      // batch: device table of views
+  const int* entry_base;   // batch: first queue entry of each view
+  int n_views;
+};
+
+template <bool COUNT, bool BATCH>
+__global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(TraceArgs A) {
   __shared__ int stk_all[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
+  __shared__ int pxb[HDOF_MAX_VIEWS + 1];
   int spill[HDOF_SPILL_STACK];
   const int t = threadIdx.x, lane = t & 63;
   int* stk = stk_all + t;
-  const int N = k.W * k.H;
-  int total = *total_p;
-  if (total < 0) total = 0;
-  if ((size_t)total > cap) {
-    if (blockIdx.x == 0 && t == 0) atomicOr(flags, HDOF_FLAG_CAPACITY);
-    total = (int)cap;
+  if (BATCH) {
+    for (int v = t; v < A.n_views; v += HDOF_TRACE_BLOCK) pxb[v] = A.views[v].px_base;
+    __syncthreads();
   }
+  int total = *A.total_p;
+  if (total < 0) total = 0;
+  if ((size_t)total > A.cap) {
+    if (blockIdx.x == 0 && t == 0) atomicOr(A.flags, HDOF_FLAG_CAPACITY);
+    total = (int)A.cap;
+  }
+  const int nseg = A.segments;
   const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   bool active = false, drained = false;
   int e = 0, steps = 0;
-  int seg = blockIdx.x % HDOF_SEGMENTS, tried = 0;
+  int seg = blockIdx.x % nseg, tried = 0;
+  float S1 = A.v0.l.S1;
   Ray r;
   Trav s;
   Work wk{0, 0};
   for (;;) {
     const unsigned long long idle = __ballot(!active);
     const int nidle = __popcll(idle);
-    if (!drained && nidle >= HDOF_REFILL) {
-      const int lo = (int)((long)total * seg / HDOF_SEGMENTS), hi = (int)((long)total * (seg + 1) / HDOF_SEGMENTS);
+    if (!drained && nidle >= A.refill) {
+      const int lo = (int)((long)total * seg / nseg), hi = (int)((long)total * (seg + 1) / nseg);
       int base = 0;
-      if (lane == 0) base = atomicAdd(&counter[seg * HDOF_SEG_STRIDE], nidle);
+      if (lane == 0) base = atomicAdd(&A.counter[seg * HDOF_SEG_STRIDE], nidle);
       base = __shfl(base, 0) + lo;
       if (base + nidle >= hi) {  // this segment is used up: go on to the next one
-        seg = (seg + 1) % HDOF_SEGMENTS;
-        drained = ++tried == HDOF_SEGMENTS;
+        seg = seg + 1 == nseg ? 0 : seg + 1;
+        drained = ++tried == nseg;
       }
       if (!active) {
         const int ee = base + __popcll(idle & lt_mask);
-        const int p = ee < hi ? queue[ee] : -1;
-        if (p >= 0 && p < N) {
+        const int g = ee < hi ? A.queue[ee] : -1;
+        bool ok;
+        int p, j;
+        const ViewK* vk = &A.v0;
+        if (BATCH) {
+          // view of batch pixel g: last view whose first pixel is <= g
+          int v = 0;
+          for (int step = HDOF_MAX_VIEWS / 2; step >= 1; step >>= 1)
+            if (v + step < A.n_views && pxb[v + step] <= g) v += step;
+          vk = &A.views[v];
+          p = g - pxb[v];
+          ok = g >= 0 && p < vk->k.W * vk->k.H;
+          j = ok ? ee - A.entry_base[v] - A.offsets[g] : 0;
+        } else {
+          p = g;
+          ok = g >= 0 && g < A.v0.k.W * A.v0.k.H;
+          j = ok ? ee - A.offsets[g] : 0;
+        }
+        if (ok) {
+          const CamK k = vk->k;
+          const LensK l = vk->l;
           V3 O, D;
-          lens_ray(k, l, p % k.W, p / k.W, (uint32_t)(ee - offsets[p]), view, seed, frame, O, D);
+          lens_ray(k, l, p % k.W, p / k.W, (uint32_t)j, vk->view, vk->seed, vk->frame, O, D);
           r = make_ray(O, D);
+          S1 = l.S1;
           trav_init(s);
           e = ee;
           steps = 0;
@@ -381,9 +425,9 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
       if (drained) break;  // nothing left to hand out: an idle lane is done
       continue;
     }
-    bool done = trav_step<HDOF_TRACE_BLOCK, COUNT>(nodes, tris, r, stk, spill, s, flags, wk);
-    if (++steps > n_nodes) {
-      atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+    bool done = trav_step<HDOF_TRACE_BLOCK, COUNT>(A.nodes, A.tris, r, stk, spill, s, A.flags, wk);
+    if (++steps > A.n_nodes) {
+      atomicOr(A.flags, HDOF_FLAG_STACK_OVERFLOW);
       done = true;
     }
     if (done) {
@@ -391,38 +435,40 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(
       V3 L = V3{0.0f, 0.0f, 0.0f};
       if (s.b.tri >= 0) {
         V3 n, a;
-        shade(tris, albedo, li, r, s.b, L, n, a);
-        z = s.b.t * l.S1;
+        shade(A.tris, A.albedo, A.li, r, s.b, L, n, a);
+        z = s.b.t * S1;
       }
-      ray_col[e] = L.x;
-      ray_col[cap + e] = L.y;
-      ray_col[2 * cap + e] = L.z;
-      ray_z[e] = z;
-      if (ray_id) ray_id[e] = s.b.tri >= 0 ? s.b.id : -1;
+      A.ray_col[e] = L.x;
+      A.ray_col[A.cap + e] = L.y;
+      A.ray_col[2 * A.cap + e] = L.z;
+      A.ray_z[e] = z;
+      if (A.ray_id) A.ray_id[e] = s.b.tri >= 0 ? s.b.id : -1;
       if (COUNT) {
-        atomicAdd(&counters[3], 1ull);
-        atomicAdd(&counters[4], (unsigned long long)wk.visits);
-        atomicAdd(&counters[5], (unsigned long long)wk.tests);
+        atomicAdd(&A.counters[3], 1ull);
+        atomicAdd(&A.counters[4], (unsigned long long)wk.visits);
+        atomicAdd(&A.counters[5], (unsigned long long)wk.tests);
       }
       active = false;
     }
   }
 }
 
-// per-pixel near/far split, hit ratio and luminance moments, fixed order
+// per-pixel near/far split, hit ratio and luminance moments, fixed order;
+// batched: *ebase is the view's first queue entry
 __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
-                            const float* __restrict__ ray_col, const float* __restrict__ ray_z, size_t cap,
-                            LensK l, float* __restrict__ cn, float* __restrict__ cf, float* __restrict__ h,
-                            float* __restrict__ m1, float* __restrict__ m2) {
+                            const int* __restrict__ ebase, const float* __restrict__ ray_col,
+                            const float* __restrict__ ray_z, size_t cap, LensK l, float* __restrict__ cn,
+                            float* __restrict__ cf, float* __restrict__ h, float* __restrict__ m1,
+                            float* __restrict__ m2) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   int s = spp[p];
   float Nw = 0.f, Fw = 0.f, snr = 0.f, sng = 0.f, snb = 0.f, sfr = 0.f, sfg = 0.f, sfb = 0.f, sy = 0.f, sy2 = 0.f;
-  long o = offsets[p];
+  long o = (long)offsets[p] + (ebase ? *ebase : 0);
   if (o < 0 || o + s > (long)cap) s = 0;  // inconsistent offsets: nothing was traced here
   if (s > 0) {
     for (int j = 0; j < s; ++j) {
-      int e = o + j;
+      long e = o + j;
       float R = ray_col[e], G = ray_col[cap + e], B = ray_col[2 * cap + e];
       float c = coc_px(l, ray_z[e]);
       float w = clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
@@ -453,7 +499,46 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   m2[p] = sy2 * is;
 }
 
+// batch: first queue entry of each view and the batch total
+__global__ void k_view_scan(const int* __restrict__ totals, int n, int* __restrict__ ebase,
+                            int* __restrict__ grand) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  long run = 0;
+  for (int v = 0; v < n; ++v) {
+    ebase[v] = (int)run;
+    run += totals[v];
+  }
+  *grand = (int)min(run, (long)0x7fffffff);
+}
+
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <bool BATCH>
+void launch_trace_kernel(hdof_ctx* ctx, const TraceArgs& A, hipStream_t st) {
+  const int grid = ctx->n_cu * ctx->tune.blocks_per_cu;
+  if (ctx->count_on)
+    hipLaunchKernelGGL((k_trace<true, BATCH>), dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_trace<false, BATCH>), dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, A);
+}
+
+TraceArgs base_args(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, size_t cap) {
+  TraceArgs A{};
+  A.nodes = sc->nodes;
+  A.tris = sc->tris;
+  A.n_nodes = sc->n_nodes;
+  A.albedo = sc->albedo;
+  A.li = li;
+  A.queue = (const int*)ctx->queue.p;
+  A.counter = (int*)ctx->work_counter.p;
+  A.ray_col = (float*)ctx->ray_col.p;
+  A.cap = cap;
+  A.flags = ctx->d_flags;
+  A.counters = ctx->d_counters;
+  A.refill = ctx->tune.refill;
+  A.segments = ctx->tune.segments;
+  return A;
+}
 
 }  // namespace
 
@@ -472,6 +557,15 @@ hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, c
   return HDOF_OK;
 }
 
+hdof_status reserve_trace(hdof_ctx* ctx, size_t cap, bool own_depth) {
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->queue, sizeof(int) * cap)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap)) != HDOF_OK) return s;
+  if (own_depth && (s = hdof_ensure(ctx->ray_z, sizeof(float) * cap)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->work_counter, sizeof(int) * 8 * HDOF_SEG_STRIDE)) != HDOF_OK) return s;
+  return HDOF_OK;
+}
+
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
@@ -479,30 +573,70 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
   const int N = k.W * k.H;
   const size_t cap = (size_t)N * (size_t)spp_max;
   hdof_status s;
-  if ((s = hdof_ensure(ctx->queue, sizeof(int) * cap)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap)) != HDOF_OK) return s;
-  if (!ray_depth && (s = hdof_ensure(ctx->ray_z, sizeof(float) * cap)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->work_counter, sizeof(int) * 256)) != HDOF_OK) return s;
+  if ((s = reserve_trace(ctx, cap, !ray_depth)) != HDOF_OK) return s;
   float* rz = ray_depth ? ray_depth : (float*)ctx->ray_z.p;
-  int* counter = (int*)ctx->work_counter.p;
-  hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (long)cap,
-                     (int*)ctx->queue.p, counter);
+  hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr, 0,
+                     (long)cap, (int*)ctx->queue.p, (int*)ctx->work_counter.p);
   hdof_prof_mark(ctx, 3, st);
-  // persistent grid: enough resident waves to cover every CU several times
-  int grid = ctx->n_cu * 12;
-  if (ctx->count_on)
-    hipLaunchKernelGGL(k_trace<true>, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
-                       k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
-                       (float*)ctx->ray_col.p, rz, ray_id, cap, ctx->d_flags, ctx->d_counters);
-  else
-    hipLaunchKernelGGL(k_trace<false>, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
-                       k, l, li, (const int*)ctx->queue.p, offsets, total, counter, seed, frame, view,
-                       (float*)ctx->ray_col.p, rz, ray_id, cap, ctx->d_flags, ctx->d_counters);
+  TraceArgs A = base_args(ctx, sc, li, cap);
+  A.offsets = offsets;
+  A.total_p = total;
+  A.ray_z = rz;
+  A.ray_id = ray_id;
+  A.v0 = ViewK{k, l, seed, frame, view, 0};
+  launch_trace_kernel<false>(ctx, A, st);
   hdof_prof_mark(ctx, 4, st);
-  hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
+  hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr,
                      (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near, out.c_far,
                      out.hit_ratio, out.lum_m1, out.lum_m2);
   hdof_prof_mark(ctx, 5, st);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
+}
+
+// Batched trace: the views' masks have written per-view counts, view-local
+// offsets and totals[v]; one scan gives each view's first queue entry, each
+// view fills its part of the queue, ONE persistent launch traces all views,
+// then each view reduces its own pixels.  `views` is the device copy of
+// `hviews` (same order).
+hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, int spp_max,
+                                 int n_views, const BatchView* hviews, const void* views_dev,
+                                 const uint8_t* spp, const int32_t* offsets, const int32_t* totals,
+                                 int32_t* ebase, int32_t* grand, hdof_rt_bufs* rt, hipStream_t st) {
+  long npx = 0;
+  for (int v = 0; v < n_views; ++v) npx += (long)hviews[v].k.W * hviews[v].k.H;
+  const size_t cap = (size_t)npx * (size_t)spp_max;
+  hdof_status s;
+  if ((s = reserve_trace(ctx, cap, true)) != HDOF_OK) return s;
+  hipLaunchKernelGGL(k_view_scan, dim3(1), dim3(64), 0, st, totals, n_views, ebase, grand);
+  for (int v = 0; v < n_views; ++v) {
+    const int N = hviews[v].k.W * hviews[v].k.H, pb = hviews[v].px_base;
+    hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb, N,
+                       (const int*)(ebase + v), pb, (long)cap, (int*)ctx->queue.p, (int*)ctx->work_counter.p);
+  }
+  TraceArgs A = base_args(ctx, sc, li, cap);
+  A.offsets = offsets;
+  A.total_p = grand;
+  A.ray_z = (float*)ctx->ray_z.p;
+  A.ray_id = nullptr;
+  A.views = (const ViewK*)views_dev;
+  A.entry_base = ebase;
+  A.n_views = n_views;
+  A.v0 = ViewK{hviews[0].k, hviews[0].l, 0, 0, 0, 0};
+  launch_trace_kernel<true>(ctx, A, st);
+  for (int v = 0; v < n_views; ++v) {
+    const int N = hviews[v].k.W * hviews[v].k.H, pb = hviews[v].px_base;
+    hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb, N,
+                       (const int*)(ebase + v), (const float*)ctx->ray_col.p, (const float*)ctx->ray_z.p, cap,
+                       hviews[v].l, rt[v].c_near, rt[v].c_far, rt[v].hit_ratio, rt[v].lum_m1, rt[v].lum_m2);
+  }
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+size_t batch_view_bytes() { return sizeof(ViewK); }
+
+void batch_view_pack(const BatchView* hv, int n, void* out) {
+  ViewK* o = (ViewK*)out;
+  for (int v = 0; v < n; ++v) o[v] = ViewK{hv[v].k, hv[v].l, hv[v].seed, hv[v].frame, hv[v].view, hv[v].px_base};
 }

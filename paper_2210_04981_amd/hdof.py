@@ -78,6 +78,18 @@ class FrameBufs(C.Structure):
                 ("pp", P)]
 
 
+class View(C.Structure):
+    _fields_ = [("cam", Camera), ("lens", Lens), ("seed", C.c_uint32), ("frame", C.c_uint32),
+                ("view", C.c_uint32), ("d_out", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("refill", C.c_int32), ("segments", C.c_int32)]
+
+
+MAX_VIEWS = 64
+
+
 class SceneInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int32), ("n_nodes", C.c_int32), ("max_depth", C.c_int32),
                 ("leaf_size", C.c_int32), ("device_bytes", C.c_int64)]
@@ -110,6 +122,13 @@ _PROTOS = {
                         C.POINTER(FrameParams), _u32, _u32, _u32, P, C.POINTER(FrameBufs), P]),
     "hdof_profile_begin": (_S, [P]),
     "hdof_profile_end": (_S, [P, C.POINTER(C.c_float), C.POINTER(_i32)]),
+    "hdof_frame_batched": (_S, [P, P, C.POINTER(Light), C.POINTER(FrameParams), _i32, C.POINTER(View), P]),
+    "hdof_batch_create": (_S, [P, P, C.POINTER(Light), C.POINTER(FrameParams), _i32, C.POINTER(View),
+                               C.POINTER(P)]),
+    "hdof_batch_launch": (_S, [P, P]),
+    "hdof_batch_destroy": (None, [P]),
+    "hdof_set_tuning": (_S, [P, C.POINTER(Tuning)]),
+    "hdof_get_tuning": (_S, [P, C.POINTER(Tuning)]),
     "hdof_counters_begin": (_S, [P]),
     "hdof_counters_end": (_S, [P, C.POINTER(C.c_int64)]),
 }
@@ -498,3 +517,68 @@ def hdof_counters_end(ctx: Context) -> dict:
     _check(_lib.hdof_counters_end(ctx.handle, c), "hdof_counters_end")
     return dict(gbuffer_rays=c[0], gbuffer_visits=c[1], gbuffer_tests=c[2],
                 trace_rays=c[3], trace_visits=c[4], trace_tests=c[5])
+
+
+# ----------------------------------------------------------------------------
+# batched form and tuning
+# ----------------------------------------------------------------------------
+
+def _views(views, outs) -> "C.Array":
+    if len(views) != len(outs) or not 1 <= len(views) <= MAX_VIEWS:
+        raise ValueError(f"need 1..{MAX_VIEWS} views, one output each")
+    arr = (View * len(views))()
+    for i, (v, o) in enumerate(zip(views, outs)):
+        cam, lns, seed, frame, view = v
+        arr[i] = View(cam, lns, int(seed), int(frame), int(view),
+                      _ptr(o, torch.float32, 3 * int(cam.width) * int(cam.height), f"out[{i}]"))
+    return arr
+
+
+def hdof_frame_batched(ctx: Context, scene: Scene, lit: Light, params: FrameParams, views, outs=None,
+                       stream=None):
+    """views: list of (Camera, Lens, seed, frame, view); returns the outputs."""
+    if outs is None:
+        outs = [torch.empty(3, v[0].height, v[0].width, dtype=torch.float32, device="cuda") for v in views]
+    arr = _views(views, outs)
+    _check(_lib.hdof_frame_batched(ctx.handle, scene.handle, C.byref(lit), C.byref(params), len(views), arr,
+                                   _stream(stream)), "hdof_frame_batched")
+    return outs
+
+
+class Batch:
+    """A batch of views captured into a HIP graph (hdof_batch_create)."""
+
+    def __init__(self, ctx: Context, scene: Scene, lit: Light, params: FrameParams, views, outs):
+        self.outs = outs
+        arr = _views(views, outs)
+        h = P()
+        _check(_lib.hdof_batch_create(ctx.handle, scene.handle, C.byref(lit), C.byref(params), len(views), arr,
+                                      C.byref(h)), "hdof_batch_create")
+        self.handle = h
+        self._keep = (ctx, scene)
+
+    def launch(self, stream=None):
+        _check(_lib.hdof_batch_launch(self.handle, _stream(stream)), "hdof_batch_launch")
+        return self.outs
+
+    def close(self):
+        if self.handle:
+            _lib.hdof_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hdof_set_tuning(ctx: Context, blocks_per_cu=12, refill=64, segments=8) -> None:
+    t = Tuning(int(blocks_per_cu), int(refill), int(segments))
+    _check(_lib.hdof_set_tuning(ctx.handle, C.byref(t)), "hdof_set_tuning")
+
+
+def hdof_get_tuning(ctx: Context) -> dict:
+    t = Tuning()
+    _check(_lib.hdof_get_tuning(ctx.handle, C.byref(t)), "hdof_get_tuning")
+    return dict(blocks_per_cu=t.blocks_per_cu, refill=t.refill, segments=t.segments)
