@@ -72,6 +72,8 @@ def lib():
         L.or_pp_radius.argtypes = [i32, i32, P, f64, i32, P]
         L.or_postfilter.argtypes = [P, i32, i32, P, P, P, P, P, i64, P]
         L.or_composite.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, f64, i32, P]
+        L.or_pp_radius_arg.argtypes = [i32, i32, P, f64, i32, P, P]
+        L.or_pp_composite_backward.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, f64, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -373,3 +375,22 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
     out = composite(cam, lens, gb["color"], cpp, depth, spp, rt["c_near"], rt["c_far"],
                     rt["hit_ratio"], comp)
     return dict(gbuffer=gb, mask=mk, spp=spp, rt=rt, history=hist, reproj=rep, pp=cpp, out=out)
+
+
+def pp_composite_backward(camera, lens, color, depth, spp, c_near, c_far, hit, pp, cp, grad_out):
+    """Adjoint of post-filter + composite: (dL/dC_r (3,H,W), dL/dS1, dL/dA)
+    for dL/dout = grad_out, with depth, counts and traced colours fixed."""
+    cam, W, H = cam_args(camera)
+    gcol = np.zeros((3, H, W))
+    gl = np.zeros(2)
+    ppa = _f64([pp.n_taps, pp.tile, pp.r_cap, pp.bg_ramp_px])
+    lib().or_pp_composite_backward(_p(cam), W, H, _p(_f64(lens.as_floats())), _p(_f64(color)), _p(_f64(depth)),
+                                   _p(_i32(spp)), _p(_f64(c_near)), _p(_f64(c_far)), _p(_f64(hit)), _p(ppa),
+                                   float(cp.h_t), int(cp.rt_override), _p(_f64(grad_out)), _p(gcol), _p(gl))
+    return gcol, float(gl[0]), float(gl[1])
+
+
+def pp_composite_forward(camera, lens, color, depth, spp, c_near, c_far, hit, pp, cp):
+    """out(C_r, S1, A) of the differentiable form (post-filter then composite)."""
+    cpp = postfilter(camera, lens, color, depth, pp)
+    return composite(camera, lens, color, cpp, depth, spp, c_near, c_far, hit, cp)

@@ -868,3 +868,199 @@ void or_composite(const double* cam, int W, int H, const double* lens,
     }
   }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Adjoint of post-filter + composite (the differentiable form).              */
+/* out(C_r, S1, A) with depth, counts and ray-trace colours held fixed.       */
+/* Given g = dL/dout, returns dL/dC_r (reverse mode: the gather's transpose,  */
+/* a scatter through the bilinear weights) and dL/dS1, dL/dA (forward mode    */
+/* through the recomputed gather: dc/dS1 = -A s_px / S1^2,                    */
+/* dc/dA = (1/S1 - 1/z) s_px).  The gather radius follows the CoC of its      */
+/* tile-max pixel (lowest index on ties) unless capped; clamp ramps take      */
+/* subgradient 0 at their kinks.                                              */
+/* ------------------------------------------------------------------------- */
+typedef struct { double v, ds, da; } dual;  /* value and its S1 / A derivatives */
+
+static inline dual dmk(double v, double ds, double da) { dual r = {v, ds, da}; return r; }
+static inline dual dadd(dual a, dual b) { return dmk(a.v + b.v, a.ds + b.ds, a.da + b.da); }
+static inline dual dsub(dual a, dual b) { return dmk(a.v - b.v, a.ds - b.ds, a.da - b.da); }
+static inline dual dmul(dual a, dual b) { return dmk(a.v * b.v, a.ds * b.v + a.v * b.ds, a.da * b.v + a.v * b.da); }
+static inline dual dscale(dual a, double s) { return dmk(a.v * s, a.ds * s, a.da * s); }
+static inline dual ddiv(dual a, dual b) {
+  double q = a.v / b.v;
+  return dmk(q, (a.ds - q * b.ds) / b.v, (a.da - q * b.da) / b.v);
+}
+static inline dual dconst(double v) { return dmk(v, 0.0, 0.0); }
+/* clamp with subgradient 0 outside (lo, hi) */
+static inline dual dclamp(dual x, double lo, double hi) {
+  if (x.v <= lo) return dconst(lo);
+  if (x.v >= hi) return dconst(hi);
+  return x;
+}
+static inline dual dmax0(dual x) { return x.v > 0.0 ? x : dconst(0.0); }
+static inline dual dmaxc(dual x, double c) { return x.v > c ? x : dconst(c); }
+static inline dual dabs(dual x) { return x.v >= 0.0 ? x : dscale(x, -1.0); }
+
+/* bilinear sample of (rgb, c) and its x/y derivatives at continuous q */
+static void bilerp_grad(const double* img, int W, int H, size_t N, double qx, double qy,
+                        double* s, double* sx, double* sy, int* tx, int* ty, double* tw) {
+  double gx = qx - 0.5, gy = qy - 0.5;
+  double x0f = floor(gx), y0f = floor(gy);
+  double ax = gx - x0f, ay = gy - y0f;
+  int x0 = (int)x0f, y0 = (int)y0f;
+  int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+  int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+  for (int c = 0; c < 4; ++c) {
+    const double* b = img + (size_t)c * N;
+    double v00 = b[(size_t)ya * W + xa], v10 = b[(size_t)ya * W + xb];
+    double v01 = b[(size_t)yb * W + xa], v11 = b[(size_t)yb * W + xb];
+    s[c] = (1 - ay) * ((1 - ax) * v00 + ax * v10) + ay * ((1 - ax) * v01 + ax * v11);
+    sx[c] = (1 - ay) * (v10 - v00) + ay * (v11 - v01);
+    sy[c] = (1 - ax) * (v01 - v00) + ax * (v11 - v10);
+  }
+  tx[0] = xa; ty[0] = ya; tw[0] = (1 - ax) * (1 - ay);
+  tx[1] = xb; ty[1] = ya; tw[1] = ax * (1 - ay);
+  tx[2] = xa; ty[2] = yb; tw[2] = (1 - ax) * ay;
+  tx[3] = xb; ty[3] = yb; tw[3] = ax * ay;
+}
+
+/* gather radius per pixel and the pixel whose CoC sets it (-1 when capped
+ * or zero): tile max of r (lowest index on ties), then max over the tiles
+ * within ceil(r_cap / tile) (largest value, lowest pixel index on ties). */
+void or_pp_radius_arg(int W, int H, const double* cimg, double r_cap, int tile, double* Rout, int64_t* arg) {
+  int TW = (W + tile - 1) / tile, TH = (H + tile - 1) / tile;
+  double* rt = (double*)calloc((size_t)TW * TH, sizeof(double));
+  int64_t* ra = (int64_t*)malloc(sizeof(int64_t) * (size_t)TW * TH);
+  for (size_t t = 0; t < (size_t)TW * TH; ++t) ra[t] = -1;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x, t = (size_t)(y / tile) * TW + x / tile;
+      double r = 0.5 * fabs(cimg[p]);
+      if (ra[t] < 0 || r > rt[t] || (r == rt[t] && (int64_t)p < ra[t])) { rt[t] = r; ra[t] = (int64_t)p; }
+    }
+  int K = (int)ceil(r_cap / tile);
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      int tx = x / tile, ty = y / tile;
+      double m = -1.0;
+      int64_t am = -1;
+      for (int dy = -K; dy <= K; ++dy)
+        for (int dx = -K; dx <= K; ++dx) {
+          int yy = ty + dy, xx = tx + dx;
+          if (yy < 0 || yy >= TH || xx < 0 || xx >= TW) continue;
+          size_t t = (size_t)yy * TW + xx;
+          if (rt[t] > m || (rt[t] == m && ra[t] < am)) { m = rt[t]; am = ra[t]; }
+        }
+      size_t p = (size_t)y * W + x;
+      Rout[p] = mind(r_cap, m);
+      arg[p] = (m < r_cap && m > 0.0) ? am : -1;
+    }
+  free(rt); free(ra);
+}
+
+void or_pp_composite_backward(const double* cam, int W, int H, const double* lens, const double* color,
+                              const double* z, const int* spp, const double* c_near, const double* c_far,
+                              const double* hit, const double* pp, double h_t, int rt_override,
+                              const double* g, double* gcolor, double* glens /* dS1, dA */) {
+  cam_t k = mk_cam(cam, W, H);
+  size_t N = (size_t)W * H;
+  int NT = (int)pp[0], tile = (int)pp[1];
+  double r_cap = pp[2], ramp = pp[3];
+  double A = lens[1], S1 = lens[2];
+  double* img = (double*)malloc(sizeof(double) * 4 * N);
+  double* R = (double*)malloc(sizeof(double) * N);
+  int64_t* arg = (int64_t*)malloc(sizeof(int64_t) * N);
+  /* dc/dS1 (same for every pixel) and dc/dA per pixel */
+  double dcs = -A * k.spx / (S1 * S1);
+  double* dca = (double*)malloc(sizeof(double) * N);
+  for (size_t p = 0; p < N; ++p) {
+    for (int c = 0; c < 3; ++c) img[(size_t)c * N + p] = color[(size_t)c * N + p];
+    img[3 * N + p] = coc_px(&k, lens, z[p]);
+    dca[p] = (1.0 / S1 - 1.0 / z[p]) * k.spx;
+  }
+  or_pp_radius_arg(W, H, img + 3 * N, r_cap, tile, R, arg);
+  memset(gcolor, 0, sizeof(double) * 3 * N);
+  double gs = 0.0, ga = 0.0;
+  double gam = OR_PI * (3.0 - sqrt(5.0));
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x;
+      dual cp = dmk(img[3 * N + p], dcs, dca[p]);
+      /* composite weights */
+      dual phi = dclamp(dsub(dabs(cp), dconst(OR_SQRT2)), 0.0, 1.0);
+      dual nu = dclamp(dsub(dconst(0.5), dscale(cp, 1.0 / (2.0 * OR_SQRT2))), 0.0, 1.0);
+      double h = hit[p];
+      int traced = spp[p] > 0;
+      double rho = traced ? 1.0 : 0.0;
+      double beta = traced ? clampd(1.0 - h / h_t, 0.0, 1.0) : 0.0;
+      /* coefficients of C_rt and C_pp in the out-of-focus colour */
+      dual acoef = dadd(dscale(nu, rho), dscale(dsub(dconst(1.0), nu), beta));
+      dual bcoef = dadd(dscale(nu, 1.0 - rho), dscale(dsub(dconst(1.0), nu), 1.0 - beta));
+      double gq[3];
+      for (int c = 0; c < 3; ++c) gq[c] = g[(size_t)c * N + p];
+      if (rt_override && traced) continue;  /* out = C_rt: independent of C_r, S1, A */
+      /* forward-mode post-filter at p */
+      dual rp = dscale(dabs(cp), 0.5);
+      dual rp5 = dmaxc(rp, 0.5);
+      dual w0 = ddiv(dconst(1.0), dmul(rp5, rp5));
+      dual Rd = dconst(R[p]);
+      if (arg[p] >= 0) {
+        double cm = img[3 * N + arg[p]];
+        double sg = cm >= 0.0 ? 0.5 : -0.5;
+        Rd = dmk(R[p], sg * dcs, sg * dca[arg[p]]);
+      }
+      dual num[3], den = w0;
+      for (int c = 0; c < 3; ++c) num[c] = dscale(w0, img[(size_t)c * N + p]);
+      /* per-tap weights kept for the colour scatter */
+      double wk_v[256];
+      int tx[256][4], ty[256][4];
+      double tw[256][4];
+      for (int kk = 1; kk <= NT && Rd.v > 0.0; ++kk) {
+        double rad = sqrt((kk - 0.5) / NT);
+        double ux = rad * cos(kk * gam), uy = rad * sin(kk * gam);
+        double qx = x + 0.5 + Rd.v * ux, qy = y + 0.5 + Rd.v * uy;
+        double s[4], sx[4], sy[4];
+        bilerp_grad(img, W, H, N, qx, qy, s, sx, sy, tx[kk - 1], ty[kk - 1], tw[kk - 1]);
+        /* d(sample)/dtheta: position moves with R, c also changes in place */
+        double dsp_s = ux * Rd.ds, dsp_a = ux * Rd.da, dsq_s = uy * Rd.ds, dsq_a = uy * Rd.da;
+        dual smp[3];
+        for (int c = 0; c < 3; ++c) smp[c] = dmk(s[c], sx[c] * dsp_s + sy[c] * dsq_s, sx[c] * dsp_a + sy[c] * dsq_a);
+        /* bilinear of dc/dA: interpolate dca with the same weights */
+        double dca_q = 0.0;
+        for (int i = 0; i < 4; ++i) dca_q += tw[kk - 1][i] * dca[(size_t)ty[kk - 1][i] * W + tx[kk - 1][i]];
+        dual cq = dmk(s[3], dcs + sx[3] * dsp_s + sy[3] * dsq_s, dca_q + sx[3] * dsp_a + sy[3] * dsq_a);
+        dual rq = dscale(dabs(cq), 0.5);
+        dual tk = dclamp(dscale(dsub(cq, cp), 1.0 / ramp), 0.0, 1.0);
+        dual reff = dsub(rq, dmul(tk, dmax0(dsub(rq, rp))));
+        dual dk = dscale(Rd, rad);
+        dual a = dclamp(dadd(dsub(reff, dk), dconst(0.5)), 0.0, 1.0);
+        dual rq5 = dmaxc(rq, 0.5);
+        dual w = ddiv(dmul(a, dscale(dmul(Rd, Rd), 1.0 / NT)), dmul(rq5, rq5));
+        for (int c = 0; c < 3; ++c) num[c] = dadd(num[c], dmul(w, smp[c]));
+        den = dadd(den, w);
+        wk_v[kk - 1] = w.v;
+      }
+      int ntaps = Rd.v > 0.0 ? NT : 0;
+      double crt[3];
+      for (int c = 0; c < 3; ++c) crt[c] = h * c_near[(size_t)c * N + p] + (1.0 - h) * c_far[(size_t)c * N + p];
+      for (int c = 0; c < 3; ++c) {
+        dual cpp = ddiv(num[c], den);
+        double cr = img[(size_t)c * N + p];
+        /* out = (1 - phi) C_r + phi (a C_rt + b C_pp) */
+        dual oof = dadd(dscale(acoef, crt[c]), dmul(bcoef, cpp));
+        dual out = dadd(dscale(dsub(dconst(1.0), phi), cr), dmul(phi, oof));
+        gs += gq[c] * out.ds;
+        ga += gq[c] * out.da;
+        /* colour: direct term, then the post-filter's transpose */
+        gcolor[(size_t)c * N + p] += gq[c] * (1.0 - phi.v);
+        double gpp = gq[c] * phi.v * bcoef.v / den.v;
+        gcolor[(size_t)c * N + p] += gpp * w0.v;
+        for (int kk = 0; kk < ntaps; ++kk)
+          for (int i = 0; i < 4; ++i)
+            gcolor[(size_t)c * N + (size_t)ty[kk][i] * W + tx[kk][i]] += gpp * wk_v[kk] * tw[kk][i];
+      }
+    }
+  glens[0] = gs;
+  glens[1] = ga;
+  free(img); free(R); free(arg); free(dca);
+}
