@@ -327,6 +327,28 @@ hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* tuning);
 hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
 
 /* ---------------------------------------------------------------------- */
+/* Differentiable form                                                      */
+/* ---------------------------------------------------------------------- */
+
+/* Adjoint of hdof_postfilter followed by hdof_composite, as a function of the
+ * sharp colour C_r, the focus distance S1 and the aperture A, with depth,
+ * ray counts and ray-traced colours held fixed.  Given dL/dout
+ * (d_grad_out [3][H][W]) it writes dL/dC_r (d_grad_color [3][H][W]; the
+ * post-filter's transpose is scattered with float atomics, so its low bits
+ * depend on their order) and {dL/dS1, dL/dA} (d_grad_lens, 2 device floats,
+ * summed in a fixed order).  The gather is recomputed, no weights are
+ * stored.  Derivatives: dc/dS1 = -A s_px / S1^2, dc/dA = (1/S1 - 1/z) s_px;
+ * the gather radius follows the CoC of the pixel that sets its tile maximum
+ * (lowest index on ties) unless capped at r_cap; clamp ramps have slope 0 at
+ * and beyond their ends.  d_grad_color must not alias the inputs. */
+hdof_status hdof_postfilter_composite_backward(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                                               const uint8_t* d_spp, hdof_rt_bufs rt,
+                                               const hdof_camera* cam, const hdof_lens* lens,
+                                               const hdof_pp_params* pp, const hdof_composite_params* comp,
+                                               const float* d_grad_out, float* d_grad_color,
+                                               float* d_grad_lens, hdof_stream stream);
+
+/* ---------------------------------------------------------------------- */
 /* Stage timing                                                             */
 /* ---------------------------------------------------------------------- */
 

@@ -193,6 +193,9 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
+  buf_free(ctx->ppb_unit);
+  buf_free(ctx->ppb_args);
+  buf_free(ctx->ppb_partial);
   buf_free(ctx->b_arena);
   buf_free(ctx->b_views);
   buf_free(ctx->b_totals);
@@ -831,4 +834,24 @@ extern "C" hdof_status hdof_batch_launch(hdof_batch* b, hdof_stream stream) {
   TRY(check_ctx(b->ctx));
   HDOF_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
   return HDOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// differentiable form
+// ---------------------------------------------------------------------------
+extern "C" hdof_status hdof_postfilter_composite_backward(
+    hdof_ctx* ctx, const float* d_color, const float* d_depth, const uint8_t* d_spp, hdof_rt_bufs rt,
+    const hdof_camera* cam, const hdof_lens* lens, const hdof_pp_params* pp, const hdof_composite_params* comp,
+    const float* d_grad_out, float* d_grad_color, float* d_grad_lens, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(d_color && d_depth && d_spp && d_grad_out && d_grad_color && d_grad_lens,
+          "color, depth, spp and gradient buffers must be non-NULL");
+  REQUIRE(rt.c_near && rt.c_far && rt.hit_ratio, "c_near, c_far and hit_ratio must be non-NULL");
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_pp(pp));
+  TRY(check_comp(comp));
+  CamK k = make_camk(cam);
+  return launch_ppc_backward(ctx, d_color, d_depth, d_spp, rt, k, make_lensk(lens, k), *pp, *comp, d_grad_out,
+                             d_grad_color, d_grad_lens, (hipStream_t)stream);
 }

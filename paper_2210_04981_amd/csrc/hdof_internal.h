@@ -64,6 +64,8 @@ struct hdof_ctx {
   // post-filter scratch
   Buf pp_pack, pp_tile, pp_rad, pp_taps;
   int pp_taps_n = 0;  // tap count the table currently holds
+  // adjoint scratch: CoC per unit aperture, tile / radius arg pixels, block partials
+  Buf ppb_unit, ppb_args, ppb_partial;
   // variance history (previous frame) and its reprojection into this frame
   int hist_w = 0, hist_h = 0;
   bool hist_any = false;
@@ -250,6 +252,10 @@ hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const u
                               const float* depth, const float* m1, const float* m2, hipStream_t st);
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st);
+hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* depth, const uint8_t* spp,
+                                hdof_rt_bufs rt, const CamK& k, const LensK& l, const hdof_pp_params& pp,
+                                const hdof_composite_params& cp, const float* grad_out, float* grad_color,
+                                float* grad_lens, hipStream_t st);
 hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
                              const uint8_t* spp, hdof_rt_bufs rt, const CamK& k, const LensK& l,
                              const hdof_composite_params& cp, float* out, hipStream_t st);

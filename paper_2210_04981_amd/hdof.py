@@ -129,6 +129,8 @@ _PROTOS = {
     "hdof_batch_destroy": (None, [P]),
     "hdof_set_tuning": (_S, [P, C.POINTER(Tuning)]),
     "hdof_get_tuning": (_S, [P, C.POINTER(Tuning)]),
+    "hdof_postfilter_composite_backward": (_S, [P, P, P, P, RTBufs, C.POINTER(Camera), C.POINTER(Lens),
+                                                C.POINTER(PPParams), C.POINTER(CompositeParams), P, P, P, P]),
     "hdof_counters_begin": (_S, [P]),
     "hdof_counters_end": (_S, [P, C.POINTER(C.c_int64)]),
 }
@@ -582,3 +584,50 @@ def hdof_get_tuning(ctx: Context) -> dict:
     t = Tuning()
     _check(_lib.hdof_get_tuning(ctx.handle, C.byref(t)), "hdof_get_tuning")
     return dict(blocks_per_cu=t.blocks_per_cu, refill=t.refill, segments=t.segments)
+
+
+# ----------------------------------------------------------------------------
+# differentiable form
+# ----------------------------------------------------------------------------
+
+def hdof_postfilter_composite_backward(ctx: Context, color, depth, spp, rt: RTResult, cam: Camera, lns: Lens,
+                                       pp: PPParams, cp: CompositeParams, grad_out, grad_color=None,
+                                       grad_lens=None, stream=None):
+    """dL/dC_r (3,H,W) and dL/d(S1, A) (2,) on the device for dL/dout = grad_out."""
+    n = _npx(cam)
+    grad_color = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device=color.device) \
+        if grad_color is None else grad_color
+    grad_lens = torch.empty(2, dtype=torch.float32, device=color.device) if grad_lens is None else grad_lens
+    _check(_lib.hdof_postfilter_composite_backward(
+        ctx.handle, _ptr(color, torch.float32, 3 * n, "color"), _ptr(depth, torch.float32, n, "depth"),
+        _ptr(spp, torch.uint8, n, "spp"), rt.bufs(n), C.byref(cam), C.byref(lns), C.byref(pp), C.byref(cp),
+        _ptr(grad_out, torch.float32, 3 * n, "grad_out"), _ptr(grad_color, torch.float32, 3 * n, "grad_color"),
+        _ptr(grad_lens, torch.float32, 2, "grad_lens"), _stream(stream)), "hdof_postfilter_composite_backward")
+    return grad_color, grad_lens
+
+
+class HybridDoFPost(torch.autograd.Function):
+    """out = composite(C_r, postfilter(C_r; S1, A); S1, A) with depth, ray
+    counts and ray-traced colours fixed.  Differentiable in the sharp colour,
+    the focus distance and the aperture; the backward pass is the library's
+    hand-written adjoint (gather recomputed, nothing stored but the inputs).
+
+    apply(color, focus, aperture, depth, spp, rt, camera, focal_length, pp, comp, ctx)
+    with focus and aperture 0-dim float tensors."""
+
+    @staticmethod
+    def forward(fctx, color, focus, aperture, depth, spp, rt, cam, focal_length, pp, comp, hctx):
+        lns = lens(focal_length, float(aperture), float(focus))
+        cpp = hdof_postfilter(hctx, color, depth, cam, lns, pp)
+        out = hdof_composite(hctx, color, cpp, depth, spp, rt, cam, lns, comp)
+        fctx.save_for_backward(color, depth, spp)
+        fctx.meta = (rt, cam, lns, pp, comp, hctx)
+        return out
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        color, depth, spp = fctx.saved_tensors
+        rt, cam, lns, pp, comp, hctx = fctx.meta
+        gc, gl = hdof_postfilter_composite_backward(hctx, color, depth, spp, rt, cam, lns, pp, comp,
+                                                    grad_out.contiguous())
+        return gc, gl[0], gl[1], None, None, None, None, None, None, None, None
