@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and backward timings")
     ap.add_argument("--scene-seed", type=int, default=0)
     return ap.parse_args()
 
@@ -149,11 +150,94 @@ def main():
         "roofline": roofline,
         "paper_context": "143 fps hybrid on GeForce RTX 2080 Ti, The Modern Living Room (context only)",
     }
+    if not args.no_forms:
+        res["forms"] = {"batched": bench_batched(hdof, ctx, sc, ms_per_step),
+                        "backward": bench_backward(hdof, ctx, sc, cfg, keep, ms_per_step)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, scene)
     print(json.dumps(res), flush=True)
     sc.close()
     ctx.close()
+
+
+def _time_ms(fn, reps, stream):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(hdof, ctx, sc, plain_ms):
+    """32 views (uneven sizes and lenses) of the living room: one HIP-graph
+    replay of the batched form vs the same 32 views as sequential frames."""
+    import torch
+    import scenegen as sg
+    vcfg = sg.batched_views(seed=7, n_views=32)
+    views = [(hdof.camera_of(v.camera), hdof.lens_of(v.lens), v.seed, 0, i) for i, v in enumerate(vcfg)]
+    outs = [torch.empty(3, v.camera.height, v.camera.width, dtype=torch.float32, device="cuda") for v in vcfg]
+    light = hdof.light_of(vcfg[0].light)
+    params = hdof.frame_params_of(vcfg[0])
+    stream = torch.cuda.current_stream()
+    print("[bench] batched: capturing the graph", file=sys.stderr, flush=True)
+    b = hdof.Batch(ctx, sc, light, params, views, outs)
+    for _ in range(2):
+        b.launch(stream)
+    graph_ms = _time_ms(lambda: b.launch(stream), 5, stream)
+    eager_ms = _time_ms(lambda: hdof.hdof_frame_batched(ctx, sc, light, params, views, outs, stream=stream), 3, stream)
+
+    def sequential():
+        for (cam, lns, seed, frame, view), o in zip(views, outs):
+            hdof.hdof_frame(ctx, sc, cam, None, lns, light, params, seed=seed, frame=frame, view=view, out=o,
+                            stream=stream)
+    sequential()
+    seq_ms = _time_ms(sequential, 3, stream)
+    b.close()
+    npx = sum(v.camera.width * v.camera.height for v in vcfg)
+    return {"workload": "32 views of the living room, 640x360..2560x1440, f/1.4-2.8, focus 0.8-5 m",
+            "views": len(views), "pixels": npx, "graph_replay_ms": round(graph_ms, 3),
+            "eager_batched_ms": round(eager_ms, 3), "sequential_plain_ms": round(seq_ms, 3),
+            "views_per_s": round(len(views) / graph_ms * 1e3, 1),
+            "mpix_per_s": round(npx / graph_ms / 1e3, 1),
+            "speedup_vs_sequential": round(seq_ms / graph_ms, 3)}
+
+
+def bench_backward(hdof, ctx, sc, cfg, keep, plain_ms):
+    """Differentiable form on 8 frames at 1080p: forward (post-filter +
+    composite) and the adjoint w.r.t. colour, focus distance and aperture."""
+    import torch
+    stream = torch.cuda.current_stream()
+    cam, lens = hdof.camera_of(cfg.camera), hdof.lens_of(cfg.lens)
+    pp, cp = hdof.pp_params_of(cfg.pp), hdof.composite_params_of(cfg.comp)
+    H, W = cfg.camera.height, cfg.camera.width
+    color, depth, spp, rt = keep.gb.color, keep.gb.depth, keep.spp, keep.rt
+    grad = torch.randn(3, H, W, device="cuda")
+    gc = torch.empty(3, H, W, device="cuda")
+    gl = torch.empty(2, device="cuda")
+    out = torch.empty(3, H, W, device="cuda")
+    ppo = torch.empty(3, H, W, device="cuda")
+
+    def fwd():
+        for _ in range(8):
+            hdof.hdof_postfilter(ctx, color, depth, cam, lens, pp, out=ppo, stream=stream)
+            hdof.hdof_composite(ctx, color, ppo, depth, spp, rt, cam, lens, cp, out=out, stream=stream)
+
+    def bwd():
+        for _ in range(8):
+            hdof.hdof_postfilter_composite_backward(ctx, color, depth, spp, rt, cam, lens, pp, cp, grad,
+                                                    grad_color=gc, grad_lens=gl, stream=stream)
+    fwd()
+    bwd()
+    fwd_ms = _time_ms(fwd, 3, stream)
+    bwd_ms = _time_ms(bwd, 3, stream)
+    return {"workload": "8 frames 1920x1080, gradient w.r.t. colour, focus distance, aperture",
+            "frames": 8, "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
+            "backward_over_forward": round(bwd_ms / fwd_ms, 3),
+            "backward_over_plain_frames": round(bwd_ms / (8 * plain_ms), 3)}
 
 
 # algorithmic HBM bytes per unit of the HBM-bound stages (see DESIGN.md)
