@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and backward timings")
     ap.add_argument("--scene-seed", type=int, default=0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (a counter calibration "
+                         "point for profiler runs)")
     return ap.parse_args()
 
 
@@ -53,6 +56,14 @@ def main():
     from paper_2210_04981_amd import hdof
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = sg.config_1080p()
     scene = sg.living_room_scene(args.scene_seed)
     ctx = hdof.Context(0)

@@ -125,6 +125,14 @@ __device__ inline V3 cross3(V3 a, V3 b) {
 __device__ inline float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 __device__ inline float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 
+// logical block index so that XCD x (blocks dispatched round-robin over 8
+// XCDs) processes one contiguous range of logical blocks
+__device__ inline int xcd_block(int b, int nb) {
+  int per = nb >> 3, rem = nb & 7;
+  int x = b & 7, i = b >> 3;
+  return x * per + min(x, rem) + i;
+}
+
 // camera constants gathered once per launch
 struct CamK {
   V3 e, r, u, w;

@@ -5,10 +5,9 @@
 //   CoC radius.
 // k_pp_dilate: gather radius per tile = min(r_cap, max radius over the tiles
 //   within ceil(r_cap / tile) tiles).
-// k_pp_gather: 16x4-pixel waves; golden-angle taps from a small table read
-//   with wave-uniform loads; four float4 texels per tap from L1/L2 (the
-//   packed image is written just before, so it is cache-resident); weights
-//   recomputed per tap, nothing stored.
+// k_pp_gather16 / k_pp_gather_any: golden-angle taps, four float4 texels per
+//   tap (16-pixel tiles: staged per tap group in LDS), weights recomputed per
+//   tap, nothing stored but the result.
 // k_composite: focus zone / near / far rules, one pass over the pixels.
 #include "hdof_internal.h"
 
@@ -71,72 +70,242 @@ __global__ void k_pp_dilate(const float* __restrict__ tile_r, int TW, int TH, in
 }
 
 
-// UNI: the post-filter tile equals the 16x16 block, so the gather radius and
-// with it every tap's integer offset and bilinear weights are uniform over
-// the block (computed once per tap in scalar registers); only the four
-// texel loads and the per-tap weight are per lane.  Blocks whose reach stays
-// inside the image skip the clamp-to-edge.
-template <bool UNI>
-__global__ __launch_bounds__(256) void k_pp_gather(const float4* __restrict__ pack,
-                                                   const float* __restrict__ rad,
-                                                   const float4* __restrict__ taps, int n_taps,
-                                                   int W, int H, int tile, float inv_ramp,
-                                                   float* __restrict__ out) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
-  const int x = x0 + (lane & 15), y = y0 + wave * 4 + (lane >> 4);
-  if (x >= W || y >= H) return;
+// ---------------------------------------------------------------- gather
+// Tap weights are carried in CoC-diameter units: for a tap with bilinear CoC
+// c_q, the paper's weight (R^2/N) a / max(r_q, 0.5)^2 equals
+// 4 (R^2/N) a / max(c_q^2, 1), so every tap uses a / max(c_q^2, 1) and the
+// centre weight 1 / max(r_p, 0.5)^2 becomes 1 / ((R^2/N) max(c_p^2, 1)); the
+// normalised sum is unchanged.  The effective radius in the same units is
+// |c_q| - t max(0, |c_q| - |c_p|) (twice the radius form).
+struct GatherAcc {
+  float ap, ncpr, inv_ramp;  // |c_p|, -c_p / ramp, 1 / ramp
+  float ar, ag, ab, ws;
+  __device__ __forceinline__ void init(const float4& cp4, float R, int n_taps, float inv_ramp_) {
+    inv_ramp = inv_ramp_;
+    ap = fabsf(cp4.w);
+    ncpr = -cp4.w * inv_ramp;
+    const float q = fmaxf(cp4.w * cp4.w, 1.0f);
+    const float w0 = R > 0.0f ? __builtin_amdgcn_rcpf(R * R / (float)n_taps * q) : 1.0f;
+    ar = w0 * cp4.x;
+    ag = w0 * cp4.y;
+    ab = w0 * cp4.z;
+    ws = w0;
+  }
+  // one tap: bilinear (rgb, c) from the four texels with weights
+  // (w00, w10, w01, w11), d = 0.5 - R |u|
+  __device__ __forceinline__ void tap(float w00, float w10, float w01, float w11, float d, const float4& v00,
+                                      const float4& v10, const float4& v01, const float4& v11) {
+    const float sr = fmaf(w11, v11.x, fmaf(w01, v01.x, fmaf(w10, v10.x, w00 * v00.x)));
+    const float sg = fmaf(w11, v11.y, fmaf(w01, v01.y, fmaf(w10, v10.y, w00 * v00.y)));
+    const float sb = fmaf(w11, v11.z, fmaf(w01, v01.z, fmaf(w10, v10.z, w00 * v00.z)));
+    const float cq = fmaf(w11, v11.w, fmaf(w01, v01.w, fmaf(w10, v10.w, w00 * v00.w)));
+    const float aq = fabsf(cq);
+    const float tk = clamp01(fmaf(cq, inv_ramp, ncpr));
+    const float reff2 = fmaf(-tk, fmaxf(0.0f, aq - ap), aq);
+    const float a = clamp01(fmaf(reff2, 0.5f, d));
+    const float wt = a * __builtin_amdgcn_rcpf(fmaxf(cq * cq, 1.0f));
+    ar = fmaf(wt, sr, ar);
+    ag = fmaf(wt, sg, ag);
+    ab = fmaf(wt, sb, ab);
+    ws += wt;
+  }
+  __device__ __forceinline__ void store(float* __restrict__ out, size_t N, size_t p) const {
+    const float iw = 1.0f / ws;
+    out[p] = ar * iw;
+    out[N + p] = ag * iw;
+    out[2 * N + p] = ab * iw;
+  }
+};
+
+// Four clamp-to-edge texels of the bilinear footprint whose corner is (xa, ya).
+__device__ __forceinline__ void texels_clamped(const float4* __restrict__ pack, int W, int H, int xa, int ya,
+                                               float4& v00, float4& v10, float4& v01, float4& v11) {
+  const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
+  const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
+  v00 = pack[(size_t)ya_ * W + xa_];
+  v10 = pack[(size_t)ya_ * W + xb_];
+  v01 = pack[(size_t)yb_ * W + xa_];
+  v11 = pack[(size_t)yb_ * W + xb_];
+}
+
+// Tap record of the 16-pixel-tile gather: bilinear weights and distance term.
+struct TapRec {
+  float w00, w10, w01, w11, d, pad0, pad1, pad2;
+};
+
+#define PPG_G 4                 // taps per staged group (one per wave)
+#define PPG_SIDE 17             // footprint side: 16 pixels + 1 bilinear neighbour
+#define PPG_TEX (PPG_SIDE * PPG_SIDE)
+#define PPG_SLOTS 5             // ceil(PPG_TEX / 64) texels staged per lane
+
+// 16-pixel tiles: one 16x16 block per tile, blocks in XCD-contiguous order;
+// the gather radius R and with it every tap's footprint offset and bilinear
+// weights are uniform over the block.  For one tap the block's 256 pixels
+// read the 17x17 texels at the tap's offset, each four times.  Taps are
+// processed in groups of four: wave w stages tap w of the next group (its
+// 17x17 clamp-to-edge texels, five 16-byte loads per lane, and the tap
+// record) into one half of a double-buffered LDS ring while the block
+// gathers the current group from the other half, so the vector-memory
+// address unit (16 clocks per 64-lane load) handles 5 loads per wave and
+// group instead of 16.
+struct Stage {
+  float4 v0, v1, v2, v3, v4;  // texels s * 64 + lane of the footprint, s = 0..4
+  TapRec tr;
+};
+
+// Lane constants of the staging: footprint texel s * 64 + lane lies at row
+// idx / 17, column idx % 17 (idx = s * 64 + lane); interior blocks address it
+// by a 32-bit byte offset from the footprint corner.
+struct StageLane {
+  int sr[PPG_SLOTS], sc[PPG_SLOTS];
+  unsigned so[PPG_SLOTS];
+  bool last;  // slot 4 holds a footprint texel
+};
+
+// Texels and record of tap j (wave-uniform) for the block at (x0, y0).
+__device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, const float4* __restrict__ taps, int j,
+                                            float R, int x0, int y0, int W, int H, bool interior,
+                                            const StageLane& sl) {
+  Stage st;
+  const float4 u = taps[j];
+  const float ox = R * u.x, oy = R * u.y;
+  const float fx = floorf(ox), fy = floorf(oy);
+  const float ax = ox - fx, ay = oy - fy, bx = 1.0f - ax, by = 1.0f - ay;
+  st.tr.w00 = bx * by;
+  st.tr.w10 = ax * by;
+  st.tr.w01 = bx * ay;
+  st.tr.w11 = ax * ay;
+  st.tr.d = 0.5f - R * u.z;
+  st.tr.pad0 = st.tr.pad1 = st.tr.pad2 = 0.0f;
+  const int gx0 = x0 + __builtin_amdgcn_readfirstlane((int)fx);
+  const int gy0 = y0 + __builtin_amdgcn_readfirstlane((int)fy);
+  st.v4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (interior) {
+    const char* base = reinterpret_cast<const char*>(pack) + (size_t)(gy0 * W + gx0) * 16;
+    st.v0 = *reinterpret_cast<const float4*>(base + sl.so[0]);
+    st.v1 = *reinterpret_cast<const float4*>(base + sl.so[1]);
+    st.v2 = *reinterpret_cast<const float4*>(base + sl.so[2]);
+    st.v3 = *reinterpret_cast<const float4*>(base + sl.so[3]);
+    if (sl.last) st.v4 = *reinterpret_cast<const float4*>(base + sl.so[4]);
+  } else {
+#define PPG_CLAMPED(s) pack[(size_t)clampi(gy0 + sl.sr[s], 0, H - 1) * W + clampi(gx0 + sl.sc[s], 0, W - 1)]
+    st.v0 = PPG_CLAMPED(0);
+    st.v1 = PPG_CLAMPED(1);
+    st.v2 = PPG_CLAMPED(2);
+    st.v3 = PPG_CLAMPED(3);
+    if (sl.last) st.v4 = PPG_CLAMPED(4);
+#undef PPG_CLAMPED
+  }
+  return st;
+}
+
+__global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ rad,
+                                                     const float4* __restrict__ taps, int n_taps, int W, int H,
+                                                     float inv_ramp, float* __restrict__ out) {
+  __shared__ float4 stg[2][PPG_G * PPG_TEX];
+  __shared__ TapRec rec[2][PPG_G];
+  const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
+  const int tile = xcd_block(blockIdx.x, TW * TH);
+  const int x0 = (tile % TW) * 16, y0 = (tile / TW) * 16;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lx = lane & 15, ly = wave * 4 + (lane >> 4);
+  const int x = x0 + lx, y = y0 + ly;
+  const bool inside = x < W && y < H;
   const size_t N = (size_t)W * H, p = (size_t)y * W + x;
-  const int TW = (W + tile - 1) / tile;
-  const float R = UNI ? rad[blockIdx.y * TW + blockIdx.x] : rad[(y / tile) * TW + x / tile];
-  const float4 cp4 = pack[p];
-  const float cp = cp4.w, rp = 0.5f * fabsf(cp);
-  const float rp5 = fmaxf(rp, 0.5f);
-  const float w0 = 1.0f / (rp5 * rp5);
-  float ar = w0 * cp4.x, ag = w0 * cp4.y, ab = w0 * cp4.z, ws = w0;
-  if (R > 0.0f) {
-    const float area = R * R / (float)n_taps;
-    const int reach = (int)ceilf(R) + 1;
-    const bool interior = UNI && x0 - reach >= 0 && x0 + 15 + reach < W && y0 - reach >= 0 && y0 + 15 + reach < H;
-    for (int kk = 0; kk < n_taps; ++kk) {
-      const float4 u = taps[kk];  // (ux, uy, |u|, 0)
-      // tap position relative to this pixel's texel grid: x + R u.x (the
-      // +0.5 pixel centre and the -0.5 texel centre cancel)
-      const float ox = R * u.x, oy = R * u.y;
-      const float fx = floorf(ox), fy = floorf(oy);
-      const float ax = ox - fx, ay = oy - fy;
-      int xa = x + (int)fx, ya = y + (int)fy;
-      int xb = xa + 1, yb = ya + 1;
-      if (!interior) {
-        xa = clampi(xa, 0, W - 1);
-        xb = clampi(xb, 0, W - 1);
-        ya = clampi(ya, 0, H - 1);
-        yb = clampi(yb, 0, H - 1);
+  const float R = rad[tile];
+  if (!(R > 0.0f)) {
+    if (inside) {
+      const float4 c = pack[p];
+      out[p] = c.x;
+      out[N + p] = c.y;
+      out[2 * N + p] = c.z;
+    }
+    return;
+  }
+  const int E = (int)ceilf(R);
+  const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H;
+  StageLane sl;
+#pragma unroll
+  for (int s = 0; s < PPG_SLOTS; ++s) {
+    const int idx = s * 64 + lane;
+    sl.sr[s] = idx / PPG_SIDE;
+    sl.sc[s] = idx - sl.sr[s] * PPG_SIDE;
+    sl.so[s] = (unsigned)(sl.sr[s] * W + sl.sc[s]) * 16u;
+  }
+  sl.last = lane < PPG_TEX - 4 * 64;
+  const int ng = (n_taps + PPG_G - 1) / PPG_G;
+  GatherAcc g;
+  g.init(inside ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f), R, n_taps, inv_ramp);
+  // group 0 -> ring half 0
+  if (wave < n_taps) {
+    const Stage st = stage_load(pack, taps, wave, R, x0, y0, W, H, interior, sl);
+    float4* dst = stg[0] + wave * PPG_TEX + lane;
+    dst[0] = st.v0;
+    dst[64] = st.v1;
+    dst[128] = st.v2;
+    dst[192] = st.v3;
+    if (sl.last) dst[256] = st.v4;
+    if (lane == 0) rec[0][wave] = st.tr;
+  }
+  const int lofs = ly * PPG_SIDE + lx;
+  for (int gi = 0; gi < ng; ++gi) {
+    __syncthreads();
+    const int b = gi & 1;
+    const int jn = (gi + 1) * PPG_G + wave;  // this wave's tap of the next group
+    Stage st;
+    if (jn < n_taps) st = stage_load(pack, taps, jn, R, x0, y0, W, H, interior, sl);
+    if (inside) {
+      const int gc = min(PPG_G, n_taps - gi * PPG_G);
+      const float4* src = stg[b] + lofs;
+#pragma unroll
+      for (int jj = 0; jj < PPG_G; ++jj) {
+        if (jj < gc) {
+          const float4* a = src + jj * PPG_TEX;
+          const TapRec t = rec[b][jj];
+          g.tap(t.w00, t.w10, t.w01, t.w11, t.d, a[0], a[1], a[PPG_SIDE], a[PPG_SIDE + 1]);
+        }
       }
-      const float4 v00 = pack[(size_t)ya * W + xa], v10 = pack[(size_t)ya * W + xb];
-      const float4 v01 = pack[(size_t)yb * W + xa], v11 = pack[(size_t)yb * W + xb];
-      const float bx = 1.0f - ax, by = 1.0f - ay;
-      const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
-      const float sr = fmaf(w11, v11.x, fmaf(w01, v01.x, fmaf(w10, v10.x, w00 * v00.x)));
-      const float sg = fmaf(w11, v11.y, fmaf(w01, v01.y, fmaf(w10, v10.y, w00 * v00.y)));
-      const float sb = fmaf(w11, v11.z, fmaf(w01, v01.z, fmaf(w10, v10.z, w00 * v00.z)));
-      const float cq = fmaf(w11, v11.w, fmaf(w01, v01.w, fmaf(w10, v10.w, w00 * v00.w)));
-      const float rq = 0.5f * fabsf(cq);
-      const float tk = clamp01((cq - cp) * inv_ramp);
-      const float reff = rq - tk * fmaxf(0.0f, rq - rp);
-      const float a = clamp01(reff + (0.5f - R * u.z));
-      const float rq5 = fmaxf(rq, 0.5f);
-      const float w = a * area * __frcp_rn(rq5 * rq5);
-      ar = fmaf(w, sr, ar);
-      ag = fmaf(w, sg, ag);
-      ab = fmaf(w, sb, ab);
-      ws += w;
+    }
+    if (jn < n_taps) {
+      float4* dst = stg[b ^ 1] + wave * PPG_TEX + lane;
+      dst[0] = st.v0;
+      dst[64] = st.v1;
+      dst[128] = st.v2;
+      dst[192] = st.v3;
+      if (sl.last) dst[256] = st.v4;
+      if (lane == 0) rec[b ^ 1][wave] = st.tr;
     }
   }
-  const float iw = 1.0f / ws;
-  out[p] = ar * iw;
-  out[N + p] = ag * iw;
-  out[2 * N + p] = ab * iw;
+  if (inside) g.store(out, N, p);
+}
+
+// Tiles of 4 or 8 pixels: per-lane radius and per-lane tap geometry, every
+// texel clamped to the edge.
+__global__ __launch_bounds__(256) void k_pp_gather_any(const float4* __restrict__ pack, const float* __restrict__ rad,
+                                                       const float4* __restrict__ taps, int n_taps, int W, int H,
+                                                       int tile, float inv_ramp, float* __restrict__ out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int x = blockIdx.x * 16 + (lane & 15), y = blockIdx.y * 16 + wave * 4 + (lane >> 4);
+  if (x >= W || y >= H) return;
+  const int TW = (W + tile - 1) / tile;
+  const size_t N = (size_t)W * H, p = (size_t)y * W + x;
+  const float R = rad[(y / tile) * TW + x / tile];
+  const float4 cp4 = pack[p];
+  GatherAcc g;
+  g.init(cp4, R, n_taps, inv_ramp);
+  if (R > 0.0f) {
+    for (int k = 0; k < n_taps; ++k) {
+      const float4 u = taps[k];
+      const float ox = R * u.x, oy = R * u.y;
+      const float fx = floorf(ox), fy = floorf(oy);
+      const float ax = ox - fx, ay = oy - fy, bx = 1.0f - ax, by = 1.0f - ay;
+      float4 v00, v10, v01, v11;
+      texels_clamped(pack, W, H, x + (int)fx, y + (int)fy, v00, v10, v01, v11);
+      g.tap(bx * by, ax * by, bx * ay, ax * ay, 0.5f - R * u.z, v00, v10, v01, v11);
+    }
+  }
+  g.store(out, N, p);
 }
 
 __global__ void k_composite(const float* __restrict__ color, const float* __restrict__ pp,
@@ -444,11 +613,11 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
                      TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
   hdof_prof_mark(ctx, 7, st);
   if (t == 16)
-    hipLaunchKernelGGL(k_pp_gather<true>, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
-                       (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
-                       (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
+    hipLaunchKernelGGL(k_pp_gather16, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+                       (const float*)ctx->pp_rad.p, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
+                       1.0f / pp.bg_ramp_px, out);
   else
-    hipLaunchKernelGGL(k_pp_gather<false>, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_pp_gather_any, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
                        (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
                        (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
   HDOF_HIP(hipGetLastError());

@@ -105,7 +105,7 @@ __device__ inline void tri_test(const Ray& r, const float4* __restrict__ tris, i
   const float det = U + V + W;
   if (det == 0.0f) return;
   const float T = U * shear(r.mz, r.oz, a) + V * shear(r.mz, r.oz, q) + W * shear(r.mz, r.oz, c);
-  const float t = T * __frcp_rn(det);
+  const float t = T * __builtin_amdgcn_rcpf(det);
   if (!(t > 0.0f)) return;
   const int id = __float_as_int(a.w);
   if (t < b.t || (t == b.t && id < b.id)) {
@@ -230,14 +230,6 @@ __device__ inline void shade(const float4* __restrict__ tris, const float* __res
   L = V3{alb.x * fmaf(li.I.x, irr, li.ka.x), alb.y * fmaf(li.I.y, irr, li.ka.y),
          alb.z * fmaf(li.I.z, irr, li.ka.z)};
   n = nn;
-}
-
-// logical block index so that XCD x (blocks dispatched round-robin over 8
-// XCDs) processes one contiguous range of logical blocks
-__device__ inline int xcd_block(int b, int nb) {
-  int per = nb >> 3, rem = nb & 7;
-  int x = b & 7, i = b >> 3;
-  return x * per + min(x, rem) + i;
 }
 
 template <bool COUNT>

@@ -193,11 +193,25 @@ def test_trace_matches_oracle(hd, ctx, which):
     sc.close()
 
 
-@pytest.mark.parametrize("which", ["tiny_strong", "room_small", "uniform_big_coc"])
+def _mixed_depth(H, W, cell, seed):
+    """Piecewise-constant depth over square cells (0.35..9 m) with a focus-
+    plane band: gather radii from 0 to the cap, sharp CoC steps."""
+    rng = np.random.default_rng(seed)
+    cz = rng.uniform(0.35, 9.0, ((H + cell - 1) // cell, (W + cell - 1) // cell))
+    cz[rng.uniform(size=cz.shape) < 0.2] = 2.0
+    return np.kron(cz, np.ones((cell, cell)))[:H, :W]
+
+
+@pytest.mark.parametrize("which", ["tiny_strong", "room_small", "uniform_big_coc", "room_640",
+                                   "mixed_radius_t16", "uniform_r30_t16"])
 def test_postfilter_matches_oracle(hd, ctx, which):
+    """Tiles of 16 take the LDS window for ceil(R) <= 23 and direct reads
+    (interior and clamped) beyond; tiles of 8 take the per-lane form."""
     print_case(f"postfilter {which}")
     if which == "tiny_strong":
         scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.2)
+    elif which in ("room_640", "mixed_radius_t16"):
+        scene, cfg = sg.living_room_scene(0), sg.config_1080p(640, 360)
     else:
         scene, cfg = sg.living_room_scene(0), sg.config_1080p(320, 180)
     ref_gb = oracle.gbuffer(oracle.Scene(scene.verts, scene.albedo), cfg.camera, cfg.lens, cfg.light)
@@ -206,6 +220,12 @@ def test_postfilter_matches_oracle(hd, ctx, which):
     if which == "uniform_big_coc":
         z = np.full_like(z, 0.3)
         pp = sg.PPParams(n_taps=32, tile=8, r_cap=20.0, bg_ramp_px=0.5)
+    elif which == "mixed_radius_t16":
+        z = f32(_mixed_depth(360, 640, 12, 5))
+        col = f32(np.random.default_rng(6).uniform(0, 1, (3, 360, 640)))
+    elif which == "uniform_r30_t16":
+        z = np.full_like(z, 0.3)
+        pp = sg.PPParams(n_taps=48, tile=16, r_cap=30.0, bg_ramp_px=1.0)
     ref = oracle.postfilter(cfg.camera, cfg.lens, col, z, pp)
     got = hd.hdof_postfilter(ctx, to_dev(col, torch.float32), to_dev(z, torch.float32), hd.camera_of(cfg.camera),
                              hd.lens_of(cfg.lens), hd.pp_params_of(pp))
