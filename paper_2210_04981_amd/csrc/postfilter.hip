@@ -128,15 +128,19 @@ __device__ __forceinline__ void texels_clamped(const float4* __restrict__ pack, 
   v11 = pack[(size_t)yb_ * W + xb_];
 }
 
-// Tap record of the 16-pixel-tile gather: bilinear weights and distance term.
+// Tap record of the 16-pixel-tile gather: bilinear weights.
 struct TapRec {
-  float w00, w10, w01, w11, d, pad0, pad1, pad2;
+  float w00, w10, w01, w11;
 };
 
 #define PPG_G 4                 // taps per staged group (one per wave)
 #define PPG_SIDE 17             // footprint side: 16 pixels + 1 bilinear neighbour
 #define PPG_TEX (PPG_SIDE * PPG_SIDE)
 #define PPG_SLOTS 5             // ceil(PPG_TEX / 64) texels staged per lane
+#ifndef PPG_STRIDE
+#define PPG_STRIDE 17           // LDS row stride of a staged footprint, in texels
+#endif
+#define PPG_TAPSZ (PPG_SIDE * PPG_STRIDE)
 
 // 16-pixel tiles: one 16x16 block per tile, blocks in XCD-contiguous order;
 // the gather radius R and with it every tap's footprint offset and bilinear
@@ -159,7 +163,8 @@ struct Stage {
 struct StageLane {
   int sr[PPG_SLOTS], sc[PPG_SLOTS];
   unsigned so[PPG_SLOTS];
-  bool last;  // slot 4 holds a footprint texel
+  int lo[PPG_SLOTS];  // LDS texel index within the tap's footprint
+  bool last;          // slot 4 holds a footprint texel
 };
 
 // Texels and record of tap j (wave-uniform) for the block at (x0, y0).
@@ -175,8 +180,6 @@ __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, con
   st.tr.w10 = ax * by;
   st.tr.w01 = bx * ay;
   st.tr.w11 = ax * ay;
-  st.tr.d = 0.5f - R * u.z;
-  st.tr.pad0 = st.tr.pad1 = st.tr.pad2 = 0.0f;
   const int gx0 = x0 + __builtin_amdgcn_readfirstlane((int)fx);
   const int gy0 = y0 + __builtin_amdgcn_readfirstlane((int)fy);
   st.v4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -202,7 +205,7 @@ __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, con
 __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ rad,
                                                      const float4* __restrict__ taps, int n_taps, int W, int H,
                                                      float inv_ramp, float* __restrict__ out) {
-  __shared__ float4 stg[2][PPG_G * PPG_TEX];
+  __shared__ float4 stg[2][PPG_G * PPG_TAPSZ];
   __shared__ TapRec rec[2][PPG_G];
   const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
   const int tile = xcd_block(blockIdx.x, TW * TH);
@@ -232,6 +235,7 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
     sl.sr[s] = idx / PPG_SIDE;
     sl.sc[s] = idx - sl.sr[s] * PPG_SIDE;
     sl.so[s] = (unsigned)(sl.sr[s] * W + sl.sc[s]) * 16u;
+    sl.lo[s] = sl.sr[s] * PPG_STRIDE + sl.sc[s];
   }
   sl.last = lane < PPG_TEX - 4 * 64;
   const int ng = (n_taps + PPG_G - 1) / PPG_G;
@@ -240,15 +244,15 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   // group 0 -> ring half 0
   if (wave < n_taps) {
     const Stage st = stage_load(pack, taps, wave, R, x0, y0, W, H, interior, sl);
-    float4* dst = stg[0] + wave * PPG_TEX + lane;
-    dst[0] = st.v0;
-    dst[64] = st.v1;
-    dst[128] = st.v2;
-    dst[192] = st.v3;
-    if (sl.last) dst[256] = st.v4;
+    float4* dst = stg[0] + wave * PPG_TAPSZ;
+    dst[sl.lo[0]] = st.v0;
+    dst[sl.lo[1]] = st.v1;
+    dst[sl.lo[2]] = st.v2;
+    dst[sl.lo[3]] = st.v3;
+    if (sl.last) dst[sl.lo[4]] = st.v4;
     if (lane == 0) rec[0][wave] = st.tr;
   }
-  const int lofs = ly * PPG_SIDE + lx;
+  const int lofs = ly * PPG_STRIDE + lx;
   for (int gi = 0; gi < ng; ++gi) {
     __syncthreads();
     const int b = gi & 1;
@@ -261,19 +265,20 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
 #pragma unroll
       for (int jj = 0; jj < PPG_G; ++jj) {
         if (jj < gc) {
-          const float4* a = src + jj * PPG_TEX;
+          const float4* a = src + jj * PPG_TAPSZ;
           const TapRec t = rec[b][jj];
-          g.tap(t.w00, t.w10, t.w01, t.w11, t.d, a[0], a[1], a[PPG_SIDE], a[PPG_SIDE + 1]);
+          const float d = 0.5f - R * taps[gi * PPG_G + jj].z;
+          g.tap(t.w00, t.w10, t.w01, t.w11, d, a[0], a[1], a[PPG_STRIDE], a[PPG_STRIDE + 1]);
         }
       }
     }
     if (jn < n_taps) {
-      float4* dst = stg[b ^ 1] + wave * PPG_TEX + lane;
-      dst[0] = st.v0;
-      dst[64] = st.v1;
-      dst[128] = st.v2;
-      dst[192] = st.v3;
-      if (sl.last) dst[256] = st.v4;
+      float4* dst = stg[b ^ 1] + wave * PPG_TAPSZ;
+      dst[sl.lo[0]] = st.v0;
+      dst[sl.lo[1]] = st.v1;
+      dst[sl.lo[2]] = st.v2;
+      dst[sl.lo[3]] = st.v3;
+      if (sl.last) dst[sl.lo[4]] = st.v4;
       if (lane == 0) rec[b ^ 1][wave] = st.tr;
     }
   }
