@@ -157,20 +157,21 @@ struct Stage {
   TapRec tr;
 };
 
-// Lane constants of the staging: footprint texel s * 64 + lane lies at row
-// idx / 17, column idx % 17 (idx = s * 64 + lane); interior blocks address it
-// by a 32-bit byte offset from the footprint corner.
+// Lane constants of the staging: footprint texel idx = s * 64 + lane lies at
+// row idx / 17, column idx % 17 (lanes past the 289th texel repeat texel
+// 256 + lane - 64 and do not store it); interior blocks address texels by a
+// 32-bit byte offset from the footprint corner.
 struct StageLane {
   int sr[PPG_SLOTS], sc[PPG_SLOTS];
   unsigned so[PPG_SLOTS];
   int lo[PPG_SLOTS];  // LDS texel index within the tap's footprint
-  bool last;          // slot 4 holds a footprint texel
+  bool last;          // slot 4 holds a footprint texel of its own
 };
 
-// Texels and record of tap j (wave-uniform) for the block at (x0, y0).
+// Texels and record of tap j (wave-uniform, < n_taps) for the block at (x0, y0).
+template <bool INTERIOR>
 __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, const float4* __restrict__ taps, int j,
-                                            float R, int x0, int y0, int W, int H, bool interior,
-                                            const StageLane& sl) {
+                                            float R, int x0, int y0, int W, int H, const StageLane& sl) {
   Stage st;
   const float4 u = taps[j];
   const float ox = R * u.x, oy = R * u.y;
@@ -182,24 +183,78 @@ __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, con
   st.tr.w11 = ax * ay;
   const int gx0 = x0 + __builtin_amdgcn_readfirstlane((int)fx);
   const int gy0 = y0 + __builtin_amdgcn_readfirstlane((int)fy);
-  st.v4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (interior) {
+  if (INTERIOR) {
     const char* base = reinterpret_cast<const char*>(pack) + (size_t)(gy0 * W + gx0) * 16;
     st.v0 = *reinterpret_cast<const float4*>(base + sl.so[0]);
     st.v1 = *reinterpret_cast<const float4*>(base + sl.so[1]);
     st.v2 = *reinterpret_cast<const float4*>(base + sl.so[2]);
     st.v3 = *reinterpret_cast<const float4*>(base + sl.so[3]);
-    if (sl.last) st.v4 = *reinterpret_cast<const float4*>(base + sl.so[4]);
+    st.v4 = *reinterpret_cast<const float4*>(base + sl.so[4]);
   } else {
 #define PPG_CLAMPED(s) pack[(size_t)clampi(gy0 + sl.sr[s], 0, H - 1) * W + clampi(gx0 + sl.sc[s], 0, W - 1)]
     st.v0 = PPG_CLAMPED(0);
     st.v1 = PPG_CLAMPED(1);
     st.v2 = PPG_CLAMPED(2);
     st.v3 = PPG_CLAMPED(3);
-    if (sl.last) st.v4 = PPG_CLAMPED(4);
+    st.v4 = PPG_CLAMPED(4);
 #undef PPG_CLAMPED
   }
   return st;
+}
+
+__device__ __forceinline__ void stage_store(float4* __restrict__ dst, TapRec* __restrict__ rdst, const Stage& st,
+                                            const StageLane& sl, int lane) {
+  dst[sl.lo[0]] = st.v0;
+  dst[sl.lo[1]] = st.v1;
+  dst[sl.lo[2]] = st.v2;
+  dst[sl.lo[3]] = st.v3;
+  if (sl.last) dst[sl.lo[4]] = st.v4;
+  if (lane == 0) *rdst = st.tr;
+}
+
+// The tap loop of one block.  Groups are always full: a wave whose tap of
+// the group lies past n_taps stages tap n_taps - 1 again, and that slot's
+// distance term is -1e30 so its coverage, and with it its weight, is 0.
+template <bool INTERIOR>
+__device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], TapRec (*rec)[PPG_G],
+                                            const float4* __restrict__ pack, const float4* __restrict__ taps,
+                                            int n_taps, float R, int x0, int y0, int W, int H, int wave, int lane,
+                                            int lofs, bool inside, GatherAcc& g) {
+  StageLane sl;
+#pragma unroll
+  for (int s = 0; s < PPG_SLOTS; ++s) {
+    const int idx = s * 64 + lane < PPG_TEX ? s * 64 + lane : s * 64 + lane - 64;
+    sl.sr[s] = idx / PPG_SIDE;
+    sl.sc[s] = idx - sl.sr[s] * PPG_SIDE;
+    sl.so[s] = (unsigned)(sl.sr[s] * W + sl.sc[s]) * 16u;
+    sl.lo[s] = sl.sr[s] * PPG_STRIDE + sl.sc[s];
+  }
+  sl.last = lane < PPG_TEX - 4 * 64;
+  const int ng = (n_taps + PPG_G - 1) / PPG_G;
+  {
+    const Stage st = stage_load<INTERIOR>(pack, taps, min(wave, n_taps - 1), R, x0, y0, W, H, sl);
+    stage_store(stg[0] + wave * PPG_TAPSZ, &rec[0][wave], st, sl, lane);
+  }
+  const float* __restrict__ uz = reinterpret_cast<const float*>(taps) + 2;
+  for (int gi = 0; gi < ng; ++gi) {
+    __syncthreads();
+    const int b = gi & 1;
+    const bool more = gi + 1 < ng;
+    Stage st;
+    if (more) st = stage_load<INTERIOR>(pack, taps, min((gi + 1) * PPG_G + wave, n_taps - 1), R, x0, y0, W, H, sl);
+    if (inside) {
+      const float4* src = stg[b] + lofs;
+#pragma unroll
+      for (int jj = 0; jj < PPG_G; ++jj) {
+        const int j = gi * PPG_G + jj;
+        const float d = j < n_taps ? 0.5f - R * uz[4 * j] : -1e30f;
+        const float4* a = src + jj * PPG_TAPSZ;
+        const TapRec t = rec[b][jj];
+        g.tap(t.w00, t.w10, t.w01, t.w11, d, a[0], a[1], a[PPG_STRIDE], a[PPG_STRIDE + 1]);
+      }
+    }
+    if (more) stage_store(stg[b ^ 1] + wave * PPG_TAPSZ, &rec[b ^ 1][wave], st, sl, lane);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ rad,
@@ -228,60 +283,13 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   }
   const int E = (int)ceilf(R);
   const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H;
-  StageLane sl;
-#pragma unroll
-  for (int s = 0; s < PPG_SLOTS; ++s) {
-    const int idx = s * 64 + lane;
-    sl.sr[s] = idx / PPG_SIDE;
-    sl.sc[s] = idx - sl.sr[s] * PPG_SIDE;
-    sl.so[s] = (unsigned)(sl.sr[s] * W + sl.sc[s]) * 16u;
-    sl.lo[s] = sl.sr[s] * PPG_STRIDE + sl.sc[s];
-  }
-  sl.last = lane < PPG_TEX - 4 * 64;
-  const int ng = (n_taps + PPG_G - 1) / PPG_G;
   GatherAcc g;
   g.init(inside ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f), R, n_taps, inv_ramp);
-  // group 0 -> ring half 0
-  if (wave < n_taps) {
-    const Stage st = stage_load(pack, taps, wave, R, x0, y0, W, H, interior, sl);
-    float4* dst = stg[0] + wave * PPG_TAPSZ;
-    dst[sl.lo[0]] = st.v0;
-    dst[sl.lo[1]] = st.v1;
-    dst[sl.lo[2]] = st.v2;
-    dst[sl.lo[3]] = st.v3;
-    if (sl.last) dst[sl.lo[4]] = st.v4;
-    if (lane == 0) rec[0][wave] = st.tr;
-  }
   const int lofs = ly * PPG_STRIDE + lx;
-  for (int gi = 0; gi < ng; ++gi) {
-    __syncthreads();
-    const int b = gi & 1;
-    const int jn = (gi + 1) * PPG_G + wave;  // this wave's tap of the next group
-    Stage st;
-    if (jn < n_taps) st = stage_load(pack, taps, jn, R, x0, y0, W, H, interior, sl);
-    if (inside) {
-      const int gc = min(PPG_G, n_taps - gi * PPG_G);
-      const float4* src = stg[b] + lofs;
-#pragma unroll
-      for (int jj = 0; jj < PPG_G; ++jj) {
-        if (jj < gc) {
-          const float4* a = src + jj * PPG_TAPSZ;
-          const TapRec t = rec[b][jj];
-          const float d = 0.5f - R * taps[gi * PPG_G + jj].z;
-          g.tap(t.w00, t.w10, t.w01, t.w11, d, a[0], a[1], a[PPG_STRIDE], a[PPG_STRIDE + 1]);
-        }
-      }
-    }
-    if (jn < n_taps) {
-      float4* dst = stg[b ^ 1] + wave * PPG_TAPSZ;
-      dst[sl.lo[0]] = st.v0;
-      dst[sl.lo[1]] = st.v1;
-      dst[sl.lo[2]] = st.v2;
-      dst[sl.lo[3]] = st.v3;
-      if (sl.last) dst[sl.lo[4]] = st.v4;
-      if (lane == 0) rec[b ^ 1][wave] = st.tr;
-    }
-  }
+  if (interior)
+    gather_taps<true>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
+  else
+    gather_taps<false>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
   if (inside) g.store(out, N, p);
 }
 
