@@ -193,7 +193,6 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
-  buf_free(ctx->ppb_unit);
   buf_free(ctx->ppb_args);
   buf_free(ctx->ppb_partial);
   buf_free(ctx->b_arena);

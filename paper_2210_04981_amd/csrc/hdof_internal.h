@@ -65,7 +65,7 @@ struct hdof_ctx {
   Buf pp_pack, pp_tile, pp_rad, pp_taps;
   int pp_taps_n = 0;  // tap count the table currently holds
   // adjoint scratch: CoC per unit aperture, tile / radius arg pixels, block partials
-  Buf ppb_unit, ppb_args, ppb_partial;
+  Buf ppb_args, ppb_partial;
   // variance history (previous frame) and its reprojection into this frame
   int hist_w = 0, hist_h = 0;
   bool hist_any = false;

@@ -363,7 +363,7 @@ __device__ inline D3 operator-(D3 x, D3 y) { return D3{x.v - y.v, x.s - y.s, x.a
 __device__ inline D3 operator*(D3 x, D3 y) { return D3{x.v * y.v, fmaf(x.s, y.v, x.v * y.s), fmaf(x.a, y.v, x.v * y.a)}; }
 __device__ inline D3 operator*(float k, D3 x) { return D3{k * x.v, k * x.s, k * x.a}; }
 __device__ inline D3 dquot(D3 x, D3 y) {
-  float q = x.v / y.v, iy = 1.0f / y.v;
+  const float iy = __builtin_amdgcn_rcpf(y.v), q = x.v * iy;
   return D3{q, (x.s - q * y.s) * iy, (x.a - q * y.a) * iy};
 }
 // clamp with zero slope outside the open interval (lo, hi)
@@ -371,11 +371,10 @@ __device__ inline D3 dclamp(D3 x, float lo, float hi) { return x.v <= lo ? dc(lo
 __device__ inline D3 dmaxc(D3 x, float c) { return x.v > c ? x : dc(c); }
 __device__ inline D3 dabs(D3 x) { return x.v >= 0.f ? x : D3{-x.v, -x.s, -x.a}; }
 
-// pack (rgb, c) plus the CoC per unit aperture, tile max with its pixel
+// pack (rgb, c), tile max with its pixel
 __global__ __launch_bounds__(256) void k_ppb_pack(const float* __restrict__ color, const float* __restrict__ depth,
                                                   CamK k, LensK l, int tile, float4* __restrict__ pack,
-                                                  float* __restrict__ unit_coc, float* __restrict__ tile_r,
-                                                  int* __restrict__ tile_arg) {
+                                                  float* __restrict__ tile_r, int* __restrict__ tile_arg) {
   __shared__ float red[256];
   __shared__ int redi[256];
   const int tid = threadIdx.x;
@@ -385,10 +384,8 @@ __global__ __launch_bounds__(256) void k_ppb_pack(const float* __restrict__ colo
   int idx = 0x7fffffff;
   if (x < k.W && y < k.H) {
     size_t p = (size_t)y * k.W + x;
-    float u = (l.invS1 - 1.0f / depth[p]) * k.spx;
-    float c = l.A * u;
+    float c = coc_px(l, depth[p]);
     pack[p] = make_float4(color[p], color[N + p], color[2 * N + p], c);
-    unit_coc[p] = u;
     r = 0.5f * fabsf(c);
     idx = (int)p;
   }
@@ -444,26 +441,78 @@ __global__ void k_fill_f(float* __restrict__ p, size_t n, float v) {
   if (i < n) p[i] = v;
 }
 
+#define PPB_WIN_E 23                     // largest ceil(R) accumulated in one LDS window per block
+#define PPB_WIN (17 + 2 * PPB_WIN_E)     // window side at that radius
+#define PPB_FOOT (PPG_SIDE * PPG_SIDE)   // one tap's 17x17 footprint
+
+// Sample geometry of tap u at radius R relative to a pixel's texel grid: the
+// footprint corner offset (floor R u) and the bilinear fractions.
+struct TapGeo {
+  int ix, iy;
+  float ax, ay;
+};
+__device__ __forceinline__ TapGeo tap_geo(float R, float4 u) {
+  const float ox = R * u.x, oy = R * u.y;
+  const float fx = floorf(ox), fy = floorf(oy);
+  return TapGeo{(int)fx, (int)fy, ox - fx, oy - fy};
+}
+
+// Adjoint of post-filter + composite.  Pass 1 per pixel: the gather again in
+// forward mode (value, d/dS1, d/dA through the CoC, the tile radius and the
+// sample positions), then the composite backward, which gives the focus and
+// aperture gradients (block partials) and the colour gradient of the pixel
+// itself.  Pass 2: the colour gradient flowing through the gather weights,
+// scattered to the four texels of every tap.  16-pixel tiles (UNI) share
+// one tap geometry per block: per tap the block's contributions land on one
+// 17x17 footprint, which is formed in LDS as a transposed bilinear gather of
+// the pixels' posts (no LDS atomics) and then added to one
+// (17 + 2 ceil R)^2 LDS window for ceil R <= PPB_WIN_E (flushed once with
+// global atomics) or straight to global memory (larger R); window and
+// footprint texels are image texels clamped to the edge, as in the gather.
+// Other tile sizes add straight to global memory per pixel and tap.
+template <bool UNI>
 __global__ __launch_bounds__(256) void k_ppc_backward(
-    const float4* __restrict__ pack, const float* __restrict__ unit_coc, const float* __restrict__ rad,
-    const int* __restrict__ rad_arg, const float4* __restrict__ taps, int n_taps, int W, int H, int tile,
-    float inv_ramp, LensK l, float spx, const uint8_t* __restrict__ spp, const float* __restrict__ cn,
-    const float* __restrict__ cf, const float* __restrict__ hr, float inv_ht, int rt_override,
-    const float* __restrict__ g, float* __restrict__ gcol, float2* __restrict__ partial) {
+    const float4* __restrict__ pack, const float* __restrict__ rad, const int* __restrict__ rad_arg,
+    const float4* __restrict__ taps, int n_taps, int W, int H, int tile, float inv_ramp, LensK l, float spx,
+    const uint8_t* __restrict__ spp, const float* __restrict__ cn, const float* __restrict__ cf,
+    const float* __restrict__ hr, float inv_ht, int rt_override, const float* __restrict__ g,
+    float* __restrict__ gcol, float2* __restrict__ partial) {
+  __shared__ float acc[UNI ? 3 * PPB_WIN * PPB_WIN : 1];
+  __shared__ float4 posts[UNI ? 2 : 1][UNI ? 256 : 1];
   __shared__ float2 red[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int x = blockIdx.x * 16 + (lane & 15), y = blockIdx.y * 16 + wave * 4 + (lane >> 4);
+  const int TWb = (W + 15) >> 4, THb = (H + 15) >> 4;
+  const int blk = UNI ? xcd_block(blockIdx.x, TWb * THb) : blockIdx.x;
+  const int x0 = (blk % TWb) * 16, y0 = (blk / TWb) * 16;
+  const int lx = lane & 15, ly = wave * 4 + (lane >> 4);
+  const int x = x0 + lx, y = y0 + ly;
   float gs = 0.0f, ga = 0.0f;
   const size_t N = (size_t)W * H;
   const float dcs = -l.A * spx * l.invS1 * l.invS1;  // dc/dS1 (every pixel)
+  const float inv_A = l.A > 0.0f ? 1.0f / l.A : 0.0f;  // unit CoC = c / A
   const bool inside = x < W && y < H;
   const size_t p = inside ? (size_t)y * W + x : 0;
   const bool traced = inside && spp[p] > 0;
-  if (inside && !(rt_override && traced)) {
-    const int TW = (W + tile - 1) / tile;
-    const int ti = (y / tile) * TW + x / tile;
-    const float4 cp4 = pack[p];
-    const D3 cpv = dk(cp4.w, dcs, unit_coc[p]);
+  const bool active = inside && !(rt_override && traced);
+  const int TW = (W + tile - 1) / tile;
+  const int ti = UNI ? blk : (inside ? (y / tile) * TW + x / tile : 0);
+  const float Rv = rad[ti];
+  const int E = (int)ceilf(Rv);
+  // scatter mode of the block (UNI): 0 global, 1 window, 2 per-tap footprint
+  int mode = 0;
+  if (UNI && Rv > 0.0f) mode = E <= PPB_WIN_E ? 1 : 2;
+  const int wd = 17 + 2 * E;
+  if (UNI && mode == 1) {
+    for (int i = tid; i < 3 * wd * wd; i += 256) acc[i] = 0.0f;
+    __syncthreads();
+  }
+  const int ntap = Rv > 0.0f ? n_taps : 0;
+  float4 cp4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float gpp[3] = {0.f, 0.f, 0.f};
+  float area = 0.0f;
+  if (active) {
+    cp4 = pack[p];
+    const D3 cpv = dk(cp4.w, dcs, cp4.w * inv_A);
     // composite weights
     const D3 phi = dclamp(dabs(cpv) - dc(HDOF_SQRT2), 0.f, 1.f);
     const D3 nu = dclamp(dc(0.5f) - 0.35355339059327376f * cpv, 0.f, 1.f);
@@ -476,26 +525,20 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
     const D3 rp = 0.5f * dabs(cpv);
     const D3 rp5 = dmaxc(rp, 0.5f);
     const D3 w0 = dquot(dc(1.f), rp5 * rp5);
-    D3 R = dc(rad[ti]);
+    D3 R = dc(Rv);
     const int m = rad_arg[ti];
     if (m >= 0) {
-      const float sg = pack[m].w >= 0.f ? 0.5f : -0.5f;
-      R = dk(R.v, sg * dcs, sg * unit_coc[m]);
+      const float cm = pack[m].w;
+      const float sg = cm >= 0.f ? 0.5f : -0.5f;
+      R = dk(R.v, sg * dcs, sg * cm * inv_A);
     }
     D3 nr = w0 * dc(cp4.x), ng = w0 * dc(cp4.y), nb = w0 * dc(cp4.z), den = w0;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const int ntap = R.v > 0.f ? n_taps : 0;
     for (int kk = 0; kk < ntap; ++kk) {
       const float4 u = taps[kk];
-      const float gx = fmaf(R.v, u.x, px) - 0.5f, gy = fmaf(R.v, u.y, py) - 0.5f;
-      const float fx0 = floorf(gx), fy0 = floorf(gy);
-      const float ax = gx - fx0, ay = gy - fy0, bx = 1.f - ax, by = 1.f - ay;
-      const int ix = (int)fx0, iy = (int)fy0;
-      const int xa = min(max(ix, 0), W - 1), xb = min(max(ix + 1, 0), W - 1);
-      const int ya = min(max(iy, 0), H - 1), yb = min(max(iy + 1, 0), H - 1);
-      const size_t i00 = (size_t)ya * W + xa, i10 = (size_t)ya * W + xb, i01 = (size_t)yb * W + xa,
-                   i11 = (size_t)yb * W + xb;
-      const float4 v00 = pack[i00], v10 = pack[i10], v01 = pack[i01], v11 = pack[i11];
+      const TapGeo tg = tap_geo(R.v, u);
+      const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
+      float4 v00, v10, v01, v11;
+      texels_clamped(pack, W, H, x + tg.ix, y + tg.iy, v00, v10, v01, v11);
       const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
       // samples, their spatial slopes, and their motion with R
       const float dxs = u.x * R.s, dxa = u.x * R.a, dys = u.y * R.s, dya = u.y * R.a;
@@ -505,8 +548,7 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
   const float sy_##c = bx * (v01.c - v00.c) + ax * (v11.c - v10.c);
       SAMPLE(x) SAMPLE(y) SAMPLE(z) SAMPLE(w)
 #undef SAMPLE
-      const float uq = w00 * unit_coc[i00] + w10 * unit_coc[i10] + w01 * unit_coc[i01] + w11 * unit_coc[i11];
-      const D3 cq = dk(s_w, dcs + sx_w * dxs + sy_w * dys, uq + sx_w * dxa + sy_w * dya);
+      const D3 cq = dk(s_w, dcs + sx_w * dxs + sy_w * dys, s_w * inv_A + sx_w * dxa + sy_w * dya);
       const D3 rq = 0.5f * dabs(cq);
       const D3 tk = dclamp(inv_ramp * (cq - cpv), 0.f, 1.f);
       const D3 dpos = dmaxc(rq - rp, 0.f);
@@ -523,7 +565,6 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
     const float gq[3] = {g[p], g[N + p], g[2 * N + p]};
     const D3 num[3] = {nr, ng, nb};
     const float cr[3] = {cp4.x, cp4.y, cp4.z};
-    float gpp[3];
     const float iden = 1.0f / den.v;
     for (int c = 0; c < 3; ++c) {
       const float crt = h * cn[c * N + p] + (1.f - h) * cf[c * N + p];
@@ -533,38 +574,106 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
       gs = fmaf(gq[c], out.s, gs);
       ga = fmaf(gq[c], out.a, ga);
       gpp[c] = gq[c] * phi.v * bcoef.v * iden;
-      atomicAdd(&gcol[c * N + p], fmaf(gq[c], 1.f - phi.v, gpp[c] * w0.v));
+      const float own = fmaf(gq[c], 1.f - phi.v, gpp[c] * w0.v);
+      if (mode == 1)
+        acc[(c * wd + ly + E) * wd + lx + E] += own;  // this pixel's own window texel
+      else
+        atomicAdd(&gcol[c * N + p], own);
     }
-    if (gpp[0] != 0.f || gpp[1] != 0.f || gpp[2] != 0.f) {
-      // second pass over the taps: the weights again (value only) and the scatter
-      const float rpv = rp.v, area = R.v * R.v / (float)n_taps;
-      for (int kk = 0; kk < ntap; ++kk) {
-        const float4 u = taps[kk];
-        const float gx = fmaf(R.v, u.x, px) - 0.5f, gy = fmaf(R.v, u.y, py) - 0.5f;
-        const float fx0 = floorf(gx), fy0 = floorf(gy);
-        const float ax = gx - fx0, ay = gy - fy0, bx = 1.f - ax, by = 1.f - ay;
-        const int ix = (int)fx0, iy = (int)fy0;
-        const int xa = min(max(ix, 0), W - 1), xb = min(max(ix + 1, 0), W - 1);
-        const int ya = min(max(iy, 0), H - 1), yb = min(max(iy + 1, 0), H - 1);
-        const size_t i00 = (size_t)ya * W + xa, i10 = (size_t)ya * W + xb, i01 = (size_t)yb * W + xa,
-                     i11 = (size_t)yb * W + xb;
-        const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
-        const float cq = w00 * pack[i00].w + w10 * pack[i10].w + w01 * pack[i01].w + w11 * pack[i11].w;
+    area = R.v * R.v / (float)n_taps;
+  }
+  // pass 2: the weights again (value only) and the scatter of gpp * weight
+  const bool scat = active && (gpp[0] != 0.f || gpp[1] != 0.f || gpp[2] != 0.f);
+  const float rpv = 0.5f * fabsf(cp4.w);
+  if (UNI && mode != 0) {
+    // per tap: every pixel posts gpp * weight, then footprint texel (r, q)
+    // collects the posts of pixels (r - dy, q - dx) with the block-uniform
+    // bilinear weight of corner (dx, dy)
+    for (int kk = 0; kk < ntap; ++kk) {
+      const float4 u = taps[kk];
+      const TapGeo tg = tap_geo(Rv, u);
+      const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
+      float4 post = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (scat) {
+        float4 v00, v10, v01, v11;
+        texels_clamped(pack, W, H, x + tg.ix, y + tg.iy, v00, v10, v01, v11);
+        const float cq = bx * by * v00.w + ax * by * v10.w + bx * ay * v01.w + ax * ay * v11.w;
         const float rq = 0.5f * fabsf(cq);
         const float tk = clamp01((cq - cp4.w) * inv_ramp);
-        const float reff = rq - tk * fmaxf(0.f, rq - rpv);
-        const float a = clamp01(reff - R.v * u.z + 0.5f);
-        if (a == 0.f) continue;
+        const float a = clamp01(rq - tk * fmaxf(0.f, rq - rpv) - Rv * u.z + 0.5f);
         const float rq5 = fmaxf(rq, 0.5f);
-        const float wv = a * area / (rq5 * rq5);
-        for (int c = 0; c < 3; ++c) {
-          const float k = gpp[c] * wv;
-          float* gc = gcol + c * N;
-          atomicAdd(&gc[i00], k * w00);
-          atomicAdd(&gc[i10], k * w10);
-          atomicAdd(&gc[i01], k * w01);
-          atomicAdd(&gc[i11], k * w11);
+        const float wv = a * area * __builtin_amdgcn_rcpf(rq5 * rq5);
+        post = make_float4(gpp[0] * wv, gpp[1] * wv, gpp[2] * wv, 0.f);
+      }
+      float4* kb = posts[kk & 1];
+      kb[ly * 16 + lx] = post;
+      __syncthreads();
+      for (int t = tid; t < PPB_FOOT; t += 256) {
+        const int r = t / PPG_SIDE, q = t - r * PPG_SIDE;
+        float3 v = make_float3(0.f, 0.f, 0.f);
+#define PPB_POST(dy, dx, wgt)                                                     \
+  if (r - dy >= 0 && r - dy < 16 && q - dx >= 0 && q - dx < 16) {                \
+    const float4 k4 = kb[(r - dy) * 16 + q - dx];                                 \
+    v.x = fmaf(wgt, k4.x, v.x);                                                   \
+    v.y = fmaf(wgt, k4.y, v.y);                                                   \
+    v.z = fmaf(wgt, k4.z, v.z);                                                   \
+  }
+        PPB_POST(0, 0, bx * by)
+        PPB_POST(0, 1, ax * by)
+        PPB_POST(1, 0, bx * ay)
+        PPB_POST(1, 1, ax * ay)
+#undef PPB_POST
+        if (mode == 1) {
+          float* wp = acc + (tg.iy + E + r) * wd + tg.ix + E + q;
+          wp[0] += v.x;
+          wp[wd * wd] += v.y;
+          wp[2 * wd * wd] += v.z;
+        } else if (v.x != 0.f || v.y != 0.f || v.z != 0.f) {
+          // footprint texel (r, q) is image texel (y0 + iy + r, x0 + ix + q), clamped to the edge
+          const size_t gi = (size_t)clampi(y0 + tg.iy + r, 0, H - 1) * W + clampi(x0 + tg.ix + q, 0, W - 1);
+          atomicAdd(&gcol[gi], v.x);
+          atomicAdd(&gcol[N + gi], v.y);
+          atomicAdd(&gcol[2 * N + gi], v.z);
         }
+      }
+    }
+  } else if (scat) {
+    for (int kk = 0; kk < ntap; ++kk) {
+      const float4 u = taps[kk];
+      const TapGeo tg = tap_geo(Rv, u);
+      const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
+      const int xa = x + tg.ix, ya = y + tg.iy;
+      const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
+      const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
+      const size_t i00 = (size_t)ya_ * W + xa_, i10 = (size_t)ya_ * W + xb_, i01 = (size_t)yb_ * W + xa_,
+                   i11 = (size_t)yb_ * W + xb_;
+      const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
+      const float cq = w00 * pack[i00].w + w10 * pack[i10].w + w01 * pack[i01].w + w11 * pack[i11].w;
+      const float rq = 0.5f * fabsf(cq);
+      const float tk = clamp01((cq - cp4.w) * inv_ramp);
+      const float a = clamp01(rq - tk * fmaxf(0.f, rq - rpv) - Rv * u.z + 0.5f);
+      if (a == 0.f) continue;
+      const float rq5 = fmaxf(rq, 0.5f);
+      const float wv = a * area * __builtin_amdgcn_rcpf(rq5 * rq5);
+      for (int c = 0; c < 3; ++c) {
+        const float k = gpp[c] * wv;
+        float* gc = gcol + c * N;
+        atomicAdd(&gc[i00], k * w00);
+        atomicAdd(&gc[i10], k * w10);
+        atomicAdd(&gc[i01], k * w01);
+        atomicAdd(&gc[i11], k * w11);
+      }
+    }
+  }
+  if (UNI && mode == 1) {
+    __syncthreads();
+    const int n2 = wd * wd;
+    for (int i = tid; i < 3 * n2; i += 256) {
+      const float v = acc[i];
+      if (v != 0.f) {
+        const int c = i / n2, t = i - c * n2, r = t / wd;
+        const int gy = clampi(y0 - E + r, 0, H - 1), gx = clampi(x0 - E + t - r * wd, 0, W - 1);
+        atomicAdd(&gcol[c * N + (size_t)gy * W + gx], v);
       }
     }
   }
@@ -574,7 +683,7 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
     if (tid < o) red[tid] = make_float2(red[tid].x + red[tid + o].x, red[tid].y + red[tid + o].y);
     __syncthreads();
   }
-  if (tid == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  if (tid == 0) partial[blockIdx.x] = red[0];
 }
 
 // block partials summed in a fixed order (deterministic), in double
@@ -657,14 +766,14 @@ hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* 
   const int TW = cdiv(W, t), TH = cdiv(H, t);
   const int K = (int)ceil((double)pp.r_cap / t);
   const dim3 grid(cdiv(W, 16), cdiv(H, 16));
+  const int nblk = (int)(grid.x * grid.y);
   hdof_status s;
   if ((s = hdof_ensure(ctx->pp_pack, sizeof(float4) * N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_tile, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_rad, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->ppb_unit, sizeof(float) * N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->ppb_args, sizeof(int) * 2 * (size_t)TW * TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->ppb_partial, sizeof(float2) * (size_t)grid.x * grid.y)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->ppb_partial, sizeof(float2) * (size_t)nblk)) != HDOF_OK) return s;
   if (ctx->pp_taps_n != pp.n_taps) {
     hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
     ctx->pp_taps_n = pp.n_taps;
@@ -672,17 +781,24 @@ hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* 
   int* tile_arg = (int*)ctx->ppb_args.p;
   int* rad_arg = tile_arg + (size_t)TW * TH;
   hipLaunchKernelGGL(k_ppb_pack, grid, dim3(256), 0, st, color, depth, k, l, t, (float4*)ctx->pp_pack.p,
-                     (float*)ctx->ppb_unit.p, (float*)ctx->pp_tile.p, tile_arg);
+                     (float*)ctx->pp_tile.p, tile_arg);
   hipLaunchKernelGGL(k_ppb_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p,
                      (const int*)tile_arg, TW, TH, K, pp.r_cap, (float*)ctx->pp_rad.p, rad_arg);
   hipLaunchKernelGGL(k_fill_f, dim3(cdiv(3 * (long)N, 256)), dim3(256), 0, st, grad_color, 3 * N, 0.0f);
-  hipLaunchKernelGGL(k_ppc_backward, grid, dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
-                     (const float*)ctx->ppb_unit.p, (const float*)ctx->pp_rad.p, (const int*)rad_arg,
-                     (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, l, k.spx, spp,
-                     (const float*)rt.c_near, (const float*)rt.c_far, (const float*)rt.hit_ratio, 1.0f / cp.h_t,
-                     cp.rt_override, grad_out, grad_color, (float2*)ctx->ppb_partial.p);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const float2*)ctx->ppb_partial.p,
-                     (int)(grid.x * grid.y), grad_lens);
+  if (t == 16)
+    hipLaunchKernelGGL(k_ppc_backward<true>, dim3(nblk), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+                       (const float*)ctx->pp_rad.p, (const int*)rad_arg, (const float4*)ctx->pp_taps.p, pp.n_taps,
+                       W, H, t, 1.0f / pp.bg_ramp_px, l, k.spx, spp, (const float*)rt.c_near,
+                       (const float*)rt.c_far, (const float*)rt.hit_ratio, 1.0f / cp.h_t, cp.rt_override,
+                       grad_out, grad_color, (float2*)ctx->ppb_partial.p);
+  else
+    hipLaunchKernelGGL(k_ppc_backward<false>, dim3(nblk), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+                       (const float*)ctx->pp_rad.p, (const int*)rad_arg, (const float4*)ctx->pp_taps.p, pp.n_taps,
+                       W, H, t, 1.0f / pp.bg_ramp_px, l, k.spx, spp, (const float*)rt.c_near,
+                       (const float*)rt.c_far, (const float*)rt.hit_ratio, 1.0f / cp.h_t, cp.rt_override,
+                       grad_out, grad_color, (float2*)ctx->ppb_partial.p);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const float2*)ctx->ppb_partial.p, nblk,
+                     grad_lens);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

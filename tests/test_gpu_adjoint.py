@@ -44,11 +44,10 @@ def _small(seed):
     return cam, lens, f32(col), f32(z), spp, f32(cn), f32(cf), f32(hit), pp, sg.CompositeParams(), f32(g)
 
 
-def _room(seed=0):
-    scene, cfg = sg.living_room_scene(0), sg.config_1080p(256, 144)
+def _room(seed=0, W=256, H=144):
+    scene, cfg = sg.living_room_scene(0), sg.config_1080p(W, H)
     gb = orc.gbuffer(orc.Scene(scene.verts, scene.albedo), cfg.camera, cfg.lens, cfg.light)
     rng = np.random.default_rng(seed)
-    H, W = 144, 256
     spp = rng.integers(0, 3, (H, W)).astype(np.int32)
     hit = np.where(spp > 0, rng.uniform(0, 1, (H, W)), 0.0)
     cn, cf = rng.uniform(0, 1, (3, H, W)), rng.uniform(0, 1, (3, H, W))
@@ -68,10 +67,18 @@ def _gpu_backward(hd, ctx, cam, lens, col, z, spp, cn, cf, hit, pp, cp, g):
     return gc.cpu().numpy().astype(np.float64), gl.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("case", ["small0", "small1", "room"])
+@pytest.mark.parametrize("case", ["small0", "small1", "room", "room640"])
 def test_backward_matches_oracle_adjoint(hd, ctx, case):
+    """16-pixel tiles scatter through an LDS window (ceil R <= 23), per-tap
+    LDS footprints (larger R) or global atomics (border tiles); room640 has
+    all three, room the first and last, the small cases use 8-pixel tiles."""
     print_case(f"adjoint {case}")
-    args = _room() if case == "room" else _small(int(case[-1]))
+    if case == "room":
+        args = _room()
+    elif case == "room640":
+        args = _room(3, 640, 360)
+    else:
+        args = _small(int(case[-1]))
     gc, gl = _gpu_backward(hd, ctx, *args)
     rc, rs, ra = orc.pp_composite_backward(*args)
     assert np.max(np.abs(gc - rc)) <= 1e-5 * np.max(np.abs(rc)), np.max(np.abs(gc - rc)) / np.max(np.abs(rc))
