@@ -46,8 +46,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
-                          "in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this library runs on one GPU only: sharding a frame or a batch over "
+                          "several GPUs is a design, not code", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -251,7 +251,8 @@ def bench_backward(hdof, ctx, sc, cfg, keep, plain_ms):
             "backward_over_plain_frames": round(bwd_ms / (8 * plain_ms), 3)}
 
 
-# algorithmic HBM bytes per unit of the HBM-bound stages
+# algorithmic HBM bytes per pixel of the HBM-bound stages: what each stage
+# must read and write once
 HBM_BYTES_PER_PX = {
     "ray_mask": 16 + 1 + 4 + 9,        # read depth + normal; write spp, offsets; history (rep) write
     "var_update": 1 + 4 + 8 + 9 + 13,  # spp, depth, moments, reprojected history in; history out
@@ -260,10 +261,36 @@ HBM_BYTES_PER_PX = {
 }
 
 
-# algorithmic lane-ops per unit of work: one BVH node step
-# (two slab tests), one watertight triangle test, the per-ray setup and
-# shading, a Philox4x64-10 block, one post-filter tap
-OPS_NODE, OPS_TRI, OPS_RAY, OPS_PHILOX, OPS_TAP = 38, 45, 150, 250, 34
+# algorithmic lane-ops per unit of work: one BVH node step (two slab tests),
+# one watertight triangle test, the per-ray setup and shading, a
+# Philox4x64-10 block, one post-filter tap (bilinear rgb + c from four
+# texels 16, coverage and 1/r^2 weight 10, accumulation 4)
+OPS_NODE, OPS_TRI, OPS_RAY, OPS_PHILOX, OPS_TAP = 38, 45, 150, 250, 30
+
+# measured HBM traffic per launch of a kernel: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE summaries under profiles/, valid only while the kernel source
+# they were taken on is unchanged
+TRAFFIC_FILES = {"pp_gather": "profiles/pp_gather_1080p_living_room_traffic.txt"}
+
+
+def traffic_for(stage):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel source has changed since."""
+    import hashlib
+    path = TRAFFIC_FILES.get(stage)
+    if path is None or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    kv = {}
+    for line in open(os.path.join(ROOT, path)):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("source", ""))
+    if not os.path.isfile(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+        return None
+    return int(float(kv["traffic_bytes_per_dispatch"]))
 
 
 def roofline_for(stage, ms, n_px, rays, per_ray):
@@ -276,7 +303,7 @@ def roofline_for(stage, ms, n_px, rays, per_ray):
         b = HBM_BYTES_PER_PX[stage] * n_px
         ach = b / sec / 1e9
         return {"kernel": stage, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(stage)}
     if stage == "pp_gather":
         ops = n_px * 48 * OPS_TAP
     elif stage == "gbuffer":
@@ -287,7 +314,7 @@ def roofline_for(stage, ms, n_px, rays, per_ray):
         ops = max(rays, 1) * (v * OPS_NODE + t * OPS_TRI + OPS_RAY + OPS_PHILOX)
     ach = ops / sec / 1e12
     return {"kernel": stage, "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "Tlane-op/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": None}
+            "unit": "Tlane-op/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic_for(stage)}
 
 
 def cpu_baseline(cfg, scene):
