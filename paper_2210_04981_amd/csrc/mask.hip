@@ -53,7 +53,10 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
   __shared__ int sr[MT][MT];
   const int W = k.W, H = k.H;
   const size_t N = (size_t)W * H;
-  const int x0 = blockIdx.x * MT, y0 = blockIdx.y * MT;
+  // blocks in XCD-contiguous order: the halo rows a block stages are mostly
+  // in the L2 of its own XCD already
+  const int BX = (W + MT - 1) / MT, lb = xcd_block(blockIdx.x, BX * ((H + MT - 1) / MT));
+  const int x0 = (lb % BX) * MT, y0 = (lb / BX) * MT;
   const int tid = threadIdx.x;
   // stage depth (clamped to zmax) and normal with clamp-to-edge
   for (int i = tid; i < NIN * NIN; i += 256) {
@@ -323,7 +326,7 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   int* rowsum = (int*)ctx->mask_rowsum.p;
   int* rowtot = rowsum + TH;
   {
-    const dim3 g(cdiv(W, MT), cdiv(H, MT)), b(256);
+    const dim3 g(cdiv(W, MT) * cdiv(H, MT)), b(256);
     float* r1 = (float*)ctx->rep_m1.p;
     float* r2 = (float*)ctx->rep_m2.p;
     uint8_t* rf = (uint8_t*)ctx->rep_flags.p;

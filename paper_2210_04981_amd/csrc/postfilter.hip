@@ -21,7 +21,8 @@ __global__ __launch_bounds__(256) void k_pp_pack(const float* __restrict__ color
                                                  float* __restrict__ tile_r) {
   __shared__ float red[256];
   const int tid = threadIdx.x;
-  const int x = blockIdx.x * 16 + (tid & 15), y = blockIdx.y * 16 + (tid >> 4);
+  const int BX = (k.W + 15) >> 4, lb = xcd_block(blockIdx.x, BX * ((k.H + 15) >> 4));
+  const int x = (lb % BX) * 16 + (tid & 15), y = (lb / BX) * 16 + (tid >> 4);
   const size_t N = (size_t)k.W * k.H;
   float r = 0.0f;
   if (x < k.W && y < k.H) {
@@ -331,14 +332,17 @@ __global__ void k_composite(const float* __restrict__ color, const float* __rest
   const float c = coc_px(l, depth[p]);
   const float phi = clamp01(fabsf(c) - HDOF_SQRT2);
   const float nu = clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
+  // the traced colours enter only where the pixel was traced, the filtered
+  // colour only outside the focus zone: other loads are skipped (the mask
+  // leaves most 64-pixel rows untraced, so their lines are never fetched)
   const bool traced = spp[p] > 0;
-  const float h = hr[p];
+  const float h = traced ? hr[p] : 0.0f;
   const float rho = traced ? 1.0f : 0.0f;
   const float beta = traced ? clamp01(1.0f - h * inv_ht) : 0.0f;
   for (int q = 0; q < 3; ++q) {
     size_t i = (size_t)q * N + p;
-    float crt = h * cn[i] + (1.0f - h) * cf[i];
-    float cpp = pp[i];
+    const float crt = traced ? h * cn[i] + (1.0f - h) * cf[i] : 0.0f;
+    const float cpp = phi > 0.0f ? pp[i] : 0.0f;
     float oof = nu * (rho * crt + (1.0f - rho) * cpp) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp);
     float o = (1.0f - phi) * color[i] + phi * oof;
     if (rt_override && traced) o = crt;
@@ -348,8 +352,8 @@ __global__ void k_composite(const float* __restrict__ color, const float* __rest
 
 // ---------------------------------------------------------------------------
 // Adjoint of post-filter + composite (differentiable form).
-// Reverse mode for the colour (the gather's transpose: every tap scatters
-// its share back to its four bilinear texels with atomics), forward mode for
+// Reverse mode for the colour (the gather's transpose: every tap's share goes
+// back to its four bilinear texels), forward mode for
 // the focus distance S1 and aperture A (each value carries its two
 // derivatives through the recomputed gather: no weights are stored).
 // ---------------------------------------------------------------------------
@@ -378,7 +382,8 @@ __global__ __launch_bounds__(256) void k_ppb_pack(const float* __restrict__ colo
   __shared__ float red[256];
   __shared__ int redi[256];
   const int tid = threadIdx.x;
-  const int x = blockIdx.x * 16 + (tid & 15), y = blockIdx.y * 16 + (tid >> 4);
+  const int BX = (k.W + 15) >> 4, lb = xcd_block(blockIdx.x, BX * ((k.H + 15) >> 4));
+  const int x = (lb % BX) * 16 + (tid & 15), y = (lb / BX) * 16 + (tid >> 4);
   const size_t N = (size_t)k.W * k.H;
   float r = -1.0f;
   int idx = 0x7fffffff;
@@ -729,7 +734,7 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
     hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
     ctx->pp_taps_n = pp.n_taps;
   }
-  hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
+  hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
                      (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
   hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p, TW,
                      TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
@@ -780,7 +785,7 @@ hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* 
   }
   int* tile_arg = (int*)ctx->ppb_args.p;
   int* rad_arg = tile_arg + (size_t)TW * TH;
-  hipLaunchKernelGGL(k_ppb_pack, grid, dim3(256), 0, st, color, depth, k, l, t, (float4*)ctx->pp_pack.p,
+  hipLaunchKernelGGL(k_ppb_pack, dim3(nblk), dim3(256), 0, st, color, depth, k, l, t, (float4*)ctx->pp_pack.p,
                      (float*)ctx->pp_tile.p, tile_arg);
   hipLaunchKernelGGL(k_ppb_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p,
                      (const int*)tile_arg, TW, TH, K, pp.r_cap, (float*)ctx->pp_rad.p, rad_arg);
