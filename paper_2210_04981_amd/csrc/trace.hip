@@ -210,6 +210,71 @@ __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* 
   return s.b;
 }
 
+// Wave-coherent traversal: the lanes of a wave walk one node sequence, the
+// union of their own paths (primary rays of a 16x4 pixel strip are
+// coherent).  Node records and leaf triangles are then wave-uniform loads,
+// served by the scalar data cache instead of 64 vector fetches per node;
+// the node stack is one VGPR holding entry i in lane i; a lane tests the
+// boxes of every node the wave enters against its own closest hit, and the
+// wave enters a child when any lane's ray reaches it.  Of two such
+// children the one more lanes reach first is entered first.  Each node is
+// entered at most once per wave, so more than n_nodes steps raises the
+// device flag and stops.
+template <bool COUNT>
+__device__ inline Best traverse_wave(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                     int n_nodes, const Ray& r, bool live, int* __restrict__ flags, Work& wk) {
+  Best b = Best{INFINITY, -1, 0x7fffffff};
+  const int lane = (int)(threadIdx.x & 63);
+  int stackv = 0;  // entry i in lane i
+  int sp = 0;
+  unsigned cur = 0;  // root (internal)
+  for (int steps = 0;; ++steps) {
+    if (steps > n_nodes) {
+      if (live) atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+      break;
+    }
+    if (COUNT && live) wk.visits++;
+    const float4* nd = nodes + 4 * (size_t)cur;
+    const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+    float t0 = 0.0f, t1 = 0.0f;
+    const bool h0 = live && box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0);
+    const bool h1 = live && box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1);
+    const unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
+    const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
+    const bool l0 = (c0 & HDOF_LEAF_BIT) != 0, l1 = (c1 & HDOF_LEAF_BIT) != 0;
+    if (l0 && m0 != 0ull && h0) {
+      test_leaf(r, tris, c0, b);
+      if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
+    }
+    if (l1 && m1 != 0ull && h1) {
+      test_leaf(r, tris, c1, b);
+      if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
+    }
+    const bool v0 = !l0 && m0 != 0ull, v1 = !l1 && m1 != 0ull;
+    if (v0 && v1) {
+      const int f0 = __popcll(__ballot(h0 && (!h1 || t0 <= t1)));
+      const int f1 = __popcll(__ballot(h1 && (!h0 || t1 < t0)));
+      const unsigned nearc = f0 >= f1 ? c0 : c1, farc = f0 >= f1 ? c1 : c0;
+      if (sp < 64) {
+        stackv = lane == sp ? (int)farc : stackv;
+        ++sp;
+      } else if (live) {
+        atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+      }
+      cur = nearc;
+    } else if (v0) {
+      cur = c0;
+    } else if (v1) {
+      cur = c1;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      cur = (unsigned)__builtin_amdgcn_readlane(stackv, sp);
+    }
+  }
+  return b;
+}
+
 // Two-sided Lambertian face normal + point light, no shadow ray.
 __device__ inline void shade(const float4* __restrict__ tris, const float* __restrict__ albedo,
                              const LightK& li, const Ray& r, const Best& b, V3& L, V3& n, V3& alb) {
@@ -241,17 +306,17 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
                                                  float* __restrict__ color, int* __restrict__ tri_id,
                                                  int* __restrict__ flags,
                                                  unsigned long long* __restrict__ counters) {
-  __shared__ int stk[HDOF_LDS_STACK * 256];
   const int bx_n = (k.W + 15) >> 4, by_n = (k.H + 15) >> 4;
   const int lb = xcd_block(blockIdx.x, bx_n * by_n);
   const int bx = lb % bx_n, by = lb / bx_n;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int x = bx * 16 + (lane & 15), y = by * 16 + wave * 4 + (lane >> 4);
-  if (x >= k.W || y >= k.H) return;
-  V3 v = pixel_dir(k, x, y);
+  const bool live = x < k.W && y < k.H;
+  V3 v = pixel_dir(k, live ? x : 0, live ? y : 0);
   Ray r = make_ray(k.e, V3{l.S1 * v.x, l.S1 * v.y, l.S1 * v.z});
   Work wk{0, 0};
-  Best b = traverse<256, COUNT>(nodes, tris, n_nodes, r, stk + t, flags, wk);
+  Best b = traverse_wave<COUNT>(nodes, tris, n_nodes, r, live, flags, wk);
+  if (!live) return;
   if (COUNT) {
     atomicAdd(&counters[0], 1ull);
     atomicAdd(&counters[1], (unsigned long long)wk.visits);
