@@ -163,7 +163,9 @@ def main():
     }
     if not args.no_forms:
         res["forms"] = {"batched": bench_batched(hdof, ctx, sc, ms_per_step),
-                        "backward": bench_backward(hdof, ctx, sc, cfg, keep, ms_per_step)}
+                        "backward": bench_backward(hdof, ctx, sc, cfg, keep, ms_per_step),
+                        "focus_fit": bench_focus_fit(hdof, ctx, sc, cfg, ms_per_step),
+                        "temporal": bench_temporal(hdof, ctx)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, scene)
     print(json.dumps(res), flush=True)
@@ -249,6 +251,137 @@ def bench_backward(hdof, ctx, sc, cfg, keep, plain_ms):
             "frames": 8, "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
             "backward_over_forward": round(bwd_ms / fwd_ms, 3),
             "backward_over_plain_frames": round(bwd_ms / (8 * plain_ms), 3)}
+
+
+def bench_focus_fit(hdof, ctx, sc, cfg, plain_ms, steps=200):
+    """Focus-distance fit through the differentiable post-filter + composite:
+    8 frames at 1080p along the temporal camera path (frames 0-7) on the
+    living room, f/1.4.  Target: full ray tracing (every pixel at 16 spp,
+    the mean of its lens rays) at S1 = 2 m.  S1 starts at 3 m; each Adam step
+    (lr 0.02) re-runs the hybrid frame at the current S1 without gradient,
+    then the post-filter + composite with gradient; loss = L2.
+
+    Two objectives: over all pixels, and over the pixels the mask leaves to
+    the post-filter only.  The traced pixels carry the Monte Carlo noise of
+    at most 8 lens samples against the target's 16, drawn afresh as S1
+    moves, and that noise outweighs the focus-dependent part of the loss;
+    the mask itself does not depend on S1 (edges of the G-buffer, no
+    history), so the second objective is a smooth function of S1."""
+    import torch
+    import scenegen as sg
+    stream = torch.cuda.current_stream()
+    H, W = cfg.camera.height, cfg.camera.width
+    f, A = cfg.lens.focal_length, cfg.lens.aperture
+    cams = [hdof.camera_of(sg.temporal_camera(t, W, H)) for t in range(8)]
+    light, params = hdof.light_of(cfg.light), hdof.frame_params_of(cfg)
+    pp, cp = hdof.pp_params_of(cfg.pp), hdof.composite_params_of(cfg.comp)
+    full = torch.full((H, W), 16, dtype=torch.uint8, device="cuda")
+    offs = (torch.arange(H * W, device="cuda", dtype=torch.int32) * 16).view(H, W)
+    tot = torch.tensor([16 * H * W], dtype=torch.int32, device="cuda")
+    targets = []
+    for t, cam in enumerate(cams):
+        lt = hdof.lens(f, A, 2.0)
+        hdof.hdof_gbuffer(ctx, sc, cam, lt, light, stream=stream)
+        rt = hdof.hdof_trace_thin_lens(ctx, sc, cam, lt, light, 16, full, offs, tot, seed=cfg.seed, frame=t,
+                                       stream=stream)
+        targets.append((rt.hit_ratio * rt.c_near + (1 - rt.hit_ratio) * rt.c_far).detach().clone())
+    keeps = [hdof.FrameKeep.empty(H, W) for _ in cams]
+    outs = [torch.empty(3, H, W, device="cuda") for _ in cams]
+    Ad = torch.tensor(float(A), device="cuda")
+
+    def loss_at(S1, untraced_only):
+        s_now = float(S1.detach())
+        loss = None
+        for t, cam in enumerate(cams):
+            hdof.hdof_frame(ctx, sc, cam, None, hdof.lens(f, A, s_now), light, params, seed=cfg.seed, frame=t,
+                            view=0, out=outs[t], keep=keeps[t], stream=stream)
+            k = keeps[t]
+            o = hdof.HybridDoFPost.apply(k.gb.color, S1, Ad, k.gb.depth, k.spp, k.rt, cam, f, pp, cp, ctx)
+            d2 = (o - targets[t]) ** 2
+            if untraced_only:
+                d2 = d2 * (k.spp == 0).to(d2.dtype)
+            term = d2.sum()
+            loss = term if loss is None else loss + term
+        return loss
+
+    def fit(untraced_only):
+        S1 = torch.tensor(3.0, device="cuda", requires_grad=True)
+        opt = torch.optim.Adam([S1], lr=0.02)
+        trail = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for step in range(steps):
+            opt.zero_grad()
+            s_now = float(S1.detach())
+            loss = loss_at(S1, untraced_only)
+            loss.backward()
+            opt.step()
+            if step % 25 == 0 or step == steps - 1:
+                trail.append([step, round(s_now, 4), round(float(loss.detach()), 2)])
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        with torch.no_grad():
+            at2 = float(loss_at(torch.tensor(2.0, device="cuda"), untraced_only))
+            at_fit = float(loss_at(S1.detach(), untraced_only))
+        return {"final_S1": round(float(S1.detach()), 4), "loss_at_final": round(at_fit, 2),
+                "loss_at_S1_2": round(at2, 2), "trail_step_S1_loss": trail,
+                "ms_per_step": round(sec * 1e3 / steps, 3),
+                "ms_per_step_over_plain_frames": round(sec * 1e3 / steps / (8 * plain_ms), 3)}
+
+    return {"workload": "8 frames 1920x1080 (temporal camera path 0-7, living room), f/1.4; target = full ray "
+                        "tracing at 16 spp and S1 = 2 m; Adam lr 0.02 from S1 = 3 m, 200 steps",
+            "all_pixels": fit(False), "post_filtered_pixels": fit(True)}
+
+
+def bench_temporal(hdof, ctx, frames=60):
+    """The temporal configuration: ~1M triangles, 1920x1080, 60 frames along
+    a dolly + yaw camera path with the variance history carried over, focus
+    1.5 m, f/1.4, 0-16 spp.  Steady state = mean over frames 10-59."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    stream = torch.cuda.current_stream()
+    scene = sg.temporal_scene(1)
+    cfg = sg.config_temporal()
+    H, W = cfg.camera.height, cfg.camera.width
+    verts = torch.from_numpy(scene.verts).cuda()
+    alb = torch.from_numpy(scene.albedo).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc = hdof.hdof_build_bvh(ctx, verts, alb)
+    torch.cuda.synchronize()
+    bvh_ms = (time.perf_counter() - t0) * 1e3
+    cams = [hdof.camera_of(sg.temporal_camera(t, W, H)) for t in range(frames)]
+    lens, light, params = hdof.lens_of(cfg.lens), hdof.light_of(cfg.light), hdof.frame_params_of(cfg)
+    keep = hdof.FrameKeep.empty(H, W)
+    out = torch.empty(3, H, W, device="cuda")
+    totals = torch.zeros(frames, dtype=torch.int32, device="cuda")
+
+    def run(record=None):
+        for t in range(frames):
+            if record:
+                record[t][0].record(stream)
+            hdof.hdof_frame(ctx, sc, cams[t], cams[t - 1] if t else None, lens, light, params, seed=cfg.seed,
+                            frame=t, view=0, out=out, keep=keep, stream=stream)
+            if record:
+                record[t][1].record(stream)
+            totals[t:t + 1].copy_(keep.total)
+    run()  # warm-up pass (allocations)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+    run(ev)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    rays = totals.cpu().numpy().astype(np.int64)
+    st = slice(10, frames)
+    stats = sc.stats()
+    sc.close()
+    return {"workload": f"{frames}-frame path (dolly 1 cm + yaw 0.2 deg per frame), 1920x1080, "
+                        f"{scene.n_tris} triangles, f/1.4, focus 1.5 m, 0-16 spp, variance history",
+            "bvh_build_ms_host_timed": round(bvh_ms, 2), "bvh": stats,
+            "steady_ms": round(float(ms[st].mean()), 4), "steady_p90_ms": round(float(np.quantile(ms[st], 0.9)), 4),
+            "frame0_ms": round(float(ms[0]), 4),
+            "steady_rays_per_frame": int(rays[st].mean()),
+            "steady_traced_mrays_per_s": round(float(rays[st].sum() / (ms[st].sum() * 1e-3) / 1e6), 1)}
 
 
 # algorithmic HBM bytes per pixel of the HBM-bound stages: what each stage
