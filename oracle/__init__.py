@@ -66,7 +66,8 @@ def lib():
         L.or_mask.argtypes = [i32, i32, P, P, P, f64, f64, f64, f64, i32, i32, i32,
                               P, P, P, P, P, P, P, P, P]
         L.or_trace.argtypes = [P, P, i32, i32, P, P, P, P, i64, P, u64, u64, u64,
-                               P, P, P, P, i64, P, P, P, P, P, P]
+                               P, P, P, P, i64, P, P, P, P, P, P, P]
+        L.or_recon.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, f64, P, P, P, P, P, P]
         L.or_var_reproject.argtypes = [P, i32, i32, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
         L.or_var_update.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P]
         L.or_pp_radius.argtypes = [i32, i32, P, f64, i32, P]
@@ -241,7 +242,8 @@ def trace(scene: Scene, camera, lens, light, spp, pix=None, seed=0, frame=0, vie
           per_ray: bool = True) -> dict:
     """Thin-lens distributed ray trace + per-pixel reduction (paper, Ray
     Trace).  `spp` is the per-pixel count (full image (H,W) when pix is None,
-    else one count per listed pixel)."""
+    else one count per listed pixel).  `far_pos` (4 planes): far-weighted
+    mean hit point of the rays that hit, and its weight."""
     cam, W, H = cam_args(camera)
     sp = _i32(spp).reshape(-1)
     pixa = None if pix is None else _i64(pix)
@@ -260,14 +262,16 @@ def trace(scene: Scene, camera, lens, light, spp, pix=None, seed=0, frame=0, vie
     m1 = np.zeros(n)
     m2 = np.zeros(n)
     pa = np.zeros(n, np.int32)
+    fp = np.zeros((4, n))
     lib().or_trace(scene.handle, _p(cam), W, H, _p(_f64(lens.as_floats())),
                    _p(_f64(light.as_floats())), _p(pixa), _p(sp), n,
                    _p(base) if per_ray else None, int(seed), int(frame), int(view),
                    _p(rid), _p(rz), _p(rL), _p(ra), nr,
-                   _p(cn), _p(cf), _p(h), _p(m1), _p(m2), _p(pa))
+                   _p(cn), _p(cf), _p(h), _p(m1), _p(m2), _p(pa), _p(fp))
     out = dict(c_near=cn, c_far=cf, hit_ratio=h, lum_m1=m1, lum_m2=m2, px_amb=pa,
-               ray_base=base, ray_id=rid, ray_z=rz, ray_L=rL, ray_amb=ra)
+               ray_base=base, ray_id=rid, ray_z=rz, ray_L=rL, ray_amb=ra, far_pos=fp)
     if pix is None:
+        out["far_pos"] = fp.reshape(4, H, W)
         for k in ("c_near", "c_far"):
             out[k] = out[k].reshape(3, H, W)
         for k in ("hit_ratio", "lum_m1", "lum_m2", "px_amb"):
@@ -375,6 +379,27 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
     out = composite(cam, lens, gb["color"], cpp, depth, spp, rt["c_near"], rt["c_far"],
                     rt["hit_ratio"], comp)
     return dict(gbuffer=gb, mask=mk, spp=spp, rt=rt, history=hist, reproj=rep, pp=cpp, out=out)
+
+
+def empty_recon_history(H: int, W: int) -> dict:
+    return dict(planes=np.zeros((8, H, W)), valid=np.zeros((H, W), np.int32), depth=np.zeros((H, W)))
+
+
+def recon(camera, depth, spp, prev_camera, hist: dict, hit, c_near, c_far, far_pos, alpha=0.2,
+          px_amb=None) -> dict:
+    """Temporal reconstruction of the near and far traced colours (paper,
+    Reconstruction): returns the reconstructed c_near, c_far, the new
+    history and the ambiguity flags.  `prev_camera` None: no history."""
+    cam, W, H = cam_args(camera)
+    pc = None if prev_camera is None else cam_args(prev_camera)[0]
+    cno, cfo = np.zeros((3, H, W)), np.zeros((3, H, W))
+    ho, vo, zo = np.zeros((8, H, W)), np.zeros((H, W), np.int32), np.zeros((H, W))
+    am = np.zeros((H, W), np.int32)
+    lib().or_recon(_p(cam), W, H, _p(_f64(depth)), _p(_i32(spp)), _p(pc), _p(_f64(hist["planes"])),
+                   _p(_i32(hist["valid"])), _p(_f64(hist["depth"])), _p(_f64(hit)), _p(_f64(c_near)),
+                   _p(_f64(c_far)), _p(_f64(far_pos)), _p(None if px_amb is None else _i32(px_amb)), float(alpha),
+                   _p(cno), _p(cfo), _p(ho), _p(vo), _p(zo), _p(am))
+    return dict(c_near=cno, c_far=cfo, history=dict(planes=ho, valid=vo, depth=zo), amb=am)
 
 
 def pp_composite_backward(camera, lens, color, depth, spp, c_near, c_far, hit, pp, cp, grad_out):

@@ -22,6 +22,9 @@
  *       or_mask, or_var_reproject, or_var_update
  *   Ray Trace (lens samples in a circle, near/far split by Z, hit ratio)
  *       or_trace
+ *   Reconstruction (temporal: EMA, near/far reprojection, hit-ratio
+ *   normalisation)
+ *       or_recon
  *   Design (post-process filter) + Reconstruction (CoC-radius rejection)
  *       or_postfilter
  *   Composite (focus zone below sqrt(2), near rule, far hit-ratio blend)
@@ -408,7 +411,7 @@ void or_cast_rays(const or_scene* s, int n, const double* O, const double* D, in
 }
 
 /* ------------------------------------------------------------------------- */
-/* Shading (our reading of "deferred shading"): two-sided Lambertian face      */
+/* Shading (our reading of the paper's deferred shading): two-sided Lambertian */
 /* normal, one point light with inverse-square falloff, ambient term, no      */
 /* shadow rays.  light[9] = position, rgb intensity, rgb ambient.             */
 /* ------------------------------------------------------------------------- */
@@ -610,12 +613,16 @@ int or_mask(int W, int H, const double* z, const double* nrm, const double* V,
 /*   h = sum w / s (hit ratio), lum_m1 = mean Y, lum_m2 = mean Y^2.           */
 /* Per-ray outputs (nullable) go to ray_base[i] + j; ray_base = exclusive      */
 /* prefix sum of spp over the list.  px_amb = any ray of the pixel ambiguous. */
+/* far_pos (nullable, 4 planes of n): over the rays that hit, the far-weighted */
+/* mean hit point sum (1-w) P / sum (1-w) (planes 0-2) and sum (1-w) (plane */
+/* 3); 0 when no ray hits with a far weight.                                  */
 /* ------------------------------------------------------------------------- */
 void or_trace(const or_scene* s, const double* cam, int W, int H, const double* lens, const double* light,
               const int64_t* pix, const int* spp, int64_t n, const int64_t* ray_base,
               uint64_t seed, uint64_t frame, uint64_t view,
               int* ray_id, double* ray_z, double* ray_L, int* ray_amb, int64_t n_rays,
-              double* c_near, double* c_far, double* hit, double* m1, double* m2, int* px_amb) {
+              double* c_near, double* c_far, double* hit, double* m1, double* m2, int* px_amb,
+              double* far_pos) {
   cam_t k = mk_cam(cam, W, H);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t i = 0; i < n; ++i) {
@@ -623,6 +630,7 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
     int x = (int)(p % W), y = (int)(p / W);
     int ns = spp[i];
     double Nw = 0.0, Fw = 0.0, sn[3] = {0, 0, 0}, sf[3] = {0, 0, 0}, sy = 0.0, sy2 = 0.0;
+    double Pw = 0.0, sP[3] = {0, 0, 0};
     int pa = 0;
     for (int j = 0; j < ns; ++j) {
       double O[3], D[3];
@@ -635,6 +643,10 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
       double w = clampd(0.5 - c / (2.0 * OR_SQRT2), 0.0, 1.0);
       Nw += w; Fw += 1.0 - w;
       for (int q = 0; q < 3; ++q) { sn[q] += w * L[q]; sf[q] += (1.0 - w) * L[q]; }
+      if (h.id >= 0) {
+        Pw += 1.0 - w;
+        for (int q = 0; q < 3; ++q) sP[q] += (1.0 - w) * (O[q] + h.t * D[q]);
+      }
       sy += Y; sy2 += Y * Y;
       pa |= h.amb;
       if (ray_base) {
@@ -655,6 +667,10 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
     m1[i] = ns > 0 ? sy / ns : 0.0;
     m2[i] = ns > 0 ? sy2 / ns : 0.0;
     if (px_amb) px_amb[i] = pa;
+    if (far_pos) {
+      for (int q = 0; q < 3; ++q) far_pos[(size_t)q * n + i] = Pw > 0.0 ? sP[q] / Pw : 0.0;
+      far_pos[(size_t)3 * n + i] = Pw;
+    }
   }
 }
 
@@ -733,6 +749,134 @@ void or_var_update(int W, int H, const int* spp, const double* rm1, const double
     }
     zh[p] = z[p];
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Temporal reconstruction of the near and far ray-traced colours (our        */
+/* reading of the paper's Reconstruction section: an exponential moving       */
+/* average like TAA, near pixels reprojected by their screen-space motion,    */
+/* far pixels through the average world position of their far hits with a    */
+/* neighbour fallback, colours composed with the latest hit ratio but         */
+/* normalised by the accumulated one).                                        */
+/* History per pixel: 8 planes N_r N_g N_b Hn F_r F_g F_b Hf (premultiplied   */
+/* near colour h C_tn and its accumulated hit ratio; premultiplied far colour */
+/* (1-h) C_tf and the hit ratio accumulated along the far path), a valid     */
+/* flag and the depth of the frame that wrote it.                            */
+/* For a traced pixel p with hit ratio h:                                     */
+/*   near: X = e + z v (the G-buffer surface), nearest previous pixel q_n;    */
+/*     usable if the previous camera exists, q_n is inside and valid and      */
+/*     |z_prev - z_expected| / z_expected <= 0.01.                            */
+/*   far: X_f = p's far-hit mean if its far weight > 0, else the plain mean   */
+/*     of the far-hit means of its 8 neighbours that have one; nearest        */
+/*     previous pixel q_f; usable if X_f exists, q_f is inside and valid.     */
+/*   N' = (1-a) N(q_n) + a h C_tn, Hn' = (1-a) Hn(q_n) + a h   (else h C_tn, h)*/
+/*   F' = (1-a) F(q_f) + a (1-h) C_tf, Hf' = (1-a) Hf(q_f) + a h              */
+/*                                              (else (1-h) C_tf, h)          */
+/*   out near = N'/Hn' (C_tn if Hn' = 0), out far = F'/(1-Hf') (C_tf if       */
+/*   Hf' = 1); the composite then mixes them with the latest h.               */
+/* Untraced pixels: colours unchanged, history invalid.  amb marks a rounded  */
+/* coordinate within OR_EPS of a pixel boundary, a depth ratio within OR_EPS  */
+/* of the bound, or an ambiguous ray (trace px_amb) in p or in the           */
+/* neighbours its far position comes from.                                    */
+/* ------------------------------------------------------------------------- */
+static int reproj_px(const cam_t* kp, int PW, int PH, const double* X, size_t* q, double* zc, int* am) {
+  double d[3];
+  v_sub(X, kp->e, d);
+  *zc = v_dot(d, kp->w);
+  if (!(*zc > 0.0)) return 0;
+  double sxp = v_dot(d, kp->r) / *zc, syp = v_dot(d, kp->u) / *zc;
+  double fx = (sxp / kp->tx + 1.0) * 0.5 * PW;
+  double fy = (1.0 - syp / kp->ty) * 0.5 * PH;
+  double px = floor(fx), py = floor(fy);
+  if (fx - px < OR_EPS * maxd(1.0, fabs(fx)) || px + 1.0 - fx < OR_EPS * maxd(1.0, fabs(fx))) *am = 1;
+  if (fy - py < OR_EPS * maxd(1.0, fabs(fy)) || py + 1.0 - fy < OR_EPS * maxd(1.0, fabs(fy))) *am = 1;
+  if (!(px >= 0 && px < PW && py >= 0 && py < PH)) return 0;
+  *q = (size_t)py * PW + (size_t)px;
+  return 1;
+}
+
+void or_recon(const double* cam, int W, int H, const double* z, const int* spp,
+              const double* pcam /* NULL: no history */, const double* hist, const int* hvalid, const double* hz,
+              const double* hit, const double* cn, const double* cf, const double* far_pos, const int* px_amb,
+              double alpha, double* cn_out, double* cf_out, double* hist_out, int* hvalid_out, double* hz_out,
+              int* amb) {
+  cam_t k = mk_cam(cam, W, H), kp;
+  if (pcam) kp = mk_cam(pcam, W, H);
+  size_t N = (size_t)W * H;
+#pragma omp parallel for
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x;
+      int am = 0;
+      hz_out[p] = z[p];
+      if (spp[p] <= 0) {
+        for (int c = 0; c < 3; ++c) { cn_out[c * N + p] = cn[c * N + p]; cf_out[c * N + p] = cf[c * N + p]; }
+        for (int c = 0; c < 8; ++c) hist_out[c * N + p] = 0.0;
+        hvalid_out[p] = 0;
+        if (amb) amb[p] = 0;
+        continue;
+      }
+      double h = hit[p];
+      if (px_amb && px_amb[p]) am = 1;
+      /* near path */
+      int okn = 0;
+      size_t qn = 0;
+      if (pcam) {
+        double v[3], X[3], zc;
+        pixel_dir(&k, x, y, v);
+        for (int a = 0; a < 3; ++a) X[a] = k.e[a] + z[p] * v[a];
+        if (reproj_px(&kp, W, H, X, &qn, &zc, &am) && hvalid[qn]) {
+          double rel = fabs(hz[qn] - zc) / zc;
+          if (fabs(rel - 0.01) < OR_EPS) am = 1;
+          okn = rel <= 0.01;
+        }
+      }
+      /* far path */
+      int okf = 0;
+      size_t qf = 0;
+      if (pcam) {
+        double Xf[3] = {0, 0, 0};
+        int have = 0;
+        if (far_pos[3 * N + p] > 0.0) {
+          for (int a = 0; a < 3; ++a) Xf[a] = far_pos[a * N + p];
+          have = 1;
+        } else {
+          int cnt = 0;
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              int xx = x + dx, yy = y + dy;
+              if ((dx == 0 && dy == 0) || xx < 0 || xx >= W || yy < 0 || yy >= H) continue;
+              size_t o = (size_t)yy * W + xx;
+              if (spp[o] > 0 && far_pos[3 * N + o] > 0.0) {
+                for (int a = 0; a < 3; ++a) Xf[a] += far_pos[a * N + o];
+                if (px_amb && px_amb[o]) am = 1;
+                ++cnt;
+              }
+            }
+          if (cnt > 0) { for (int a = 0; a < 3; ++a) Xf[a] /= cnt; have = 1; }
+        }
+        double zc;
+        if (have && reproj_px(&kp, W, H, Xf, &qf, &zc, &am) && hvalid[qf]) okf = 1;
+      }
+      double Np[3], Fp[3], Hn, Hf;
+      for (int c = 0; c < 3; ++c) {
+        Np[c] = okn ? (1.0 - alpha) * hist[c * N + qn] + alpha * h * cn[c * N + p] : h * cn[c * N + p];
+        Fp[c] = okf ? (1.0 - alpha) * hist[(4 + c) * N + qf] + alpha * (1.0 - h) * cf[c * N + p]
+                    : (1.0 - h) * cf[c * N + p];
+      }
+      Hn = okn ? (1.0 - alpha) * hist[3 * N + qn] + alpha * h : h;
+      Hf = okf ? (1.0 - alpha) * hist[7 * N + qf] + alpha * h : h;
+      for (int c = 0; c < 3; ++c) {
+        cn_out[c * N + p] = Hn > 0.0 ? Np[c] / Hn : cn[c * N + p];
+        cf_out[c * N + p] = 1.0 - Hf > 0.0 ? Fp[c] / (1.0 - Hf) : cf[c * N + p];
+        hist_out[c * N + p] = Np[c];
+        hist_out[(4 + c) * N + p] = Fp[c];
+      }
+      hist_out[3 * N + p] = Hn;
+      hist_out[7 * N + p] = Hf;
+      hvalid_out[p] = 1;
+      if (amb) amb[p] = am;
+    }
 }
 
 /* ------------------------------------------------------------------------- */
