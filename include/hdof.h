@@ -9,6 +9,8 @@
  *   temporally accumulated luminance variance (Ray Trace)    -> hdof_ray_mask
  *   thin-lens distributed ray tracing of the masked pixels,
  *   near/far split and hit ratio (Ray Trace)                 -> hdof_trace_thin_lens
+ *   temporal reconstruction of the near and far traced
+ *   colours (Reconstruction)                                 -> hdof_rt_reconstruct
  *   variance history update (Ray Trace)                      -> hdof_variance_update
  *   post-process gather filter (Design; rejection rule from
  *   Reconstruction)                                          -> hdof_postfilter
@@ -106,10 +108,19 @@ typedef struct {
   int32_t rt_override;
 } hdof_composite_params;
 
+/* Temporal reconstruction of the traced colours (paper, Reconstruction).
+ * enable in {0, 1}; alpha in (0, 1]: weight of the current frame in the
+ * exponential moving average. */
+typedef struct {
+  int32_t enable;
+  float alpha;
+} hdof_recon_params;
+
 typedef struct {
   hdof_mask_params mask;
   hdof_pp_params pp;
   hdof_composite_params comp;
+  hdof_recon_params recon;
 } hdof_frame_params;
 
 /* G-buffer planes: depth [H][W] (axial, 1e4 on a miss), normal [3][H][W]
@@ -216,13 +227,51 @@ hdof_status hdof_ray_mask(hdof_ctx* ctx, const hdof_gbuffer_bufs* in, const hdof
  * *d_total its sum (as hdof_ray_mask writes them); d_total stays on the
  * device.  Optional debug outputs per queue entry (index d_offsets[p] + j):
  * d_ray_tri_id (hit triangle, -1 on miss) and d_ray_depth (axial depth);
- * each needs W*H*spp_max entries. */
+ * each needs W*H*spp_max entries.  Optional d_far_pos [4][H][W]: over the
+ * pixel's rays that hit, the (1 - w)-weighted mean hit point (planes 0-2,
+ * world coordinates) and the weight sum (plane 3; 0: no far hit), the input
+ * of hdof_rt_reconstruct. */
 hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
                                  const hdof_lens* lens, const hdof_light* light, int32_t spp_max,
                                  const uint8_t* d_spp, const int32_t* d_offsets,
                                  const int32_t* d_total, uint32_t seed, uint32_t frame,
                                  uint32_t view, hdof_rt_bufs out, int32_t* d_ray_tri_id,
-                                 float* d_ray_depth, hdof_stream stream);
+                                 float* d_ray_depth, float* d_far_pos, hdof_stream stream);
+
+/* Temporal reconstruction of the near and far traced colours (paper,
+ * Reconstruction: exponential moving average as in TAA; near pixels
+ * reprojected by their screen-space motion, far pixels through the average
+ * world position of their far hits or of their neighbours'; colours
+ * normalised by the accumulated hit ratio, composed with the latest one by
+ * hdof_composite).  Per traced pixel (d_spp > 0) with hit ratio h:
+ *   near: the G-buffer point e + z v reprojected into `prev` (nearest pixel
+ *     q_n), usable when the history is valid there and its depth agrees
+ *     within 1 %; far: d_far_pos of the pixel when its weight is > 0, else
+ *     the mean of its 8 neighbours' that are, reprojected (nearest pixel
+ *     q_f), usable when the history is valid there.
+ *   N = (1-alpha) N(q_n) + alpha h C_tn,     Hn = (1-alpha) Hn(q_n) + alpha h
+ *   F = (1-alpha) F(q_f) + alpha (1-h) C_tf, Hf = (1-alpha) Hf(q_f) + alpha h
+ *   (restarted as h C_tn, h, (1-h) C_tf, h without usable history);
+ *   rt.c_near <- N / Hn, rt.c_far <- F / (1 - Hf) (unchanged when the
+ *   denominator is 0).  Untraced pixels keep their colours.
+ * The context's history (written by the previous call at the same size) is
+ * read when prev != NULL and replaced by this frame's.  rt.c_near and
+ * rt.c_far are updated in place; rt.hit_ratio is read.  params->enable is
+ * not consulted (the call always reconstructs). */
+hdof_status hdof_rt_reconstruct(hdof_ctx* ctx, const hdof_camera* cam, const hdof_camera* prev,
+                                const float* d_depth, const uint8_t* d_spp, const float* d_far_pos,
+                                hdof_rt_bufs rt, const hdof_recon_params* params, hdof_stream stream);
+
+/* Replace / read / clear the context's reconstruction history (width x
+ * height): d_planes [8][H][W] = premultiplied near rgb, near hit ratio,
+ * premultiplied far rgb, far-path hit ratio; d_valid [H][W] (1 = valid);
+ * d_depth [H][W] = the depth of the frame that wrote it.  Load/save enqueue
+ * copies on `stream`. */
+hdof_status hdof_recon_history_load(hdof_ctx* ctx, int32_t width, int32_t height, const float* d_planes,
+                                    const uint8_t* d_valid, const float* d_depth, hdof_stream stream);
+hdof_status hdof_recon_history_save(hdof_ctx* ctx, float* d_planes, uint8_t* d_valid, float* d_depth,
+                                    hdof_stream stream);
+hdof_status hdof_recon_history_reset(hdof_ctx* ctx);
 
 /* Variance history update (paper, Ray Trace: temporally accumulated variance).
  * Where traced: EMA with weight params->var_alpha over the reprojected
@@ -268,8 +317,11 @@ hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_p
                            const hdof_composite_params* params, float* d_out, hdof_stream stream);
 
 /* Whole frame: G-buffer -> mask (reprojecting the history when prev != NULL)
- * -> trace -> variance update -> post-process -> composite.  d_out
- * [3][H][W].  `keep` (nullable) supplies caller buffers for intermediates. */
+ * -> trace -> variance update -> temporal reconstruction of the traced
+ * colours (when params->recon.enable; its history is read when prev !=
+ * NULL) -> post-process -> composite.  d_out [3][H][W].  `keep` (nullable)
+ * supplies caller buffers for intermediates (keep->rt receives the
+ * reconstructed colours when reconstruction is on). */
 hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
                        const hdof_camera* prev, const hdof_lens* lens, const hdof_light* light,
                        const hdof_frame_params* params, uint32_t seed, uint32_t frame,
@@ -293,7 +345,9 @@ typedef struct {
   float* d_out;
 } hdof_view;
 
-/* Every view's G-buffer, mask, post-filter and composite (one launch each),
+/* The batched form rejects params->recon.enable = 1 (HDOF_ERR_UNSUPPORTED):
+ * a reconstruction history belongs to one view's camera path.
+ * Every view's G-buffer, mask, post-filter and composite (one launch each),
  * one device-side scan of the per-view ray totals, ONE queue over all views
  * and ONE persistent thin-lens trace launch for the whole batch.  No
  * variance history (each view is a first frame).  1 <= n_views <=
@@ -354,9 +408,10 @@ hdof_status hdof_postfilter_composite_backward(hdof_ctx* ctx, const float* d_col
 
 /* Stages hdof_frame brackets with HIP events while profiling is on, in
  * order: G-buffer, ray mask, queue build, thin-lens trace kernel, per-pixel
- * reduction, variance update, post-filter preparation (pack, tile radius,
- * taps), post-filter gather, composite. */
-#define HDOF_PROFILE_STAGES 9
+ * reduction, variance update, temporal reconstruction (0 when disabled),
+ * post-filter preparation (pack, tile radius, taps), post-filter gather,
+ * composite. */
+#define HDOF_PROFILE_STAGES 10
 
 /* Start recording stage events in every following hdof_frame call (events
  * are recorded on the frame's stream; the host is not synchronised). */

@@ -348,10 +348,12 @@ def composite(camera, lens, color, cpp, depth, spp, c_near, c_far, hit, cp):
 
 
 def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view=0,
-          rt_full_spp: int | None = None) -> dict:
+          rt_full_spp: int | None = None, recon_history=None) -> dict:
     """One frame of the hot path in the paper's stage order:
     G-buffer -> ray mask (with reprojected variance when a history is given)
-    -> thin-lens trace -> variance update -> post-process -> composite.
+    -> thin-lens trace -> variance update -> temporal reconstruction of the
+    traced colours (when cfg.recon.enable; its history is `recon_history`,
+    used when prev_camera is given) -> post-process -> composite.
     `rt_full_spp` forces a full mask of that many samples (full ray-traced
     reference: every pixel traced, composite overridden)."""
     cam, lens, light = cfg.camera, cfg.lens, cfg.light
@@ -371,6 +373,13 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
         rep = dict(lum_m1=np.zeros((H, W)), lum_m2=np.zeros((H, W)),
                    flags=np.zeros((H, W), np.int32))
     hist = var_update(spp, rep, rt["lum_m1"], rt["lum_m2"], cfg.mask.var_alpha, depth)
+    rc = None
+    rcfg = getattr(cfg, "recon", None)
+    if rcfg is not None and rcfg.enable:
+        rh = recon_history if recon_history is not None else empty_recon_history(H, W)
+        rc = recon(cam, depth, spp, prev_camera, rh, rt["hit_ratio"], rt["c_near"], rt["c_far"], rt["far_pos"],
+                   rcfg.alpha, rt["px_amb"])
+        rt = dict(rt, c_near=rc["c_near"], c_far=rc["c_far"])
     cpp = postfilter(cam, lens, gb["color"], depth, cfg.pp)
     comp = cfg.comp
     if rt_full_spp is not None:
@@ -378,7 +387,8 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
         comp = replace(comp, rt_override=1)
     out = composite(cam, lens, gb["color"], cpp, depth, spp, rt["c_near"], rt["c_far"],
                     rt["hit_ratio"], comp)
-    return dict(gbuffer=gb, mask=mk, spp=spp, rt=rt, history=hist, reproj=rep, pp=cpp, out=out)
+    return dict(gbuffer=gb, mask=mk, spp=spp, rt=rt, history=hist, reproj=rep, pp=cpp, out=out,
+                recon=rc)
 
 
 def empty_recon_history(H: int, W: int) -> dict:

@@ -117,6 +117,13 @@ static hdof_status check_comp(const hdof_composite_params* c) {
     if (s_ != HDOF_OK) return s_;     \
   } while (0)
 
+static hdof_status check_recon(const hdof_recon_params* r) {
+  REQUIRE(r, "recon params are NULL");
+  REQUIRE(r->enable == 0 || r->enable == 1, "recon enable must be 0 or 1");
+  REQUIRE(isfinite(r->alpha) && r->alpha > 0.0f && r->alpha <= 1.0f, "recon alpha must be in (0, 1]");
+  return HDOF_OK;
+}
+
 static hdof_status check_ctx(hdof_ctx* ctx) {
   REQUIRE(ctx, "context is NULL");
   hipError_t e = hipSetDevice(ctx->device);
@@ -326,7 +333,7 @@ extern "C" hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* sce
                                             const uint8_t* d_spp, const int32_t* d_offsets,
                                             const int32_t* d_total, uint32_t seed, uint32_t frame,
                                             uint32_t view, hdof_rt_bufs out, int32_t* d_ray_tri_id,
-                                            float* d_ray_depth, hdof_stream stream) {
+                                            float* d_ray_depth, float* d_far_pos, hdof_stream stream) {
   TRY(check_ctx(ctx));
   REQUIRE(scene, "scene is NULL");
   TRY(check_camera(cam, "current"));
@@ -338,7 +345,8 @@ extern "C" hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* sce
   TRY(check_rt(&out));
   CamK k = make_camk(cam);
   return launch_trace(ctx, scene, k, make_lensk(lens, k), make_lightk(light), spp_max, d_spp, d_offsets,
-                      d_total, seed, frame, view, out, d_ray_tri_id, d_ray_depth, (hipStream_t)stream);
+                      d_total, seed, frame, view, out, d_ray_tri_id, d_ray_depth, d_far_pos,
+                      (hipStream_t)stream);
 }
 
 extern "C" hdof_status hdof_variance_update(hdof_ctx* ctx, const hdof_camera* cam,
@@ -398,6 +406,66 @@ extern "C" hdof_status hdof_history_reset(hdof_ctx* ctx) {
   return HDOF_OK;
 }
 
+extern "C" hdof_status hdof_rt_reconstruct(hdof_ctx* ctx, const hdof_camera* cam, const hdof_camera* prev,
+                                           const float* d_depth, const uint8_t* d_spp, const float* d_far_pos,
+                                           hdof_rt_bufs rt, const hdof_recon_params* params, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_camera(cam, "current"));
+  if (prev) TRY(check_camera(prev, "previous"));
+  REQUIRE(d_depth && d_spp && d_far_pos, "depth, spp and far_pos must be non-NULL");
+  REQUIRE(rt.c_near && rt.c_far && rt.hit_ratio, "rt c_near, c_far and hit_ratio must be non-NULL");
+  TRY(check_recon(params));
+  CamK k = make_camk(cam), pk;
+  if (prev) pk = make_camk(prev);
+  return launch_recon(ctx, k, prev ? &pk : nullptr, d_depth, d_spp, d_far_pos, rt, params->alpha,
+                      (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_recon_history_load(hdof_ctx* ctx, int32_t width, int32_t height, const float* d_planes,
+                                               const uint8_t* d_valid, const float* d_depth, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(width > 0 && height > 0 && width <= 16384 && height <= 16384, "history size out of range");
+  REQUIRE(d_planes && d_valid && d_depth, "history planes must be non-NULL");
+  const size_t N = (size_t)width * height;
+  hipStream_t st = (hipStream_t)stream;
+  for (int i = 0; i < 2; ++i) {
+    TRY(hdof_ensure(ctx->rec_hist[i], sizeof(float) * 9 * N));
+    TRY(hdof_ensure(ctx->rec_valid[i], N));
+  }
+  const int cur = ctx->rec_cur;
+  HDOF_HIP(hipMemcpyAsync(ctx->rec_hist[cur].p, d_planes, sizeof(float) * 8 * N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync((float*)ctx->rec_hist[cur].p + 8 * N, d_depth, sizeof(float) * N, hipMemcpyDeviceToDevice,
+                          st));
+  HDOF_HIP(hipMemcpyAsync(ctx->rec_valid[cur].p, d_valid, N, hipMemcpyDeviceToDevice, st));
+  ctx->rec_w = width;
+  ctx->rec_h = height;
+  ctx->rec_any = true;
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_recon_history_save(hdof_ctx* ctx, float* d_planes, uint8_t* d_valid, float* d_depth,
+                                               hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(ctx->rec_any, "the context holds no reconstruction history");
+  REQUIRE(d_planes && d_valid && d_depth, "history planes must be non-NULL");
+  const size_t N = (size_t)ctx->rec_w * ctx->rec_h;
+  const int cur = ctx->rec_cur;
+  hipStream_t st = (hipStream_t)stream;
+  HDOF_HIP(hipMemcpyAsync(d_planes, ctx->rec_hist[cur].p, sizeof(float) * 8 * N, hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(d_depth, (const float*)ctx->rec_hist[cur].p + 8 * N, sizeof(float) * N,
+                          hipMemcpyDeviceToDevice, st));
+  HDOF_HIP(hipMemcpyAsync(d_valid, ctx->rec_valid[cur].p, N, hipMemcpyDeviceToDevice, st));
+  return HDOF_OK;
+}
+
+extern "C" hdof_status hdof_recon_history_reset(hdof_ctx* ctx) {
+  TRY(check_ctx(ctx));
+  HDOF_HIP(hipDeviceSynchronize());
+  ctx->rec_any = false;
+  ctx->rec_w = ctx->rec_h = 0;
+  return HDOF_OK;
+}
+
 extern "C" hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, const float* d_depth,
                                        const hdof_camera* cam, const hdof_lens* lens,
                                        const hdof_pp_params* params, float* d_out, hdof_stream stream) {
@@ -451,6 +519,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(check_mask(&params->mask));
   TRY(check_pp(&params->pp));
   TRY(check_comp(&params->comp));
+  TRY(check_recon(&params->recon));
   TRY(check_capacity(cam, params->mask.spp_max));
   REQUIRE(d_out, "out is NULL");
   hdof_frame_bufs z;
@@ -488,6 +557,15 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(hdof_ensure(ctx->queue, sizeof(int) * cap));
   TRY(hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap));
   TRY(hdof_ensure(ctx->ray_z, sizeof(float) * cap));
+  float* far_pos = nullptr;
+  if (params->recon.enable) {
+    TRY(hdof_ensure(ctx->rec_farpos, sizeof(float) * 4 * N));
+    far_pos = (float*)ctx->rec_farpos.p;
+    for (int i = 0; i < 2; ++i) {
+      TRY(hdof_ensure(ctx->rec_hist[i], sizeof(float) * 9 * N));
+      TRY(hdof_ensure(ctx->rec_valid[i], N));
+    }
+  }
   ctx->prof_in_frame = true;
   hdof_prof_mark(ctx, 0, st);
   hdof_status s = launch_gbuffer(ctx, scene, k, l, li, gb, st);
@@ -497,13 +575,16 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   hdof_prof_mark(ctx, 2, st);
   if (s == HDOF_OK)
     s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt,
-                     nullptr, nullptr, st);  // marks 3, 4, 5
+                     nullptr, nullptr, far_pos, st);  // marks 3, 4, 5
   if (s == HDOF_OK) s = launch_var_update(ctx, k, params->mask.var_alpha, spp, gb.depth, rt.lum_m1, rt.lum_m2, st);
   hdof_prof_mark(ctx, 6, st);
-  if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st);  // mark 7
-  hdof_prof_mark(ctx, 8, st);
-  if (s == HDOF_OK) s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st);
+  if (s == HDOF_OK && params->recon.enable)
+    s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt, params->recon.alpha, st);
+  hdof_prof_mark(ctx, 7, st);
+  if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st);  // mark 8
   hdof_prof_mark(ctx, 9, st);
+  if (s == HDOF_OK) s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st);
+  hdof_prof_mark(ctx, 10, st);
   ctx->prof_in_frame = false;
   if (s == HDOF_OK && ctx->prof_on) ctx->prof_frames++;
   return s;
@@ -616,6 +697,10 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
   TRY(check_mask(&params->mask));
   TRY(check_pp(&params->pp));
   TRY(check_comp(&params->comp));
+  TRY(check_recon(&params->recon));
+  if (params->recon.enable)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "temporal reconstruction needs one history per view: "
+                          "not available in the batched form");
   REQUIRE(n_views >= 1 && n_views <= HDOF_MAX_VIEWS, "n_views must be in [1, %d]", HDOF_MAX_VIEWS);
   REQUIRE(views, "views is NULL");
   L.n = n_views;

@@ -73,6 +73,12 @@ struct hdof_ctx {
   int rep_w = 0, rep_h = 0;
   bool rep_valid = false;
   Buf rep_m1, rep_m2, rep_flags;
+  // temporal reconstruction of the traced colours: ping-pong history of
+  // 9 planes (premultiplied near rgb, near hit ratio, premultiplied far rgb,
+  // far-path hit ratio, depth) + valid bytes, and the frame's far positions
+  int rec_w = 0, rec_h = 0, rec_cur = 0;
+  bool rec_any = false;
+  Buf rec_hist[2], rec_valid[2], rec_farpos;
   // frame intermediates when the caller keeps none
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
@@ -252,7 +258,9 @@ void batch_view_pack(const BatchView* hv, int n, void* out);
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
-                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, hipStream_t st);
+                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st);
+hdof_status launch_recon(hdof_ctx* ctx, const CamK& k, const CamK* prev, const float* depth, const uint8_t* spp,
+                         const float* far_pos, hdof_rt_bufs rt, float alpha, hipStream_t st);
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
                         int32_t* total, hipStream_t st);

@@ -738,7 +738,7 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
                      (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
   hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p, TW,
                      TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
-  hdof_prof_mark(ctx, 7, st);
+  hdof_prof_mark(ctx, 8, st);
   if (t == 16)
     hipLaunchKernelGGL(k_pp_gather16, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                        (const float*)ctx->pp_rad.p, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,

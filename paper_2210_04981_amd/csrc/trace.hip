@@ -512,24 +512,40 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(TraceArgs A) {
 
 // per-pixel near/far split, hit ratio and luminance moments, fixed order;
 // batched: *ebase is the view's first queue entry
+// FARPOS: also the far-weighted mean hit point of the pixel's rays that hit
+// (their rays regenerated from the same counters; t = z / S1 since the
+// direction's forward component is S1) and its weight, 4 planes.
+template <bool FARPOS>
 __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
                             const int* __restrict__ ebase, const float* __restrict__ ray_col,
                             const float* __restrict__ ray_z, size_t cap, LensK l, float* __restrict__ cn,
                             float* __restrict__ cf, float* __restrict__ h, float* __restrict__ m1,
-                            float* __restrict__ m2) {
+                            float* __restrict__ m2, CamK k, uint32_t seed, uint32_t frame, uint32_t view,
+                            float* __restrict__ far_pos) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   int s = spp[p];
   float Nw = 0.f, Fw = 0.f, snr = 0.f, sng = 0.f, snb = 0.f, sfr = 0.f, sfg = 0.f, sfb = 0.f, sy = 0.f, sy2 = 0.f;
+  float Pw = 0.f, spx_ = 0.f, spy_ = 0.f, spz_ = 0.f;
   long o = (long)offsets[p] + (ebase ? *ebase : 0);
   if (o < 0 || o + s > (long)cap) s = 0;  // inconsistent offsets: nothing was traced here
   if (s > 0) {
     for (int j = 0; j < s; ++j) {
       long e = o + j;
       float R = ray_col[e], G = ray_col[cap + e], B = ray_col[2 * cap + e];
-      float c = coc_px(l, ray_z[e]);
+      const float zj = ray_z[e];
+      float c = coc_px(l, zj);
       float w = clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
       float wf = 1.0f - w;
+      if (FARPOS && zj < HDOF_ZMAX) {
+        V3 O, D;
+        lens_ray(k, l, p % k.W, p / k.W, (uint32_t)j, view, seed, frame, O, D);
+        const float t = zj * l.invS1;
+        Pw += wf;
+        spx_ = fmaf(wf, fmaf(t, D.x, O.x), spx_);
+        spy_ = fmaf(wf, fmaf(t, D.y, O.y), spy_);
+        spz_ = fmaf(wf, fmaf(t, D.z, O.z), spz_);
+      }
       Nw += w;
       Fw += wf;
       snr = fmaf(w, R, snr);
@@ -554,6 +570,13 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   h[p] = Nw * is;
   m1[p] = sy * is;
   m2[p] = sy2 * is;
+  if (FARPOS) {
+    const float ip = Pw > 0.f ? 1.0f / Pw : 0.f;
+    far_pos[p] = spx_ * ip;
+    far_pos[N + p] = spy_ * ip;
+    far_pos[2 * (size_t)N + p] = spz_ * ip;
+    far_pos[3 * (size_t)N + p] = Pw;
+  }
 }
 
 // batch: first queue entry of each view and the batch total
@@ -626,7 +649,7 @@ hdof_status reserve_trace(hdof_ctx* ctx, size_t cap, bool own_depth) {
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
-                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, hipStream_t st) {
+                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st) {
   const int N = k.W * k.H;
   const size_t cap = (size_t)N * (size_t)spp_max;
   hdof_status s;
@@ -643,9 +666,14 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
   A.v0 = ViewK{k, l, seed, frame, view, 0};
   launch_trace_kernel<false>(ctx, A, st);
   hdof_prof_mark(ctx, 4, st);
-  hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr,
-                     (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near, out.c_far,
-                     out.hit_ratio, out.lum_m1, out.lum_m2);
+  if (far_pos)
+    hipLaunchKernelGGL(k_rt_reduce<true>, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
+                       (const int*)nullptr, (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near,
+                       out.c_far, out.hit_ratio, out.lum_m1, out.lum_m2, k, seed, frame, view, far_pos);
+  else
+    hipLaunchKernelGGL(k_rt_reduce<false>, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
+                       (const int*)nullptr, (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near,
+                       out.c_far, out.hit_ratio, out.lum_m1, out.lum_m2, k, seed, frame, view, (float*)nullptr);
   hdof_prof_mark(ctx, 5, st);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
@@ -683,9 +711,10 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
   launch_trace_kernel<true>(ctx, A, st);
   for (int v = 0; v < n_views; ++v) {
     const int N = hviews[v].k.W * hviews[v].k.H, pb = hviews[v].px_base;
-    hipLaunchKernelGGL(k_rt_reduce, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb, N,
+    hipLaunchKernelGGL(k_rt_reduce<false>, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb, N,
                        (const int*)(ebase + v), (const float*)ctx->ray_col.p, (const float*)ctx->ray_z.p, cap,
-                       hviews[v].l, rt[v].c_near, rt[v].c_far, rt[v].hit_ratio, rt[v].lum_m1, rt[v].lum_m2);
+                       hviews[v].l, rt[v].c_near, rt[v].c_far, rt[v].hit_ratio, rt[v].lum_m1, rt[v].lum_m2,
+                       hviews[v].k, 0u, 0u, 0u, (float*)nullptr);
   }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;

@@ -58,8 +58,12 @@ class CompositeParams(C.Structure):
     _fields_ = [("h_t", C.c_float), ("rt_override", C.c_int32)]
 
 
+class ReconParams(C.Structure):
+    _fields_ = [("enable", C.c_int32), ("alpha", C.c_float)]
+
+
 class FrameParams(C.Structure):
-    _fields_ = [("mask", MaskParams), ("pp", PPParams), ("comp", CompositeParams)]
+    _fields_ = [("mask", MaskParams), ("pp", PPParams), ("comp", CompositeParams), ("recon", ReconParams)]
 
 
 P = C.c_void_p
@@ -110,7 +114,12 @@ _PROTOS = {
     "hdof_ray_mask": (_S, [P, C.POINTER(GBufferBufs), C.POINTER(Camera), C.POINTER(Camera),
                            C.POINTER(Lens), C.POINTER(MaskParams), P, P, P, P]),
     "hdof_trace_thin_lens": (_S, [P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(Light), _i32,
-                                  P, P, P, _u32, _u32, _u32, RTBufs, P, P, P]),
+                                  P, P, P, _u32, _u32, _u32, RTBufs, P, P, P, P]),
+    "hdof_rt_reconstruct": (_S, [P, C.POINTER(Camera), C.POINTER(Camera), P, P, P, RTBufs,
+                                 C.POINTER(ReconParams), P]),
+    "hdof_recon_history_load": (_S, [P, _i32, _i32, P, P, P, P]),
+    "hdof_recon_history_save": (_S, [P, P, P, P, P]),
+    "hdof_recon_history_reset": (_S, [P]),
     "hdof_variance_update": (_S, [P, C.POINTER(Camera), C.POINTER(MaskParams), P, P, P, P, P]),
     "hdof_history_load": (_S, [P, _i32, _i32, P, P, P, P, P]),
     "hdof_history_save": (_S, [P, P, P, P, P, P]),
@@ -135,7 +144,7 @@ _PROTOS = {
     "hdof_counters_end": (_S, [P, C.POINTER(C.c_int64)]),
 }
 
-PROFILE_STAGES = ("gbuffer", "ray_mask", "queue_fill", "trace", "rt_reduce", "var_update", "pp_prep",
+PROFILE_STAGES = ("gbuffer", "ray_mask", "queue_fill", "trace", "rt_reduce", "var_update", "recon", "pp_prep",
                   "pp_gather", "composite")
 for _name, (_res, _args) in _PROTOS.items():
     _f = getattr(_lib, _name)
@@ -356,7 +365,8 @@ def hdof_ray_mask(ctx: Context, depth: torch.Tensor, normal: torch.Tensor, cam: 
 def hdof_trace_thin_lens(ctx: Context, scene: Scene, cam: Camera, lns: Lens, lit: Light, spp_max: int,
                          spp: torch.Tensor, offsets: torch.Tensor, total: torch.Tensor, seed=0, frame=0, view=0,
                          out: RTResult | None = None, ray_tri_id: torch.Tensor | None = None,
-                         ray_depth: torch.Tensor | None = None, stream=None) -> RTResult:
+                         ray_depth: torch.Tensor | None = None, far_pos: torch.Tensor | None = None,
+                         stream=None) -> RTResult:
     n = _npx(cam)
     out = RTResult.empty(cam.height, cam.width) if out is None else out
     cap = n * int(spp_max)
@@ -365,9 +375,42 @@ def hdof_trace_thin_lens(ctx: Context, scene: Scene, cam: Camera, lns: Lens, lit
                                      _ptr(offsets, torch.int32, n, "offsets"), _ptr(total, torch.int32, 1, "total"),
                                      int(seed), int(frame), int(view), out.bufs(n),
                                      _ptr(ray_tri_id, torch.int32, cap, "ray_tri_id"),
-                                     _ptr(ray_depth, torch.float32, cap, "ray_depth"), _stream(stream)),
+                                     _ptr(ray_depth, torch.float32, cap, "ray_depth"),
+                                     _ptr(far_pos, torch.float32, 4 * n, "far_pos"), _stream(stream)),
            "hdof_trace_thin_lens")
     return out
+
+
+def hdof_rt_reconstruct(ctx: Context, cam: Camera, prev: Camera | None, depth, spp, far_pos, rt: RTResult,
+                        rp: "ReconParams", stream=None) -> RTResult:
+    """Temporal reconstruction: rt.c_near and rt.c_far are updated in place."""
+    n = _npx(cam)
+    _check(_lib.hdof_rt_reconstruct(ctx.handle, C.byref(cam), C.byref(prev) if prev is not None else None,
+                                    _ptr(depth, torch.float32, n, "depth"), _ptr(spp, torch.uint8, n, "spp"),
+                                    _ptr(far_pos, torch.float32, 4 * n, "far_pos"), rt.bufs(n), C.byref(rp),
+                                    _stream(stream)), "hdof_rt_reconstruct")
+    return rt
+
+
+def hdof_recon_history_load(ctx: Context, planes, valid, depth, stream=None):
+    H, W = depth.shape
+    n = H * W
+    _check(_lib.hdof_recon_history_load(ctx.handle, W, H, _ptr(planes, torch.float32, 8 * n, "planes"),
+                                        _ptr(valid, torch.uint8, n, "valid"), _ptr(depth, torch.float32, n, "depth"),
+                                        _stream(stream)), "hdof_recon_history_load")
+
+
+def hdof_recon_history_save(ctx: Context, H: int, W: int, stream=None) -> dict:
+    out = dict(planes=torch.empty(8, H, W, dtype=torch.float32, device="cuda"),
+               valid=torch.empty(H, W, dtype=torch.uint8, device="cuda"),
+               depth=torch.empty(H, W, dtype=torch.float32, device="cuda"))
+    _check(_lib.hdof_recon_history_save(ctx.handle, out["planes"].data_ptr(), out["valid"].data_ptr(),
+                                        out["depth"].data_ptr(), _stream(stream)), "hdof_recon_history_save")
+    return out
+
+
+def hdof_recon_history_reset(ctx: Context):
+    _check(_lib.hdof_recon_history_reset(ctx.handle), "hdof_recon_history_reset")
 
 
 def hdof_variance_update(ctx: Context, cam: Camera, mp: MaskParams, spp, depth, lum_m1, lum_m2, stream=None):
@@ -493,8 +536,14 @@ def composite_params_of(c) -> CompositeParams:
     return composite_params(c.h_t, c.rt_override)
 
 
+def recon_params_of(r) -> ReconParams:
+    return ReconParams(int(bool(r.enable)), float(r.alpha))
+
+
 def frame_params_of(cfg) -> FrameParams:
-    return FrameParams(mask_params_of(cfg.mask), pp_params_of(cfg.pp), composite_params_of(cfg.comp))
+    rc = getattr(cfg, "recon", None)
+    return FrameParams(mask_params_of(cfg.mask), pp_params_of(cfg.pp), composite_params_of(cfg.comp),
+                       recon_params_of(rc) if rc is not None else ReconParams(0, 0.2))
 
 
 def hdof_profile_begin(ctx: Context) -> None:

@@ -98,6 +98,12 @@ class CompositeParams:
 
 
 @dataclass
+class ReconParams:
+    enable: bool = False
+    alpha: float = 0.2
+
+
+@dataclass
 class FrameConfig:
     """Everything one frame of the path needs besides the scene."""
     name: str
@@ -108,6 +114,7 @@ class FrameConfig:
     pp: PPParams
     comp: CompositeParams
     seed: int = 0
+    recon: ReconParams = field(default_factory=ReconParams)
 
 
 # ----------------------------------------------------------------------------
