@@ -336,7 +336,8 @@ def bench_focus_fit(hdof, ctx, sc, cfg, plain_ms, steps=200):
 def bench_temporal(hdof, ctx, frames=60):
     """The temporal configuration: ~1M triangles, 1920x1080, 60 frames along
     a dolly + yaw camera path with the variance history carried over, focus
-    1.5 m, f/1.4, 0-16 spp.  Steady state = mean over frames 10-59."""
+    1.5 m, f/1.4, 0-16 spp.  Steady state = mean over frames 10-59.  Run
+    without and with the temporal reconstruction of the traced colours."""
     import numpy as np
     import torch
     import scenegen as sg
@@ -352,7 +353,8 @@ def bench_temporal(hdof, ctx, frames=60):
     torch.cuda.synchronize()
     bvh_ms = (time.perf_counter() - t0) * 1e3
     cams = [hdof.camera_of(sg.temporal_camera(t, W, H)) for t in range(frames)]
-    lens, light, params = hdof.lens_of(cfg.lens), hdof.light_of(cfg.light), hdof.frame_params_of(cfg)
+    lens, light = hdof.lens_of(cfg.lens), hdof.light_of(cfg.light)
+    params = hdof.frame_params_of(cfg)
     keep = hdof.FrameKeep.empty(H, W)
     out = torch.empty(3, H, W, device="cuda")
     totals = torch.zeros(frames, dtype=torch.int32, device="cuda")
@@ -366,22 +368,37 @@ def bench_temporal(hdof, ctx, frames=60):
             if record:
                 record[t][1].record(stream)
             totals[t:t + 1].copy_(keep.total)
-    run()  # warm-up pass (allocations)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
-    run(ev)
-    torch.cuda.synchronize()
-    ms = np.array([a.elapsed_time(b) for a, b in ev])
-    rays = totals.cpu().numpy().astype(np.int64)
     st = slice(10, frames)
-    stats = sc.stats()
+    res = {"workload": f"{frames}-frame path (dolly 1 cm + yaw 0.2 deg per frame), 1920x1080, "
+                       f"{scene.n_tris} triangles, f/1.4, focus 1.5 m, 0-16 spp, variance history",
+           "bvh_build_ms_host_timed": round(bvh_ms, 2), "bvh": sc.stats()}
+    for name, recon in (("plain", 0), ("reconstructed", 1)):
+        params.recon.enable, params.recon.alpha = recon, 0.2
+        hdof.hdof_history_reset(ctx)
+        hdof.hdof_recon_history_reset(ctx)
+        run()  # warm-up pass (allocations)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+        run(ev)
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        rays = totals.cpu().numpy().astype(np.int64)
+        res[name] = {"steady_ms": round(float(ms[st].mean()), 4),
+                     "steady_p90_ms": round(float(np.quantile(ms[st], 0.9)), 4),
+                     "frame0_ms": round(float(ms[0]), 4),
+                     "steady_rays_per_frame": int(rays[st].mean()),
+                     "steady_traced_mrays_per_s": round(float(rays[st].sum() / (ms[st].sum() * 1e-3) / 1e6), 1)}
+    # per-stage split of the reconstructed run (profiled over frames 10-59 of a third pass)
+    hdof.hdof_history_reset(ctx)
+    hdof.hdof_recon_history_reset(ctx)
+    for t in range(frames):
+        if t == 10:
+            hdof.hdof_profile_begin(ctx)
+        hdof.hdof_frame(ctx, sc, cams[t], cams[t - 1] if t else None, lens, light, params, seed=cfg.seed,
+                        frame=t, view=0, out=out, keep=keep, stream=stream)
+    stage, nf = hdof.hdof_profile_end(ctx)
+    res["reconstructed"]["stage_ms"] = {k: round(v, 4) for k, v in stage.items()}
     sc.close()
-    return {"workload": f"{frames}-frame path (dolly 1 cm + yaw 0.2 deg per frame), 1920x1080, "
-                        f"{scene.n_tris} triangles, f/1.4, focus 1.5 m, 0-16 spp, variance history",
-            "bvh_build_ms_host_timed": round(bvh_ms, 2), "bvh": stats,
-            "steady_ms": round(float(ms[st].mean()), 4), "steady_p90_ms": round(float(np.quantile(ms[st], 0.9)), 4),
-            "frame0_ms": round(float(ms[0]), 4),
-            "steady_rays_per_frame": int(rays[st].mean()),
-            "steady_traced_mrays_per_s": round(float(rays[st].sum() / (ms[st].sum() * 1e-3) / 1e6), 1)}
+    return res
 
 
 # algorithmic HBM bytes per pixel of the HBM-bound stages: what each stage
