@@ -217,9 +217,9 @@ __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* 
 // the node stack is one VGPR holding entry i in lane i; a lane tests the
 // boxes of every node the wave enters against its own closest hit, and the
 // wave enters a child when any lane's ray reaches it.  Of two such
-// children the one more lanes reach first is entered first.  Each node is
-// entered at most once per wave, so more than n_nodes steps raises the
-// device flag and stops.
+// children the one the wave's first lane reaches first is entered first.
+// Each node is entered at most once per wave, so more than n_nodes steps
+// raises the device flag and stops.
 template <bool COUNT>
 __device__ inline Best traverse_wave(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                      int n_nodes, const Ray& r, bool live, int* __restrict__ flags, Work& wk) {
@@ -236,25 +236,28 @@ __device__ inline Best traverse_wave(const float4* __restrict__ nodes, const flo
     if (COUNT && live) wk.visits++;
     const float4* nd = nodes + 4 * (size_t)cur;
     const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-    float t0 = 0.0f, t1 = 0.0f;
-    const bool h0 = live && box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0);
-    const bool h1 = live && box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1);
+    float t0, t1;
+    const bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0) & live;
+    const bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1) & live;
     const unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
     const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
     const bool l0 = (c0 & HDOF_LEAF_BIT) != 0, l1 = (c1 & HDOF_LEAF_BIT) != 0;
-    if (l0 && m0 != 0ull && h0) {
-      test_leaf(r, tris, c0, b);
-      if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
+    if (l0 && m0 != 0ull) {
+      if (h0) {
+        test_leaf(r, tris, c0, b);
+        if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
+      }
     }
-    if (l1 && m1 != 0ull && h1) {
-      test_leaf(r, tris, c1, b);
-      if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
+    if (l1 && m1 != 0ull) {
+      if (h1) {
+        test_leaf(r, tris, c1, b);
+        if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
+      }
     }
     const bool v0 = !l0 && m0 != 0ull, v1 = !l1 && m1 != 0ull;
     if (v0 && v1) {
-      const int f0 = __popcll(__ballot(h0 && (!h1 || t0 <= t1)));
-      const int f1 = __popcll(__ballot(h1 && (!h0 || t1 < t0)));
-      const unsigned nearc = f0 >= f1 ? c0 : c1, farc = f0 >= f1 ? c1 : c0;
+      const bool first0 = __builtin_amdgcn_readfirstlane((int)(t0 <= t1)) != 0;
+      const unsigned nearc = first0 ? c0 : c1, farc = first0 ? c1 : c0;
       if (sp < 64) {
         stackv = lane == sp ? (int)farc : stackv;
         ++sp;
