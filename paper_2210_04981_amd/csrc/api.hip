@@ -577,7 +577,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
     s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt,
                      nullptr, nullptr, far_pos, st);  // marks 3, 4, 5
   if (s == HDOF_OK) s = launch_var_update(ctx, k, params->mask.var_alpha, spp, gb.depth, rt.lum_m1, rt.lum_m2, st);
-  hdof_prof_mark(ctx, 6, st);
+  if (params->recon.enable) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
   if (s == HDOF_OK && params->recon.enable)
     s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt, params->recon.alpha, st);
   hdof_prof_mark(ctx, 7, st);
@@ -595,13 +595,15 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
 // ---------------------------------------------------------------------------
 void hdof_prof_mark(hdof_ctx* ctx, int i, hipStream_t st) {
   if (!ctx->prof_on || !ctx->prof_in_frame) return;
-  size_t idx = (size_t)ctx->prof_frames * (HDOF_PROFILE_STAGES + 1) + i;
+  const size_t base = (size_t)ctx->prof_frames * (HDOF_PROFILE_STAGES + 1), idx = base + i;
   while (ctx->prof_events.size() <= idx) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     ctx->prof_events.push_back(e);
   }
-  (void)hipEventRecord(ctx->prof_events[idx], st);
+  if (ctx->prof_set.size() < base + HDOF_PROFILE_STAGES + 1) ctx->prof_set.resize(base + HDOF_PROFILE_STAGES + 1, 0);
+  if (i == 0) std::fill(ctx->prof_set.begin() + base, ctx->prof_set.begin() + base + HDOF_PROFILE_STAGES + 1, 0);
+  if (hipEventRecord(ctx->prof_events[idx], st) == hipSuccess) ctx->prof_set[idx] = 1;
 }
 
 extern "C" hdof_status hdof_profile_begin(hdof_ctx* ctx) {
@@ -617,13 +619,20 @@ extern "C" hdof_status hdof_profile_end(hdof_ctx* ctx, float* ms_out, int32_t* n
   HDOF_HIP(hipDeviceSynchronize());
   const int S = HDOF_PROFILE_STAGES;
   for (int i = 0; i < S; ++i) ms_out[i] = 0.0f;
-  for (int f = 0; f < ctx->prof_frames; ++f)
+  // stage i runs from mark i to the next recorded mark; a stage whose
+  // start mark was not recorded (it had no work) counts 0
+  for (int f = 0; f < ctx->prof_frames; ++f) {
+    const size_t base = (size_t)f * (S + 1);
     for (int i = 0; i < S; ++i) {
+      if (!ctx->prof_set[base + i]) continue;
+      int j = i + 1;
+      while (j <= S && !ctx->prof_set[base + j]) ++j;
+      if (j > S) continue;
       float ms = 0.0f;
-      HDOF_HIP(hipEventElapsedTime(&ms, ctx->prof_events[(size_t)f * (S + 1) + i],
-                                   ctx->prof_events[(size_t)f * (S + 1) + i + 1]));
+      HDOF_HIP(hipEventElapsedTime(&ms, ctx->prof_events[base + i], ctx->prof_events[base + j]));
       ms_out[i] += ms;
     }
+  }
   if (ctx->prof_frames > 0)
     for (int i = 0; i < S; ++i) ms_out[i] /= (float)ctx->prof_frames;
   if (n_frames) *n_frames = ctx->prof_frames;

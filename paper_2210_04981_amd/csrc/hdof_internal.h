@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/hdof.h"
@@ -96,6 +97,7 @@ struct hdof_ctx {
   bool prof_on = false, prof_in_frame = false;
   int prof_frames = 0;
   std::vector<hipEvent_t> prof_events;
+  std::vector<uint8_t> prof_set;  // which marks of each frame were recorded
 };
 
 // record stage boundary `i` of the current profiled frame (no-op when off)
