@@ -544,7 +544,24 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(pick_buf(u.rt.hit_ratio, ctx->f_h, 4 * N, &rt.hit_ratio));
   TRY(pick_buf(u.rt.lum_m1, ctx->f_m1, 4 * N, &rt.lum_m1));
   TRY(pick_buf(u.rt.lum_m2, ctx->f_m2, 4 * N, &rt.lum_m2));
-  TRY(pick_buf(u.pp, ctx->f_pp, 12 * N, &pp));
+  // 16-pixel post-filter tiles: the G-buffer writes the packed texels and
+  // tile radii, the gather applies the composite (the filtered colour is
+  // stored only when the caller keeps it)
+  const bool fused = params->pp.tile == 16;
+  if (fused) {
+    pp = u.pp;
+  } else {
+    TRY(pick_buf(u.pp, ctx->f_pp, 12 * N, &pp));
+  }
+  float4* pack = nullptr;
+  float* tile_r = nullptr;
+  if (fused) {
+    const size_t ntile = (size_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16);
+    TRY(hdof_ensure(ctx->pp_pack, sizeof(float4) * N));
+    TRY(hdof_ensure(ctx->pp_tile, sizeof(float) * ntile));
+    pack = (float4*)ctx->pp_pack.p;
+    tile_r = (float*)ctx->pp_tile.p;
+  }
   hipStream_t st = (hipStream_t)stream;
   CamK k = make_camk(cam);
   LensK l = make_lensk(lens, k);
@@ -568,7 +585,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   }
   ctx->prof_in_frame = true;
   hdof_prof_mark(ctx, 0, st);
-  hdof_status s = launch_gbuffer(ctx, scene, k, l, li, gb, st);
+  hdof_status s = launch_gbuffer(ctx, scene, k, l, li, gb, st, pack, tile_r);
   hdof_prof_mark(ctx, 1, st);
   if (s == HDOF_OK)
     s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st);
@@ -581,9 +598,14 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   if (s == HDOF_OK && params->recon.enable)
     s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt, params->recon.alpha, st);
   hdof_prof_mark(ctx, 7, st);
-  if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st);  // mark 8
-  hdof_prof_mark(ctx, 9, st);
-  if (s == HDOF_OK) s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st);
+  if (fused) {
+    const PostFuse pf{spp, rt, params->comp, d_out};
+    if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st, true, &pf);  // mark 8
+  } else {
+    if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st);  // mark 8
+    hdof_prof_mark(ctx, 9, st);
+    if (s == HDOF_OK) s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st);
+  }
   hdof_prof_mark(ctx, 10, st);
   ctx->prof_in_frame = false;
   if (s == HDOF_OK && ctx->prof_on) ctx->prof_frames++;
@@ -818,9 +840,14 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     float* color = (float*)(a + L.o_color) + 3 * pb;
     float* depth = (float*)(a + L.o_depth) + pb;
     float* pp = (float*)(a + L.o_pp) + 3 * pb;
-    TRY(launch_postfilter(ctx, color, depth, bv.k, bv.l, params->pp, pp, st));
-    TRY(launch_composite(ctx, color, pp, depth, (const uint8_t*)(a + L.o_spp) + pb, rt[v], bv.k, bv.l,
-                         params->comp, views[v].d_out, st));
+    const uint8_t* spp = (const uint8_t*)(a + L.o_spp) + pb;
+    if (params->pp.tile == 16) {  // composite in the gather's epilogue, as in hdof_frame
+      const PostFuse pf{spp, rt[v], params->comp, views[v].d_out};
+      TRY(launch_postfilter(ctx, color, depth, bv.k, bv.l, params->pp, nullptr, st, false, &pf));
+    } else {
+      TRY(launch_postfilter(ctx, color, depth, bv.k, bv.l, params->pp, pp, st));
+      TRY(launch_composite(ctx, color, pp, depth, spp, rt[v], bv.k, bv.l, params->comp, views[v].d_out, st));
+    }
   }
   ctx->rep_valid = false;  // the views' reprojection planes are no frame history
   return HDOF_OK;

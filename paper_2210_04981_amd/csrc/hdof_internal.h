@@ -19,6 +19,12 @@
 #define HDOF_LDS_STACK 20
 #define HDOF_SPILL_STACK 44
 #define HDOF_TRACE_BLOCK 128
+#ifndef HDOF_DEFAULT_BPC
+#define HDOF_DEFAULT_BPC 12  // persistent trace blocks per CU
+#endif
+#ifndef HDOF_TRACE_WAVES_PER_EU
+#define HDOF_TRACE_WAVES_PER_EU 1  // occupancy the trace kernel's register budget is sized for
+#endif
 // ints between the persistent trace's per-segment work counters: one
 // 128-byte line each (counters sharing a line serialise across XCDs)
 #define HDOF_SEG_STRIDE 32
@@ -84,7 +90,7 @@ struct hdof_ctx {
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
   // persistent-trace launch shape (performance only)
-  hdof_tuning tune = {12, 64, 8};
+  hdof_tuning tune = {HDOF_DEFAULT_BPC, 64, 8};
   // batched form: per-view intermediates, view table (device + pinned host)
   Buf b_arena, b_views, b_totals;
   void* b_views_host = nullptr;
@@ -243,7 +249,8 @@ __device__ inline void lens_ray(const CamK& k, const LensK& l, int x, int y, uin
 hdof_status launch_bvh_build(hdof_ctx* ctx, const float* verts, const float* albedo, int n,
                              hdof_scene* sc, hipStream_t st);
 hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
-                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st);
+                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st, float4* pack = nullptr,
+                           float* tile_r = nullptr);
 struct BatchView {
   CamK k;
   LensK l;
@@ -268,8 +275,18 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
                         int32_t* total, hipStream_t st);
 hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
                               const float* depth, const float* m1, const float* m2, hipStream_t st);
+// Composite fused into the post-filter of a whole frame (the gather writes
+// the final colour; its filtered colour goes to `out` only when non-NULL).
+struct PostFuse {
+  const uint8_t* spp;
+  hdof_rt_bufs rt;
+  hdof_composite_params cp;
+  float* out;
+};
+// packed: pack and per-tile radius already written (by the G-buffer)
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
-                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st);
+                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
+                              bool packed = false, const PostFuse* fuse = nullptr);
 hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* depth, const uint8_t* spp,
                                 hdof_rt_bufs rt, const CamK& k, const LensK& l, const hdof_pp_params& pp,
                                 const hdof_composite_params& cp, const float* grad_out, float* grad_color,

@@ -258,11 +258,74 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
   }
 }
 
-__global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ rad,
-                                                     const float4* __restrict__ taps, int n_taps, int W, int H,
-                                                     float inv_ramp, float* __restrict__ out) {
+// Composite applied in the gather's epilogue (whole frames): the same rules
+// as k_composite, with the raster colour and CoC from the packed texel.
+struct FuseK {
+  const uint8_t* spp;
+  const float *cn, *cf, *hr;
+  float inv_ht;
+  int rt_override;
+  float* out;
+};
+
+__device__ __forceinline__ void composite_px(const FuseK& fz, size_t N, size_t p, const float4& cp4, float pr,
+                                             float pg, float pb) {
+  const float c = cp4.w;
+  const float phi = clamp01(fabsf(c) - HDOF_SQRT2);
+  const float nu = clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
+  const bool traced = fz.spp[p] > 0;
+  const float h = traced ? fz.hr[p] : 0.0f;
+  const float rho = traced ? 1.0f : 0.0f;
+  const float beta = traced ? clamp01(1.0f - h * fz.inv_ht) : 0.0f;
+  const float col[3] = {cp4.x, cp4.y, cp4.z}, cpp[3] = {pr, pg, pb};
+  for (int q = 0; q < 3; ++q) {
+    const size_t i = (size_t)q * N + p;
+    const float crt = traced ? h * fz.cn[i] + (1.0f - h) * fz.cf[i] : 0.0f;
+    const float oof = nu * (rho * crt + (1.0f - rho) * cpp[q]) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp[q]);
+    float o = (1.0f - phi) * col[q] + phi * oof;
+    if (fz.rt_override && traced) o = crt;
+    fz.out[i] = o;
+  }
+}
+
+// the filtered colour of pixel p: to `out` (may be NULL when fused) and,
+// when fused, through the composite
+template <bool FUSE>
+__device__ __forceinline__ void pp_emit(float* __restrict__ out, const FuseK& fz, size_t N, size_t p,
+                                        const float4& cp4, float pr, float pg, float pb) {
+  if (out) {
+    out[p] = pr;
+    out[N + p] = pg;
+    out[2 * N + p] = pb;
+  }
+  if (FUSE) composite_px(fz, N, p, cp4, pr, pg, pb);
+}
+
+// The gather radius of tile (tx, ty): min(r_cap, max tile radius within K
+// tiles), reduced by the block (uniform result).
+__device__ __forceinline__ float block_dilated_radius(const float* __restrict__ tile_r, int TW, int TH, int tx,
+                                                      int ty, int K, float r_cap, float* wred) {
+  const int D = 2 * K + 1, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float m = 0.0f;
+  for (int i = tid; i < D * D; i += 256) {
+    const int yy = ty - K + i / D, xx = tx - K + i % D;
+    if (yy >= 0 && yy < TH && xx >= 0 && xx < TW) m = fmaxf(m, tile_r[yy * TW + xx]);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) wred[wave] = m;
+  __syncthreads();
+  return fminf(r_cap, fmaxf(fmaxf(wred[0], wred[1]), fmaxf(wred[2], wred[3])));
+}
+
+// 16-pixel tiles.  The block first reduces its tile's dilated radius from
+// the per-tile maxima; FUSE applies the composite to the result.
+template <bool FUSE>
+__global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ tile_r,
+                                                     int K, float r_cap, const float4* __restrict__ taps, int n_taps,
+                                                     int W, int H, float inv_ramp, float* __restrict__ out, FuseK fz) {
   __shared__ float4 stg[2][PPG_G * PPG_TAPSZ];
   __shared__ TapRec rec[2][PPG_G];
+  __shared__ float wred[4];
   const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
   const int tile = xcd_block(blockIdx.x, TW * TH);
   const int x0 = (tile % TW) * 16, y0 = (tile / TW) * 16;
@@ -272,26 +335,28 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   const int x = x0 + lx, y = y0 + ly;
   const bool inside = x < W && y < H;
   const size_t N = (size_t)W * H, p = (size_t)y * W + x;
-  const float R = rad[tile];
+  const float R = block_dilated_radius(tile_r, TW, TH, tile % TW, tile / TW, K, r_cap, wred);
   if (!(R > 0.0f)) {
     if (inside) {
       const float4 c = pack[p];
-      out[p] = c.x;
-      out[N + p] = c.y;
-      out[2 * N + p] = c.z;
+      pp_emit<FUSE>(out, fz, N, p, c, c.x, c.y, c.z);
     }
     return;
   }
   const int E = (int)ceilf(R);
   const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H;
+  const float4 cp4 = inside ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f);
   GatherAcc g;
-  g.init(inside ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f), R, n_taps, inv_ramp);
+  g.init(cp4, R, n_taps, inv_ramp);
   const int lofs = ly * PPG_STRIDE + lx;
   if (interior)
     gather_taps<true>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
   else
     gather_taps<false>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
-  if (inside) g.store(out, N, p);
+  if (inside) {
+    const float iw = 1.0f / g.ws;
+    pp_emit<FUSE>(out, fz, N, p, cp4, g.ar * iw, g.ag * iw, g.ab * iw);
+  }
 }
 
 // Tiles of 4 or 8 pixels: per-lane radius and per-lane tap geometry, every
@@ -720,7 +785,8 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 }  // namespace
 
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
-                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st) {
+                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st, bool packed,
+                              const PostFuse* fuse) {
   const int W = k.W, H = k.H, t = pp.tile;
   const size_t N = (size_t)W * H;
   const int TW = cdiv(W, t), TH = cdiv(H, t);
@@ -734,19 +800,35 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
     hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
     ctx->pp_taps_n = pp.n_taps;
   }
-  hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
-                     (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
-  hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p, TW,
-                     TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
+  if (!packed)
+    hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
+                       (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
+  if (t != 16)
+    hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p, TW,
+                       TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
   hdof_prof_mark(ctx, 8, st);
-  if (t == 16)
-    hipLaunchKernelGGL(k_pp_gather16, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
-                       (const float*)ctx->pp_rad.p, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
-                       1.0f / pp.bg_ramp_px, out);
-  else
+  if (t == 16) {
+    FuseK fz{};
+    if (fuse) {
+      fz = FuseK{fuse->spp, fuse->rt.c_near, fuse->rt.c_far, fuse->rt.hit_ratio, 1.0f / fuse->cp.h_t,
+                 fuse->cp.rt_override, fuse->out};
+      hipLaunchKernelGGL(k_pp_gather16<true>, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+                         (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
+                         1.0f / pp.bg_ramp_px, out, fz);
+    } else {
+      hipLaunchKernelGGL(k_pp_gather16<false>, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+                         (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
+                         1.0f / pp.bg_ramp_px, out, fz);
+    }
+  } else {
     hipLaunchKernelGGL(k_pp_gather_any, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
                        (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
                        (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
+    if (fuse) {
+      HDOF_HIP(hipGetLastError());
+      return launch_composite(ctx, color, out, depth, fuse->spp, fuse->rt, k, l, fuse->cp, fuse->out, st);
+    }
+  }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

@@ -300,7 +300,10 @@ __device__ inline void shade(const float4* __restrict__ tris, const float* __res
   n = nn;
 }
 
-template <bool COUNT>
+// PACK (frames with 16-pixel post-filter tiles): also the post-filter's
+// packed texel (shaded rgb, signed CoC of the stored depth) and the block's
+// maximum CoC radius, the block being the post-filter tile.
+template <bool COUNT, bool PACK>
 __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ nodes,
                                                  const float4* __restrict__ tris, int n_nodes,
                                                  const float* __restrict__ albedo, CamK k, LensK l,
@@ -308,7 +311,9 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
                                                  float* __restrict__ normal, float* __restrict__ alb_out,
                                                  float* __restrict__ color, int* __restrict__ tri_id,
                                                  int* __restrict__ flags,
-                                                 unsigned long long* __restrict__ counters) {
+                                                 unsigned long long* __restrict__ counters,
+                                                 float4* __restrict__ pack, float* __restrict__ tile_r) {
+  __shared__ float wmax[4];
   const int bx_n = (k.W + 15) >> 4, by_n = (k.H + 15) >> 4;
   const int lb = xcd_block(blockIdx.x, bx_n * by_n);
   const int bx = lb % bx_n, by = lb / bx_n;
@@ -319,35 +324,49 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
   Ray r = make_ray(k.e, V3{l.S1 * v.x, l.S1 * v.y, l.S1 * v.z});
   Work wk{0, 0};
   Best b = traverse_wave<COUNT>(nodes, tris, n_nodes, r, live, flags, wk);
-  if (!live) return;
-  if (COUNT) {
-    atomicAdd(&counters[0], 1ull);
-    atomicAdd(&counters[1], (unsigned long long)wk.visits);
-    atomicAdd(&counters[2], (unsigned long long)wk.tests);
-  }
-  const size_t N = (size_t)k.W * k.H, p = (size_t)y * k.W + x;
-  if (b.tri >= 0) {
-    V3 L, n, a;
-    shade(tris, albedo, li, r, b, L, n, a);
-    depth[p] = b.t * l.S1;
-    normal[p] = n.x;
-    normal[N + p] = n.y;
-    normal[2 * N + p] = n.z;
-    alb_out[p] = a.x;
-    alb_out[N + p] = a.y;
-    alb_out[2 * N + p] = a.z;
+  float rr = 0.0f;
+  if (live) {
+    if (COUNT) {
+      atomicAdd(&counters[0], 1ull);
+      atomicAdd(&counters[1], (unsigned long long)wk.visits);
+      atomicAdd(&counters[2], (unsigned long long)wk.tests);
+    }
+    const size_t N = (size_t)k.W * k.H, p = (size_t)y * k.W + x;
+    float z = HDOF_ZMAX;
+    V3 L = V3{0.0f, 0.0f, 0.0f};
+    if (b.tri >= 0) {
+      V3 n, a;
+      shade(tris, albedo, li, r, b, L, n, a);
+      z = b.t * l.S1;
+      normal[p] = n.x;
+      normal[N + p] = n.y;
+      normal[2 * N + p] = n.z;
+      alb_out[p] = a.x;
+      alb_out[N + p] = a.y;
+      alb_out[2 * N + p] = a.z;
+      tri_id[p] = b.id;
+    } else {
+      for (int c = 0; c < 3; ++c) {
+        normal[c * N + p] = 0.0f;
+        alb_out[c * N + p] = 0.0f;
+      }
+      tri_id[p] = -1;
+    }
+    depth[p] = z;
     color[p] = L.x;
     color[N + p] = L.y;
     color[2 * N + p] = L.z;
-    tri_id[p] = b.id;
-  } else {
-    depth[p] = HDOF_ZMAX;
-    for (int c = 0; c < 3; ++c) {
-      normal[c * N + p] = 0.0f;
-      alb_out[c * N + p] = 0.0f;
-      color[c * N + p] = 0.0f;
+    if (PACK) {
+      const float c = coc_px(l, z);
+      pack[p] = make_float4(L.x, L.y, L.z, c);
+      rr = 0.5f * fabsf(c);
     }
-    tri_id[p] = -1;
+  }
+  if (PACK) {
+    for (int o = 32; o > 0; o >>= 1) rr = fmaxf(rr, __shfl_xor(rr, o));
+    if (lane == 0) wmax[wave] = rr;
+    __syncthreads();
+    if (t == 0) tile_r[lb] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
   }
 }
 
@@ -409,7 +428,7 @@ struct TraceArgs {
 };
 
 template <bool COUNT, bool BATCH>
-__global__ __launch_bounds__(HDOF_TRACE_BLOCK) void k_trace(TraceArgs A) {
+__global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_trace(TraceArgs A) {
   __shared__ int stk_all[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
   __shared__ int pxb[HDOF_MAX_VIEWS + 1];
   int spill[HDOF_SPILL_STACK];
@@ -626,16 +645,13 @@ TraceArgs base_args(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, size_
 }  // namespace
 
 hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
-                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st) {
+                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st, float4* pack, float* tile_r) {
   int nb = cdiv(k.W, 16) * cdiv(k.H, 16);
-  if (ctx->count_on)
-    hipLaunchKernelGGL(k_gbuffer<true>, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
-                       k, l, li, out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags,
-                       ctx->d_counters);
-  else
-    hipLaunchKernelGGL(k_gbuffer<false>, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
-                       k, l, li, out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags,
-                       ctx->d_counters);
+  auto kern = ctx->count_on ? (pack ? k_gbuffer<true, true> : k_gbuffer<true, false>)
+                            : (pack ? k_gbuffer<false, true> : k_gbuffer<false, false>);
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo, k, l, li,
+                     out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags, ctx->d_counters, pack,
+                     tile_r);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
