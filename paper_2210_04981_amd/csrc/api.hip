@@ -585,15 +585,20 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   }
   ctx->prof_in_frame = true;
   hdof_prof_mark(ctx, 0, st);
+  TRY(hdof_ensure(ctx->work_counter, sizeof(int) * 8 * HDOF_SEG_STRIDE));
   hdof_status s = launch_gbuffer(ctx, scene, k, l, li, gb, st, pack, tile_r);
   hdof_prof_mark(ctx, 1, st);
+  // the mask's final pass also fills the ray queue (queue stage empty)
   if (s == HDOF_OK)
-    s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st);
-  hdof_prof_mark(ctx, 2, st);
+    s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st,
+                    (int*)ctx->queue.p, (long)cap, (int*)ctx->work_counter.p);
+  // the trace's per-pixel reduction also updates the variance history
+  // (variance stage empty)
+  VarFuse vf;
+  if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf);
   if (s == HDOF_OK)
     s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt,
-                     nullptr, nullptr, far_pos, st);  // marks 3, 4, 5
-  if (s == HDOF_OK) s = launch_var_update(ctx, k, params->mask.var_alpha, spp, gb.depth, rt.lum_m1, rt.lum_m2, st);
+                     nullptr, nullptr, far_pos, st, &vf, true);  // marks 3, 4
   if (params->recon.enable) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
   if (s == HDOF_OK && params->recon.enable)
     s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt, params->recon.alpha, st);

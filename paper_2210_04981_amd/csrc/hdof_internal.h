@@ -264,15 +264,31 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
                                  int32_t* ebase, int32_t* grand, hdof_rt_bufs* rt, hipStream_t st);
 size_t batch_view_bytes();
 void batch_view_pack(const BatchView* hv, int n, void* out);
+// Variance history update fused into the trace's per-pixel reduction
+// (whole frames): the reprojected history in, the new history out.
+struct VarFuse {
+  float alpha;
+  const float* depth;
+  const float *rm1, *rm2;
+  const uint8_t* rfl;
+  float *m1, *m2;
+  uint8_t* fl;
+  float* hz;
+};
+// checks the frame's reprojection, reserves the history and marks it
+// written (as launch_var_update does before its launch)
+hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const float* depth, VarFuse* vf);
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
-                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st);
+                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st,
+                         const VarFuse* vf = nullptr, bool queue_ready = false);
 hdof_status launch_recon(hdof_ctx* ctx, const CamK& k, const CamK* prev, const float* depth, const uint8_t* spp,
                          const float* far_pos, hdof_rt_bufs rt, float alpha, hipStream_t st);
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
-                        int32_t* total, hipStream_t st);
+                        int32_t* total, hipStream_t st,
+                        int* queue = nullptr, long cap = 0, int* counter = nullptr);
 hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
                               const float* depth, const float* m1, const float* m2, hipStream_t st);
 // Composite fused into the post-filter of a whole frame (the gather writes

@@ -248,6 +248,48 @@ __global__ void k_mask_write(int W, int H, int t, const int* __restrict__ tile_d
   offsets[p] = ybase[ty] + (y - ty * t) * rowsum[ty] + xpref[ty * TW + tx] + (x - tx * t) * S;
 }
 
+// Whole frames: the same write with the tile-row scan done per block (the
+// block sums the row totals before its tile row; the last row's first block
+// also writes the total), and the ray queue written here instead of by the
+// trace's queue fill (pixel index per entry, entries outside [0, cap)
+// dropped; the trace's work counters cleared).
+__global__ __launch_bounds__(256) void k_mask_write_queue(int W, int H, int t, int TH,
+                                                          const int* __restrict__ tile_dil,
+                                                          const int* __restrict__ xpref,
+                                                          const int* __restrict__ rowsum,
+                                                          const int* __restrict__ rowtot, uint8_t* __restrict__ spp,
+                                                          int* __restrict__ offsets, int* __restrict__ total,
+                                                          int* __restrict__ queue, long cap, int* __restrict__ counter) {
+  __shared__ int2 red[256];
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x * blockDim.x + tid, y = blockIdx.y;
+  const int ty = y / t;
+  int before = 0, all = 0;
+  for (int i = tid; i < TH; i += 256) {
+    const int v = rowtot[i];
+    if (i < ty) before += v;
+    all += v;
+  }
+  red[tid] = make_int2(before, all);
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] = make_int2(red[tid].x + red[tid + o].x, red[tid].y + red[tid + o].y);
+    __syncthreads();
+  }
+  const int ybase = red[0].x;
+  if (blockIdx.x == 0 && y == H - 1 && tid == 0) *total = red[0].y;
+  const size_t p = (size_t)y * W + x;
+  if (p < 8 * HDOF_SEG_STRIDE) counter[p] = 0;
+  if (x >= W) return;
+  const int TW = (W + t - 1) / t, tx = x / t;
+  const int S = tile_dil[ty * TW + tx];
+  const int o = ybase + (y - ty * t) * rowsum[ty] + xpref[ty * TW + tx] + (x - tx * t) * S;
+  spp[p] = (uint8_t)S;
+  offsets[p] = o;
+  for (int j = 0; j < S; ++j)
+    if ((long)o + j >= 0 && (long)o + j < cap) queue[o + j] = (int)p;
+}
+
 // history update after the trace
 __global__ void k_var_update(int N, float alpha, const uint8_t* __restrict__ spp,
                              const float* __restrict__ depth, const float* __restrict__ ybar,
@@ -282,7 +324,7 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
-                        int32_t* total, hipStream_t st) {
+                        int32_t* total, hipStream_t st, int* queue, long cap, int* counter) {
   const int W = k.W, H = k.H, t = mp.tile;
   const size_t N = (size_t)W * H;
   const int TW = cdiv(W, t), TH = cdiv(H, t);
@@ -341,17 +383,22 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   }
   hipLaunchKernelGGL(k_mask_rows, dim3(TH), dim3(256), 0, st, (const int*)ctx->mask_tile.p, W, H, t,
                      mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot);
-  hipLaunchKernelGGL(k_mask_rowscan, dim3(1), dim3(1024), 0, st, (const int*)rowtot, TH,
-                     (int*)ctx->mask_ybase.p, total);
-  hipLaunchKernelGGL(k_mask_write, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t,
-                     (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p,
-                     (const int*)rowsum, (const int*)ctx->mask_ybase.p, spp, offsets);
+  if (queue) {
+    hipLaunchKernelGGL(k_mask_write_queue, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t, TH,
+                       (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p, (const int*)rowsum,
+                       (const int*)rowtot, spp, offsets, total, queue, cap, counter);
+  } else {
+    hipLaunchKernelGGL(k_mask_rowscan, dim3(1), dim3(1024), 0, st, (const int*)rowtot, TH,
+                       (int*)ctx->mask_ybase.p, total);
+    hipLaunchKernelGGL(k_mask_write, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t,
+                       (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p,
+                       (const int*)rowsum, (const int*)ctx->mask_ybase.p, spp, offsets);
+  }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
 
-hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
-                              const float* depth, const float* m1, const float* m2, hipStream_t st) {
+hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const float* depth, VarFuse* vf) {
   const size_t N = (size_t)k.W * k.H;
   hdof_status s;
   if (!ctx->rep_valid || ctx->rep_w != k.W || ctx->rep_h != k.H)
@@ -361,13 +408,23 @@ hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const u
   if ((s = hdof_ensure(ctx->hist_m2, sizeof(float) * N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->hist_flags, N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->hist_z, sizeof(float) * N)) != HDOF_OK) return s;
-  hipLaunchKernelGGL(k_var_update, dim3(cdiv((long)N, 256)), dim3(256), 0, st, (int)N, alpha, spp, depth,
-                     m1, m2, (const float*)ctx->rep_m1.p, (const float*)ctx->rep_m2.p,
-                     (const uint8_t*)ctx->rep_flags.p, (float*)ctx->hist_m1.p, (float*)ctx->hist_m2.p,
-                     (uint8_t*)ctx->hist_flags.p, (float*)ctx->hist_z.p);
-  HDOF_HIP(hipGetLastError());
+  *vf = VarFuse{alpha, depth, (const float*)ctx->rep_m1.p, (const float*)ctx->rep_m2.p,
+                (const uint8_t*)ctx->rep_flags.p, (float*)ctx->hist_m1.p, (float*)ctx->hist_m2.p,
+                (uint8_t*)ctx->hist_flags.p, (float*)ctx->hist_z.p};
   ctx->hist_w = k.W;
   ctx->hist_h = k.H;
   ctx->hist_any = true;
+  return HDOF_OK;
+}
+
+hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
+                              const float* depth, const float* m1, const float* m2, hipStream_t st) {
+  const size_t N = (size_t)k.W * k.H;
+  VarFuse vf;
+  hdof_status s;
+  if ((s = var_update_prepare(ctx, k, alpha, depth, &vf)) != HDOF_OK) return s;
+  hipLaunchKernelGGL(k_var_update, dim3(cdiv((long)N, 256)), dim3(256), 0, st, (int)N, alpha, spp, depth,
+                     m1, m2, vf.rm1, vf.rm2, vf.rfl, vf.m1, vf.m2, vf.fl, vf.hz);
+  HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

@@ -537,13 +537,15 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
 // FARPOS: also the far-weighted mean hit point of the pixel's rays that hit
 // (their rays regenerated from the same counters; t = z / S1 since the
 // direction's forward component is S1) and its weight, 4 planes.
-template <bool FARPOS>
+// VAR (whole frames): the variance history update of the pixel as well,
+// from the moments just formed.
+template <bool FARPOS, bool VAR>
 __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
                             const int* __restrict__ ebase, const float* __restrict__ ray_col,
                             const float* __restrict__ ray_z, size_t cap, LensK l, float* __restrict__ cn,
                             float* __restrict__ cf, float* __restrict__ h, float* __restrict__ m1,
                             float* __restrict__ m2, CamK k, uint32_t seed, uint32_t frame, uint32_t view,
-                            float* __restrict__ far_pos) {
+                            float* __restrict__ far_pos, VarFuse vf) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   int s = spp[p];
@@ -589,9 +591,29 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   cf[p] = sfr * if_;
   cf[N + p] = sfg * if_;
   cf[2 * (size_t)N + p] = sfb * if_;
+  const float ybar = sy * is, y2bar = sy2 * is;
   h[p] = Nw * is;
-  m1[p] = sy * is;
-  m2[p] = sy2 * is;
+  m1[p] = ybar;
+  m2[p] = y2bar;
+  if (VAR) {
+    float a1 = vf.rm1[p], a2 = vf.rm2[p];
+    uint8_t f = vf.rfl[p];
+    if (spp[p] > 0) {
+      if (f & HDOF_HIST_VALID) {
+        a1 = fmaf(vf.alpha, ybar, (1.0f - vf.alpha) * a1);
+        a2 = fmaf(vf.alpha, y2bar, (1.0f - vf.alpha) * a2);
+        f = HDOF_HIST_VALID;
+      } else {
+        a1 = ybar;
+        a2 = y2bar;
+        f = HDOF_HIST_VALID | HDOF_HIST_NEW;
+      }
+    }
+    vf.m1[p] = a1;
+    vf.m2[p] = a2;
+    vf.fl[p] = f;
+    vf.hz[p] = vf.depth[p];
+  }
   if (FARPOS) {
     const float ip = Pw > 0.f ? 1.0f / Pw : 0.f;
     far_pos[p] = spx_ * ip;
@@ -668,14 +690,16 @@ hdof_status reserve_trace(hdof_ctx* ctx, size_t cap, bool own_depth) {
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
-                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st) {
+                         hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st,
+                         const VarFuse* vf, bool queue_ready) {
   const int N = k.W * k.H;
   const size_t cap = (size_t)N * (size_t)spp_max;
   hdof_status s;
   if ((s = reserve_trace(ctx, cap, !ray_depth)) != HDOF_OK) return s;
   float* rz = ray_depth ? ray_depth : (float*)ctx->ray_z.p;
-  hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr, 0,
-                     (long)cap, (int*)ctx->queue.p, (int*)ctx->work_counter.p);
+  if (!queue_ready)
+    hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr,
+                       0, (long)cap, (int*)ctx->queue.p, (int*)ctx->work_counter.p);
   hdof_prof_mark(ctx, 3, st);
   TraceArgs A = base_args(ctx, sc, li, cap);
   A.offsets = offsets;
@@ -685,15 +709,13 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
   A.v0 = ViewK{k, l, seed, frame, view, 0};
   launch_trace_kernel<false>(ctx, A, st);
   hdof_prof_mark(ctx, 4, st);
-  if (far_pos)
-    hipLaunchKernelGGL(k_rt_reduce<true>, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
-                       (const int*)nullptr, (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near,
-                       out.c_far, out.hit_ratio, out.lum_m1, out.lum_m2, k, seed, frame, view, far_pos);
-  else
-    hipLaunchKernelGGL(k_rt_reduce<false>, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N,
-                       (const int*)nullptr, (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near,
-                       out.c_far, out.hit_ratio, out.lum_m1, out.lum_m2, k, seed, frame, view, (float*)nullptr);
-  hdof_prof_mark(ctx, 5, st);
+  const VarFuse vz = vf ? *vf : VarFuse{};
+  auto kern = far_pos ? (vf ? k_rt_reduce<true, true> : k_rt_reduce<true, false>)
+                      : (vf ? k_rt_reduce<false, true> : k_rt_reduce<false, false>);
+  hipLaunchKernelGGL(kern, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr,
+                     (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near, out.c_far, out.hit_ratio,
+                     out.lum_m1, out.lum_m2, k, seed, frame, view, far_pos, vz);
+  if (!vf) hdof_prof_mark(ctx, 5, st);  // fused: the variance update stage is part of this one
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
@@ -730,10 +752,11 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
   launch_trace_kernel<true>(ctx, A, st);
   for (int v = 0; v < n_views; ++v) {
     const int N = hviews[v].k.W * hviews[v].k.H, pb = hviews[v].px_base;
-    hipLaunchKernelGGL(k_rt_reduce<false>, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb, N,
-                       (const int*)(ebase + v), (const float*)ctx->ray_col.p, (const float*)ctx->ray_z.p, cap,
+    auto red = k_rt_reduce<false, false>;
+    hipLaunchKernelGGL(red, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb,
+                       N, (const int*)(ebase + v), (const float*)ctx->ray_col.p, (const float*)ctx->ray_z.p, cap,
                        hviews[v].l, rt[v].c_near, rt[v].c_far, rt[v].hit_ratio, rt[v].lum_m1, rt[v].lum_m2,
-                       hviews[v].k, 0u, 0u, 0u, (float*)nullptr);
+                       hviews[v].k, 0u, 0u, 0u, (float*)nullptr, VarFuse{});
   }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
