@@ -373,7 +373,8 @@ void hdof_batch_destroy(hdof_batch* batch);
  * do not depend on it).  blocks_per_cu in [1, 32]; refill in [1, 64]: idle
  * lanes of a wave that trigger a refill from the queue (64 = batches of 64
  * rays); segments in [1, 8]: queue segments, one per XCD group.  Defaults
- * {12, 64, 8}. */
+ * {10, 64, 8}: ten two-wave blocks per CU is the trace kernel's register-
+ * limited residency (5 waves per SIMD), so every block starts at once. */
 typedef struct {
   int32_t blocks_per_cu, refill, segments;
 } hdof_tuning;

@@ -20,7 +20,7 @@
 #define HDOF_SPILL_STACK 44
 #define HDOF_TRACE_BLOCK 128
 #ifndef HDOF_DEFAULT_BPC
-#define HDOF_DEFAULT_BPC 12  // persistent trace blocks per CU
+#define HDOF_DEFAULT_BPC 10  // persistent trace blocks per CU (its register-limited residency)
 #endif
 #ifndef HDOF_TRACE_WAVES_PER_EU
 #define HDOF_TRACE_WAVES_PER_EU 1  // occupancy the trace kernel's register budget is sized for

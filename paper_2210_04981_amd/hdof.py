@@ -624,7 +624,7 @@ class Batch:
             pass
 
 
-def hdof_set_tuning(ctx: Context, blocks_per_cu=12, refill=64, segments=8) -> None:
+def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8) -> None:
     t = Tuning(int(blocks_per_cu), int(refill), int(segments))
     _check(_lib.hdof_set_tuning(ctx.handle, C.byref(t)), "hdof_set_tuning")
 
