@@ -176,8 +176,10 @@ hdof_status hdof_sync(hdof_ctx* ctx, hdof_stream stream);
 /* Scene (acceleration structure; the paper uses the driver's hardware BVH) */
 /* ---------------------------------------------------------------------- */
 
-/* Build a linear BVH (Morton order, Karras-style hierarchy, bottom-up refit)
- * over n_tris triangles.  d_verts: n_tris x 9 floats (v0.xyz v1.xyz v2.xyz);
+/* Build a binary BVH over n_tris triangles: Morton-ordered leaves clustered
+ * bottom-up by PLOC (nearest neighbour by merged-box surface area within a
+ * window of the Morton order), nodes placed depth-first, leaves of at most 4
+ * triangles.  d_verts: n_tris x 9 floats (v0.xyz v1.xyz v2.xyz);
  * d_albedo: n_tris x 3 floats.  The inputs are read on `stream` and may be
  * freed once the stream has passed this call.  n_tris in [1, 2^26].
  * *out is owned by the caller and freed with hdof_scene_destroy. */

@@ -66,7 +66,9 @@ def lib():
         L.or_mask.argtypes = [i32, i32, P, P, P, f64, f64, f64, f64, i32, i32, i32,
                               P, P, P, P, P, P, P, P, P]
         L.or_trace.argtypes = [P, P, i32, i32, P, P, P, P, i64, P, u64, u64, u64,
-                               P, P, P, P, i64, P, P, P, P, P, P, P]
+                               P, P, P, P, i64, P, P, P, P, P, P, P, P]
+        L.or_sp_level.argtypes = [i32, i32, P, P, P, P, P, P, f64, i32, P]
+        L.or_spatial.argtypes = [i32, i32, P, P, P, P, P, P, P, i32, f64, f64, P, P, P]
         L.or_recon.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, f64, P, P, P, P, P, P]
         L.or_var_reproject.argtypes = [P, i32, i32, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
         L.or_var_update.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P]
@@ -243,7 +245,8 @@ def trace(scene: Scene, camera, lens, light, spp, pix=None, seed=0, frame=0, vie
     """Thin-lens distributed ray trace + per-pixel reduction (paper, Ray
     Trace).  `spp` is the per-pixel count (full image (H,W) when pix is None,
     else one count per listed pixel).  `far_pos` (4 planes): far-weighted
-    mean hit point of the rays that hit, and its weight."""
+    mean hit point of the rays that hit, and its weight.  `coc_nf` (2
+    planes): mean |CoC| of the near rays and of the far rays."""
     cam, W, H = cam_args(camera)
     sp = _i32(spp).reshape(-1)
     pixa = None if pix is None else _i64(pix)
@@ -263,15 +266,17 @@ def trace(scene: Scene, camera, lens, light, spp, pix=None, seed=0, frame=0, vie
     m2 = np.zeros(n)
     pa = np.zeros(n, np.int32)
     fp = np.zeros((4, n))
+    cc = np.zeros((2, n))
     lib().or_trace(scene.handle, _p(cam), W, H, _p(_f64(lens.as_floats())),
                    _p(_f64(light.as_floats())), _p(pixa), _p(sp), n,
                    _p(base) if per_ray else None, int(seed), int(frame), int(view),
                    _p(rid), _p(rz), _p(rL), _p(ra), nr,
-                   _p(cn), _p(cf), _p(h), _p(m1), _p(m2), _p(pa), _p(fp))
+                   _p(cn), _p(cf), _p(h), _p(m1), _p(m2), _p(pa), _p(fp), _p(cc))
     out = dict(c_near=cn, c_far=cf, hit_ratio=h, lum_m1=m1, lum_m2=m2, px_amb=pa,
-               ray_base=base, ray_id=rid, ray_z=rz, ray_L=rL, ray_amb=ra, far_pos=fp)
+               ray_base=base, ray_id=rid, ray_z=rz, ray_L=rL, ray_amb=ra, far_pos=fp, coc_nf=cc)
     if pix is None:
         out["far_pos"] = fp.reshape(4, H, W)
+        out["coc_nf"] = cc.reshape(2, H, W)
         for k in ("c_near", "c_far"):
             out[k] = out[k].reshape(3, H, W)
         for k in ("hit_ratio", "lum_m1", "lum_m2", "px_amb"):
@@ -353,7 +358,9 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
     G-buffer -> ray mask (with reprojected variance when a history is given)
     -> thin-lens trace -> variance update -> temporal reconstruction of the
     traced colours (when cfg.recon.enable; its history is `recon_history`,
-    used when prev_camera is given) -> post-process -> composite.
+    used when prev_camera is given) -> spatial reconstruction (when
+    cfg.spatial.enable; variance from the updated history) -> post-process
+    -> composite.
     `rt_full_spp` forces a full mask of that many samples (full ray-traced
     reference: every pixel traced, composite overridden)."""
     cam, lens, light = cfg.camera, cfg.lens, cfg.light
@@ -380,6 +387,13 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
         rc = recon(cam, depth, spp, prev_camera, rh, rt["hit_ratio"], rt["c_near"], rt["c_far"], rt["far_pos"],
                    rcfg.alpha, rt["px_amb"])
         rt = dict(rt, c_near=rc["c_near"], c_far=rc["c_far"])
+    scfg = getattr(cfg, "spatial", None)
+    sc = None
+    if scfg is not None and scfg.enable:
+        hacc = rc["history"]["planes"][3] if rc is not None else None
+        sc = spatial(spp, rt["c_near"], rt["c_far"], rt["hit_ratio"], hacc, rt["coc_nf"], history_variance(hist),
+                     scfg.n_taps, scfg.r_cap, scfg.v_clamp)
+        rt = dict(rt, c_near=sc["c_near"], c_far=sc["c_far"])
     cpp = postfilter(cam, lens, gb["color"], depth, cfg.pp)
     comp = cfg.comp
     if rt_full_spp is not None:
@@ -388,7 +402,7 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
     out = composite(cam, lens, gb["color"], cpp, depth, spp, rt["c_near"], rt["c_far"],
                     rt["hit_ratio"], comp)
     return dict(gbuffer=gb, mask=mk, spp=spp, rt=rt, history=hist, reproj=rep, pp=cpp, out=out,
-                recon=rc)
+                recon=rc, spatial=sc)
 
 
 def empty_recon_history(H: int, W: int) -> dict:
@@ -410,6 +424,47 @@ def recon(camera, depth, spp, prev_camera, hist: dict, hit, c_near, c_far, far_p
                    _p(_f64(c_far)), _p(_f64(far_pos)), _p(None if px_amb is None else _i32(px_amb)), float(alpha),
                    _p(cno), _p(cfo), _p(ho), _p(vo), _p(zo), _p(am))
     return dict(c_near=cno, c_far=cfo, history=dict(planes=ho, valid=vo, depth=zo), amb=am)
+
+
+SP_LMAX = 5
+
+
+def sp_level(spp, c_near, c_far, hit, hit_acc, coc_nf, r_cap: float, level: int) -> np.ndarray:
+    """The level-`level` texel sums of the spatial reconstruction, (10, HL, WL):
+    near sums (3), near weight, far sums (3), far weight, radius sum, count."""
+    sp = _i32(spp)
+    H, W = sp.shape
+    WL, HL = -(-W // (1 << level)), -(-H // (1 << level))
+    out = np.zeros((10, HL, WL))
+    lib().or_sp_level(W, H, _p(sp), _p(_f64(c_near)), _p(_f64(c_far)), _p(_f64(hit)),
+                      _p(None if hit_acc is None else _f64(hit_acc)), _p(_f64(coc_nf)), float(r_cap),
+                      int(level), _p(out))
+    return out
+
+
+def spatial(spp, c_near, c_far, hit, hit_acc, coc_nf, V, n_taps=24, r_cap=64.0, v_clamp=0.01) -> dict:
+    """Spatial reconstruction of the near and far traced colours (paper,
+    Reconstruction, last paragraph): returns c_near, c_far and the
+    ambiguity flags.  `hit_acc` None: the latest hit ratio stands for the
+    accumulated one; `V` None: no variance estimate (full weight)."""
+    sp = _i32(spp)
+    H, W = sp.shape
+    cno, cfo = np.zeros((3, H, W)), np.zeros((3, H, W))
+    am = np.zeros((H, W), np.int32)
+    lib().or_spatial(W, H, _p(sp), _p(_f64(c_near)), _p(_f64(c_far)), _p(_f64(hit)),
+                     _p(None if hit_acc is None else _f64(hit_acc)), _p(_f64(coc_nf)),
+                     _p(None if V is None else _f64(V)), int(n_taps), float(r_cap), float(v_clamp),
+                     _p(cno), _p(cfo), _p(am))
+    return dict(c_near=cno, c_far=cfo, amb=am)
+
+
+def history_variance(hist: dict) -> np.ndarray:
+    """The variance estimate a variance history holds: +inf where new,
+    max(0, m2 - m1^2) where valid, 0 elsewhere."""
+    fl = _i32(hist["flags"])
+    V = np.maximum(0.0, _f64(hist["lum_m2"]) - _f64(hist["lum_m1"]) ** 2)
+    V = np.where(fl & VALID, V, 0.0)
+    return np.where(fl & NEW, np.inf, V)
 
 
 def pp_composite_backward(camera, lens, color, depth, spp, c_near, c_far, hit, pp, cp, grad_out):

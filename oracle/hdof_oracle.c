@@ -616,13 +616,17 @@ int or_mask(int W, int H, const double* z, const double* nrm, const double* V,
 /* far_pos (nullable, 4 planes of n): over the rays that hit, the far-weighted */
 /* mean hit point sum (1-w) P / sum (1-w) (planes 0-2) and sum (1-w) (plane */
 /* 3); 0 when no ray hits with a far weight.                                  */
+/* coc_nf (nullable, 2 planes of n): the average CoC size of the pixel's near */
+/* and far rays, sum w |c| / sum w and sum (1-w) |c| / sum (1-w) (0 when the */
+/* weight sum is 0; a miss counts at depth OR_ZMAX), the per-frame CoC that  */
+/* the spatial reconstruction blends.                                        */
 /* ------------------------------------------------------------------------- */
 void or_trace(const or_scene* s, const double* cam, int W, int H, const double* lens, const double* light,
               const int64_t* pix, const int* spp, int64_t n, const int64_t* ray_base,
               uint64_t seed, uint64_t frame, uint64_t view,
               int* ray_id, double* ray_z, double* ray_L, int* ray_amb, int64_t n_rays,
               double* c_near, double* c_far, double* hit, double* m1, double* m2, int* px_amb,
-              double* far_pos) {
+              double* far_pos, double* coc_nf) {
   cam_t k = mk_cam(cam, W, H);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t i = 0; i < n; ++i) {
@@ -630,7 +634,7 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
     int x = (int)(p % W), y = (int)(p / W);
     int ns = spp[i];
     double Nw = 0.0, Fw = 0.0, sn[3] = {0, 0, 0}, sf[3] = {0, 0, 0}, sy = 0.0, sy2 = 0.0;
-    double Pw = 0.0, sP[3] = {0, 0, 0};
+    double Pw = 0.0, sP[3] = {0, 0, 0}, scn = 0.0, scf = 0.0;
     int pa = 0;
     for (int j = 0; j < ns; ++j) {
       double O[3], D[3];
@@ -642,6 +646,7 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
       double c = coc_px(&k, lens, zz);
       double w = clampd(0.5 - c / (2.0 * OR_SQRT2), 0.0, 1.0);
       Nw += w; Fw += 1.0 - w;
+      scn += w * fabs(c); scf += (1.0 - w) * fabs(c);
       for (int q = 0; q < 3; ++q) { sn[q] += w * L[q]; sf[q] += (1.0 - w) * L[q]; }
       if (h.id >= 0) {
         Pw += 1.0 - w;
@@ -670,6 +675,10 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
     if (far_pos) {
       for (int q = 0; q < 3; ++q) far_pos[(size_t)q * n + i] = Pw > 0.0 ? sP[q] / Pw : 0.0;
       far_pos[(size_t)3 * n + i] = Pw;
+    }
+    if (coc_nf) {
+      coc_nf[i] = Nw > 0.0 ? scn / Nw : 0.0;
+      coc_nf[(size_t)n + i] = Fw > 0.0 ? scf / Fw : 0.0;
     }
   }
 }
@@ -875,6 +884,144 @@ void or_recon(const double* cam, int W, int H, const double* z, const int* spp,
       hist_out[3 * N + p] = Hn;
       hist_out[7 * N + p] = Hf;
       hvalid_out[p] = 1;
+      if (amb) amb[p] = am;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spatial reconstruction of the near and far ray-traced colours (our reading */
+/* of the last paragraph of the paper's Reconstruction section: the near and */
+/* far CoC sizes blended by the accumulated hit ratio set the radius and the */
+/* sampling level of detail of a circular gather; neighbours whose CoC      */
+/* radius is smaller than their distance are rejected as in the post-filter; */
+/* a clamped variance estimate weights the gathered colour).                 */
+/* Per traced pixel q (s_q = spp > 0), with H_q its accumulated hit ratio    */
+/* (the latest one, h_q, without temporal history) and cbar the mean |CoC|  */
+/* of its near / far rays:                                                   */
+/*   r_q = min(r_cap, (H_q cbar_n(q) + (1 - H_q) cbar_f(q)) / 2).            */
+/* Level L texel (i, j) = the traced pixels q of the block                  */
+/*   [i 2^L, (i+1) 2^L) x [j 2^L, (j+1) 2^L), summed:                        */
+/*   An = sum s h C_tn, Bn = sum s h, Af = sum s (1-h) C_tf, Bf = sum s (1-h),*/
+/*   rho = sum r, kappa = count   (s h: the pixel's near-ray weight).       */
+/* Traced pixel p at (x, y), N taps:                                         */
+/*   L = floor(log2(r_p sqrt(pi / N))) clamped to [0, OR_SP_LMAX] (texels no */
+/*   wider than the taps' mean spacing; L = 0 when r_p sqrt(pi/N) < 1);      */
+/*   tap k: u_k = sqrt((k - 0.5)/N) (cos k g, sin k g), g = pi (3 - sqrt 5); */
+/*   the pixel containing (x + 0.5, y + 0.5) + r_p u_k, clamped to the      */
+/*   image, shifted right by L gives the texel; d_k = r_p |u_k|;             */
+/*   a_k = clamp(rho / kappa - d_k + 0.5, 0, 1) (0 when kappa = 0).          */
+/*   G_n = (s_p h_p C_tn(p) + sum_k a_k An_k) / (s_p h_p + sum_k a_k Bn_k),   */
+/*   C_tn(p) when the denominator is 0; G_f alike with the far sums.         */
+/*   lambda = clamp(V_p / v_clamp, 0, 1), 1 where V_p = +inf or no variance  */
+/*   is given; C_tn' = C_tn + lambda (G_n - C_tn), C_tf' alike.             */
+/* Untraced pixels are copied.  amb marks a level decision within OR_EPS     */
+/* (relative) of a power of two, or a tap coordinate within OR_EPS of a     */
+/* pixel boundary.                                                           */
+/* ------------------------------------------------------------------------- */
+#define OR_SP_LMAX 5
+
+typedef struct {
+  int W, H;
+  const int* spp;
+  const double *cn, *cf, *h, *hacc, *coc;
+  double r_cap;
+} sp_in_t;
+
+static double sp_radius(const sp_in_t* I, size_t q) {
+  double Hq = I->hacc ? I->hacc[q] : I->h[q];
+  size_t N = (size_t)I->W * I->H;
+  return mind(I->r_cap, 0.5 * (Hq * I->coc[q] + (1.0 - Hq) * I->coc[N + q]));
+}
+
+/* the sums of level-L texel (i, j): o[0..2] An, o[3] Bn, o[4..6] Af, o[7] Bf,
+ * o[8] rho, o[9] kappa */
+static void sp_texel(const sp_in_t* I, int L, int i, int j, double* o) {
+  size_t N = (size_t)I->W * I->H;
+  for (int a = 0; a < 10; ++a) o[a] = 0.0;
+  int b = 1 << L;
+  for (int y = j * b; y < (j + 1) * b && y < I->H; ++y)
+    for (int x = i * b; x < (i + 1) * b && x < I->W; ++x) {
+      size_t q = (size_t)y * I->W + x;
+      if (I->spp[q] <= 0) continue;
+      double s = I->spp[q], hq = I->h[q];
+      for (int c = 0; c < 3; ++c) {
+        o[c] += s * hq * I->cn[c * N + q];
+        o[4 + c] += s * (1.0 - hq) * I->cf[c * N + q];
+      }
+      o[3] += s * hq;
+      o[7] += s * (1.0 - hq);
+      o[8] += sp_radius(I, q);
+      o[9] += 1.0;
+    }
+}
+
+void or_sp_level(int W, int H, const int* spp, const double* cn, const double* cf, const double* h,
+                 const double* hacc, const double* coc, double r_cap, int L, double* out) {
+  sp_in_t I = {W, H, spp, cn, cf, h, hacc, coc, r_cap};
+  int WL = (W + (1 << L) - 1) >> L, HL = (H + (1 << L) - 1) >> L;
+  size_t NL = (size_t)WL * HL;
+#pragma omp parallel for
+  for (int j = 0; j < HL; ++j)
+    for (int i = 0; i < WL; ++i) {
+      double o[10];
+      sp_texel(&I, L, i, j, o);
+      for (int a = 0; a < 10; ++a) out[a * NL + (size_t)j * WL + i] = o[a];
+    }
+}
+
+static int near_boundary(double v) {
+  double f = floor(v);
+  double e = OR_EPS * maxd(1.0, fabs(v));
+  return v - f < e || f + 1.0 - v < e;
+}
+
+void or_spatial(int W, int H, const int* spp, const double* cn, const double* cf, const double* h,
+                const double* hacc, const double* coc, const double* V, int n_taps, double r_cap,
+                double v_clamp, double* cn_out, double* cf_out, int* amb) {
+  sp_in_t I = {W, H, spp, cn, cf, h, hacc, coc, r_cap};
+  size_t N = (size_t)W * H;
+  const double g = OR_PI * (3.0 - sqrt(5.0));
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      size_t p = (size_t)y * W + x;
+      int am = 0;
+      for (int c = 0; c < 3; ++c) { cn_out[c * N + p] = cn[c * N + p]; cf_out[c * N + p] = cf[c * N + p]; }
+      if (spp[p] <= 0) { if (amb) amb[p] = 0; continue; }
+      double rp = sp_radius(&I, p);
+      double spacing = rp * sqrt(OR_PI / n_taps);
+      int L = 0;
+      if (spacing >= 1.0) L = (int)floor(log2(spacing));
+      if (L > OR_SP_LMAX) L = OR_SP_LMAX;
+      if (spacing > 0.0) {
+        double lg = log2(spacing);
+        if (fabs(lg - floor(lg + 0.5)) < OR_EPS && floor(lg + 0.5) >= 0.0 && floor(lg + 0.5) <= OR_SP_LMAX) am = 1;
+      }
+      double sn = spp[p] * h[p], sf = spp[p] * (1.0 - h[p]);
+      double An[3], Af[3], Bn = sn, Bf = sf;
+      for (int c = 0; c < 3; ++c) { An[c] = sn * cn[c * N + p]; Af[c] = sf * cf[c * N + p]; }
+      for (int k = 1; k <= n_taps; ++k) {
+        double rr = sqrt((k - 0.5) / n_taps);
+        double ux = rr * cos(k * g), uy = rr * sin(k * g);
+        double fx = x + 0.5 + rp * ux, fy = y + 0.5 + rp * uy;
+        if (near_boundary(fx) || near_boundary(fy)) am = 1;
+        int px = clampi((int)floor(fx), 0, W - 1), py = clampi((int)floor(fy), 0, H - 1);
+        double o[10];
+        sp_texel(&I, L, px >> L, py >> L, o);
+        if (o[9] <= 0.0) continue;
+        double a = clampd(o[8] / o[9] - rp * rr + 0.5, 0.0, 1.0);
+        for (int c = 0; c < 3; ++c) { An[c] += a * o[c]; Af[c] += a * o[4 + c]; }
+        Bn += a * o[3];
+        Bf += a * o[7];
+      }
+      double lam = 1.0;
+      if (V && !isinf(V[p])) lam = clampd(V[p] / v_clamp, 0.0, 1.0);
+      for (int c = 0; c < 3; ++c) {
+        double Gn = Bn > 0.0 ? An[c] / Bn : cn[c * N + p];
+        double Gf = Bf > 0.0 ? Af[c] / Bf : cf[c * N + p];
+        cn_out[c * N + p] = cn[c * N + p] + lam * (Gn - cn[c * N + p]);
+        cf_out[c * N + p] = cf[c * N + p] + lam * (Gf - cf[c * N + p]);
+      }
       if (amb) amb[p] = am;
     }
 }

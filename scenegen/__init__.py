@@ -104,6 +104,14 @@ class ReconParams:
 
 
 @dataclass
+class SpatialParams:
+    enable: bool = False
+    n_taps: int = 24
+    r_cap: float = 64.0
+    v_clamp: float = 0.01
+
+
+@dataclass
 class FrameConfig:
     """Everything one frame of the path needs besides the scene."""
     name: str
@@ -115,6 +123,7 @@ class FrameConfig:
     comp: CompositeParams
     seed: int = 0
     recon: ReconParams = field(default_factory=ReconParams)
+    spatial: SpatialParams = field(default_factory=SpatialParams)
 
 
 # ----------------------------------------------------------------------------
