@@ -11,6 +11,8 @@
  *   near/far split and hit ratio (Ray Trace)                 -> hdof_trace_thin_lens
  *   temporal reconstruction of the near and far traced
  *   colours (Reconstruction)                                 -> hdof_rt_reconstruct
+ *   spatial reconstruction of the traced colours
+ *   (Reconstruction)                                         -> hdof_rt_spatial
  *   variance history update (Ray Trace)                      -> hdof_variance_update
  *   post-process gather filter (Design; rejection rule from
  *   Reconstruction)                                          -> hdof_postfilter
@@ -116,11 +118,22 @@ typedef struct {
   float alpha;
 } hdof_recon_params;
 
+/* Spatial reconstruction of the traced colours (paper, Reconstruction, last
+ * paragraph).  enable in {0, 1} (read by hdof_frame only); n_taps in
+ * [1, 256]: golden-angle taps of the gather; r_cap in [0, 256]: largest
+ * gather radius (px); v_clamp > 0: variance estimate at and above which the
+ * gathered colour fully replaces the pixel's own. */
+typedef struct {
+  int32_t enable, n_taps;
+  float r_cap, v_clamp;
+} hdof_spatial_params;
+
 typedef struct {
   hdof_mask_params mask;
   hdof_pp_params pp;
   hdof_composite_params comp;
   hdof_recon_params recon;
+  hdof_spatial_params spatial;
 } hdof_frame_params;
 
 /* G-buffer planes: depth [H][W] (axial, 1e4 on a miss), normal [3][H][W]
@@ -232,13 +245,17 @@ hdof_status hdof_ray_mask(hdof_ctx* ctx, const hdof_gbuffer_bufs* in, const hdof
  * each needs W*H*spp_max entries.  Optional d_far_pos [4][H][W]: over the
  * pixel's rays that hit, the (1 - w)-weighted mean hit point (planes 0-2,
  * world coordinates) and the weight sum (plane 3; 0: no far hit), the input
- * of hdof_rt_reconstruct. */
+ * of hdof_rt_reconstruct.  Optional d_coc_nf [2][H][W]: the average CoC
+ * size (diameter, px) of the pixel's near rays, sum w |c| / sum w, and of
+ * its far rays, sum (1 - w) |c| / sum (1 - w) (0 where the weight sum is 0;
+ * a miss counts at depth 1e4), the input of hdof_rt_spatial. */
 hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
                                  const hdof_lens* lens, const hdof_light* light, int32_t spp_max,
                                  const uint8_t* d_spp, const int32_t* d_offsets,
                                  const int32_t* d_total, uint32_t seed, uint32_t frame,
                                  uint32_t view, hdof_rt_bufs out, int32_t* d_ray_tri_id,
-                                 float* d_ray_depth, float* d_far_pos, hdof_stream stream);
+                                 float* d_ray_depth, float* d_far_pos, float* d_coc_nf,
+                                 hdof_stream stream);
 
 /* Temporal reconstruction of the near and far traced colours (paper,
  * Reconstruction: exponential moving average as in TAA; near pixels
@@ -274,6 +291,32 @@ hdof_status hdof_recon_history_load(hdof_ctx* ctx, int32_t width, int32_t height
 hdof_status hdof_recon_history_save(hdof_ctx* ctx, float* d_planes, uint8_t* d_valid, float* d_depth,
                                     hdof_stream stream);
 hdof_status hdof_recon_history_reset(hdof_ctx* ctx);
+
+/* Spatial reconstruction of the near and far traced colours (paper,
+ * Reconstruction: the near and far CoC sizes blended by the accumulated hit
+ * ratio scale a circular gather and set its level of detail; samples whose
+ * CoC radius is smaller than their distance are rejected; a clamped variance
+ * estimate weights the gathered colour).  Per traced pixel q (d_spp > 0),
+ * with H the accumulated hit ratio (d_hit_acc, or rt.hit_ratio when NULL)
+ * and d_coc_nf as hdof_trace_thin_lens writes it:
+ *   r_q = min(r_cap, (H c_near_avg + (1 - H) c_far_avg) / 2).
+ * A level-L texel (L = 1..5, 2^L x 2^L pixels) sums over its traced pixels
+ * s h C_near, s h, s (1-h) C_far, s (1-h), r and their count (s = rays,
+ * h = hit ratio); level 0 is the pixels themselves.  A traced pixel p uses
+ * L = floor(log2(r_p sqrt(pi / n_taps))) clamped to [0, 5] and the taps
+ * u_k of hdof_postfilter scaled by r_p: each tap takes the level-L texel of
+ * the pixel it falls in (clamped to the image) with weight
+ * clamp(rbar - r_p |u_k| + 0.5, 0, 1), rbar the texel's mean radius.
+ * G_near = (s h C_near(p) + sum of weighted near sums) / (s h + sum of
+ * weighted near weights) (C_near(p) when the denominator is 0), G_far
+ * alike; lambda = clamp(V / v_clamp, 0, 1) with V = d_variance[p] (+inf or
+ * d_variance == NULL: lambda = 1); out = C + lambda (G - C).  Untraced
+ * pixels are copied.  Outputs [3][H][W] must not alias the inputs.  Uses
+ * library scratch (the pyramid, 48 B per 4 pixels). */
+hdof_status hdof_rt_spatial(hdof_ctx* ctx, int32_t width, int32_t height, const uint8_t* d_spp,
+                            hdof_rt_bufs rt, const float* d_hit_acc, const float* d_coc_nf,
+                            const float* d_variance, const hdof_spatial_params* params,
+                            float* d_c_near_out, float* d_c_far_out, hdof_stream stream);
 
 /* Variance history update (paper, Ray Trace: temporally accumulated variance).
  * Where traced: EMA with weight params->var_alpha over the reprojected
@@ -321,9 +364,12 @@ hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_p
 /* Whole frame: G-buffer -> mask (reprojecting the history when prev != NULL)
  * -> trace -> variance update -> temporal reconstruction of the traced
  * colours (when params->recon.enable; its history is read when prev !=
- * NULL) -> post-process -> composite.  d_out [3][H][W].  `keep` (nullable)
- * supplies caller buffers for intermediates (keep->rt receives the
- * reconstructed colours when reconstruction is on). */
+ * NULL) -> spatial reconstruction (when params->spatial.enable; accumulated
+ * hit ratio from the temporal history when that runs, variance estimate from
+ * the variance history just updated) -> post-process -> composite.
+ * d_out [3][H][W].  `keep` (nullable) supplies caller buffers for
+ * intermediates (keep->rt receives the reconstructed colours when
+ * reconstruction is on).  The batched form refuses both reconstructions. */
 hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
                        const hdof_camera* prev, const hdof_lens* lens, const hdof_light* light,
                        const hdof_frame_params* params, uint32_t seed, uint32_t frame,
@@ -347,8 +393,10 @@ typedef struct {
   float* d_out;
 } hdof_view;
 
-/* The batched form rejects params->recon.enable = 1 (HDOF_ERR_UNSUPPORTED):
- * a reconstruction history belongs to one view's camera path.
+/* The batched form rejects params->recon.enable = 1 and
+ * params->spatial.enable = 1 (HDOF_ERR_UNSUPPORTED): a reconstruction
+ * history belongs to one view's camera path, and the spatial stage is not
+ * batched.
  * Every view's G-buffer, mask, post-filter and composite (one launch each),
  * one device-side scan of the per-view ray totals, ONE queue over all views
  * and ONE persistent thin-lens trace launch for the whole batch.  No
@@ -411,7 +459,8 @@ hdof_status hdof_postfilter_composite_backward(hdof_ctx* ctx, const float* d_col
 
 /* Stages hdof_frame brackets with HIP events while profiling is on, in
  * order: G-buffer, ray mask, queue build, thin-lens trace kernel, per-pixel
- * reduction, variance update, temporal reconstruction (0 when disabled),
+ * reduction, variance update, temporal and spatial reconstruction (0 when
+ * both are disabled),
  * post-filter preparation (pack, tile radius, taps), post-filter gather,
  * composite. */
 #define HDOF_PROFILE_STAGES 10

@@ -444,18 +444,19 @@ def sp_level(spp, c_near, c_far, hit, hit_acc, coc_nf, r_cap: float, level: int)
 
 def spatial(spp, c_near, c_far, hit, hit_acc, coc_nf, V, n_taps=24, r_cap=64.0, v_clamp=0.01) -> dict:
     """Spatial reconstruction of the near and far traced colours (paper,
-    Reconstruction, last paragraph): returns c_near, c_far and the
-    ambiguity flags.  `hit_acc` None: the latest hit ratio stands for the
-    accumulated one; `V` None: no variance estimate (full weight)."""
+    Reconstruction, last paragraph): returns c_near, c_far and `cond`, the
+    conditioning of each output on the acceptance weights (near, far).
+    `hit_acc` None: the latest hit ratio stands for the accumulated one; `V`
+    None: no variance estimate (full weight)."""
     sp = _i32(spp)
     H, W = sp.shape
     cno, cfo = np.zeros((3, H, W)), np.zeros((3, H, W))
-    am = np.zeros((H, W), np.int32)
+    cond = np.zeros((2, H, W))
     lib().or_spatial(W, H, _p(sp), _p(_f64(c_near)), _p(_f64(c_far)), _p(_f64(hit)),
                      _p(None if hit_acc is None else _f64(hit_acc)), _p(_f64(coc_nf)),
                      _p(None if V is None else _f64(V)), int(n_taps), float(r_cap), float(v_clamp),
-                     _p(cno), _p(cfo), _p(am))
-    return dict(c_near=cno, c_far=cfo, amb=am)
+                     _p(cno), _p(cfo), _p(cond))
+    return dict(c_near=cno, c_far=cfo, cond=cond)
 
 
 def history_variance(hist: dict) -> np.ndarray:

@@ -124,6 +124,15 @@ static hdof_status check_recon(const hdof_recon_params* r) {
   return HDOF_OK;
 }
 
+static hdof_status check_spatial(const hdof_spatial_params* sp) {
+  REQUIRE(sp, "spatial params are NULL");
+  REQUIRE(sp->enable == 0 || sp->enable == 1, "spatial enable must be 0 or 1");
+  REQUIRE(sp->n_taps >= 1 && sp->n_taps <= 256, "spatial n_taps must be in [1, 256]");
+  REQUIRE(isfinite(sp->r_cap) && sp->r_cap >= 0.0f && sp->r_cap <= 256.0f, "spatial r_cap must be in [0, 256]");
+  REQUIRE(isfinite(sp->v_clamp) && sp->v_clamp > 0.0f, "spatial v_clamp must be finite and > 0");
+  return HDOF_OK;
+}
+
 static hdof_status check_ctx(hdof_ctx* ctx) {
   REQUIRE(ctx, "context is NULL");
   hipError_t e = hipSetDevice(ctx->device);
@@ -197,7 +206,9 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->hist_m2, &ctx->hist_flags, &ctx->hist_z, &ctx->rep_m1, &ctx->rep_m2,
                 &ctx->rep_flags, &ctx->f_depth, &ctx->f_normal, &ctx->f_albedo, &ctx->f_color,
                 &ctx->f_triid, &ctx->f_spp, &ctx->f_offsets, &ctx->f_total, &ctx->f_cn, &ctx->f_cf,
-                &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp};
+                &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp, &ctx->rec_hist[0], &ctx->rec_hist[1],
+                &ctx->rec_valid[0], &ctx->rec_valid[1], &ctx->rec_farpos, &ctx->sp_levels, &ctx->sp_taps,
+                &ctx->sp_cn, &ctx->sp_cf, &ctx->sp_coc};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
   buf_free(ctx->ppb_args);
@@ -333,7 +344,8 @@ extern "C" hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* sce
                                             const uint8_t* d_spp, const int32_t* d_offsets,
                                             const int32_t* d_total, uint32_t seed, uint32_t frame,
                                             uint32_t view, hdof_rt_bufs out, int32_t* d_ray_tri_id,
-                                            float* d_ray_depth, float* d_far_pos, hdof_stream stream) {
+                                            float* d_ray_depth, float* d_far_pos, float* d_coc_nf,
+                                            hdof_stream stream) {
   TRY(check_ctx(ctx));
   REQUIRE(scene, "scene is NULL");
   TRY(check_camera(cam, "current"));
@@ -346,7 +358,7 @@ extern "C" hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* sce
   CamK k = make_camk(cam);
   return launch_trace(ctx, scene, k, make_lensk(lens, k), make_lightk(light), spp_max, d_spp, d_offsets,
                       d_total, seed, frame, view, out, d_ray_tri_id, d_ray_depth, d_far_pos,
-                      (hipStream_t)stream);
+                      (hipStream_t)stream, nullptr, false, d_coc_nf);
 }
 
 extern "C" hdof_status hdof_variance_update(hdof_ctx* ctx, const hdof_camera* cam,
@@ -466,6 +478,23 @@ extern "C" hdof_status hdof_recon_history_reset(hdof_ctx* ctx) {
   return HDOF_OK;
 }
 
+extern "C" hdof_status hdof_rt_spatial(hdof_ctx* ctx, int32_t width, int32_t height, const uint8_t* d_spp,
+                                       hdof_rt_bufs rt, const float* d_hit_acc, const float* d_coc_nf,
+                                       const float* d_variance, const hdof_spatial_params* params,
+                                       float* d_c_near_out, float* d_c_far_out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(width > 0 && height > 0 && width <= 16384 && height <= 16384, "image size out of range");
+  REQUIRE(d_spp && d_coc_nf, "spp and coc_nf must be non-NULL");
+  REQUIRE(rt.c_near && rt.c_far && rt.hit_ratio, "rt c_near, c_far and hit_ratio must be non-NULL");
+  REQUIRE(d_c_near_out && d_c_far_out, "outputs must be non-NULL");
+  REQUIRE(d_c_near_out != rt.c_near && d_c_near_out != rt.c_far && d_c_far_out != rt.c_near &&
+              d_c_far_out != rt.c_far && d_c_near_out != d_c_far_out,
+          "outputs must not alias the input colours or each other");
+  TRY(check_spatial(params));
+  return launch_spatial(ctx, width, height, d_spp, rt, d_hit_acc, d_coc_nf, d_variance, false, *params,
+                        d_c_near_out, d_c_far_out, (hipStream_t)stream);
+}
+
 extern "C" hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, const float* d_depth,
                                        const hdof_camera* cam, const hdof_lens* lens,
                                        const hdof_pp_params* params, float* d_out, hdof_stream stream) {
@@ -520,6 +549,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(check_pp(&params->pp));
   TRY(check_comp(&params->comp));
   TRY(check_recon(&params->recon));
+  TRY(check_spatial(&params->spatial));
   TRY(check_capacity(cam, params->mask.spp_max));
   REQUIRE(d_out, "out is NULL");
   hdof_frame_bufs z;
@@ -574,6 +604,20 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(hdof_ensure(ctx->queue, sizeof(int) * cap));
   TRY(hdof_ensure(ctx->ray_col, sizeof(float) * 3 * cap));
   TRY(hdof_ensure(ctx->ray_z, sizeof(float) * cap));
+  // spatial reconstruction: the trace (and the temporal stage) work on
+  // scratch colours that the spatial gather reads, writing the frame's
+  float* coc_nf = nullptr;
+  hdof_rt_bufs rt_tr = rt;
+  const bool spatial = params->spatial.enable;
+  if (spatial) {
+    TRY(hdof_ensure(ctx->sp_cn, sizeof(float) * 3 * N));
+    TRY(hdof_ensure(ctx->sp_cf, sizeof(float) * 3 * N));
+    TRY(hdof_ensure(ctx->sp_coc, sizeof(float) * 2 * N));
+    TRY(spatial_reserve(ctx, cam->width, cam->height));
+    rt_tr.c_near = (float*)ctx->sp_cn.p;
+    rt_tr.c_far = (float*)ctx->sp_cf.p;
+    coc_nf = (float*)ctx->sp_coc.p;
+  }
   float* far_pos = nullptr;
   if (params->recon.enable) {
     TRY(hdof_ensure(ctx->rec_farpos, sizeof(float) * 4 * N));
@@ -597,11 +641,16 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   VarFuse vf;
   if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf);
   if (s == HDOF_OK)
-    s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt,
-                     nullptr, nullptr, far_pos, st, &vf, true);  // marks 3, 4
-  if (params->recon.enable) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
+    s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt_tr,
+                     nullptr, nullptr, far_pos, st, &vf, true, coc_nf);  // marks 3, 4
+  if (params->recon.enable || spatial) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
   if (s == HDOF_OK && params->recon.enable)
-    s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt, params->recon.alpha, st);
+    s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt_tr, params->recon.alpha, st);
+  // the accumulated hit ratio: plane 3 of the temporal history just written
+  if (s == HDOF_OK && spatial)
+    s = launch_spatial(ctx, cam->width, cam->height, spp, rt_tr,
+                       params->recon.enable ? (const float*)ctx->rec_hist[ctx->rec_cur].p + 3 * N : nullptr, coc_nf,
+                       nullptr, true, params->spatial, rt.c_near, rt.c_far, st);
   hdof_prof_mark(ctx, 7, st);
   if (fused) {
     const PostFuse pf{spp, rt, params->comp, d_out};
@@ -734,6 +783,10 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
   TRY(check_pp(&params->pp));
   TRY(check_comp(&params->comp));
   TRY(check_recon(&params->recon));
+  TRY(check_spatial(&params->spatial));
+  if (params->spatial.enable)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the batched form does not run the spatial reconstruction "
+                                                "(call hdof_frame per view)");
   if (params->recon.enable)
     return hdof_set_error(HDOF_ERR_UNSUPPORTED, "temporal reconstruction needs one history per view: "
                           "not available in the batched form");

@@ -86,6 +86,10 @@ struct hdof_ctx {
   int rec_w = 0, rec_h = 0, rec_cur = 0;
   bool rec_any = false;
   Buf rec_hist[2], rec_valid[2], rec_farpos;
+  // spatial reconstruction: box pyramid of the traced pixels (levels 1..5),
+  // its tap table, and the frame's pre-gather colours and CoC averages
+  Buf sp_levels, sp_taps, sp_cn, sp_cf, sp_coc;
+  int sp_taps_n = 0;
   // frame intermediates when the caller keeps none
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
@@ -282,9 +286,16 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
                          hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st,
-                         const VarFuse* vf = nullptr, bool queue_ready = false);
+                         const VarFuse* vf = nullptr, bool queue_ready = false, float* coc_nf = nullptr);
 hdof_status launch_recon(hdof_ctx* ctx, const CamK& k, const CamK* prev, const float* depth, const uint8_t* spp,
                          const float* far_pos, hdof_rt_bufs rt, float alpha, hipStream_t st);
+// spatial reconstruction: in -> (cn_out, cf_out); hacc nullable (latest hit
+// ratio); variance plane nullable; var_from_history: the variance estimate
+// of the context's current variance history instead
+hdof_status spatial_reserve(hdof_ctx* ctx, int W, int H);
+hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof_rt_bufs in, const float* hacc,
+                           const float* coc_nf, const float* variance, bool var_from_history,
+                           const hdof_spatial_params& sp, float* cn_out, float* cf_out, hipStream_t st);
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
                         int32_t* total, hipStream_t st,

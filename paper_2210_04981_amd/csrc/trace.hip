@@ -539,18 +539,20 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
 // direction's forward component is S1) and its weight, 4 planes.
 // VAR (whole frames): the variance history update of the pixel as well,
 // from the moments just formed.
+// coc_nf (nullable, 2 planes): the average CoC size of the near rays and of
+// the far rays, sum w |c| / sum w and sum (1 - w) |c| / sum (1 - w).
 template <bool FARPOS, bool VAR>
 __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
                             const int* __restrict__ ebase, const float* __restrict__ ray_col,
                             const float* __restrict__ ray_z, size_t cap, LensK l, float* __restrict__ cn,
                             float* __restrict__ cf, float* __restrict__ h, float* __restrict__ m1,
                             float* __restrict__ m2, CamK k, uint32_t seed, uint32_t frame, uint32_t view,
-                            float* __restrict__ far_pos, VarFuse vf) {
+                            float* __restrict__ far_pos, VarFuse vf, float* __restrict__ coc_nf) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   int s = spp[p];
   float Nw = 0.f, Fw = 0.f, snr = 0.f, sng = 0.f, snb = 0.f, sfr = 0.f, sfg = 0.f, sfb = 0.f, sy = 0.f, sy2 = 0.f;
-  float Pw = 0.f, spx_ = 0.f, spy_ = 0.f, spz_ = 0.f;
+  float Pw = 0.f, spx_ = 0.f, spy_ = 0.f, spz_ = 0.f, scn = 0.f, scf = 0.f;
   long o = (long)offsets[p] + (ebase ? *ebase : 0);
   if (o < 0 || o + s > (long)cap) s = 0;  // inconsistent offsets: nothing was traced here
   if (s > 0) {
@@ -572,6 +574,8 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
       }
       Nw += w;
       Fw += wf;
+      scn = fmaf(w, fabsf(c), scn);
+      scf = fmaf(wf, fabsf(c), scf);
       snr = fmaf(w, R, snr);
       sng = fmaf(w, G, sng);
       snb = fmaf(w, B, snb);
@@ -620,6 +624,10 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
     far_pos[N + p] = spy_ * ip;
     far_pos[2 * (size_t)N + p] = spz_ * ip;
     far_pos[3 * (size_t)N + p] = Pw;
+  }
+  if (coc_nf) {
+    coc_nf[p] = scn * in_;
+    coc_nf[N + p] = scf * if_;
   }
 }
 
@@ -691,7 +699,7 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,
                          hdof_rt_bufs out, int32_t* ray_id, float* ray_depth, float* far_pos, hipStream_t st,
-                         const VarFuse* vf, bool queue_ready) {
+                         const VarFuse* vf, bool queue_ready, float* coc_nf) {
   const int N = k.W * k.H;
   const size_t cap = (size_t)N * (size_t)spp_max;
   hdof_status s;
@@ -714,7 +722,7 @@ hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, con
                       : (vf ? k_rt_reduce<false, true> : k_rt_reduce<false, false>);
   hipLaunchKernelGGL(kern, dim3(cdiv(N, 256)), dim3(256), 0, st, spp, offsets, N, (const int*)nullptr,
                      (const float*)ctx->ray_col.p, (const float*)rz, cap, l, out.c_near, out.c_far, out.hit_ratio,
-                     out.lum_m1, out.lum_m2, k, seed, frame, view, far_pos, vz);
+                     out.lum_m1, out.lum_m2, k, seed, frame, view, far_pos, vz, coc_nf);
   if (!vf) hdof_prof_mark(ctx, 5, st);  // fused: the variance update stage is part of this one
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
@@ -756,7 +764,7 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
     hipLaunchKernelGGL(red, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb,
                        N, (const int*)(ebase + v), (const float*)ctx->ray_col.p, (const float*)ctx->ray_z.p, cap,
                        hviews[v].l, rt[v].c_near, rt[v].c_far, rt[v].hit_ratio, rt[v].lum_m1, rt[v].lum_m2,
-                       hviews[v].k, 0u, 0u, 0u, (float*)nullptr, VarFuse{});
+                       hviews[v].k, 0u, 0u, 0u, (float*)nullptr, VarFuse{}, (float*)nullptr);
   }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;

@@ -62,8 +62,13 @@ class ReconParams(C.Structure):
     _fields_ = [("enable", C.c_int32), ("alpha", C.c_float)]
 
 
+class SpatialParams(C.Structure):
+    _fields_ = [("enable", C.c_int32), ("n_taps", C.c_int32), ("r_cap", C.c_float), ("v_clamp", C.c_float)]
+
+
 class FrameParams(C.Structure):
-    _fields_ = [("mask", MaskParams), ("pp", PPParams), ("comp", CompositeParams), ("recon", ReconParams)]
+    _fields_ = [("mask", MaskParams), ("pp", PPParams), ("comp", CompositeParams), ("recon", ReconParams),
+                ("spatial", SpatialParams)]
 
 
 P = C.c_void_p
@@ -114,7 +119,8 @@ _PROTOS = {
     "hdof_ray_mask": (_S, [P, C.POINTER(GBufferBufs), C.POINTER(Camera), C.POINTER(Camera),
                            C.POINTER(Lens), C.POINTER(MaskParams), P, P, P, P]),
     "hdof_trace_thin_lens": (_S, [P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(Light), _i32,
-                                  P, P, P, _u32, _u32, _u32, RTBufs, P, P, P, P]),
+                                  P, P, P, _u32, _u32, _u32, RTBufs, P, P, P, P, P]),
+    "hdof_rt_spatial": (_S, [P, _i32, _i32, P, RTBufs, P, P, P, C.POINTER(SpatialParams), P, P, P]),
     "hdof_rt_reconstruct": (_S, [P, C.POINTER(Camera), C.POINTER(Camera), P, P, P, RTBufs,
                                  C.POINTER(ReconParams), P]),
     "hdof_recon_history_load": (_S, [P, _i32, _i32, P, P, P, P]),
@@ -366,7 +372,7 @@ def hdof_trace_thin_lens(ctx: Context, scene: Scene, cam: Camera, lns: Lens, lit
                          spp: torch.Tensor, offsets: torch.Tensor, total: torch.Tensor, seed=0, frame=0, view=0,
                          out: RTResult | None = None, ray_tri_id: torch.Tensor | None = None,
                          ray_depth: torch.Tensor | None = None, far_pos: torch.Tensor | None = None,
-                         stream=None) -> RTResult:
+                         coc_nf: torch.Tensor | None = None, stream=None) -> RTResult:
     n = _npx(cam)
     out = RTResult.empty(cam.height, cam.width) if out is None else out
     cap = n * int(spp_max)
@@ -376,9 +382,25 @@ def hdof_trace_thin_lens(ctx: Context, scene: Scene, cam: Camera, lns: Lens, lit
                                      int(seed), int(frame), int(view), out.bufs(n),
                                      _ptr(ray_tri_id, torch.int32, cap, "ray_tri_id"),
                                      _ptr(ray_depth, torch.float32, cap, "ray_depth"),
-                                     _ptr(far_pos, torch.float32, 4 * n, "far_pos"), _stream(stream)),
+                                     _ptr(far_pos, torch.float32, 4 * n, "far_pos"),
+                                     _ptr(coc_nf, torch.float32, 2 * n, "coc_nf"), _stream(stream)),
            "hdof_trace_thin_lens")
     return out
+
+
+def hdof_rt_spatial(ctx: Context, H: int, W: int, spp, rt: RTResult, hit_acc, coc_nf, variance,
+                    sp: "SpatialParams", c_near_out=None, c_far_out=None, stream=None):
+    """Spatial reconstruction of rt.c_near / rt.c_far into new planes
+    (returned as (c_near, c_far)); hit_acc and variance may be None."""
+    n = H * W
+    cno = torch.empty(3, H, W, device="cuda") if c_near_out is None else c_near_out
+    cfo = torch.empty(3, H, W, device="cuda") if c_far_out is None else c_far_out
+    _check(_lib.hdof_rt_spatial(ctx.handle, int(W), int(H), _ptr(spp, torch.uint8, n, "spp"), rt.bufs(n),
+                                _ptr(hit_acc, torch.float32, n, "hit_acc"), _ptr(coc_nf, torch.float32, 2 * n, "coc_nf"),
+                                _ptr(variance, torch.float32, n, "variance"), C.byref(sp),
+                                _ptr(cno, torch.float32, 3 * n, "c_near_out"), _ptr(cfo, torch.float32, 3 * n, "c_far_out"),
+                                _stream(stream)), "hdof_rt_spatial")
+    return cno, cfo
 
 
 def hdof_rt_reconstruct(ctx: Context, cam: Camera, prev: Camera | None, depth, spp, far_pos, rt: RTResult,
@@ -540,10 +562,16 @@ def recon_params_of(r) -> ReconParams:
     return ReconParams(int(bool(r.enable)), float(r.alpha))
 
 
+def spatial_params_of(sp) -> SpatialParams:
+    return SpatialParams(int(bool(sp.enable)), int(sp.n_taps), float(sp.r_cap), float(sp.v_clamp))
+
+
 def frame_params_of(cfg) -> FrameParams:
     rc = getattr(cfg, "recon", None)
+    sc = getattr(cfg, "spatial", None)
     return FrameParams(mask_params_of(cfg.mask), pp_params_of(cfg.pp), composite_params_of(cfg.comp),
-                       recon_params_of(rc) if rc is not None else ReconParams(0, 0.2))
+                       recon_params_of(rc) if rc is not None else ReconParams(0, 0.2),
+                       spatial_params_of(sc) if sc is not None else SpatialParams(0, 24, 64.0, 0.01))
 
 
 def hdof_profile_begin(ctx: Context) -> None:

@@ -356,5 +356,32 @@ def half_plane_scene(z_near: float, x_edge: float, z_far: float) -> Scene:
     return _assemble([occ, wall], [(1.0, 0.0, 0.0), (0.0, 0.0, 1.0)], {"name": "half_plane"})
 
 
+def spatial_inputs(H: int, W: int, seed: int, coverage: float, coc_max: float = 150.0) -> dict:
+    """Seeded per-pixel inputs of the spatial reconstruction shaped like a
+    frame's: traced pixels clustered in 8x8 tiles (a fraction `coverage` of
+    the tiles, 90 % of their pixels, 1-8 rays each), hit ratios with mass at
+    0 and 1, colours in [0, 1.5], near/far CoC sizes in [0, coc_max] px,
+    accumulated hit ratios, and variance estimates in [0, 0.03] with 10 %
+    not yet estimated (+inf)."""
+    rng = np.random.default_rng(seed)
+    TH, TW = -(-H // 8), -(-W // 8)
+    tiles = rng.uniform(size=(TH, TW)) < coverage
+    on = np.repeat(np.repeat(tiles, 8, 0), 8, 1)[:H, :W] & (rng.uniform(size=(H, W)) < 0.9)
+    spp = np.where(on, rng.integers(1, 9, (H, W)), 0).astype(np.uint8)
+    h = rng.uniform(0, 1, (H, W))
+    u = rng.uniform(size=(H, W))
+    h[u < 0.3] = 1.0
+    h[(u >= 0.3) & (u < 0.45)] = 0.0
+    V = rng.uniform(0, 0.03, (H, W))
+    V[rng.uniform(size=(H, W)) < 0.1] = np.inf
+    return dict(spp=spp,
+                c_near=rng.uniform(0, 1.5, (3, H, W)).astype(F32),
+                c_far=rng.uniform(0, 1.5, (3, H, W)).astype(F32),
+                hit_ratio=h.astype(F32),
+                hit_acc=rng.uniform(0, 1, (H, W)).astype(F32),
+                coc_nf=rng.uniform(0, coc_max, (2, H, W)).astype(F32),
+                variance=V.astype(F32))
+
+
 def random_rgb(shape, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).uniform(0.0, 1.0, shape).astype(F32)
