@@ -351,7 +351,8 @@ def bench_temporal(hdof, ctx, frames=60):
     """The temporal configuration: ~1M triangles, 1920x1080, 60 frames along
     a dolly + yaw camera path with the variance history carried over, focus
     1.5 m, f/1.4, 0-16 spp.  Steady state = mean over frames 10-59.  Run
-    without and with the temporal reconstruction of the traced colours."""
+    without reconstruction, with the temporal reconstruction of the traced
+    colours, and with the temporal and the spatial reconstruction."""
     import numpy as np
     import torch
     import scenegen as sg
@@ -386,8 +387,10 @@ def bench_temporal(hdof, ctx, frames=60):
     res = {"workload": f"{frames}-frame path (dolly 1 cm + yaw 0.2 deg per frame), 1920x1080, "
                        f"{scene.n_tris} triangles, f/1.4, focus 1.5 m, 0-16 spp, variance history",
            "bvh_build_ms_host_timed": round(bvh_ms, 2), "bvh": sc.stats()}
-    for name, recon in (("plain", 0), ("reconstructed", 1)):
+    runs = (("plain", 0, 0), ("reconstructed", 1, 0), ("reconstructed_spatial", 1, 1))
+    for name, recon, spatial in runs:
         params.recon.enable, params.recon.alpha = recon, 0.2
+        params.spatial.enable = spatial
         hdof.hdof_history_reset(ctx)
         hdof.hdof_recon_history_reset(ctx)
         run()  # warm-up pass (allocations)
@@ -401,16 +404,18 @@ def bench_temporal(hdof, ctx, frames=60):
                      "frame0_ms": round(float(ms[0]), 4),
                      "steady_rays_per_frame": int(rays[st].mean()),
                      "steady_traced_mrays_per_s": round(float(rays[st].sum() / (ms[st].sum() * 1e-3) / 1e6), 1)}
-    # per-stage split of the reconstructed run (profiled over frames 10-59 of a third pass)
-    hdof.hdof_history_reset(ctx)
-    hdof.hdof_recon_history_reset(ctx)
-    for t in range(frames):
-        if t == 10:
-            hdof.hdof_profile_begin(ctx)
-        hdof.hdof_frame(ctx, sc, cams[t], cams[t - 1] if t else None, lens, light, params, seed=cfg.seed,
-                        frame=t, view=0, out=out, keep=keep, stream=stream)
-    stage, nf = hdof.hdof_profile_end(ctx)
-    res["reconstructed"]["stage_ms"] = {k: round(v, 4) for k, v in stage.items()}
+    # per-stage split of the reconstructed runs (profiled over frames 10-59 of another pass)
+    for name, recon, spatial in runs[1:]:
+        params.recon.enable, params.spatial.enable = recon, spatial
+        hdof.hdof_history_reset(ctx)
+        hdof.hdof_recon_history_reset(ctx)
+        for t in range(frames):
+            if t == 10:
+                hdof.hdof_profile_begin(ctx)
+            hdof.hdof_frame(ctx, sc, cams[t], cams[t - 1] if t else None, lens, light, params, seed=cfg.seed,
+                            frame=t, view=0, out=out, keep=keep, stream=stream)
+        stage, nf = hdof.hdof_profile_end(ctx)
+        res[name]["stage_ms"] = {k: round(v, 4) for k, v in stage.items()}
     sc.close()
     return res
 

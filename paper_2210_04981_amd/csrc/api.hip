@@ -650,7 +650,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   if (s == HDOF_OK && spatial)
     s = launch_spatial(ctx, cam->width, cam->height, spp, rt_tr,
                        params->recon.enable ? (const float*)ctx->rec_hist[ctx->rec_cur].p + 3 * N : nullptr, coc_nf,
-                       nullptr, true, params->spatial, rt.c_near, rt.c_far, st);
+                       nullptr, true, params->spatial, rt.c_near, rt.c_far, st, true);
   hdof_prof_mark(ctx, 7, st);
   if (fused) {
     const PostFuse pf{spp, rt, params->comp, d_out};

@@ -291,11 +291,13 @@ hdof_status launch_recon(hdof_ctx* ctx, const CamK& k, const CamK* prev, const f
                          const float* far_pos, hdof_rt_bufs rt, float alpha, hipStream_t st);
 // spatial reconstruction: in -> (cn_out, cf_out); hacc nullable (latest hit
 // ratio); variance plane nullable; var_from_history: the variance estimate
-// of the context's current variance history instead
+// of the context's current variance history instead; zero_untraced: the
+// untraced inputs are known to be 0 (written without reading them)
 hdof_status spatial_reserve(hdof_ctx* ctx, int W, int H);
 hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof_rt_bufs in, const float* hacc,
                            const float* coc_nf, const float* variance, bool var_from_history,
-                           const hdof_spatial_params& sp, float* cn_out, float* cf_out, hipStream_t st);
+                           const hdof_spatial_params& sp, float* cn_out, float* cf_out, hipStream_t st,
+                           bool zero_untraced = false);
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
                         int32_t* total, hipStream_t st,

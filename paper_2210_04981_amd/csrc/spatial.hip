@@ -20,6 +20,7 @@
 #include <cmath>
 
 #define SP_LMAX 5
+#define SP_G 4  // taps per load group of the gather
 
 namespace {
 
@@ -63,25 +64,42 @@ __global__ __launch_bounds__(256) void k_sp_levels(SpIn I, float4* __restrict__ 
   float a[10];
 #pragma unroll
   for (int i = 0; i < 10; ++i) a[i] = 0.0f;
-  for (int dy = 0; dy < 2; ++dy)
-    for (int dx = 0; dx < 2; ++dx) {
-      const int x = rx * 32 + qx * 2 + dx, y = ry * 32 + qy * 2 + dy;
-      if (x >= I.W || y >= I.H) continue;
-      const size_t q = (size_t)y * I.W + x;
-      const int s = I.spp[q];
-      if (s == 0) continue;
-      const float hq = I.h[q], wn = (float)s * hq, wf = (float)s * (1.0f - hq);
-      a[0] = fmaf(wn, I.cn[q], a[0]);
-      a[1] = fmaf(wn, I.cn[N + q], a[1]);
-      a[2] = fmaf(wn, I.cn[2 * N + q], a[2]);
+  // the quad's counts first, then all of its values at once (a frame's ray
+  // mask is uniform over its tiles, so a quad is traced wholly or not at all)
+  size_t q[4];
+  int sv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int x = rx * 32 + qx * 2 + (i & 1), y = ry * 32 + qy * 2 + (i >> 1);
+    const bool in = x < I.W && y < I.H;
+    q[i] = in ? (size_t)y * I.W + x : 0;
+    sv[i] = in ? (int)I.spp[q[i]] : 0;
+  }
+  if ((sv[0] | sv[1] | sv[2] | sv[3]) != 0) {
+    float hq[4], r[4], c[4][6];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      hq[i] = I.h[q[i]];
+      r[i] = sp_radius(I, q[i], N);
+      c[i][0] = I.cn[q[i]], c[i][1] = I.cn[N + q[i]], c[i][2] = I.cn[2 * N + q[i]];
+      c[i][3] = I.cf[q[i]], c[i][4] = I.cf[N + q[i]], c[i][5] = I.cf[2 * N + q[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (sv[i] == 0) continue;
+      const float wn = (float)sv[i] * hq[i], wf = (float)sv[i] * (1.0f - hq[i]);
+      a[0] = fmaf(wn, c[i][0], a[0]);
+      a[1] = fmaf(wn, c[i][1], a[1]);
+      a[2] = fmaf(wn, c[i][2], a[2]);
       a[3] += wn;
-      a[4] = fmaf(wf, I.cf[q], a[4]);
-      a[5] = fmaf(wf, I.cf[N + q], a[5]);
-      a[6] = fmaf(wf, I.cf[2 * N + q], a[6]);
+      a[4] = fmaf(wf, c[i][3], a[4]);
+      a[5] = fmaf(wf, c[i][4], a[5]);
+      a[6] = fmaf(wf, c[i][5], a[6]);
       a[7] += wf;
-      a[8] += sp_radius(I, q, N);
+      a[8] += r[i];
       a[9] += 1.0f;
     }
+  }
   sp_emit(lv, I.W, I.H, 1, rx * 16 + qx, ry * 16 + qy, a);
 #pragma unroll
   for (int i = 0; i < 10; ++i) red[i][t] = a[i];
@@ -126,29 +144,41 @@ struct SpVar {
   float v_clamp;
 };
 
-// spc = float(sqrt(pi / n_taps)), formed on the host in double
+// One 16x16-pixel block per 256 threads, each wave an 8x8 quadrant: the
+// ray mask is uniform over its 8x8 tiles, so a wave is wholly traced or
+// wholly untraced and the gather's lanes do not idle beside copying ones.
+// spc = float(sqrt(pi / n_taps)), formed on the host in double.
+// zero_untraced: write 0 for untraced pixels without reading them (the
+// whole-frame path, whose untraced inputs are 0 by construction).
 template <int VSRC>
 __global__ __launch_bounds__(256) void k_sp_gather(SpIn I, const float4* __restrict__ lv,
                                                    const float4* __restrict__ taps, int n_taps, float spc,
                                                    SpVar var, float* __restrict__ cn_out,
-                                                   float* __restrict__ cf_out) {
+                                                   float* __restrict__ cf_out, int zero_untraced) {
   const int W = I.W, H = I.H;
   const size_t N = (size_t)W * H;
-  const size_t p = (size_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (p >= N) return;
-  const float cn0 = I.cn[p], cn1 = I.cn[N + p], cn2 = I.cn[2 * N + p];
-  const float cf0 = I.cf[p], cf1 = I.cf[N + p], cf2 = I.cf[2 * N + p];
+  const int b = xcd_block(blockIdx.x, gridDim.x), BW = (W + 15) >> 4;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int x = (b % BW) * 16 + (w & 1) * 8 + (l & 7), y = (b / BW) * 16 + (w >> 1) * 8 + (l >> 3);
+  if (x >= W || y >= H) return;
+  const size_t p = (size_t)y * W + x;
   const int s = I.spp[p];
   if (s == 0) {
-    cn_out[p] = cn0;
-    cn_out[N + p] = cn1;
-    cn_out[2 * N + p] = cn2;
-    cf_out[p] = cf0;
-    cf_out[N + p] = cf1;
-    cf_out[2 * N + p] = cf2;
+    float c[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (!zero_untraced) {
+      c[0] = I.cn[p], c[1] = I.cn[N + p], c[2] = I.cn[2 * N + p];
+      c[3] = I.cf[p], c[4] = I.cf[N + p], c[5] = I.cf[2 * N + p];
+    }
+    cn_out[p] = c[0];
+    cn_out[N + p] = c[1];
+    cn_out[2 * N + p] = c[2];
+    cf_out[p] = c[3];
+    cf_out[N + p] = c[4];
+    cf_out[2 * N + p] = c[5];
     return;
   }
-  const int x = (int)(p % W), y = (int)(p / W);
+  const float cn0 = I.cn[p], cn1 = I.cn[N + p], cn2 = I.cn[2 * N + p];
+  const float cf0 = I.cf[p], cf1 = I.cf[N + p], cf2 = I.cf[2 * N + p];
   const float rp = sp_radius(I, p, N);
   // level: texels no wider than the taps' mean spacing r sqrt(pi / n)
   const float spacing = rp * spc;
@@ -158,45 +188,76 @@ __global__ __launch_bounds__(256) void k_sp_gather(SpIn I, const float4* __restr
   float An0 = wn0 * cn0, An1 = wn0 * cn1, An2 = wn0 * cn2, Bn = wn0;
   float Af0 = wf0 * cf0, Af1 = wf0 * cf1, Af2 = wf0 * cf2, Bf = wf0;
   const float fx0 = (float)x + 0.5f, fy0 = (float)y + 0.5f;
+  // taps in groups of SP_G: every load of a group is issued before any of
+  // its sums, so a wave waits once per group rather than once per tap
   if (L == 0) {
-    for (int k = 0; k < n_taps; ++k) {
-      const float4 u = taps[k];
-      const int px = min(max((int)floorf(fmaf(rp, u.x, fx0)), 0), W - 1);
-      const int py = min(max((int)floorf(fmaf(rp, u.y, fy0)), 0), H - 1);
-      const size_t q = (size_t)py * W + px;
-      const int sq = I.spp[q];
-      if (sq == 0) continue;
-      const float a = clamp01(sp_radius(I, q, N) - rp * u.z + 0.5f);
-      const float hq = I.h[q], wn = a * (float)sq * hq, wf = a * (float)sq * (1.0f - hq);
-      An0 = fmaf(wn, I.cn[q], An0);
-      An1 = fmaf(wn, I.cn[N + q], An1);
-      An2 = fmaf(wn, I.cn[2 * N + q], An2);
-      Bn += wn;
-      Af0 = fmaf(wf, I.cf[q], Af0);
-      Af1 = fmaf(wf, I.cf[N + q], Af1);
-      Af2 = fmaf(wf, I.cf[2 * N + q], Af2);
-      Bf += wf;
+    for (int k0 = 0; k0 < n_taps; k0 += SP_G) {
+      size_t q[SP_G];
+      int sq[SP_G];
+      float d[SP_G];
+#pragma unroll
+      for (int g = 0; g < SP_G; ++g) {
+        const int k = min(k0 + g, n_taps - 1);
+        const float4 u = taps[k];
+        const int px = min(max((int)floorf(fmaf(rp, u.x, fx0)), 0), W - 1);
+        const int py = min(max((int)floorf(fmaf(rp, u.y, fy0)), 0), H - 1);
+        q[g] = (size_t)py * W + px;
+        d[g] = rp * u.z;
+        sq[g] = k0 + g < n_taps ? (int)I.spp[q[g]] : 0;
+      }
+      float r[SP_G], hq[SP_G], c[SP_G][6];
+#pragma unroll
+      for (int g = 0; g < SP_G; ++g) {
+        r[g] = sp_radius(I, q[g], N);
+        hq[g] = I.h[q[g]];
+        c[g][0] = I.cn[q[g]], c[g][1] = I.cn[N + q[g]], c[g][2] = I.cn[2 * N + q[g]];
+        c[g][3] = I.cf[q[g]], c[g][4] = I.cf[N + q[g]], c[g][5] = I.cf[2 * N + q[g]];
+      }
+#pragma unroll
+      for (int g = 0; g < SP_G; ++g) {
+        const float a = sq[g] > 0 ? clamp01(r[g] - d[g] + 0.5f) : 0.0f;
+        const float wn = a * (float)sq[g] * hq[g], wf = a * (float)sq[g] * (1.0f - hq[g]);
+        An0 = fmaf(wn, c[g][0], An0);
+        An1 = fmaf(wn, c[g][1], An1);
+        An2 = fmaf(wn, c[g][2], An2);
+        Bn += wn;
+        Af0 = fmaf(wf, c[g][3], Af0);
+        Af1 = fmaf(wf, c[g][4], Af1);
+        Af2 = fmaf(wf, c[g][5], Af2);
+        Bf += wf;
+      }
     }
   } else {
     const int WL = (W + (1 << L) - 1) >> L;
     const float4* lvl = lv + 3 * sp_level_offset(W, H, L);
-    for (int k = 0; k < n_taps; ++k) {
-      const float4 u = taps[k];
-      const int px = min(max((int)floorf(fmaf(rp, u.x, fx0)), 0), W - 1);
-      const int py = min(max((int)floorf(fmaf(rp, u.y, fy0)), 0), H - 1);
-      const float4* tx = lvl + 3 * ((size_t)(py >> L) * WL + (px >> L));
-      const float4 t2 = tx[2];
-      if (!(t2.y > 0.0f)) continue;
-      const float4 t0 = tx[0], t1 = tx[1];
-      const float a = clamp01(t2.x / t2.y - rp * u.z + 0.5f);
-      An0 = fmaf(a, t0.x, An0);
-      An1 = fmaf(a, t0.y, An1);
-      An2 = fmaf(a, t0.z, An2);
-      Bn = fmaf(a, t0.w, Bn);
-      Af0 = fmaf(a, t1.x, Af0);
-      Af1 = fmaf(a, t1.y, Af1);
-      Af2 = fmaf(a, t1.z, Af2);
-      Bf = fmaf(a, t1.w, Bf);
+    for (int k0 = 0; k0 < n_taps; k0 += SP_G) {
+      float4 t0[SP_G], t1[SP_G], t2[SP_G];
+      float d[SP_G];
+#pragma unroll
+      for (int g = 0; g < SP_G; ++g) {
+        const int k = min(k0 + g, n_taps - 1);
+        const float4 u = taps[k];
+        const int px = min(max((int)floorf(fmaf(rp, u.x, fx0)), 0), W - 1);
+        const int py = min(max((int)floorf(fmaf(rp, u.y, fy0)), 0), H - 1);
+        const float4* tx = lvl + 3 * ((size_t)(py >> L) * WL + (px >> L));
+        t0[g] = tx[0];
+        t1[g] = tx[1];
+        t2[g] = tx[2];
+        d[g] = k0 + g < n_taps ? rp * u.z : INFINITY;  // a tap past the end accepts nothing
+      }
+#pragma unroll
+      for (int g = 0; g < SP_G; ++g) {
+        const bool any = t2[g].y > 0.0f;
+        const float a = any ? clamp01(t2[g].x / t2[g].y - d[g] + 0.5f) : 0.0f;
+        An0 = fmaf(a, t0[g].x, An0);
+        An1 = fmaf(a, t0[g].y, An1);
+        An2 = fmaf(a, t0[g].z, An2);
+        Bn = fmaf(a, t0[g].w, Bn);
+        Af0 = fmaf(a, t1[g].x, Af0);
+        Af1 = fmaf(a, t1[g].y, Af1);
+        Af2 = fmaf(a, t1[g].z, Af2);
+        Bf = fmaf(a, t1[g].w, Bf);
+      }
     }
   }
   float lam = 1.0f;
@@ -222,8 +283,6 @@ __global__ __launch_bounds__(256) void k_sp_gather(SpIn I, const float4* __restr
   cf_out[2 * N + p] = fmaf(lam, gf2 - cf2, cf2);
 }
 
-inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
-
 }  // namespace
 
 size_t spatial_level_bytes(int W, int H) { return sizeof(float4) * 3 * sp_level_offset(W, H, SP_LMAX + 1); }
@@ -236,7 +295,8 @@ hdof_status spatial_reserve(hdof_ctx* ctx, int W, int H) {
 
 hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof_rt_bufs in, const float* hacc,
                            const float* coc_nf, const float* variance, bool var_from_history,
-                           const hdof_spatial_params& sp, float* cn_out, float* cf_out, hipStream_t st) {
+                           const hdof_spatial_params& sp, float* cn_out, float* cf_out, hipStream_t st,
+                           bool zero_untraced) {
   hdof_status s;
   if ((s = spatial_reserve(ctx, W, H)) != HDOF_OK) return s;
   if (ctx->sp_taps_n != sp.n_taps) {  // the table depends on the tap count only
@@ -249,20 +309,21 @@ hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof
   hipLaunchKernelGGL(k_sp_levels, dim3(regions), dim3(256), 0, st, I, lv);
   SpVar var{variance, nullptr, nullptr, nullptr, sp.v_clamp};
   const float spc = (float)std::sqrt(3.14159265358979323846 / (double)sp.n_taps);
-  const size_t N = (size_t)W * H;
+  const int blocks = ((W + 15) >> 4) * ((H + 15) >> 4);
+  const int zu = zero_untraced ? 1 : 0;
   const float4* taps = (const float4*)ctx->sp_taps.p;
   if (var_from_history) {
     var.m1 = (const float*)ctx->hist_m1.p;
     var.m2 = (const float*)ctx->hist_m2.p;
     var.fl = (const uint8_t*)ctx->hist_flags.p;
-    hipLaunchKernelGGL(k_sp_gather<SP_VAR_HIST>, dim3(cdiv(N, 256)), dim3(256), 0, st, I, (const float4*)lv, taps,
-                       sp.n_taps, spc, var, cn_out, cf_out);
+    hipLaunchKernelGGL(k_sp_gather<SP_VAR_HIST>, dim3(blocks), dim3(256), 0, st, I, (const float4*)lv, taps,
+                       sp.n_taps, spc, var, cn_out, cf_out, zu);
   } else if (variance) {
-    hipLaunchKernelGGL(k_sp_gather<SP_VAR_PLANE>, dim3(cdiv(N, 256)), dim3(256), 0, st, I, (const float4*)lv, taps,
-                       sp.n_taps, spc, var, cn_out, cf_out);
+    hipLaunchKernelGGL(k_sp_gather<SP_VAR_PLANE>, dim3(blocks), dim3(256), 0, st, I, (const float4*)lv, taps,
+                       sp.n_taps, spc, var, cn_out, cf_out, zu);
   } else {
-    hipLaunchKernelGGL(k_sp_gather<SP_VAR_NONE>, dim3(cdiv(N, 256)), dim3(256), 0, st, I, (const float4*)lv, taps,
-                       sp.n_taps, spc, var, cn_out, cf_out);
+    hipLaunchKernelGGL(k_sp_gather<SP_VAR_NONE>, dim3(blocks), dim3(256), 0, st, I, (const float4*)lv, taps,
+                       sp.n_taps, spc, var, cn_out, cf_out, zu);
   }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
