@@ -87,7 +87,10 @@ typedef struct {
 /* Adaptive ray mask (paper, Ray Trace).  sigma in (0, 2]: Gaussian on depth
  * and normal before the 3x3 Sobel; tau_*: score normalisers (> 0);
  * var_alpha in [0, 1]: EMA weight of the luminance moments; spp_max in
- * [1, 255]; tile in {1, 2, 4, 8, 16}: mask tile edge in pixels (tile max);
+ * [1, 255]; tile in {1, 2, 4, 8, 16}: mask tile edge in pixels (tile max),
+ * or 0: the edge scaled by the frame's largest CoC radius R over its pixels
+ * (paper, Discussion: mask resolution from the maximum CoC), 4 for R < 16 px,
+ * 8 for R < 32 px, else 16, chosen on the device each frame;
  * dilate in [0, 8]: tile dilation radius. */
 typedef struct {
   float sigma, tau_depth, tau_normal, tau_var, var_alpha;

@@ -62,6 +62,8 @@ def lib():
         L.or_cast_rays.argtypes = [P, i32, P, P, i32, P, P, P]
         L.or_gbuffer.argtypes = [P, P, i32, i32, P, P, P, i64, P, P, P, P, P, P]
         L.or_gauss_taps.argtypes = [f64, P, P]
+        L.or_mask_scaled_tile.restype = i32
+        L.or_mask_scaled_tile.argtypes = [P, i32, i32, P, P, P]
         L.or_mask.restype = i32
         L.or_mask.argtypes = [i32, i32, P, P, P, f64, f64, f64, f64, i32, i32, i32,
                               P, P, P, P, P, P, P, P, P]
@@ -211,13 +213,29 @@ def gauss_taps(sigma: float):
     return taps[: 2 * r.value + 1].copy()
 
 
-def mask(depth, normal, mp, V=None) -> dict:
+def scaled_tile(camera, lens, depth):
+    """Mask tile edge scaled by the frame's maximum CoC radius R (paper,
+    Discussion): (tile, R)."""
+    cam, W, H = cam_args(camera)
+    r = np.zeros(1)
+    t = lib().or_mask_scaled_tile(_p(cam), W, H, _p(_f64(lens.as_floats())), _p(_f64(depth).reshape(H, W)), _p(r))
+    return int(t), float(r[0])
+
+
+def mask(depth, normal, mp, V=None, camera=None, lens=None) -> dict:
     """Adaptive ray mask (paper, Ray Trace): Gaussian + Sobel on depth and
     normal, variance score, tile max + dilation, exclusive scan.  Returns the
-    per-pixel count s with its ambiguity bounds s_lo/s_hi, offsets, total and
-    the intermediate blurred channels and scores."""
+    per-pixel count s with its ambiguity bounds s_lo/s_hi, offsets, total,
+    the tile edge used and the intermediate blurred channels and scores.
+    mp.tile == 0: the tile edge is scaled by the frame's maximum CoC
+    (needs the camera and lens)."""
     depth = _f64(depth)
     H, W = depth.shape
+    tile, r_max = int(mp.tile), None
+    if tile == 0:
+        if camera is None or lens is None:
+            raise ValueError("oracle mask: tile 0 needs the camera and lens")
+        tile, r_max = scaled_tile(camera, lens, depth)
     normal = _f64(normal).reshape(3, H, W)
     Va = None if V is None else _f64(V).reshape(H, W)
     N = W * H
@@ -231,13 +249,13 @@ def mask(depth, normal, mp, V=None) -> dict:
     off = np.zeros((H, W), np.int64)
     tot = np.zeros(1, np.int64)
     rc = lib().or_mask(W, H, _p(depth), _p(normal), _p(Va), float(mp.sigma), float(mp.tau_depth),
-                       float(mp.tau_normal), float(mp.tau_var), int(mp.spp_max), int(mp.tile),
+                       float(mp.tau_normal), float(mp.tau_var), int(mp.spp_max), tile,
                        int(mp.dilate), _p(blur), _p(gz), _p(gn), _p(m), _p(s), _p(slo), _p(shi),
                        _p(off), _p(tot))
     if rc != 0:
         raise ValueError("oracle mask: bad parameters")
     return dict(blur=blur, g_z=gz, g_n=gn, score=m, spp=s, spp_lo=slo, spp_hi=shi,
-                offsets=off, total=int(tot[0]))
+                offsets=off, total=int(tot[0]), tile=tile, r_max=r_max)
 
 
 def trace(scene: Scene, camera, lens, light, spp, pix=None, seed=0, frame=0, view=0,
@@ -372,7 +390,7 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
     if prev_camera is not None and history is not None:
         rep = var_reproject(cam, depth, prev_camera, history)
         V = rep["V"]
-    mk = mask(depth, gb["normal"], cfg.mask, V)
+    mk = mask(depth, gb["normal"], cfg.mask, V, cam, lens)
     spp = mk["spp"] if rt_full_spp is None else np.full((H, W), rt_full_spp, np.int32)
     rt = trace(scene, cam, lens, light, spp, seed=cfg.seed, frame=frame_index, view=view,
                per_ray=False)

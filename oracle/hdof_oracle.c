@@ -503,6 +503,19 @@ void or_gauss_taps(double sigma, int* radius, double* taps /* >= 13 */) {
 
 static inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+/* Mask resolution scaled by the frame's maximum CoC (our reading of the    */
+/* paper's Discussion, which plans to scale the ray mask's resolution with  */
+/* the maximum CoC against tiling artifacts): R = max over the pixels of    */
+/* |c(z)| / 2, tile edge 4 for R < 16 px, 8 for R < 32 px, else 16 (about   */
+/* R / 2, within the tile sizes the mask supports).  *r_max receives R.     */
+int or_mask_scaled_tile(const double* cam, int W, int H, const double* lens, const double* z, double* r_max) {
+  cam_t k = mk_cam(cam, W, H);
+  double R = 0.0;
+  for (size_t p = 0; p < (size_t)W * H; ++p) R = maxd(R, 0.5 * fabs(coc_px(&k, lens, z[p])));
+  if (r_max) *r_max = R;
+  return R < 16.0 ? 4 : (R < 32.0 ? 8 : 16);
+}
+
 int or_mask(int W, int H, const double* z, const double* nrm, const double* V,
             double sigma, double tau_z, double tau_n, double tau_v,
             int spp_max, int tile, int dilate,

@@ -91,7 +91,7 @@ static hdof_status check_mask(const hdof_mask_params* m) {
           "mask thresholds must be finite and > 0");
   REQUIRE(m->var_alpha >= 0.0f && m->var_alpha <= 1.0f, "var_alpha must be in [0, 1]");
   REQUIRE(m->spp_max >= 1 && m->spp_max <= 255, "spp_max must be in [1, 255]");
-  REQUIRE(pow2_in(m->tile, 1, 16), "mask tile must be 1, 2, 4, 8 or 16");
+  REQUIRE(m->tile == 0 || pow2_in(m->tile, 1, 16), "mask tile must be 0 (scaled by the CoC), 1, 2, 4, 8 or 16");
   REQUIRE(m->dilate >= 0 && m->dilate <= 8, "mask dilate must be in [0, 8]");
   return HDOF_OK;
 }
@@ -201,7 +201,7 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   Buf* all[] = {&ctx->queue, &ctx->ray_col, &ctx->ray_z, &ctx->work_counter, &ctx->mask_tile,
-                &ctx->mask_tile_dil, &ctx->mask_xpref, &ctx->mask_rowsum, &ctx->mask_ybase,
+                &ctx->mask_tile_dil, &ctx->mask_xpref, &ctx->mask_rowsum, &ctx->mask_ybase, &ctx->mask_auto,
                 &ctx->pp_pack, &ctx->pp_tile, &ctx->pp_rad, &ctx->pp_taps, &ctx->hist_m1,
                 &ctx->hist_m2, &ctx->hist_flags, &ctx->hist_z, &ctx->rep_m1, &ctx->rep_m2,
                 &ctx->rep_flags, &ctx->f_depth, &ctx->f_normal, &ctx->f_albedo, &ctx->f_color,
@@ -335,8 +335,9 @@ extern "C" hdof_status hdof_ray_mask(hdof_ctx* ctx, const hdof_gbuffer_bufs* in,
   CamK k = make_camk(cam);
   CamK pk;
   if (prev) pk = make_camk(prev);
+  const LensK l = make_lensk(lens, k);
   return launch_mask(ctx, in->depth, in->normal, k, prev ? &pk : nullptr, *params, d_spp, d_offsets, d_total,
-                     (hipStream_t)stream);
+                     (hipStream_t)stream, nullptr, 0, nullptr, &l);
 }
 
 extern "C" hdof_status hdof_trace_thin_lens(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
@@ -635,7 +636,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   // the mask's final pass also fills the ray queue (queue stage empty)
   if (s == HDOF_OK)
     s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st,
-                    (int*)ctx->queue.p, (long)cap, (int*)ctx->work_counter.p);
+                    (int*)ctx->queue.p, (long)cap, (int*)ctx->work_counter.p, &l);
   // the trace's per-pixel reduction also updates the variance history
   // (variance stage empty)
   VarFuse vf;
@@ -838,15 +839,9 @@ static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params,
   TRY(hdof_ensure(ctx->b_views, batch_view_bytes() * HDOF_MAX_VIEWS));
   TRY(hdof_ensure(ctx->b_totals, sizeof(int) * (3 * HDOF_MAX_VIEWS + 1)));
   TRY(reserve_trace(ctx, (size_t)L.npx * params->mask.spp_max, true));
-  // mask scratch for the largest view (tile grids, reprojection planes)
-  const int t = params->mask.tile;
-  const size_t tiles = (size_t)((L.max_w + t - 1) / t + 1) * (size_t)((L.max_h + t - 1) / t + 1);
-  const size_t th = (size_t)(L.max_h + t - 1) / t + 1;
-  TRY(hdof_ensure(ctx->mask_tile, sizeof(int) * tiles));
-  TRY(hdof_ensure(ctx->mask_tile_dil, sizeof(int) * tiles));
-  TRY(hdof_ensure(ctx->mask_xpref, sizeof(int) * tiles));
-  TRY(hdof_ensure(ctx->mask_rowsum, sizeof(int) * 2 * th));
-  TRY(hdof_ensure(ctx->mask_ybase, sizeof(int) * th));
+  // mask scratch for the largest view (tile grids, reprojection planes): the
+  // widest and the tallest view bound every grid, the most pixels the planes
+  TRY(mask_reserve(ctx, L.max_w, L.max_h, params->mask));
   TRY(hdof_ensure(ctx->rep_m1, sizeof(float) * L.max_px));
   TRY(hdof_ensure(ctx->rep_m2, sizeof(float) * L.max_px));
   TRY(hdof_ensure(ctx->rep_flags, L.max_px));
@@ -887,7 +882,7 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     rt[v].lum_m2 = (float*)(a + L.o_m2) + pb;
     TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
     TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
-                    (int32_t*)(a + L.o_offs) + pb, totals + v, st));
+                    (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l));
   }
   TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
                            (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,

@@ -68,6 +68,7 @@ struct hdof_ctx {
   Buf queue, ray_col, ray_z, work_counter;
   // mask scratch
   Buf mask_tile, mask_tile_dil, mask_xpref, mask_rowsum, mask_ybase;
+  Buf mask_auto;  // tile 0: per-score-block CoC radius maxima + the chosen tile edge
   // post-filter scratch
   Buf pp_pack, pp_tile, pp_rad, pp_taps;
   int pp_taps_n = 0;  // tap count the table currently holds
@@ -298,10 +299,13 @@ hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof
                            const float* coc_nf, const float* variance, bool var_from_history,
                            const hdof_spatial_params& sp, float* cn_out, float* cf_out, hipStream_t st,
                            bool zero_untraced = false);
+// the mask's scratch for a W x H frame (tile 0: every candidate grid)
+hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp);
+// lens: needed for tile 0 (the mask tile scaled by the frame's maximum CoC)
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
                         int32_t* total, hipStream_t st,
-                        int* queue = nullptr, long cap = 0, int* counter = nullptr);
+                        int* queue = nullptr, long cap = 0, int* counter = nullptr, const LensK* lens = nullptr);
 hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
                               const float* depth, const float* m1, const float* m2, hipStream_t st);
 // Composite fused into the post-filter of a whole frame (the gather writes

@@ -9,6 +9,12 @@
 // k_mask_rows / k_mask_rowscan / k_mask_write: per-pixel counts are constant
 // over a mask tile, so the row-major exclusive scan over pixels reduces to a
 // scan over tile rows; the device-side total is written last.
+// Tile 0 scales the mask resolution with the frame's maximum CoC: the score
+// pass also forms the tile maxima for 4-, 8- and 16-pixel tiles and each
+// block's largest CoC radius, k_mask_pick reduces those to the frame's
+// maximum R and picks the tile edge (4 below 16 px, 8 below 32 px, else
+// 16: about R / 2), and the later passes read it from device memory, so the
+// choice never reaches the host.
 #include "hdof_internal.h"
 
 #define MT 16          // pixels per block edge
@@ -24,7 +30,26 @@ struct MaskK {
   int gr;
   float inv_tz, inv_tn, inv_tv;
   int spp_max, tile, dilate;
+  float coc_scale, inv_s1;  // tile 0: the CoC of a depth, coc_scale (inv_s1 - 1/z)
 };
+
+// tile 0: the tile-maximum grids of the three candidate tile edges and each
+// score block's largest CoC radius
+struct MaskAuto {
+  int *tm4, *tm8, *tm16;
+  float* blk_r;
+};
+
+__device__ inline void emit_tile_max(int t, const int (*sr)[MT], int tx, int ty, int x, int y, int W,
+                                     int* __restrict__ tile_max) {
+  if ((tx % t) == 0 && (ty % t) == 0) {
+    int mx = 0;
+    for (int dy = 0; dy < t; ++dy)
+      for (int dx = 0; dx < t; ++dx) mx = max(mx, sr[ty + dy][tx + dx]);
+    const int TW = (W + t - 1) / t;
+    tile_max[(y / t) * TW + x / t] = mx;
+  }
+}
 
 struct HistIn {
   const float* m1;
@@ -44,7 +69,7 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
                                                     HistIn hi, float* __restrict__ rep_m1,
                                                     float* __restrict__ rep_m2,
                                                     uint8_t* __restrict__ rep_flags,
-                                                    int* __restrict__ tile_max) {
+                                                    int* __restrict__ tile_max, MaskAuto au) {
   // (depth, nx, ny, nz) of one pixel per float4; all extents compile-time
   constexpr int AP = GR + 1, NIN = MT + 2 * AP;
   __shared__ float4 in[NIN][NIN];
@@ -103,6 +128,7 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
   const int tx = tid & 15, ty = tid >> 4;
   const int x = x0 + tx, y = y0 + ty;
   int s_raw = 0;
+  float rc = 0.0f;  // CoC radius (tile 0)
   if (x < W && y < H) {
     // Sobel: yb index = local + 1
     const float4 a00 = yb[ty][tx], a10 = yb[ty][tx + 1], a20 = yb[ty][tx + 2];
@@ -152,27 +178,62 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
     rep_flags[p] = fl;
     float m = fmaxf(gz * mk.inv_tz, fmaxf(gn * mk.inv_tn, V * mk.inv_tv));
     if (m >= 1.0f) s_raw = (int)ceilf(fminf(m, (float)mk.spp_max));
+    if (mk.tile == 0) rc = 0.5f * fabsf(mk.coc_scale * (mk.inv_s1 - 1.0f / depth[p]));
   }
   sr[ty][tx] = s_raw;
   __syncthreads();
-  const int t = mk.tile;
-  if ((tx % t) == 0 && (ty % t) == 0 && x < W && y < H) {
-    int mx = 0;
-    for (int dy = 0; dy < t; ++dy)
-      for (int dx = 0; dx < t; ++dx) mx = max(mx, sr[ty + dy][tx + dx]);
-    const int TW = (W + t - 1) / t;
-    tile_max[(y / t) * TW + x / t] = mx;
+  if (x >= W || y >= H) {
+    // nothing to emit; the CoC reduction below still needs every lane
+  } else if (mk.tile > 0) {
+    emit_tile_max(mk.tile, sr, tx, ty, x, y, W, tile_max);
+  } else {
+    emit_tile_max(4, sr, tx, ty, x, y, W, au.tm4);
+    emit_tile_max(8, sr, tx, ty, x, y, W, au.tm8);
+    emit_tile_max(16, sr, tx, ty, x, y, W, au.tm16);
+  }
+  if (mk.tile == 0) {
+    __shared__ float wr[4];
+    for (int o = 32; o > 0; o >>= 1) rc = fmaxf(rc, __shfl_xor(rc, o));
+    if ((tid & 63) == 0) wr[tid >> 6] = rc;
+    __syncthreads();
+    if (tid == 0) au.blk_r[lb] = fmaxf(fmaxf(wr[0], wr[1]), fmaxf(wr[2], wr[3]));
   }
 }
 
+// tile 0: the frame's largest CoC radius R over the score blocks' maxima,
+// tile edge 4 (R < 16), 8 (R < 32) or 16
+__global__ __launch_bounds__(1024) void k_mask_pick(const float* __restrict__ blk_r, int nb, int* __restrict__ tsel) {
+  __shared__ float wr[16];
+  const int tid = threadIdx.x;
+  float r = 0.0f;
+  for (int i = tid; i < nb; i += 1024) r = fmaxf(r, blk_r[i]);
+  for (int o = 32; o > 0; o >>= 1) r = fmaxf(r, __shfl_xor(r, o));
+  if ((tid & 63) == 0) wr[tid >> 6] = r;
+  __syncthreads();
+  if (tid == 0) {
+    float R = 0.0f;
+    for (int i = 0; i < 16; ++i) R = fmaxf(R, wr[i]);
+    tsel[0] = R < 16.0f ? 4 : (R < 32.0f ? 8 : 16);
+  }
+}
+
+// the tile edge in force: the launch's, or the one k_mask_pick chose
+__device__ inline int mask_tile_of(int t, const int* __restrict__ tsel) { return tsel ? *tsel : t; }
+
 // per tile row: dilated tile values, x-prefix of (value * tile width), row sum
+// (tile 0: launched for the rows of 4-pixel tiles; rows past the chosen
+// tile edge's grid exit)
 __global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_max, int W, int H,
                                                    int t, int dil, int* __restrict__ tile_dil,
                                                    int* __restrict__ xpref, int* __restrict__ rowsum,
-                                                   int* __restrict__ rowtot) {
+                                                   int* __restrict__ rowtot, const int* __restrict__ tsel,
+                                                   MaskAuto au) {
   __shared__ int part[256];
+  t = mask_tile_of(t, tsel);
+  if (tsel) tile_max = t == 4 ? au.tm4 : (t == 8 ? au.tm8 : au.tm16);
   const int TW = (W + t - 1) / t, TH = (H + t - 1) / t;
   const int ty = blockIdx.x, tid = threadIdx.x;
+  if (ty >= TH) return;
   const int chunk = (TW + 255) / 256;
   const int lo = tid * chunk, hi = min(TW, lo + chunk);
   int local = 0;
@@ -211,9 +272,10 @@ __global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_
 
 // exclusive scan over tile rows (one block), total to the caller's buffer
 __global__ void k_mask_rowscan(const int* __restrict__ rowtot, int TH, int* __restrict__ ybase,
-                               int* __restrict__ total) {
+                               int* __restrict__ total, int H, int t, const int* __restrict__ tsel) {
   __shared__ int part[1024];
   const int tid = threadIdx.x;
+  if (tsel) TH = (H + *tsel - 1) / *tsel;
   const int chunk = (TH + 1023) / 1024;
   const int lo = tid * chunk, hi = min(TH, lo + chunk);
   int s = 0;
@@ -237,9 +299,10 @@ __global__ void k_mask_rowscan(const int* __restrict__ rowtot, int TH, int* __re
 __global__ void k_mask_write(int W, int H, int t, const int* __restrict__ tile_dil,
                              const int* __restrict__ xpref, const int* __restrict__ rowsum,
                              const int* __restrict__ ybase, uint8_t* __restrict__ spp,
-                             int* __restrict__ offsets) {
+                             int* __restrict__ offsets, const int* __restrict__ tsel) {
   int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= W) return;
+  t = mask_tile_of(t, tsel);
   const int TW = (W + t - 1) / t;
   int tx = x / t, ty = y / t;
   int S = tile_dil[ty * TW + tx];
@@ -259,9 +322,14 @@ __global__ __launch_bounds__(256) void k_mask_write_queue(int W, int H, int t, i
                                                           const int* __restrict__ rowsum,
                                                           const int* __restrict__ rowtot, uint8_t* __restrict__ spp,
                                                           int* __restrict__ offsets, int* __restrict__ total,
-                                                          int* __restrict__ queue, long cap, int* __restrict__ counter) {
+                                                          int* __restrict__ queue, long cap, int* __restrict__ counter,
+                                                          const int* __restrict__ tsel) {
   __shared__ int2 red[256];
   const int tid = threadIdx.x;
+  if (tsel) {
+    t = *tsel;
+    TH = (H + t - 1) / t;
+  }
   const int x = blockIdx.x * blockDim.x + tid, y = blockIdx.y;
   const int ty = y / t;
   int before = 0, all = 0;
@@ -322,12 +390,36 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
+// tile-grid sizes of a frame: tile 0 reserves for the 4-pixel grid (the
+// largest) plus the 8- and 16-pixel maxima grids
+static size_t grid_tiles(int W, int H, int t) { return (size_t)cdiv(W, t) * cdiv(H, t); }
+
+hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp) {
+  const size_t N = (size_t)W * H;
+  const int t = mp.tile > 0 ? mp.tile : 4;
+  const size_t tiles = grid_tiles(W, H, t), TH = cdiv(H, t);
+  const size_t extra = mp.tile > 0 ? 0 : grid_tiles(W, H, 8) + grid_tiles(W, H, 16);
+  const size_t blocks = (size_t)cdiv(W, MT) * cdiv(H, MT);
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->mask_tile, sizeof(int) * (tiles + extra))) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_tile_dil, sizeof(int) * tiles)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_xpref, sizeof(int) * tiles)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_rowsum, sizeof(int) * 2 * TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_ybase, sizeof(int) * TH)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_auto, sizeof(float) * (blocks + 1))) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->rep_m1, sizeof(float) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->rep_m2, sizeof(float) * N)) != HDOF_OK) return s;
+  return hdof_ensure(ctx->rep_flags, N);
+}
+
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
-                        int32_t* total, hipStream_t st, int* queue, long cap, int* counter) {
-  const int W = k.W, H = k.H, t = mp.tile;
-  const size_t N = (size_t)W * H;
-  const int TW = cdiv(W, t), TH = cdiv(H, t);
+                        int32_t* total, hipStream_t st, int* queue, long cap, int* counter, const LensK* lens) {
+  const int W = k.W, H = k.H;
+  const bool scaled = mp.tile == 0;
+  if (scaled && !lens) return hdof_set_error(HDOF_ERR_INVALID_ARG, "mask tile 0 (scaled by the CoC) needs the lens");
+  const int t = scaled ? 4 : mp.tile;  // the grid the launches are sized for
+  const int TH = cdiv(H, t);
   MaskK mk;
   // Gaussian taps exp(-i^2 / 2 sigma^2), radius floor(3 sigma + 0.5), normalised
   int gr = (int)floor(3.0 * mp.sigma + 0.5);
@@ -339,17 +431,12 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   mk.inv_tn = 1.0f / mp.tau_normal;
   mk.inv_tv = 1.0f / mp.tau_var;
   mk.spp_max = mp.spp_max;
-  mk.tile = t;
+  mk.tile = mp.tile;
   mk.dilate = mp.dilate;
+  mk.coc_scale = lens ? lens->coc_scale : 0.0f;
+  mk.inv_s1 = lens ? lens->invS1 : 0.0f;
   hdof_status s;
-  if ((s = hdof_ensure(ctx->mask_tile, sizeof(int) * (size_t)TW * TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->mask_tile_dil, sizeof(int) * (size_t)TW * TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->mask_xpref, sizeof(int) * (size_t)TW * TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->mask_rowsum, sizeof(int) * 2 * (size_t)TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->mask_ybase, sizeof(int) * (size_t)TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->rep_m1, sizeof(float) * N)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->rep_m2, sizeof(float) * N)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->rep_flags, N)) != HDOF_OK) return s;
+  if ((s = mask_reserve(ctx, W, H, mp)) != HDOF_OK) return s;
   HistIn hi{};
   hi.valid = 0;
   if (prev && ctx->hist_any && ctx->hist_w == prev->W && ctx->hist_h == prev->H) {
@@ -367,32 +454,43 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   ctx->rep_valid = true;
   int* rowsum = (int*)ctx->mask_rowsum.p;
   int* rowtot = rowsum + TH;
+  const int nblk = cdiv(W, MT) * cdiv(H, MT);
+  MaskAuto au{};
+  const int* tsel = nullptr;
+  if (scaled) {
+    au.tm4 = (int*)ctx->mask_tile.p;
+    au.tm8 = au.tm4 + grid_tiles(W, H, 4);
+    au.tm16 = au.tm8 + grid_tiles(W, H, 8);
+    au.blk_r = (float*)ctx->mask_auto.p;
+    tsel = (const int*)(au.blk_r + nblk);
+  }
   {
-    const dim3 g(cdiv(W, MT) * cdiv(H, MT)), b(256);
+    const dim3 g(nblk), b(256);
     float* r1 = (float*)ctx->rep_m1.p;
     float* r2 = (float*)ctx->rep_m2.p;
     uint8_t* rf = (uint8_t*)ctx->rep_flags.p;
     int* tm = (int*)ctx->mask_tile.p;
     switch (gr) {
 #define CASE(R) \
-  case R: hipLaunchKernelGGL(k_mask_score<R>, g, b, 0, st, depth, normal, k, mk, hi, r1, r2, rf, tm); break;
+  case R: hipLaunchKernelGGL(k_mask_score<R>, g, b, 0, st, depth, normal, k, mk, hi, r1, r2, rf, tm, au); break;
       CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
 #undef CASE
       default: return hdof_set_error(HDOF_ERR_INVALID_ARG, "Gaussian radius %d above %d", gr, MAX_GR);
     }
   }
+  if (scaled) hipLaunchKernelGGL(k_mask_pick, dim3(1), dim3(1024), 0, st, (const float*)au.blk_r, nblk, (int*)tsel);
   hipLaunchKernelGGL(k_mask_rows, dim3(TH), dim3(256), 0, st, (const int*)ctx->mask_tile.p, W, H, t,
-                     mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot);
+                     mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot, tsel, au);
   if (queue) {
     hipLaunchKernelGGL(k_mask_write_queue, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t, TH,
                        (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p, (const int*)rowsum,
-                       (const int*)rowtot, spp, offsets, total, queue, cap, counter);
+                       (const int*)rowtot, spp, offsets, total, queue, cap, counter, tsel);
   } else {
     hipLaunchKernelGGL(k_mask_rowscan, dim3(1), dim3(1024), 0, st, (const int*)rowtot, TH,
-                       (int*)ctx->mask_ybase.p, total);
+                       (int*)ctx->mask_ybase.p, total, H, t, tsel);
     hipLaunchKernelGGL(k_mask_write, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t,
                        (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p,
-                       (const int*)rowsum, (const int*)ctx->mask_ybase.p, spp, offsets);
+                       (const int*)rowsum, (const int*)ctx->mask_ybase.p, spp, offsets, tsel);
   }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;

@@ -138,6 +138,65 @@ def test_ray_mask_matches_oracle(hd, ctx, case):
     assert int(tot.item()) == int(s.sum())
 
 
+@pytest.mark.parametrize("f_number,tile", [(1.4, 4), (1.0, 8), (0.5, 16)])
+def test_ray_mask_scaled_tile(hd, ctx, f_number, tile):
+    """Mask tile 0: the tile edge is picked on the device from the frame's
+    largest CoC radius (all three edges reached by the apertures), and the
+    counts equal the oracle's and the GPU's own mask at that fixed edge."""
+    from dataclasses import replace
+    print_case(f"ray mask scaled tile f/{f_number}")
+    scene, cfg = sg.living_room_scene(0), sg.config_1080p(333, 187)
+    lens = sg.lens_fnumber(cfg.lens.focal_length, f_number, cfg.lens.focus_distance)
+    ref_gb = oracle.gbuffer(oracle.Scene(scene.verts, scene.albedo), cfg.camera, lens, cfg.light)
+    depth, normal = f32(ref_gb["depth"]), f32(ref_gb["normal"])
+    t_ref, r_max = oracle.scaled_tile(cfg.camera, lens, depth)
+    assert t_ref == tile
+    assert min(abs(r_max - 16), abs(r_max - 32)) > 1e-3 * r_max  # clear of the band edges
+    mp = sg.MaskParams(sigma=1.0, tile=0, dilate=1, spp_max=8)
+    ref = oracle.mask(depth, normal, mp, None, cfg.camera, lens)
+    assert ref["tile"] == tile
+    cam = hd.camera_of(cfg.camera)
+    d_t, n_t = to_dev(depth, torch.float32), to_dev(normal, torch.float32)
+    spp, offs, tot = hd.hdof_ray_mask(ctx, d_t, n_t, cam, None, hd.lens_of(lens), hd.mask_params_of(mp))
+    spp_f, offs_f, tot_f = hd.hdof_ray_mask(ctx, d_t, n_t, cam, None, hd.lens_of(lens),
+                                            hd.mask_params_of(replace(mp, tile=tile)))
+    torch.cuda.synchronize()
+    assert torch.equal(spp, spp_f) and torch.equal(offs, offs_f) and torch.equal(tot, tot_f)
+    s = spp.cpu().numpy().astype(np.int64)
+    lo, hi = ref["spp_lo"], ref["spp_hi"]
+    assert np.all((s >= lo) & (s <= hi))
+    uniq = lo == hi
+    assert np.array_equal(s[uniq], ref["spp"][uniq]) and uniq.mean() > 0.99
+
+
+def test_frame_with_scaled_mask_tile(hd, ctx):
+    """hdof_frame with mask tile 0 (the fused queue-filling mask reads the
+    device-side choice) equals the frame with the chosen edge fixed."""
+    print_case("frame with scaled mask tile")
+    W, H = 320, 180
+    scene, cfg = sg.living_room_scene(0), sg.config_1080p(W, H)
+    sc = upload_scene(hd, ctx, scene)
+    lens = sg.lens_fnumber(cfg.lens.focal_length, 1.0, cfg.lens.focus_distance)
+    gb = oracle.gbuffer(oracle.Scene(scene.verts, scene.albedo), cfg.camera, lens, cfg.light)
+    t, r_max = oracle.scaled_tile(cfg.camera, lens, f32(gb["depth"]))
+    assert t == 8 and min(abs(r_max - 16), abs(r_max - 32)) > 1e-3 * r_max
+    outs = []
+    for tile in (0, t):
+        p = hd.frame_params_of(cfg)
+        p.mask.tile = tile
+        k = hd.FrameKeep.empty(H, W)
+        out = torch.empty(3, H, W, device="cuda")
+        hd.hdof_history_reset(ctx)
+        hd.hdof_frame(ctx, sc, hd.camera_of(cfg.camera), None, hd.lens_of(lens), hd.light_of(cfg.light), p,
+                      frame=0, out=out, keep=k)
+        torch.cuda.synchronize()
+        outs.append((out, k))
+    assert torch.equal(outs[0][1].spp, outs[1][1].spp)
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert int(outs[0][1].total.item()) > 1000
+    sc.close()
+
+
 @pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_small"])
 def test_trace_matches_oracle(hd, ctx, which):
     print_case(f"trace {which}")

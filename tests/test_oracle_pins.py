@@ -598,3 +598,47 @@ def test_frame_new_regions_get_max_rays(orc):
     traced0 = f0["spp"] > 0
     assert traced0.any() and not traced0.all()
     assert np.all(f1["spp"][traced0] == cfg.mask.spp_max)
+
+
+# ----------------------------------------------------------------------------
+# mask resolution scaled by the maximum CoC
+# ----------------------------------------------------------------------------
+
+def test_scaled_tile_of_a_wall(orc):
+    """A wall filling the view at depth z: every pixel's CoC radius is the
+    thin-lens |c|/2 = A s_px |1/S1 - 1/z| / 2 (s_px = W / (2 tan(fov/2))),
+    and the tile edge follows the bands R < 16 -> 4, R < 32 -> 8, else 16."""
+    z = 0.3
+    wall = np.array([[-9, -9, z, 9, -9, z, 9, 9, z], [-9, -9, z, 9, 9, z, -9, 9, z]])
+    S = orc.Scene(wall, np.array([[0.5, 0.5, 0.5]] * 2))
+    cfg = sg.config_tiny()
+    cam = cfg.camera
+    gb = orc.gbuffer(S, cam, cfg.lens, cfg.light)
+    assert np.allclose(gb["depth"], z, rtol=1e-9)
+    s_px = cam.width / (2 * cam.tan_half_fov_x)
+    seen = set()
+    for A in (0.02, 0.1, 0.2, 0.3, 0.4):
+        lens = sg.Lens(cfg.lens.focal_length, A, cfg.lens.focus_distance)
+        R = A * s_px * abs(1 / lens.focus_distance - 1 / z) / 2
+        t, r = orc.scaled_tile(cam, lens, gb["depth"])
+        assert abs(r - R) < 1e-6 * max(R, 1), (A, r, R)
+        assert t == (4 if R < 16 else (8 if R < 32 else 16)), (A, R, t)
+        seen.add(t)
+    assert seen == {4, 8, 16}
+
+
+def test_scaled_tile_mask_equals_the_fixed_tile(orc):
+    """tile = 0 is the mask with the tile edge the maximum CoC picks."""
+    from dataclasses import replace
+    sc = sg.living_room_scene(0)
+    cfg = sg.config_1080p(160, 90)
+    gb = orc.gbuffer(orc.Scene(sc.verts, sc.albedo), cfg.camera, cfg.lens, cfg.light)
+    for N in (2.8, 0.5, 0.25):
+        lens = sg.lens_fnumber(cfg.lens.focal_length, N, cfg.lens.focus_distance)
+        a = orc.mask(gb["depth"], gb["normal"], replace(cfg.mask, tile=0), None, cfg.camera, lens)
+        b = orc.mask(gb["depth"], gb["normal"], replace(cfg.mask, tile=a["tile"]), None)
+        assert np.array_equal(a["spp"], b["spp"]) and a["total"] == b["total"]
+    # a larger aperture never picks a finer mask
+    tiles = [orc.scaled_tile(cfg.camera, sg.lens_fnumber(cfg.lens.focal_length, N, cfg.lens.focus_distance),
+                             gb["depth"])[0] for N in (8, 2.8, 1.4, 0.5, 0.25)]
+    assert tiles == sorted(tiles) and len(set(tiles)) >= 2
