@@ -179,12 +179,53 @@ def main():
         res["forms"] = {"batched": bench_batched(hdof, ctx, sc, ms_per_step),
                         "backward": bench_backward(hdof, ctx, sc, cfg, keep, ms_per_step),
                         "focus_fit": bench_focus_fit(hdof, ctx, sc, cfg, ms_per_step),
-                        "temporal": bench_temporal(hdof, ctx)}
+                        "temporal": bench_temporal(hdof, ctx),
+                        "scaled_mask": bench_scaled_mask(hdof, ctx, sc, cfg, ms_per_step, rays)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, scene)
     print(json.dumps(res), flush=True)
     sc.close()
     ctx.close()
+
+
+def bench_scaled_mask(hdof, ctx, sc, cfg, plain_ms, plain_rays, steps=50):
+    """The headline frame with the mask tile scaled by the frame's maximum
+    CoC (mask tile 0) instead of the fixed 8-pixel tile: frame time, traced
+    rays and the mask stage."""
+    import torch
+    stream = torch.cuda.current_stream()
+    H, W = cfg.camera.height, cfg.camera.width
+    cam, lens, light = hdof.camera_of(cfg.camera), hdof.lens_of(cfg.lens), hdof.light_of(cfg.light)
+    params = hdof.frame_params_of(cfg)
+    params.mask.tile = 0
+    keep = hdof.FrameKeep.empty(H, W)
+    out = torch.empty(3, H, W, device="cuda")
+
+    def step():
+        hdof.hdof_frame(ctx, sc, cam, None, lens, light, params, seed=cfg.seed, frame=0, view=0, out=out,
+                        keep=keep, stream=stream)
+    for _ in range(3):
+        step()
+    ms = _time_ms(step, steps, stream)
+    hdof.hdof_profile_begin(ctx)
+    for _ in range(steps):
+        step()
+    stage, _ = hdof.hdof_profile_end(ctx)
+    rays = int(keep.total.item())
+    spp = keep.spp.cpu()
+    # the edge in force, read back from the count pattern: the largest of
+    # 16, 8, 4 over whose tiles every count is constant
+    tile = 4
+    for t in (16, 8):
+        Hc, Wc = (H // t) * t, (W // t) * t
+        blk = spp[:Hc, :Wc].reshape(Hc // t, t, Wc // t, t)
+        if bool((blk == blk[:, :1, :, :1]).all()):
+            tile = t
+            break
+    return {"workload": "1920x1080 living room, mask tile scaled by the frame's maximum CoC",
+            "tile_in_force": tile, "frame_ms": round(ms, 4), "frame_ms_fixed_tile_8": round(plain_ms, 4),
+            "traced_rays": rays, "traced_rays_fixed_tile_8": plain_rays,
+            "ray_mask_ms": round(stage["ray_mask"], 4), "trace_ms": round(stage["trace"], 4)}
 
 
 def _time_ms(fn, reps, stream):
