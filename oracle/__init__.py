@@ -60,7 +60,8 @@ def lib():
         L.or_coc.argtypes = [P, i32, i32, P, f64]
         L.or_lens_ray.argtypes = [P, i32, i32, P, i32, i32, u64, u64, u64, u64, i32, P, P]
         L.or_cast_rays.argtypes = [P, i32, P, P, i32, P, P, P]
-        L.or_gbuffer.argtypes = [P, P, i32, i32, P, P, P, i64, P, P, P, P, P, P]
+        L.or_gbuffer.argtypes = [P, P, i32, i32, P, P, P, i64, P, P, P, P, P, P, P]
+        L.or_scene_set_spec.argtypes = [P, P]
         L.or_gauss_taps.argtypes = [f64, P, P]
         L.or_mask_scaled_tile.restype = i32
         L.or_mask_scaled_tile.argtypes = [P, i32, i32, P, P, P]
@@ -76,7 +77,7 @@ def lib():
         L.or_var_update.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P]
         L.or_pp_radius.argtypes = [i32, i32, P, f64, i32, P]
         L.or_postfilter.argtypes = [P, i32, i32, P, P, P, P, P, i64, P]
-        L.or_composite.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, f64, i32, P]
+        L.or_composite.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, f64, i32, P, f64, P]
         L.or_pp_radius_arg.argtypes = [i32, i32, P, f64, i32, P, P]
         L.or_pp_composite_backward.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, f64, i32, P, P, P]
         _lib = L
@@ -127,11 +128,16 @@ def philox4x64_10(ctr, key) -> np.ndarray:
 class Scene:
     """Triangle soup + the oracle's own median-split BVH (double precision)."""
 
-    def __init__(self, verts, albedo):
+    def __init__(self, verts, albedo, spec=None):
+        """spec: per-triangle (k_s, shininess) of the specular lobe, or None
+        (Lambertian)."""
         self.verts = _f64(verts).reshape(-1, 9)
         self.albedo = _f64(albedo).reshape(-1, 3)
         self.n = self.verts.shape[0]
         self._h = lib().or_scene_create(_p(self.verts), _p(self.albedo), self.n)
+        self.spec = None if spec is None else _f64(spec).reshape(-1, 2)
+        if self.spec is not None:
+            lib().or_scene_set_spec(self._h, _p(self.spec))
 
     @property
     def handle(self):
@@ -186,8 +192,8 @@ def lens_ray(camera, lens, x, y, j, seed=0, frame=0, view=0, pinhole=False):
 
 def gbuffer(scene: Scene, camera, lens, light, pix=None) -> dict:
     """Pinhole G-buffer (paper, Design): depth, normal, albedo, shaded colour,
-    triangle id and ambiguity for every pixel (or for the listed linear
-    pixel indices)."""
+    triangle id, ambiguity and specular luminance for every pixel (or for the
+    listed linear pixel indices)."""
     cam, W, H = cam_args(camera)
     pixa = None if pix is None else _i64(pix)
     n = W * H if pix is None else pixa.shape[0]
@@ -197,10 +203,11 @@ def gbuffer(scene: Scene, camera, lens, light, pix=None) -> dict:
     col = np.zeros((3, n))
     tid = np.zeros(n, np.int32)
     amb = np.zeros(n, np.int32)
+    ys = np.zeros(n)
     lib().or_gbuffer(scene.handle, _p(cam), W, H, _p(_f64(lens.as_floats())),
                      _p(_f64(light.as_floats())), _p(pixa), n,
-                     _p(z), _p(nrm), _p(alb), _p(col), _p(tid), _p(amb))
-    out = dict(depth=z, normal=nrm, albedo=alb, color=col, tri_id=tid, amb=amb)
+                     _p(z), _p(nrm), _p(alb), _p(col), _p(tid), _p(amb), _p(ys))
+    out = dict(depth=z, normal=nrm, albedo=alb, color=col, tri_id=tid, amb=amb, spec=ys)
     if pix is None:
         out = {k: (v.reshape(-1, H, W) if v.ndim == 2 else v.reshape(H, W)) for k, v in out.items()}
     return out
@@ -361,13 +368,27 @@ def postfilter(camera, lens, color, depth, pp, pix=None):
     return out.reshape(3, H, W) if pix is None else out
 
 
-def composite(camera, lens, color, cpp, depth, spp, c_near, c_far, hit, cp):
+def composite(camera, lens, color, cpp, depth, spp, c_near, c_far, hit, cp, pp_spec=None):
+    """Composite (paper, Composite); with `pp_spec` (the post-filtered
+    specular luminance) and cp.spec_y > 0 the near traced pixels favour the
+    post-process colour by clamp(pp_spec / spec_y, 0, 1)."""
     cam, W, H = cam_args(camera)
     out = np.zeros((3, H, W))
+    spec_y = float(getattr(cp, "spec_y", 0.0))
     lib().or_composite(_p(cam), W, H, _p(_f64(lens.as_floats())), _p(_f64(color)), _p(_f64(cpp)),
                        _p(_f64(depth)), _p(_i32(spp)), _p(_f64(c_near)), _p(_f64(c_far)),
-                       _p(_f64(hit)), float(cp.h_t), int(cp.rt_override), _p(out))
+                       _p(_f64(hit)), float(cp.h_t), int(cp.rt_override),
+                       _p(None if pp_spec is None else _f64(pp_spec)), spec_y, _p(out))
     return out
+
+
+def postfilter_spec(camera, lens, spec, depth, pp, pix=None):
+    """The post-filtered specular luminance: the post-filter's gather (same
+    radius, taps and weights) applied to the G-buffer's specular luminance."""
+    ys = _f64(spec)
+    out = postfilter(camera, lens, np.broadcast_to(ys.reshape(1, *ys.shape[-2:]), (3,) + ys.shape[-2:]),
+                     depth, pp, pix)
+    return out[0]
 
 
 def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view=0,
@@ -417,10 +438,13 @@ def frame(scene: Scene, cfg, prev_camera=None, history=None, frame_index=0, view
     if rt_full_spp is not None:
         from dataclasses import replace
         comp = replace(comp, rt_override=1)
+    pps = None
+    if getattr(comp, "spec_y", 0.0) > 0.0:
+        pps = postfilter_spec(cam, lens, gb["spec"], depth, cfg.pp)
     out = composite(cam, lens, gb["color"], cpp, depth, spp, rt["c_near"], rt["c_far"],
-                    rt["hit_ratio"], comp)
+                    rt["hit_ratio"], comp, pps)
     return dict(gbuffer=gb, mask=mk, spp=spp, rt=rt, history=hist, reproj=rep, pp=cpp, out=out,
-                recon=rc, spatial=sc)
+                recon=rc, spatial=sc, pp_spec=pps)
 
 
 def empty_recon_history(H: int, W: int) -> dict:

@@ -200,6 +200,7 @@ typedef struct {
   int n;
   double* v;    /* n * 9 */
   double* alb;  /* n * 3 */
+  double* spec; /* n * 2 (k_s, shininess) or NULL: Lambertian */
   int* idx;     /* permutation of triangles, leaves own contiguous ranges */
   onode_t* nodes;
   int nnodes;
@@ -284,7 +285,17 @@ or_scene* or_scene_create(const double* verts, const double* albedo, int n) {
 
 void or_scene_destroy(or_scene* s) {
   if (!s) return;
-  free(s->v); free(s->alb); free(s->idx); free(s->nodes); free(s);
+  free(s->v); free(s->alb); free(s->spec); free(s->idx); free(s->nodes); free(s);
+}
+
+/* specular materials per triangle (input order): k_s >= 0, shininess >= 1; */
+/* NULL makes every triangle Lambertian again                               */
+void or_scene_set_spec(or_scene* s, const double* spec) {
+  free(s->spec);
+  s->spec = NULL;
+  if (!spec) return;
+  s->spec = (double*)malloc(sizeof(double) * 2 * (size_t)(s->n > 0 ? s->n : 1));
+  memcpy(s->spec, spec, sizeof(double) * 2 * (size_t)s->n);
 }
 
 int or_scene_nodes(const or_scene* s) { return s->nnodes; }
@@ -414,9 +425,15 @@ void or_cast_rays(const or_scene* s, int n, const double* O, const double* D, in
 /* Shading (our reading of the paper's deferred shading): two-sided Lambertian */
 /* normal, one point light with inverse-square falloff, ambient term, no      */
 /* shadow rays.  light[9] = position, rgb intensity, rgb ambient.             */
+/* Specular materials (the bright highlights whose bokeh the paper's         */
+/* composite treats apart): a Blinn-Phong lobe added to the colour,          */
+/* k_s I max(0, n.h)^shininess / max(d^2, 1e-4) while the light is on the    */
+/* viewer's side (n.l > 0), h the unit half vector of the light direction   */
+/* and the direction back along the ray; *ys_out = its luminance.           */
 /* ------------------------------------------------------------------------- */
+static inline double luminance(const double* L);
 static void shade(const or_scene* s, const double* light, int tri, const double* O, const double* D,
-                  double t, double* L, double* n_out) {
+                  double t, double* L, double* n_out, double* ys_out) {
   const double* v = s->v + 9 * (size_t)tri;
   double e1[3], e2[3], n[3];
   v_sub(v + 3, v, e1); v_sub(v + 6, v, e2); v_cross(e1, e2, n);
@@ -432,6 +449,18 @@ static void shade(const or_scene* s, const double* light, int tri, const double*
   double irr = maxd(0.0, cosv) / maxd(d2, 1e-4);
   const double* al = s->alb + 3 * (size_t)tri;
   for (int c = 0; c < 3; ++c) L[c] = al[c] * (light[6 + c] + light[3 + c] * irr);
+  double ys = 0.0;
+  if (s->spec && s->spec[2 * (size_t)tri] > 0.0 && cosv > 0.0) {
+    double hv[3], dl = v_len(D);
+    for (int a = 0; a < 3; ++a) hv[a] = l[a] / d - D[a] / dl;
+    double hl = v_len(hv);
+    double nh = hl > 0.0 ? maxd(0.0, v_dot(n, hv) / hl) : 0.0;
+    double f = s->spec[2 * (size_t)tri] * pow(nh, s->spec[2 * (size_t)tri + 1]) / maxd(d2, 1e-4);
+    double Ls[3];
+    for (int c = 0; c < 3; ++c) { Ls[c] = f * light[3 + c]; L[c] += Ls[c]; }
+    ys = luminance(Ls);
+  }
+  if (ys_out) *ys_out = ys;
   if (n_out) for (int a = 0; a < 3; ++a) n_out[a] = n[a];
 }
 
@@ -446,7 +475,7 @@ static inline double luminance(const double* L) { return 0.2126 * L[0] + 0.7152 
 /* ------------------------------------------------------------------------- */
 void or_gbuffer(const or_scene* s, const double* cam, int W, int H, const double* lens,
                 const double* light, const int64_t* pix, int64_t n,
-                double* z, double* nrm, double* alb, double* col, int* id, int* amb) {
+                double* z, double* nrm, double* alb, double* col, int* id, int* amb, double* spec) {
   cam_t k = mk_cam(cam, W, H);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; ++i) {
@@ -456,9 +485,9 @@ void or_gbuffer(const or_scene* s, const double* cam, int W, int H, const double
     lens_ray(&k, lens, x, y, 0, 0, 0, 0, 1, O, D);
     ohit_t h = cast_ray(s, O, D, 0);
     double L[3] = {0, 0, 0}, nn[3] = {0, 0, 0}, al[3] = {0, 0, 0};
-    double zz = OR_ZMAX;
+    double zz = OR_ZMAX, ys = 0.0;
     if (h.id >= 0) {
-      shade(s, light, h.id, O, D, h.t, L, nn);
+      shade(s, light, h.id, O, D, h.t, L, nn, &ys);
       for (int c = 0; c < 3; ++c) al[c] = s->alb[3 * (size_t)h.id + c];
       zz = h.t * lens[2];
     }
@@ -470,6 +499,7 @@ void or_gbuffer(const or_scene* s, const double* cam, int W, int H, const double
     }
     id[i] = h.id;
     amb[i] = h.amb;
+    if (spec) spec[i] = ys;
   }
 }
 
@@ -654,7 +684,7 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
       lens_ray(&k, lens, x, y, (uint64_t)j, seed, frame, view, 0, O, D);
       ohit_t h = cast_ray(s, O, D, 0);
       double L[3] = {0, 0, 0}, zz = OR_ZMAX;
-      if (h.id >= 0) { shade(s, light, h.id, O, D, h.t, L, NULL); zz = h.t * lens[2]; }
+      if (h.id >= 0) { shade(s, light, h.id, O, D, h.t, L, NULL, NULL); zz = h.t * lens[2]; }
       double Y = luminance(L);
       double c = coc_px(&k, lens, zz);
       double w = clampd(0.5 - c / (2.0 * OR_SQRT2), 0.0, 1.0);
@@ -1158,7 +1188,7 @@ void or_postfilter(const double* cam, int W, int H, const double* lens, const do
 void or_composite(const double* cam, int W, int H, const double* lens,
                   const double* color, const double* cpp, const double* z, const int* spp,
                   const double* c_near, const double* c_far, const double* hit,
-                  double h_t, int rt_override, double* out) {
+                  double h_t, int rt_override, const double* pp_spec, double spec_y, double* out) {
   cam_t k = mk_cam(cam, W, H);
   size_t N = (size_t)W * H;
   for (size_t p = 0; p < N; ++p) {
@@ -1169,10 +1199,15 @@ void or_composite(const double* cam, int W, int H, const double* lens,
     int traced = spp[p] > 0;
     double rho = traced ? 1.0 : 0.0;
     double beta = traced ? clampd(1.0 - h / h_t, 0.0, 1.0) : 0.0;
+    /* specular bokeh: near and traced, the post-process colour is favoured */
+    /* by sigma = clamp(Y_s,pp / spec_y, 0, 1), Y_s,pp the post-filtered   */
+    /* specular luminance                                                  */
+    double sig = (pp_spec && spec_y > 0.0) ? clampd(pp_spec[p] / spec_y, 0.0, 1.0) : 0.0;
     for (int q = 0; q < 3; ++q) {
       double crt = h * c_near[(size_t)q * N + p] + (1.0 - h) * c_far[(size_t)q * N + p];
       double cp = cpp[(size_t)q * N + p];
-      double oof = nu * (rho * crt + (1.0 - rho) * cp) + (1.0 - nu) * (beta * crt + (1.0 - beta) * cp);
+      double cnear = crt + sig * (cp - crt);
+      double oof = nu * (rho * cnear + (1.0 - rho) * cp) + (1.0 - nu) * (beta * crt + (1.0 - beta) * cp);
       double o = (1.0 - phi) * color[(size_t)q * N + p] + phi * oof;
       if (rt_override && traced) o = crt;
       out[(size_t)q * N + p] = o;

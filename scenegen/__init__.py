@@ -65,6 +65,7 @@ class Scene:
     verts: np.ndarray   # (n, 9) float32: v0.xyz, v1.xyz, v2.xyz
     albedo: np.ndarray  # (n, 3) float32
     meta: dict = field(default_factory=dict)
+    spec: np.ndarray | None = None  # (n, 2) float32 (k_s, shininess) or None: Lambertian
 
     @property
     def n_tris(self) -> int:
@@ -95,6 +96,7 @@ class PPParams:
 class CompositeParams:
     h_t: float = 0.5
     rt_override: int = 0
+    spec_y: float = 0.0  # > 0: specular luminance at which near traced pixels take the post-process colour
 
 
 @dataclass
@@ -221,6 +223,7 @@ def _assemble(parts, albedos, meta) -> Scene:
     verts = np.concatenate(parts).astype(F32)
     alb = np.concatenate([np.broadcast_to(np.asarray(a, np.float64), (p.shape[0], 3))
                           if np.ndim(a) == 1 else a for p, a in zip(parts, albedos)])
+    meta = dict(meta, part_tris=[int(p.shape[0]) for p in parts])
     return Scene(np.ascontiguousarray(verts), np.ascontiguousarray(alb.astype(F32)), meta)
 
 
@@ -278,6 +281,26 @@ def living_room_scene(seed: int = 0, n_objects: int = 20, depth_max: float = 6.0
         albs.append(alb)
     return _assemble(parts, albs, {"name": "living_room", "seed": seed,
                                    "n_objects": n_objects, "kinds": kinds})
+
+
+def glossy_living_room_scene(seed: int = 0, **kw) -> Scene:
+    """The living room with specular materials: every sphere gets a
+    Blinn-Phong lobe with k_s ~ U[0.3, 1] and shininess ~ U[16, 256]; walls
+    and boxes stay Lambertian (the highlights whose bokeh the composite
+    treats apart)."""
+    sc = living_room_scene(seed, **kw)
+    rng = np.random.default_rng(seed + 1000)
+    spec = np.zeros((sc.n_tris, 2), F32)
+    spec[:, 1] = 1.0
+    counts = sc.meta["part_tris"]
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    for kind, a, n in zip(["room"] + sc.meta["kinds"], starts, counts):
+        if kind == "sphere":
+            spec[a:a + n, 0] = rng.uniform(0.3, 1.0)
+            spec[a:a + n, 1] = rng.uniform(16.0, 256.0)
+    sc.spec = spec
+    sc.meta = dict(sc.meta, name="glossy_living_room")
+    return sc
 
 
 def default_light_tiny() -> Light:
