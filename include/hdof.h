@@ -107,10 +107,14 @@ typedef struct {
 
 /* Composite.  h_t > 0: hit ratio below which far pixels blend towards the
  * ray-traced colour; rt_override != 0: output the ray-traced colour wherever
- * a pixel was traced (full ray-traced reference mode). */
+ * a pixel was traced (full ray-traced reference mode); spec_y >= 0: the
+ * specular bokeh rule (paper, Composite): near traced pixels move from the
+ * ray-traced towards the post-process colour by clamp(Y_s,pp / spec_y, 0, 1),
+ * Y_s,pp the post-filtered specular luminance (0 = off). */
 typedef struct {
   float h_t;
   int32_t rt_override;
+  float spec_y;
 } hdof_composite_params;
 
 /* Temporal reconstruction of the traced colours (paper, Reconstruction).
@@ -142,10 +146,12 @@ typedef struct {
 /* G-buffer planes: depth [H][W] (axial, 1e4 on a miss), normal [3][H][W]
  * (face normal facing the viewer; 0 on a miss), albedo [3][H][W], color
  * [3][H][W] (shaded sharp image C_r), tri_id [H][W] (input triangle index,
- * -1 on a miss). */
+ * -1 on a miss), spec [H][W] (optional, may be NULL: luminance of the
+ * specular part of color; 0 for a Lambertian scene). */
 typedef struct {
   float *depth, *normal, *albedo, *color;
   int32_t* tri_id;
+  float* spec;
 } hdof_gbuffer_bufs;
 
 /* Per-pixel ray-trace results: c_near, c_far [3][H][W] (near- and far-field
@@ -191,6 +197,15 @@ hdof_status hdof_sync(hdof_ctx* ctx, hdof_stream stream);
 /* ---------------------------------------------------------------------- */
 /* Scene (acceleration structure; the paper uses the driver's hardware BVH) */
 /* ---------------------------------------------------------------------- */
+
+/* Specular materials (paper, Composite: specular bokeh): d_spec holds
+ * n_tris x 2 floats (k_s >= 0, shininess >= 1) in input triangle order,
+ * copied on `stream`; every shading (G-buffer, traced rays) then adds the
+ * Blinn-Phong lobe k_s I max(0, n.h)^shininess / max(d^2, 1e-4) while the
+ * light is on the viewer's side (h: unit half vector of the light direction
+ * and the direction back along the ray).  d_spec == NULL synchronises the
+ * device and makes the scene Lambertian again. */
+hdof_status hdof_scene_set_specular(hdof_scene* scene, const float* d_spec, hdof_stream stream);
 
 /* Build a binary BVH over n_tris triangles: Morton-ordered leaves clustered
  * bottom-up by PLOC (nearest neighbour by merged-box surface area within a
@@ -354,15 +369,32 @@ hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, const float* d_
                             const hdof_camera* cam, const hdof_lens* lens,
                             const hdof_pp_params* params, float* d_out, hdof_stream stream);
 
+/* The post-filter plus the post-filtered specular luminance (paper,
+ * Composite: the specular component's intensity in the post-process colour):
+ * hdof_postfilter on d_color into d_out, and the same gather (radius, taps,
+ * weights) applied to d_spec [H][W] (the G-buffer's specular luminance) into
+ * d_spec_out [H][W].  d_spp (nullable): where given, only pixels with
+ * d_spp > 0 gather the specular plane (the composite reads no other), the
+ * rest are 0. */
+hdof_status hdof_postfilter_specular(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                                     const float* d_spec, const uint8_t* d_spp, const hdof_camera* cam,
+                                     const hdof_lens* lens, const hdof_pp_params* params, float* d_out,
+                                     float* d_spec_out, hdof_stream stream);
+
 /* Composite (paper, Composite).  phi = clamp(|c| - sqrt 2, 0, 1) blends the
  * sharp colour (focus zone |c| < sqrt 2) with the out-of-focus colour; near
  * field: ray-traced colour where traced, else post-process; far field:
  * beta = clamp(1 - h / h_t, 0, 1) of ray-traced over post-process where
- * traced.  C_rt = h c_near + (1 - h) c_far.  d_out may alias d_pp. */
+ * traced.  C_rt = h c_near + (1 - h) c_far.  With d_pp_spec (the post-
+ * filtered specular luminance, as hdof_postfilter_specular writes it) and
+ * params->spec_y > 0, the near traced colour is C_rt + sigma (C_pp - C_rt),
+ * sigma = clamp(d_pp_spec / spec_y, 0, 1); d_pp_spec may be NULL (rule
+ * off).  d_out may alias d_pp. */
 hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_pp,
                            const float* d_depth, const uint8_t* d_spp, hdof_rt_bufs rt,
                            const hdof_camera* cam, const hdof_lens* lens,
-                           const hdof_composite_params* params, float* d_out, hdof_stream stream);
+                           const hdof_composite_params* params, const float* d_pp_spec, float* d_out,
+                           hdof_stream stream);
 
 /* Whole frame: G-buffer -> mask (reprojecting the history when prev != NULL)
  * -> trace -> variance update -> temporal reconstruction of the traced

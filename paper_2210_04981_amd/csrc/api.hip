@@ -108,6 +108,7 @@ static hdof_status check_pp(const hdof_pp_params* p) {
 static hdof_status check_comp(const hdof_composite_params* c) {
   REQUIRE(c, "composite params are NULL");
   REQUIRE(isfinite(c->h_t) && c->h_t > 0.0f, "h_t must be > 0");
+  REQUIRE(isfinite(c->spec_y) && c->spec_y >= 0.0f, "spec_y must be finite and >= 0");
   return HDOF_OK;
 }
 
@@ -206,7 +207,7 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->hist_m2, &ctx->hist_flags, &ctx->hist_z, &ctx->rep_m1, &ctx->rep_m2,
                 &ctx->rep_flags, &ctx->f_depth, &ctx->f_normal, &ctx->f_albedo, &ctx->f_color,
                 &ctx->f_triid, &ctx->f_spp, &ctx->f_offsets, &ctx->f_total, &ctx->f_cn, &ctx->f_cf,
-                &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp, &ctx->rec_hist[0], &ctx->rec_hist[1],
+                &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp, &ctx->f_spec, &ctx->f_pps, &ctx->rec_hist[0], &ctx->rec_hist[1],
                 &ctx->rec_valid[0], &ctx->rec_valid[1], &ctx->rec_farpos, &ctx->sp_levels, &ctx->sp_taps,
                 &ctx->sp_cn, &ctx->sp_cf, &ctx->sp_coc};
   for (Buf* b : all) buf_free(*b);
@@ -268,8 +269,30 @@ extern "C" void hdof_scene_destroy(hdof_scene* sc) {
   if (sc->nodes) hipFree(sc->nodes);
   if (sc->tris) hipFree(sc->tris);
   if (sc->albedo) hipFree(sc->albedo);
+  if (sc->spec) hipFree(sc->spec);
   if (sc->depth_out) hipFree(sc->depth_out);
   delete sc;
+}
+
+extern "C" hdof_status hdof_scene_set_specular(hdof_scene* sc, const float* d_spec, hdof_stream stream) {
+  REQUIRE(sc, "scene is NULL");
+  TRY(check_ctx(sc->ctx));
+  if (!d_spec) {
+    if (sc->spec) {
+      HDOF_HIP(hipDeviceSynchronize());  // frames in flight may still read the table
+      HDOF_HIP(hipFree(sc->spec));
+      sc->bytes -= sizeof(float) * 2 * (int64_t)sc->n_tris;
+      sc->spec = nullptr;
+    }
+    return HDOF_OK;
+  }
+  if (!sc->spec) {
+    HDOF_HIP(hipMalloc(&sc->spec, sizeof(float) * 2 * (size_t)sc->n_tris));
+    sc->bytes += sizeof(float) * 2 * (int64_t)sc->n_tris;
+  }
+  HDOF_HIP(hipMemcpyAsync(sc->spec, d_spec, sizeof(float) * 2 * (size_t)sc->n_tris, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+  return HDOF_OK;
 }
 
 extern "C" hdof_status hdof_scene_stats(hdof_scene* sc, hdof_scene_info* out) {
@@ -508,10 +531,28 @@ extern "C" hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, cons
   return launch_postfilter(ctx, d_color, d_depth, k, make_lensk(lens, k), *params, d_out, (hipStream_t)stream);
 }
 
+extern "C" hdof_status hdof_postfilter_specular(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                                                const float* d_spec, const uint8_t* d_spp, const hdof_camera* cam,
+                                                const hdof_lens* lens, const hdof_pp_params* params, float* d_out,
+                                                float* d_spec_out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(d_color && d_depth && d_out && d_spec && d_spec_out, "color, depth, out, spec and spec_out must be non-NULL");
+  REQUIRE(d_spec_out != d_spec, "spec_out must not alias spec");
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_pp(params));
+  CamK k = make_camk(cam);
+  const LensK l = make_lensk(lens, k);
+  hipStream_t st = (hipStream_t)stream;
+  TRY(launch_postfilter(ctx, d_color, d_depth, k, l, *params, d_out, st));
+  return launch_pp_spec(ctx, d_spec, d_spp, k, l, *params, d_spec_out, st);
+}
+
 extern "C" hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_pp,
                                       const float* d_depth, const uint8_t* d_spp, hdof_rt_bufs rt,
                                       const hdof_camera* cam, const hdof_lens* lens,
-                                      const hdof_composite_params* params, float* d_out, hdof_stream stream) {
+                                      const hdof_composite_params* params, const float* d_pp_spec, float* d_out,
+                                      hdof_stream stream) {
   TRY(check_ctx(ctx));
   REQUIRE(d_color && d_pp && d_depth && d_spp && d_out, "color, pp, depth, spp and out must be non-NULL");
   TRY(check_rt(&rt));
@@ -520,7 +561,7 @@ extern "C" hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const
   TRY(check_comp(params));
   CamK k = make_camk(cam);
   return launch_composite(ctx, d_color, d_pp, d_depth, d_spp, rt, k, make_lensk(lens, k), *params, d_out,
-                          (hipStream_t)stream);
+                          (hipStream_t)stream, d_pp_spec);
 }
 
 template <typename T>
@@ -567,6 +608,16 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(pick_buf(u.gb.albedo, ctx->f_albedo, 12 * N, &gb.albedo));
   TRY(pick_buf(u.gb.color, ctx->f_color, 12 * N, &gb.color));
   TRY(pick_buf(u.gb.tri_id, ctx->f_triid, 4 * N, &gb.tri_id));
+  // specular bokeh: the G-buffer's specular luminance and its post-filtered
+  // value at the traced pixels (the composite's rule reads no other)
+  const bool spec_on = scene->spec && params->comp.spec_y > 0.0f;
+  float* pps = nullptr;
+  gb.spec = u.gb.spec;
+  if (spec_on) {
+    TRY(pick_buf(u.gb.spec, ctx->f_spec, 4 * N, &gb.spec));
+    TRY(hdof_ensure(ctx->f_pps, 4 * N));
+    pps = (float*)ctx->f_pps.p;
+  }
   TRY(pick_buf(u.spp, ctx->f_spp, N, &spp));
   TRY(pick_buf(u.offsets, ctx->f_offsets, 4 * N, &offs));
   TRY(pick_buf(u.total, ctx->f_total, 4, &total));
@@ -654,12 +705,16 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
                        nullptr, true, params->spatial, rt.c_near, rt.c_far, st, true);
   hdof_prof_mark(ctx, 7, st);
   if (fused) {
-    const PostFuse pf{spp, rt, params->comp, d_out};
+    // the G-buffer wrote the packed texels and tile radii the specular gather reads
+    if (s == HDOF_OK && spec_on) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);
+    const PostFuse pf{spp, rt, params->comp, d_out, pps};
     if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st, true, &pf);  // mark 8
   } else {
     if (s == HDOF_OK) s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, st);  // mark 8
+    if (s == HDOF_OK && spec_on) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);
     hdof_prof_mark(ctx, 9, st);
-    if (s == HDOF_OK) s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st);
+    if (s == HDOF_OK)
+      s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st, pps);
   }
   hdof_prof_mark(ctx, 10, st);
   ctx->prof_in_frame = false;
@@ -788,6 +843,9 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
   if (params->spatial.enable)
     return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the batched form does not run the spatial reconstruction "
                                                 "(call hdof_frame per view)");
+  if (scene->spec && params->comp.spec_y > 0.0f)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the batched form does not apply the specular bokeh rule "
+                                                "(call hdof_frame per view)");
   if (params->recon.enable)
     return hdof_set_error(HDOF_ERR_UNSUPPORTED, "temporal reconstruction needs one history per view: "
                           "not available in the batched form");
@@ -875,6 +933,7 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     gb.albedo = (float*)(a + L.o_albedo) + 3 * pb;
     gb.color = (float*)(a + L.o_color) + 3 * pb;
     gb.tri_id = (int32_t*)(a + L.o_tri) + pb;
+    gb.spec = nullptr;
     rt[v].c_near = (float*)(a + L.o_cn) + 3 * pb;
     rt[v].c_far = (float*)(a + L.o_cf) + 3 * pb;
     rt[v].hit_ratio = (float*)(a + L.o_h) + pb;
@@ -1024,6 +1083,8 @@ extern "C" hdof_status hdof_postfilter_composite_backward(
   TRY(check_lens(lens));
   TRY(check_pp(pp));
   TRY(check_comp(comp));
+  if (comp->spec_y > 0.0f)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the adjoint does not differentiate the specular bokeh rule");
   CamK k = make_camk(cam);
   return launch_ppc_backward(ctx, d_color, d_depth, d_spp, rt, k, make_lensk(lens, k), *pp, *comp, d_grad_out,
                              d_grad_color, d_grad_lens, (hipStream_t)stream);

@@ -48,6 +48,7 @@ struct hdof_scene {
   float4* nodes;   // 4 float4 per node: child boxes x/y (2), z (1), children (1)
   float4* tris;    // 3 float4 per triangle in leaf order; .w of the first = input index
   float* albedo;   // 3 floats per triangle, input order
+  float* spec;     // 2 floats per triangle (k_s, shininess), input order; NULL: Lambertian
   int32_t* depth_out;  // [1] tree depth (computed at build)
   int64_t bytes;
 };
@@ -93,7 +94,7 @@ struct hdof_ctx {
   int sp_taps_n = 0;
   // frame intermediates when the caller keeps none
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
-  Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp;
+  Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp, f_spec, f_pps;
   // persistent-trace launch shape (performance only)
   hdof_tuning tune = {HDOF_DEFAULT_BPC, 64, 8};
   // batched form: per-view intermediates, view table (device + pinned host)
@@ -315,6 +316,7 @@ struct PostFuse {
   hdof_rt_bufs rt;
   hdof_composite_params cp;
   float* out;
+  const float* pps;  // nullable: post-filtered specular luminance (the specular bokeh rule)
 };
 // packed: pack and per-tile radius already written (by the G-buffer)
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
@@ -326,4 +328,10 @@ hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* 
                                 float* grad_lens, hipStream_t st);
 hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
                              const uint8_t* spp, hdof_rt_bufs rt, const CamK& k, const LensK& l,
-                             const hdof_composite_params& cp, float* out, hipStream_t st);
+                             const hdof_composite_params& cp, float* out, hipStream_t st,
+                             const float* pps = nullptr);
+// the post-filtered specular luminance of the traced pixels (all pixels when
+// spp is NULL); reads the frame's post-filter preparation (packed CoC, tile
+// radii, taps), so it follows the G-buffer's packing or launch_postfilter
+hdof_status launch_pp_spec(hdof_ctx* ctx, const float* ys, const uint8_t* spp, const CamK& k, const LensK& l,
+                           const hdof_pp_params& pp, float* out, hipStream_t st);

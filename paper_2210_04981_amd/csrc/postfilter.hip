@@ -266,6 +266,8 @@ struct FuseK {
   float inv_ht;
   int rt_override;
   float* out;
+  const float* pps;  // nullable: post-filtered specular luminance
+  float inv_sy;      // 1 / spec_y, 0: no specular bokeh rule
 };
 
 __device__ __forceinline__ void composite_px(const FuseK& fz, size_t N, size_t p, const float4& cp4, float pr,
@@ -277,11 +279,13 @@ __device__ __forceinline__ void composite_px(const FuseK& fz, size_t N, size_t p
   const float h = traced ? fz.hr[p] : 0.0f;
   const float rho = traced ? 1.0f : 0.0f;
   const float beta = traced ? clamp01(1.0f - h * fz.inv_ht) : 0.0f;
+  const float sig = (fz.pps && traced && fz.inv_sy > 0.0f) ? clamp01(fz.pps[p] * fz.inv_sy) : 0.0f;
   const float col[3] = {cp4.x, cp4.y, cp4.z}, cpp[3] = {pr, pg, pb};
   for (int q = 0; q < 3; ++q) {
     const size_t i = (size_t)q * N + p;
     const float crt = traced ? h * fz.cn[i] + (1.0f - h) * fz.cf[i] : 0.0f;
-    const float oof = nu * (rho * crt + (1.0f - rho) * cpp[q]) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp[q]);
+    const float cnear = fmaf(sig, cpp[q] - crt, crt);
+    const float oof = nu * (rho * cnear + (1.0f - rho) * cpp[q]) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp[q]);
     float o = (1.0f - phi) * col[q] + phi * oof;
     if (fz.rt_override && traced) o = crt;
     fz.out[i] = o;
@@ -387,11 +391,66 @@ __global__ __launch_bounds__(256) void k_pp_gather_any(const float4* __restrict_
   g.store(out, N, p);
 }
 
+// The post-filtered specular luminance (the specular bokeh rule of the
+// composite): the post-filter's gather, radius, taps and weights, applied to
+// the G-buffer's specular luminance plane.  One 16x16 block per 16-pixel
+// tile, each wave an 8x8 quadrant (aligned with the ray mask's tiles); with
+// spp given only traced pixels gather (the rule reads no other), the rest
+// are 0.  Texels are fetched directly (a few traced pixels per frame).
+// Radius: t == 16, the block's dilated tile radius from tile_r; otherwise
+// the pixel's tile entry of the dilated radii.
+__global__ __launch_bounds__(256) void k_pp_spec(const float4* __restrict__ pack, const float* __restrict__ ys,
+                                                 const uint8_t* __restrict__ spp, const float* __restrict__ tile_r,
+                                                 const float* __restrict__ rad, int t, int K, float r_cap,
+                                                 const float4* __restrict__ taps, int n_taps, int W, int H,
+                                                 float inv_ramp, float* __restrict__ out) {
+  __shared__ float wred[4];
+  const int BW = (W + 15) >> 4, BH = (H + 15) >> 4;
+  const int b = xcd_block(blockIdx.x, BW * BH), bx = b % BW, by = b / BW;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int x = bx * 16 + (w & 1) * 8 + (l & 7), y = by * 16 + (w >> 1) * 8 + (l >> 3);
+  float R;
+  if (t == 16) {
+    R = block_dilated_radius(tile_r, BW, BH, bx, by, K, r_cap, wred);
+  } else {
+    const int TW = (W + t - 1) / t;
+    R = (x < W && y < H) ? rad[(y / t) * TW + x / t] : 0.0f;
+  }
+  if (x >= W || y >= H) return;
+  const size_t p = (size_t)y * W + x;
+  if (spp && spp[p] == 0) {
+    out[p] = 0.0f;
+    return;
+  }
+  const float4 cp4 = pack[p];
+  GatherAcc g;
+  g.init(make_float4(ys[p], 0.0f, 0.0f, cp4.w), R, n_taps, inv_ramp);
+  for (int j = 0; j < n_taps; ++j) {
+    const float4 u = taps[j];
+    const float ox = R * u.x, oy = R * u.y;
+    const float fx = floorf(ox), fy = floorf(oy);
+    const float ax = ox - fx, ay = oy - fy, bxw = 1.0f - ax, byw = 1.0f - ay;
+    const int xa = x + (int)fx, ya = y + (int)fy;
+    float4 v00, v10, v01, v11;
+    texels_clamped(pack, W, H, xa, ya, v00, v10, v01, v11);
+    const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
+    const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
+    v00.x = ys[(size_t)ya_ * W + xa_];
+    v10.x = ys[(size_t)ya_ * W + xb_];
+    v01.x = ys[(size_t)yb_ * W + xa_];
+    v11.x = ys[(size_t)yb_ * W + xb_];
+    g.tap(bxw * byw, ax * byw, bxw * ay, ax * ay, 0.5f - R * u.z, v00, v10, v01, v11);
+  }
+  out[p] = g.ar / g.ws;
+}
+
+// pps (nullable): the post-filtered specular luminance; inv_sy = 1 / spec_y
+// (0: the specular bokeh rule is off)
 __global__ void k_composite(const float* __restrict__ color, const float* __restrict__ pp,
                             const float* __restrict__ depth, const uint8_t* __restrict__ spp,
                             const float* __restrict__ cn, const float* __restrict__ cf,
                             const float* __restrict__ hr, LensK l, int N, float inv_ht, int rt_override,
-                            float* __restrict__ out) {
+                            const float* __restrict__ pps, float inv_sy, float* __restrict__ out) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   const float c = coc_px(l, depth[p]);
@@ -404,11 +463,13 @@ __global__ void k_composite(const float* __restrict__ color, const float* __rest
   const float h = traced ? hr[p] : 0.0f;
   const float rho = traced ? 1.0f : 0.0f;
   const float beta = traced ? clamp01(1.0f - h * inv_ht) : 0.0f;
+  const float sig = (pps && traced && inv_sy > 0.0f) ? clamp01(pps[p] * inv_sy) : 0.0f;
   for (int q = 0; q < 3; ++q) {
     size_t i = (size_t)q * N + p;
     const float crt = traced ? h * cn[i] + (1.0f - h) * cf[i] : 0.0f;
     const float cpp = phi > 0.0f ? pp[i] : 0.0f;
-    float oof = nu * (rho * crt + (1.0f - rho) * cpp) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp);
+    const float cnear = fmaf(sig, cpp - crt, crt);
+    float oof = nu * (rho * cnear + (1.0f - rho) * cpp) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp);
     float o = (1.0f - phi) * color[i] + phi * oof;
     if (rt_override && traced) o = crt;
     out[i] = o;
@@ -811,7 +872,8 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
     FuseK fz{};
     if (fuse) {
       fz = FuseK{fuse->spp, fuse->rt.c_near, fuse->rt.c_far, fuse->rt.hit_ratio, 1.0f / fuse->cp.h_t,
-                 fuse->cp.rt_override, fuse->out};
+                 fuse->cp.rt_override, fuse->out, fuse->pps,
+                 fuse->pps && fuse->cp.spec_y > 0.0f ? 1.0f / fuse->cp.spec_y : 0.0f};
       hipLaunchKernelGGL(k_pp_gather16<true>, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                          (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
@@ -826,7 +888,8 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
                        (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
     if (fuse) {
       HDOF_HIP(hipGetLastError());
-      return launch_composite(ctx, color, out, depth, fuse->spp, fuse->rt, k, l, fuse->cp, fuse->out, st);
+      return launch_composite(ctx, color, out, depth, fuse->spp, fuse->rt, k, l, fuse->cp, fuse->out, st,
+                              fuse->pps);
     }
   }
   HDOF_HIP(hipGetLastError());
@@ -835,11 +898,32 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
 
 hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
                              const uint8_t* spp, hdof_rt_bufs rt, const CamK& k, const LensK& l,
-                             const hdof_composite_params& cp, float* out, hipStream_t st) {
+                             const hdof_composite_params& cp, float* out, hipStream_t st, const float* pps) {
   (void)ctx;
   const int N = k.W * k.H;
+  const float inv_sy = pps && cp.spec_y > 0.0f ? 1.0f / cp.spec_y : 0.0f;
   hipLaunchKernelGGL(k_composite, dim3(cdiv(N, 256)), dim3(256), 0, st, color, pp, depth, spp, rt.c_near,
-                     rt.c_far, rt.hit_ratio, l, N, 1.0f / cp.h_t, cp.rt_override, out);
+                     rt.c_far, rt.hit_ratio, l, N, 1.0f / cp.h_t, cp.rt_override, pps, inv_sy, out);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+hdof_status launch_pp_spec(hdof_ctx* ctx, const float* ys, const uint8_t* spp, const CamK& k, const LensK& l,
+                           const hdof_pp_params& pp, float* out, hipStream_t st) {
+  (void)l;
+  const int W = k.W, H = k.H, t = pp.tile;
+  const int K = (int)ceil((double)pp.r_cap / t);
+  if (!ctx->pp_pack.p || !ctx->pp_tile.p || (t != 16 && !ctx->pp_rad.p))
+    return hdof_set_error(HDOF_ERR_INVALID_ARG, "specular post-filter before the frame's post-filter preparation");
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
+  if (ctx->pp_taps_n != pp.n_taps) {
+    hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
+    ctx->pp_taps_n = pp.n_taps;
+  }
+  hipLaunchKernelGGL(k_pp_spec, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, (const float4*)ctx->pp_pack.p, ys,
+                     spp, (const float*)ctx->pp_tile.p, (const float*)ctx->pp_rad.p, t, K, pp.r_cap,
+                     (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, 1.0f / pp.bg_ramp_px, out);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

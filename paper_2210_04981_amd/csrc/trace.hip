@@ -278,9 +278,14 @@ __device__ inline Best traverse_wave(const float4* __restrict__ nodes, const flo
   return b;
 }
 
-// Two-sided Lambertian face normal + point light, no shadow ray.
+// Two-sided Lambertian face normal + point light, no shadow ray; with a
+// specular table (k_s, shininess per input triangle) a Blinn-Phong lobe
+// k_s I max(0, n.h)^shininess / max(d^2, 1e-4) is added while the light is
+// on the viewer's side, h the unit half vector of the light direction and
+// the direction back along the ray; ys = the lobe's luminance.
 __device__ inline void shade(const float4* __restrict__ tris, const float* __restrict__ albedo,
-                             const LightK& li, const Ray& r, const Best& b, V3& L, V3& n, V3& alb) {
+                             const float2* __restrict__ spec, const LightK& li, const Ray& r, const Best& b, V3& L,
+                             V3& n, V3& alb, float& ys) {
   float4 a = tris[3 * b.tri], q = tris[3 * b.tri + 1], c = tris[3 * b.tri + 2];
   V3 e1 = V3{q.x - a.x, q.y - a.y, q.z - a.z};
   V3 e2 = V3{c.x - a.x, c.y - a.y, c.z - a.z};
@@ -298,15 +303,31 @@ __device__ inline void shade(const float4* __restrict__ tris, const float* __res
   L = V3{alb.x * fmaf(li.I.x, irr, li.ka.x), alb.y * fmaf(li.I.y, irr, li.ka.y),
          alb.z * fmaf(li.I.z, irr, li.ka.z)};
   n = nn;
+  ys = 0.0f;
+  if (spec) {
+    const float2 m = spec[b.id];
+    if (m.x > 0.0f && cosv > 0.0f) {
+      const float il2 = rsqrtf(d2), iD = rsqrtf(dot3(r.D, r.D));
+      const V3 h = V3{fmaf(l.x, il2, -r.D.x * iD), fmaf(l.y, il2, -r.D.y * iD), fmaf(l.z, il2, -r.D.z * iD)};
+      const float hh = dot3(h, h);
+      const float nh = hh > 0.0f ? fmaxf(0.0f, dot3(nn, h) * rsqrtf(hh)) : 0.0f;
+      const float f = m.x * powf(nh, m.y) / fmaxf(d2, 1e-4f);
+      L = V3{fmaf(f, li.I.x, L.x), fmaf(f, li.I.y, L.y), fmaf(f, li.I.z, L.z)};
+      ys = f * fmaf(0.2126f, li.I.x, fmaf(0.7152f, li.I.y, 0.0722f * li.I.z));
+    }
+  }
 }
 
 // PACK (frames with 16-pixel post-filter tiles): also the post-filter's
 // packed texel (shaded rgb, signed CoC of the stored depth) and the block's
 // maximum CoC radius, the block being the post-filter tile.
+// spec_out (nullable): the specular luminance plane.
 template <bool COUNT, bool PACK>
 __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ nodes,
                                                  const float4* __restrict__ tris, int n_nodes,
-                                                 const float* __restrict__ albedo, CamK k, LensK l,
+                                                 const float* __restrict__ albedo,
+                                                 const float2* __restrict__ spec, float* __restrict__ spec_out,
+                                                 CamK k, LensK l,
                                                  LightK li, float* __restrict__ depth,
                                                  float* __restrict__ normal, float* __restrict__ alb_out,
                                                  float* __restrict__ color, int* __restrict__ tri_id,
@@ -332,11 +353,11 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
       atomicAdd(&counters[2], (unsigned long long)wk.tests);
     }
     const size_t N = (size_t)k.W * k.H, p = (size_t)y * k.W + x;
-    float z = HDOF_ZMAX;
+    float z = HDOF_ZMAX, ys = 0.0f;
     V3 L = V3{0.0f, 0.0f, 0.0f};
     if (b.tri >= 0) {
       V3 n, a;
-      shade(tris, albedo, li, r, b, L, n, a);
+      shade(tris, albedo, spec, li, r, b, L, n, a, ys);
       z = b.t * l.S1;
       normal[p] = n.x;
       normal[N + p] = n.y;
@@ -353,6 +374,7 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
       tri_id[p] = -1;
     }
     depth[p] = z;
+    if (spec_out) spec_out[p] = ys;
     color[p] = L.x;
     color[N + p] = L.y;
     color[2 * N + p] = L.z;
@@ -409,6 +431,7 @@ struct TraceArgs {
   const float4* tris;
   int n_nodes;
   const float* albedo;
+  const float2* spec;  // nullable: Lambertian
   LightK li;
   const int* queue;
   const int* offsets;
@@ -514,7 +537,8 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
       V3 L = V3{0.0f, 0.0f, 0.0f};
       if (s.b.tri >= 0) {
         V3 n, a;
-        shade(A.tris, A.albedo, A.li, r, s.b, L, n, a);
+        float ys;
+        shade(A.tris, A.albedo, A.spec, A.li, r, s.b, L, n, a, ys);
         z = s.b.t * S1;
       }
       A.ray_col[e] = L.x;
@@ -654,12 +678,18 @@ void launch_trace_kernel(hdof_ctx* ctx, const TraceArgs& A, hipStream_t st) {
     hipLaunchKernelGGL((k_trace<false, BATCH>), dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, A);
 }
 
+__global__ void k_zero_f(float* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0f;
+}
+
 TraceArgs base_args(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, size_t cap) {
   TraceArgs A{};
   A.nodes = sc->nodes;
   A.tris = sc->tris;
   A.n_nodes = sc->n_nodes;
   A.albedo = sc->albedo;
+  A.spec = (const float2*)sc->spec;
   A.li = li;
   A.queue = (const int*)ctx->queue.p;
   A.counter = (int*)ctx->work_counter.p;
@@ -679,9 +709,12 @@ hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, c
   int nb = cdiv(k.W, 16) * cdiv(k.H, 16);
   auto kern = ctx->count_on ? (pack ? k_gbuffer<true, true> : k_gbuffer<true, false>)
                             : (pack ? k_gbuffer<false, true> : k_gbuffer<false, false>);
-  hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo, k, l, li,
-                     out.depth, out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags, ctx->d_counters, pack,
-                     tile_r);
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                     (const float2*)sc->spec, sc->spec ? out.spec : nullptr, k, l, li, out.depth, out.normal,
+                     out.albedo, out.color, out.tri_id, ctx->d_flags, ctx->d_counters, pack, tile_r);
+  // a Lambertian scene has no specular part: its plane is 0
+  if (!sc->spec && out.spec) hipLaunchKernelGGL(k_zero_f, dim3(cdiv(k.W * k.H, 256)), dim3(256), 0, st, out.spec,
+                                                k.W * k.H);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

@@ -55,7 +55,7 @@ class PPParams(C.Structure):
 
 
 class CompositeParams(C.Structure):
-    _fields_ = [("h_t", C.c_float), ("rt_override", C.c_int32)]
+    _fields_ = [("h_t", C.c_float), ("rt_override", C.c_int32), ("spec_y", C.c_float)]
 
 
 class ReconParams(C.Structure):
@@ -75,7 +75,7 @@ P = C.c_void_p
 
 
 class GBufferBufs(C.Structure):
-    _fields_ = [("depth", P), ("normal", P), ("albedo", P), ("color", P), ("tri_id", P)]
+    _fields_ = [("depth", P), ("normal", P), ("albedo", P), ("color", P), ("tri_id", P), ("spec", P)]
 
 
 class RTBufs(C.Structure):
@@ -132,7 +132,10 @@ _PROTOS = {
     "hdof_history_reset": (_S, [P]),
     "hdof_postfilter": (_S, [P, P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(PPParams), P, P]),
     "hdof_composite": (_S, [P, P, P, P, P, RTBufs, C.POINTER(Camera), C.POINTER(Lens),
-                            C.POINTER(CompositeParams), P, P]),
+                            C.POINTER(CompositeParams), P, P, P]),
+    "hdof_postfilter_specular": (_S, [P, P, P, P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(PPParams),
+                                      P, P, P]),
+    "hdof_scene_set_specular": (_S, [P, P, P]),
     "hdof_frame": (_S, [P, P, C.POINTER(Camera), C.POINTER(Camera), C.POINTER(Lens), C.POINTER(Light),
                         C.POINTER(FrameParams), _u32, _u32, _u32, P, C.POINTER(FrameBufs), P]),
     "hdof_profile_begin": (_S, [P]),
@@ -215,8 +218,8 @@ def pp_params(n_taps=48, tile=16, r_cap=64.0, bg_ramp_px=1.0) -> PPParams:
     return PPParams(n_taps, tile, r_cap, bg_ramp_px)
 
 
-def composite_params(h_t=0.5, rt_override=0) -> CompositeParams:
-    return CompositeParams(h_t, rt_override)
+def composite_params(h_t=0.5, rt_override=0, spec_y=0.0) -> CompositeParams:
+    return CompositeParams(h_t, rt_override, spec_y)
 
 
 # ----------------------------------------------------------------------------
@@ -277,6 +280,12 @@ def hdof_create(device: int = 0) -> Context:
     return Context(device)
 
 
+def hdof_scene_set_specular(scene: "Scene", spec: torch.Tensor | None, stream=None) -> None:
+    """Per-triangle (k_s, shininess) specular table (n, 2), or None (Lambertian)."""
+    _check(_lib.hdof_scene_set_specular(scene.handle, _ptr(spec, torch.float32, 2 * scene.n_tris, "spec"),
+                                        _stream(stream)), "hdof_scene_set_specular")
+
+
 def hdof_build_bvh(ctx: Context, verts: torch.Tensor, albedo: torch.Tensor, stream=None) -> Scene:
     n = verts.shape[0]
     pv = _ptr(verts, torch.float32, 9 * n, "verts")
@@ -299,12 +308,14 @@ class GBuffer:
     albedo: torch.Tensor
     color: torch.Tensor
     tri_id: torch.Tensor
+    spec: torch.Tensor | None = None  # specular luminance (optional)
 
     @staticmethod
-    def empty(H: int, W: int, device="cuda") -> "GBuffer":
+    def empty(H: int, W: int, device="cuda", spec: bool = False) -> "GBuffer":
         f = dict(dtype=torch.float32, device=device)
         return GBuffer(torch.empty(H, W, **f), torch.empty(3, H, W, **f), torch.empty(3, H, W, **f),
-                       torch.empty(3, H, W, **f), torch.empty(H, W, dtype=torch.int32, device=device))
+                       torch.empty(3, H, W, **f), torch.empty(H, W, dtype=torch.int32, device=device),
+                       torch.empty(H, W, **f) if spec else None)
 
     def bufs(self) -> GBufferBufs:
         n = self.depth.numel()
@@ -312,7 +323,8 @@ class GBuffer:
                            _ptr(self.normal, torch.float32, 3 * n, "normal"),
                            _ptr(self.albedo, torch.float32, 3 * n, "albedo"),
                            _ptr(self.color, torch.float32, 3 * n, "color"),
-                           _ptr(self.tri_id, torch.int32, n, "tri_id"))
+                           _ptr(self.tri_id, torch.int32, n, "tri_id"),
+                           _ptr(self.spec, torch.float32, n, "spec"))
 
 
 @dataclass
@@ -476,15 +488,32 @@ def hdof_postfilter(ctx: Context, color, depth, cam: Camera, lns: Lens, pp: PPPa
 
 
 def hdof_composite(ctx: Context, color, pp_col, depth, spp, rt: RTResult, cam: Camera, lns: Lens,
-                   cp: CompositeParams, out=None, stream=None):
+                   cp: CompositeParams, out=None, stream=None, pp_spec=None):
     n = _npx(cam)
     out = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device=color.device) if out is None else out
     _check(_lib.hdof_composite(ctx.handle, _ptr(color, torch.float32, 3 * n, "color"),
                                _ptr(pp_col, torch.float32, 3 * n, "pp"), _ptr(depth, torch.float32, n, "depth"),
                                _ptr(spp, torch.uint8, n, "spp"), rt.bufs(n), C.byref(cam), C.byref(lns),
-                               C.byref(cp), _ptr(out, torch.float32, 3 * n, "out"), _stream(stream)),
+                               C.byref(cp), _ptr(pp_spec, torch.float32, n, "pp_spec"),
+                               _ptr(out, torch.float32, 3 * n, "out"), _stream(stream)),
            "hdof_composite")
     return out
+
+
+def hdof_postfilter_specular(ctx: Context, color, depth, spec, spp, cam: Camera, lns: Lens, pp: PPParams,
+                             out=None, spec_out=None, stream=None):
+    """The post-filter plus the post-filtered specular luminance: (out, spec_out)."""
+    n = _npx(cam)
+    out = torch.empty(3, cam.height, cam.width, dtype=torch.float32, device=color.device) if out is None else out
+    spec_out = torch.empty(cam.height, cam.width, dtype=torch.float32, device=color.device) \
+        if spec_out is None else spec_out
+    _check(_lib.hdof_postfilter_specular(ctx.handle, _ptr(color, torch.float32, 3 * n, "color"),
+                                         _ptr(depth, torch.float32, n, "depth"), _ptr(spec, torch.float32, n, "spec"),
+                                         _ptr(spp, torch.uint8, n, "spp"), C.byref(cam), C.byref(lns), C.byref(pp),
+                                         _ptr(out, torch.float32, 3 * n, "out"),
+                                         _ptr(spec_out, torch.float32, n, "spec_out"), _stream(stream)),
+           "hdof_postfilter_specular")
+    return out, spec_out
 
 
 @dataclass
@@ -555,7 +584,7 @@ def pp_params_of(p) -> PPParams:
 
 
 def composite_params_of(c) -> CompositeParams:
-    return composite_params(c.h_t, c.rt_override)
+    return composite_params(c.h_t, c.rt_override, float(getattr(c, "spec_y", 0.0)))
 
 
 def recon_params_of(r) -> ReconParams:

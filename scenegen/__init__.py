@@ -284,10 +284,11 @@ def living_room_scene(seed: int = 0, n_objects: int = 20, depth_max: float = 6.0
 
 
 def glossy_living_room_scene(seed: int = 0, **kw) -> Scene:
-    """The living room with specular materials: every sphere gets a
-    Blinn-Phong lobe with k_s ~ U[0.3, 1] and shininess ~ U[16, 256]; walls
-    and boxes stay Lambertian (the highlights whose bokeh the composite
-    treats apart)."""
+    """The living room with specular materials: every object gets a
+    Blinn-Phong lobe with k_s ~ U[0.3, 1], shininess ~ U[16, 256] for the
+    spheres and U[4, 32] for the boxes (broad highlights on flat faces);
+    the walls stay Lambertian.  These are the highlights whose bokeh the
+    composite treats apart."""
     sc = living_room_scene(seed, **kw)
     rng = np.random.default_rng(seed + 1000)
     spec = np.zeros((sc.n_tris, 2), F32)
@@ -295,9 +296,10 @@ def glossy_living_room_scene(seed: int = 0, **kw) -> Scene:
     counts = sc.meta["part_tris"]
     starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
     for kind, a, n in zip(["room"] + sc.meta["kinds"], starts, counts):
-        if kind == "sphere":
-            spec[a:a + n, 0] = rng.uniform(0.3, 1.0)
-            spec[a:a + n, 1] = rng.uniform(16.0, 256.0)
+        if kind == "room":
+            continue
+        spec[a:a + n, 0] = rng.uniform(0.3, 1.0)
+        spec[a:a + n, 1] = rng.uniform(16.0, 256.0) if kind == "sphere" else rng.uniform(4.0, 32.0)
     sc.spec = spec
     sc.meta = dict(sc.meta, name="glossy_living_room")
     return sc

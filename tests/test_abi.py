@@ -73,7 +73,10 @@ def test_null_arguments_rejected(hd):
     assert b"context" in L.hdof_last_error()
     assert L.hdof_postfilter(None, None, None, C.byref(cam), C.byref(lns), C.byref(pp), None, None) == INVALID
     assert L.hdof_composite(None, None, None, None, None, hd.RTBufs(), C.byref(cam), C.byref(lns), C.byref(cp),
-                            None, None) == INVALID
+                            None, None, None) == INVALID
+    assert L.hdof_postfilter_specular(None, None, None, None, None, C.byref(cam), C.byref(lns), C.byref(pp),
+                                      None, None, None) == INVALID
+    assert L.hdof_scene_set_specular(None, None, None) == INVALID
     assert L.hdof_history_reset(None) == INVALID
     h = C.c_void_p()
     assert L.hdof_build_bvh(None, None, None, 1, C.byref(h), None) == INVALID
