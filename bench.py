@@ -180,12 +180,49 @@ def main():
                         "backward": bench_backward(hdof, ctx, sc, cfg, keep, ms_per_step),
                         "focus_fit": bench_focus_fit(hdof, ctx, sc, cfg, ms_per_step),
                         "temporal": bench_temporal(hdof, ctx),
-                        "scaled_mask": bench_scaled_mask(hdof, ctx, sc, cfg, ms_per_step, rays)}
+                        "scaled_mask": bench_scaled_mask(hdof, ctx, sc, cfg, ms_per_step, rays),
+                        "specular": bench_specular(hdof, ctx, cfg)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, scene)
     print(json.dumps(res), flush=True)
     sc.close()
     ctx.close()
+
+
+def bench_specular(hdof, ctx, cfg, steps=50):
+    """The headline frame on the glossy living room (Blinn-Phong objects):
+    without the composite's specular bokeh rule, and with it (spec_y = 0.3:
+    the G-buffer keeps the specular luminance, the traced pixels gather it
+    with the post-filter's weights, the composite favours the post-process
+    colour by it)."""
+    import torch
+    import scenegen as sg
+    stream = torch.cuda.current_stream()
+    scene = sg.glossy_living_room_scene(0)
+    H, W = cfg.camera.height, cfg.camera.width
+    sc = hdof.hdof_build_bvh(ctx, torch.from_numpy(scene.verts).cuda(), torch.from_numpy(scene.albedo).cuda())
+    hdof.hdof_scene_set_specular(sc, torch.from_numpy(scene.spec).cuda())
+    cam, lens, light = hdof.camera_of(cfg.camera), hdof.lens_of(cfg.lens), hdof.light_of(cfg.light)
+    out = torch.empty(3, H, W, device="cuda")
+    res = {"workload": "1920x1080 glossy living room (every object Blinn-Phong), f/1.4, focus 2 m"}
+    for name, spec_y in (("without_rule", 0.0), ("with_rule", 0.3)):
+        params = hdof.frame_params_of(cfg)
+        params.comp.spec_y = spec_y
+
+        def step():
+            hdof.hdof_frame(ctx, sc, cam, None, lens, light, params, seed=cfg.seed, frame=0, view=0, out=out,
+                            stream=stream)
+        for _ in range(3):
+            step()
+        ms = _time_ms(step, steps, stream)
+        hdof.hdof_profile_begin(ctx)
+        for _ in range(steps):
+            step()
+        stage, _ = hdof.hdof_profile_end(ctx)
+        res[name] = {"frame_ms": round(ms, 4), "pp_prep_ms": round(stage["pp_prep"], 4),
+                     "pp_gather_ms": round(stage["pp_gather"], 4), "trace_ms": round(stage["trace"], 4)}
+    sc.close()
+    return res
 
 
 def bench_scaled_mask(hdof, ctx, sc, cfg, plain_ms, plain_rays, steps=50):

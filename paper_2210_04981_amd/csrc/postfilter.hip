@@ -393,55 +393,84 @@ __global__ __launch_bounds__(256) void k_pp_gather_any(const float4* __restrict_
 
 // The post-filtered specular luminance (the specular bokeh rule of the
 // composite): the post-filter's gather, radius, taps and weights, applied to
-// the G-buffer's specular luminance plane.  One 16x16 block per 16-pixel
-// tile, each wave an 8x8 quadrant (aligned with the ray mask's tiles); with
-// spp given only traced pixels gather (the rule reads no other), the rest
-// are 0.  Texels are fetched directly (a few traced pixels per frame).
-// Radius: t == 16, the block's dilated tile radius from tile_r; otherwise
-// the pixel's tile entry of the dilated radii.
+// the G-buffer's specular luminance plane.  With spp given only traced
+// pixels gather (the rule reads no other), the rest are 0.  Texels are
+// fetched directly: a frame traces a few percent of its pixels.  One 8x8
+// block (a ray-mask tile) per 256 threads, four lanes per pixel splitting
+// its taps (tap j on lane j mod 4, sums joined by lane exchanges), so the
+// few traced tiles get four times the memory parallelism of a lane per
+// pixel; a block without a traced pixel writes 0 and leaves.  Blocks run in
+// launch order, round-robin over the XCDs (the traced pixels cluster along
+// a few silhouettes, which XCD-contiguous ranges would give to one XCD).
+// Radius: tile 16, the dilated radius of the block's 16-pixel tile from
+// tile_r; otherwise the pixel's tile entry of the dilated radii.
 __global__ __launch_bounds__(256) void k_pp_spec(const float4* __restrict__ pack, const float* __restrict__ ys,
                                                  const uint8_t* __restrict__ spp, const float* __restrict__ tile_r,
-                                                 const float* __restrict__ rad, int t, int K, float r_cap,
+                                                 const float* __restrict__ rad, int tile, int K, float r_cap,
                                                  const float4* __restrict__ taps, int n_taps, int W, int H,
                                                  float inv_ramp, float* __restrict__ out) {
   __shared__ float wred[4];
-  const int BW = (W + 15) >> 4, BH = (H + 15) >> 4;
-  const int b = xcd_block(blockIdx.x, BW * BH), bx = b % BW, by = b / BW;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int x = bx * 16 + (w & 1) * 8 + (l & 7), y = by * 16 + (w >> 1) * 8 + (l >> 3);
-  float R;
-  if (t == 16) {
-    R = block_dilated_radius(tile_r, BW, BH, bx, by, K, r_cap, wred);
-  } else {
-    const int TW = (W + t - 1) / t;
-    R = (x < W && y < H) ? rad[(y / t) * TW + x / t] : 0.0f;
-  }
-  if (x >= W || y >= H) return;
-  const size_t p = (size_t)y * W + x;
-  if (spp && spp[p] == 0) {
-    out[p] = 0.0f;
+  const int BW = (W + 7) >> 3;
+  const int bx = blockIdx.x % BW, by = blockIdx.x / BW;
+  const int pi = threadIdx.x >> 2, sub = threadIdx.x & 3;
+  const int x = bx * 8 + (pi & 7), y = by * 8 + (pi >> 3);
+  const bool in = x < W && y < H;
+  const size_t p = in ? (size_t)y * W + x : 0;
+  const bool act = in && (!spp || spp[p] > 0);
+  if (!__syncthreads_or(act)) {
+    if (in && sub == 0) out[p] = 0.0f;
     return;
   }
-  const float4 cp4 = pack[p];
-  GatherAcc g;
-  g.init(make_float4(ys[p], 0.0f, 0.0f, cp4.w), R, n_taps, inv_ramp);
-  for (int j = 0; j < n_taps; ++j) {
-    const float4 u = taps[j];
-    const float ox = R * u.x, oy = R * u.y;
-    const float fx = floorf(ox), fy = floorf(oy);
-    const float ax = ox - fx, ay = oy - fy, bxw = 1.0f - ax, byw = 1.0f - ay;
-    const int xa = x + (int)fx, ya = y + (int)fy;
-    float4 v00, v10, v01, v11;
-    texels_clamped(pack, W, H, xa, ya, v00, v10, v01, v11);
-    const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
-    const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
-    v00.x = ys[(size_t)ya_ * W + xa_];
-    v10.x = ys[(size_t)ya_ * W + xb_];
-    v01.x = ys[(size_t)yb_ * W + xa_];
-    v11.x = ys[(size_t)yb_ * W + xb_];
-    g.tap(bxw * byw, ax * byw, bxw * ay, ax * ay, 0.5f - R * u.z, v00, v10, v01, v11);
+  float R;
+  if (tile == 16) {
+    R = block_dilated_radius(tile_r, (W + 15) >> 4, (H + 15) >> 4, bx >> 1, by >> 1, K, r_cap, wred);
+  } else {
+    const int TW = (W + tile - 1) / tile;
+    R = in ? rad[(y / tile) * TW + x / tile] : 0.0f;
   }
-  out[p] = g.ar / g.ws;
+  if (!act) {  // the pixel's four lanes leave together
+    if (in && sub == 0) out[p] = 0.0f;
+    return;
+  }
+  GatherAcc g;
+  g.init(make_float4(ys[p], 0.0f, 0.0f, pack[p].w), R, n_taps, inv_ramp);
+  if (sub != 0) g.ar = g.ws = 0.0f;  // the centre counts once
+  // this lane's taps sub, sub + 4, ... in groups of four: a group's loads
+  // are all issued before its sums (a tap past the end accepts nothing)
+  for (int j0 = sub; j0 < n_taps; j0 += 16) {
+    float4 v[4][4];
+    float wb[4][4], d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = min(j0 + 4 * q, n_taps - 1);
+      const float4 u = taps[j];
+      const float ox = R * u.x, oy = R * u.y;
+      const float fx = floorf(ox), fy = floorf(oy);
+      const float ax = ox - fx, ay = oy - fy, bxw = 1.0f - ax, byw = 1.0f - ay;
+      wb[q][0] = bxw * byw;
+      wb[q][1] = ax * byw;
+      wb[q][2] = bxw * ay;
+      wb[q][3] = ax * ay;
+      d[q] = j0 + 4 * q < n_taps ? 0.5f - R * u.z : -1e30f;
+      const int xa = x + (int)fx, ya = y + (int)fy;
+      const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
+      const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
+      const size_t i00 = (size_t)ya_ * W + xa_, i10 = (size_t)ya_ * W + xb_;
+      const size_t i01 = (size_t)yb_ * W + xa_, i11 = (size_t)yb_ * W + xb_;
+      v[q][0] = make_float4(ys[i00], 0.0f, 0.0f, pack[i00].w);
+      v[q][1] = make_float4(ys[i10], 0.0f, 0.0f, pack[i10].w);
+      v[q][2] = make_float4(ys[i01], 0.0f, 0.0f, pack[i01].w);
+      v[q][3] = make_float4(ys[i11], 0.0f, 0.0f, pack[i11].w);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g.tap(wb[q][0], wb[q][1], wb[q][2], wb[q][3], d[q], v[q][0], v[q][1], v[q][2], v[q][3]);
+  }
+  float ar = g.ar, ws = g.ws;
+  ar += __shfl_xor(ar, 1);
+  ws += __shfl_xor(ws, 1);
+  ar += __shfl_xor(ar, 2);
+  ws += __shfl_xor(ws, 2);
+  if (sub == 0) out[p] = ar / ws;
 }
 
 // pps (nullable): the post-filtered specular luminance; inv_sy = 1 / spec_y
@@ -921,7 +950,7 @@ hdof_status launch_pp_spec(hdof_ctx* ctx, const float* ys, const uint8_t* spp, c
     hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
     ctx->pp_taps_n = pp.n_taps;
   }
-  hipLaunchKernelGGL(k_pp_spec, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, (const float4*)ctx->pp_pack.p, ys,
+  hipLaunchKernelGGL(k_pp_spec, dim3(cdiv(W, 8) * cdiv(H, 8)), dim3(256), 0, st, (const float4*)ctx->pp_pack.p, ys,
                      spp, (const float*)ctx->pp_tile.p, (const float*)ctx->pp_rad.p, t, K, pp.r_cap,
                      (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, 1.0f / pp.bg_ramp_px, out);
   HDOF_HIP(hipGetLastError());

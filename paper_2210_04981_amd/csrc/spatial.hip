@@ -157,7 +157,10 @@ __global__ __launch_bounds__(256) void k_sp_gather(SpIn I, const float4* __restr
                                                    float* __restrict__ cf_out, int zero_untraced) {
   const int W = I.W, H = I.H;
   const size_t N = (size_t)W * H;
-  const int b = xcd_block(blockIdx.x, gridDim.x), BW = (W + 15) >> 4;
+  // blocks in launch order, round-robin over the XCDs: the traced pixels
+  // cluster along a few silhouettes, and XCD-contiguous ranges would give
+  // most of them to one XCD
+  const int b = blockIdx.x, BW = (W + 15) >> 4;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int x = (b % BW) * 16 + (w & 1) * 8 + (l & 7), y = (b / BW) * 16 + (w >> 1) * 8 + (l >> 3);
   if (x >= W || y >= H) return;
