@@ -58,7 +58,7 @@ def lib():
         L.or_philox4x64_10.argtypes = [P, P, P]
         L.or_coc.restype = f64
         L.or_coc.argtypes = [P, i32, i32, P, f64]
-        L.or_lens_ray.argtypes = [P, i32, i32, P, i32, i32, u64, u64, u64, u64, i32, P, P]
+        L.or_lens_ray.argtypes = [P, i32, i32, P, i32, i32, u64, u64, u64, u64, i32, P, P, P]
         L.or_cast_rays.argtypes = [P, i32, P, P, i32, P, P, P]
         L.or_gbuffer.argtypes = [P, P, i32, i32, P, P, P, i64, P, P, P, P, P, P, P]
         L.or_scene_set_spec.argtypes = [P, P]
@@ -177,13 +177,16 @@ def coc(camera, lens, z) -> float:
     return lib().or_coc(_p(cam), W, H, _p(_f64(lens.as_floats())), float(z))
 
 
-def lens_ray(camera, lens, x, y, j, seed=0, frame=0, view=0, pinhole=False):
+def lens_ray(camera, lens, x, y, j, seed=0, frame=0, view=0, pinhole=False, weight=False):
+    """Thin-lens ray (O, D) of sample j of pixel (x, y); with weight=True
+    also the sample's spherical-aberration weight."""
     cam, W, H = cam_args(camera)
     O = np.zeros(3)
     D = np.zeros(3)
+    w = np.zeros(1)
     lib().or_lens_ray(_p(cam), W, H, _p(_f64(lens.as_floats())), int(x), int(y), int(j),
-                      int(seed), int(frame), int(view), int(pinhole), _p(O), _p(D))
-    return O, D
+                      int(seed), int(frame), int(view), int(pinhole), _p(O), _p(D), _p(w))
+    return (O, D, float(w[0])) if weight else (O, D)
 
 
 # ----------------------------------------------------------------------------

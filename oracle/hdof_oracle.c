@@ -87,7 +87,11 @@ void or_set_threads(int n) {
 /* ------------------------------------------------------------------------- */
 /* Camera and thin lens                                                       */
 /* cam[13] = eye(3), right(3), up(3), fwd(3), tan_half_fov_x                  */
-/* lens[3] = focal length f, aperture diameter A, focus distance S1           */
+/* lens[6] = focal length f, aperture diameter A, focus distance S1, blades   */
+/* B (0: a disk, else a regular B-gon, B >= 3, of circumradius A/2),        */
+/* rotation theta of its first vertex (rad), spherical aberration s_a        */
+/* (relative weight 1 + s_a (2 rho^2 - 1) of a lens sample at normalised    */
+/* radius rho, clamped at 0).  The CoC stays the circumscribed circle's.    */
 /* ------------------------------------------------------------------------- */
 typedef struct {
   double e[3], r[3], u[3], w[3];
@@ -164,31 +168,66 @@ static void lens_uniforms(uint64_t pix, uint64_t j, uint64_t view, uint64_t seed
   *u1 = (double)(o[1] >> 40) * (1.0 / 16777216.0);
 }
 
-/* Thin-lens ray for sample j of pixel p: a uniform point on the lens disk of
- * radius A/2 (polar mapping sqrt(u0), 2 pi u1), aimed through the point where
- * the pixel's pinhole ray meets the focus plane.  Origin O = e + l,
- * direction D = S1 v - l (not normalised; D . w = S1, so axial depth = t S1). */
+/* Relative weight of a lens sample (or post-filter tap) at normalised     */
+/* radius rho under spherical aberration s_a (our reading of the paper's    */
+/* future work on the relative weight of samples): 1 + s_a (2 rho^2 - 1),  */
+/* clamped at 0; 1 for s_a = 0.                                             */
+static double sa_weight(double sa, double rho) { return maxd(0.0, 1.0 + sa * (2.0 * rho * rho - 1.0)); }
+
+/* The boundary radius of the regular B-gon of circumradius 1 whose first  */
+/* vertex is at angle theta, in direction phi.                              */
+static double poly_radius(int B, double theta, double phi) {
+  double sector = 2.0 * OR_PI / B;
+  double a = fmod(phi - theta, sector);
+  if (a < 0.0) a += sector;
+  return cos(OR_PI / B) / cos(a - OR_PI / B);
+}
+
+/* Thin-lens ray for sample j of pixel p: a uniform point on the aperture,
+ * aimed through the point where the pixel's pinhole ray meets the focus
+ * plane.  Disk (B = 0): radius A/2, polar mapping sqrt(u0), 2 pi u1.
+ * Regular B-gon of circumradius a = A/2 (our reading of the paper's future
+ * work on aperture silhouettes): the fan triangle k = floor(B u0) from the
+ * centre to vertices k, k + 1, and in it the point sqrt(f) ((1 - u1) V_k +
+ * u1 V_k+1), f = B u0 - k (uniform over the triangle, so over the polygon).
+ * Origin O = e + l, direction D = S1 v - l (not normalised; D . w = S1, so
+ * axial depth = t S1).  *w_out = the spherical-aberration weight of the
+ * sample (1 for s_a = 0). */
 static void lens_ray(const cam_t* k, const double* lens, int x, int y, uint64_t j,
                      uint64_t seed, uint64_t frame, uint64_t view, int pinhole,
-                     double* O, double* D) {
+                     double* O, double* D, double* w_out) {
   double v[3];
   pixel_dir(k, x, y, v);
-  double l[3] = {0, 0, 0};
+  double l[3] = {0, 0, 0}, rho_n = 0.0;
   if (!pinhole) {
-    double u0, u1;
+    double u0, u1, lx, ly;
     lens_uniforms((uint64_t)y * k->W + x, j, view, seed, frame, &u0, &u1);
-    double rho = 0.5 * lens[1] * sqrt(u0);
-    double th = 2.0 * OR_PI * u1;
-    double lx = rho * cos(th), ly = rho * sin(th);
+    double a = 0.5 * lens[1];
+    int B = (int)lens[3];
+    if (B >= 3) {
+      int kk = (int)floor(u0 * B);
+      if (kk > B - 1) kk = B - 1;
+      double f = u0 * B - kk, sq = sqrt(f);
+      double t0 = lens[4] + 2.0 * OR_PI * kk / B, t1 = lens[4] + 2.0 * OR_PI * (kk + 1) / B;
+      lx = a * sq * ((1.0 - u1) * cos(t0) + u1 * cos(t1));
+      ly = a * sq * ((1.0 - u1) * sin(t0) + u1 * sin(t1));
+    } else {
+      double rho = a * sqrt(u0);
+      double th = 2.0 * OR_PI * u1;
+      lx = rho * cos(th);
+      ly = rho * sin(th);
+    }
+    rho_n = a > 0.0 ? sqrt(lx * lx + ly * ly) / a : 0.0;
     for (int i = 0; i < 3; ++i) l[i] = lx * k->r[i] + ly * k->u[i];
   }
   for (int i = 0; i < 3; ++i) { O[i] = k->e[i] + l[i]; D[i] = lens[2] * v[i] - l[i]; }
+  if (w_out) *w_out = sa_weight(lens[5], rho_n);
 }
 
 void or_lens_ray(const double* cam, int W, int H, const double* lens, int x, int y, uint64_t j,
-                 uint64_t seed, uint64_t frame, uint64_t view, int pinhole, double* O, double* D) {
+                 uint64_t seed, uint64_t frame, uint64_t view, int pinhole, double* O, double* D, double* w) {
   cam_t k = mk_cam(cam, W, H);
-  lens_ray(&k, lens, x, y, j, seed, frame, view, pinhole, O, D);
+  lens_ray(&k, lens, x, y, j, seed, frame, view, pinhole, O, D, w);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -482,7 +521,7 @@ void or_gbuffer(const or_scene* s, const double* cam, int W, int H, const double
     int64_t p = pix ? pix[i] : i;
     int x = (int)(p % W), y = (int)(p / W);
     double O[3], D[3];
-    lens_ray(&k, lens, x, y, 0, 0, 0, 0, 1, O, D);
+    lens_ray(&k, lens, x, y, 0, 0, 0, 0, 1, O, D, NULL);
     ohit_t h = cast_ray(s, O, D, 0);
     double L[3] = {0, 0, 0}, nn[3] = {0, 0, 0}, al[3] = {0, 0, 0};
     double zz = OR_ZMAX, ys = 0.0;
@@ -654,6 +693,8 @@ int or_mask(int W, int H, const double* z, const double* nrm, const double* V,
 /*   "split ... based on its Z-distance from the separating focus plane").    */
 /*   C_tn = sum w L / sum w, C_tf = sum (1-w) L / sum (1-w) (0 if empty),      */
 /*   h = sum w / s (hit ratio), lum_m1 = mean Y, lum_m2 = mean Y^2.           */
+/*   Under spherical aberration every sum (and s) weights ray j by its lens  */
+/*   sample's aberration weight (1 when s_a = 0).                             */
 /* Per-ray outputs (nullable) go to ray_base[i] + j; ray_base = exclusive      */
 /* prefix sum of spp over the list.  px_amb = any ray of the pixel ambiguous. */
 /* far_pos (nullable, 4 planes of n): over the rays that hit, the far-weighted */
@@ -679,23 +720,26 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
     double Nw = 0.0, Fw = 0.0, sn[3] = {0, 0, 0}, sf[3] = {0, 0, 0}, sy = 0.0, sy2 = 0.0;
     double Pw = 0.0, sP[3] = {0, 0, 0}, scn = 0.0, scf = 0.0;
     int pa = 0;
+    double Sw = 0.0;  /* sum of the samples' aberration weights (ns for s_a = 0) */
     for (int j = 0; j < ns; ++j) {
-      double O[3], D[3];
-      lens_ray(&k, lens, x, y, (uint64_t)j, seed, frame, view, 0, O, D);
+      double O[3], D[3], om;
+      lens_ray(&k, lens, x, y, (uint64_t)j, seed, frame, view, 0, O, D, &om);
       ohit_t h = cast_ray(s, O, D, 0);
       double L[3] = {0, 0, 0}, zz = OR_ZMAX;
       if (h.id >= 0) { shade(s, light, h.id, O, D, h.t, L, NULL, NULL); zz = h.t * lens[2]; }
       double Y = luminance(L);
       double c = coc_px(&k, lens, zz);
       double w = clampd(0.5 - c / (2.0 * OR_SQRT2), 0.0, 1.0);
-      Nw += w; Fw += 1.0 - w;
-      scn += w * fabs(c); scf += (1.0 - w) * fabs(c);
-      for (int q = 0; q < 3; ++q) { sn[q] += w * L[q]; sf[q] += (1.0 - w) * L[q]; }
+      double wn = om * w, wf = om * (1.0 - w);
+      Sw += om;
+      Nw += wn; Fw += wf;
+      scn += wn * fabs(c); scf += wf * fabs(c);
+      for (int q = 0; q < 3; ++q) { sn[q] += wn * L[q]; sf[q] += wf * L[q]; }
       if (h.id >= 0) {
-        Pw += 1.0 - w;
-        for (int q = 0; q < 3; ++q) sP[q] += (1.0 - w) * (O[q] + h.t * D[q]);
+        Pw += wf;
+        for (int q = 0; q < 3; ++q) sP[q] += wf * (O[q] + h.t * D[q]);
       }
-      sy += Y; sy2 += Y * Y;
+      sy += om * Y; sy2 += om * Y * Y;
       pa |= h.amb;
       if (ray_base) {
         int64_t r = ray_base[i] + j;
@@ -711,9 +755,9 @@ void or_trace(const or_scene* s, const double* cam, int W, int H, const double* 
       c_near[(size_t)q * n + i] = Nw > 0.0 ? sn[q] / Nw : 0.0;
       c_far[(size_t)q * n + i] = Fw > 0.0 ? sf[q] / Fw : 0.0;
     }
-    hit[i] = ns > 0 ? Nw / ns : 0.0;
-    m1[i] = ns > 0 ? sy / ns : 0.0;
-    m2[i] = ns > 0 ? sy2 / ns : 0.0;
+    hit[i] = Sw > 0.0 ? Nw / Sw : 0.0;
+    m1[i] = Sw > 0.0 ? sy / Sw : 0.0;
+    m2[i] = Sw > 0.0 ? sy2 / Sw : 0.0;
     if (px_amb) px_amb[i] = pa;
     if (far_pos) {
       for (int q = 0; q < 3; ++q) far_pos[(size_t)q * n + i] = Pw > 0.0 ? sP[q] / Pw : 0.0;
@@ -1089,6 +1133,12 @@ void or_spatial(int W, int H, const int* spp, const double* cn, const double* cf
 /*  r_eff = r_q - t max(0, r_q - r_p), a = clamp(r_eff - d_k + 0.5, 0, 1),   */
 /*  w_k = a (R^2 / N) / max(r_q, 0.5)^2, centre w_0 = 1 / max(r_p, 0.5)^2.   */
 /*  C_pp = (w_0 C_p + sum w_k C_q) / (w_0 + sum w_k).                        */
+/*  Aperture B-gon (B >= 3): u_k is moved radially onto the polygon,        */
+/*  u_k' = u_k P(angle of u_k), P the polygon's boundary radius, so the tap */
+/*  keeps the gauge distance |u_k| of the polygonal CoC (d_k unchanged);   */
+/*  spherical aberration multiplies w_k by the weight of radius |u_k'|.     */
+/*  The sampling kernel so takes the aperture's silhouette and weighting    */
+/*  (our reading of the paper's future work).                               */
 /* pp[4] = n_taps, tile, r_cap, bg_ramp_px.  Out for listed pixels.           */
 /* ------------------------------------------------------------------------- */
 static void bilerp(const double* img, int W, int H, double fx, double fy, double* o, int nch, size_t plane) {
@@ -1145,6 +1195,7 @@ void or_postfilter(const double* cam, int W, int H, const double* lens, const do
   }
   or_pp_radius(W, H, img + 3 * N, r_cap, tile, R);
   double g = OR_PI * (3.0 - sqrt(5.0));
+  int B = (int)lens[3];
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < n; ++i) {
     int64_t p = pix ? pix[i] : i;
@@ -1156,7 +1207,11 @@ void or_postfilter(const double* cam, int W, int H, const double* lens, const do
     for (int c = 0; c < 3; ++c) acc[c] = w0 * img[(size_t)c * N + p];
     for (int kk = 1; kk <= NT; ++kk) {
       double rad = sqrt((kk - 0.5) / NT);
-      double ux = rad * cos(kk * g), uy = rad * sin(kk * g);
+      /* aperture B-gon: the tap moved radially onto the polygon (its gauge */
+      /* distance stays rad); aberration weight of its radius               */
+      double sc = B >= 3 ? poly_radius(B, lens[4], kk * g) : 1.0;
+      double ux = rad * sc * cos(kk * g), uy = rad * sc * sin(kk * g);
+      double om = sa_weight(lens[5], rad * sc);
       double qx = x + 0.5 + Rp * ux, qy = y + 0.5 + Rp * uy;
       double smp[4];
       bilerp(img, W, H, qx, qy, smp, 4, N);
@@ -1165,7 +1220,7 @@ void or_postfilter(const double* cam, int W, int H, const double* lens, const do
       double t = clampd((cq - cp) / ramp, 0.0, 1.0);
       double reff = rq - t * maxd(0.0, rq - rp);
       double a = clampd(reff - dk + 0.5, 0.0, 1.0);
-      double w = a * (Rp * Rp / NT) / (maxd(rq, 0.5) * maxd(rq, 0.5));
+      double w = om * a * (Rp * Rp / NT) / (maxd(rq, 0.5) * maxd(rq, 0.5));
       for (int c = 0; c < 3; ++c) acc[c] += w * smp[c];
       wsum += w;
     }

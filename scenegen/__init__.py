@@ -40,13 +40,21 @@ class Camera:
 
 @dataclass
 class Lens:
-    """Thin lens: focal length f (m), aperture diameter A = f/N (m), focus distance S1 (m)."""
+    """Thin lens: focal length f (m), aperture diameter A = f/N (m), focus
+    distance S1 (m); aperture shape: blades = 0 (a disk) or a regular
+    polygon of that many blades (>= 3) inscribed in the disk, rotated by
+    `rotation` (rad); spherical aberration `sa` (relative sample weight
+    1 + sa (2 rho^2 - 1) at normalised radius rho, clamped at 0)."""
     focal_length: float
     aperture: float
     focus_distance: float
+    blades: int = 0
+    rotation: float = 0.0
+    sa: float = 0.0
 
     def as_floats(self) -> np.ndarray:
-        return np.array([self.focal_length, self.aperture, self.focus_distance], F32)
+        return np.array([self.focal_length, self.aperture, self.focus_distance, self.blades, self.rotation,
+                         self.sa], F32)
 
 
 @dataclass
