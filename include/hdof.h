@@ -76,6 +76,14 @@ typedef struct {
  * negative = near field (in front of the focus plane), positive = far. */
 typedef struct {
   float focal_length, aperture, focus_distance;
+  /* aperture silhouette and spherical aberration (paper, Discussion: bokeh
+   * shapes other than the disk, relative weights of the samples): blades 0
+   * = the disk, 3..16 = the regular polygon inscribed in the aperture
+   * circle with its first vertex at `rotation` (rad); sa in [-4, 4]: a lens
+   * sample (or post-filter tap) at normalised radius rho weighs
+   * max(0, 1 + sa (2 rho^2 - 1)).  0, 0, 0 = the thin lens of the paper. */
+  int32_t blades;
+  float rotation, sa;
 } hdof_lens;
 
 /* One point light (position, rgb intensity) and an rgb ambient term for the

@@ -72,6 +72,10 @@ static hdof_status check_lens(const hdof_lens* l) {
   REQUIRE(isfinite(l->aperture) && l->aperture >= 0.0f, "aperture must be >= 0");
   REQUIRE(isfinite(l->focus_distance) && l->focus_distance > l->focal_length,
           "focus_distance (S1) must exceed the focal length");
+  REQUIRE(l->blades == 0 || (l->blades >= 3 && l->blades <= HDOF_MAX_BLADES), "blades must be 0 or in [3, %d]",
+          HDOF_MAX_BLADES);
+  REQUIRE(isfinite(l->rotation) && fabsf(l->rotation) <= 1e3f, "rotation must be finite");
+  REQUIRE(isfinite(l->sa) && l->sa >= -4.0f && l->sa <= 4.0f, "sa must be in [-4, 4]");
   return HDOF_OK;
 }
 
@@ -858,6 +862,8 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
   for (int v = 0; v < n_views; ++v) {
     TRY(check_camera(&views[v].cam, "view"));
     TRY(check_lens(&views[v].lens));
+    if (views[v].lens.blades != 0 || views[v].lens.sa != 0.0f)
+      return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the batched form takes the disk aperture only (view %d)", v);
     REQUIRE(views[v].d_out, "view %d has no output", v);
     CamK k = make_camk(&views[v].cam);
     L.hv[v] = BatchView{k, make_lensk(&views[v].lens, k), views[v].seed, views[v].frame, views[v].view, (int)L.npx};
@@ -1085,6 +1091,8 @@ extern "C" hdof_status hdof_postfilter_composite_backward(
   TRY(check_comp(comp));
   if (comp->spec_y > 0.0f)
     return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the adjoint does not differentiate the specular bokeh rule");
+  if (lens->blades != 0 || lens->sa != 0.0f)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the adjoint takes the disk aperture only");
   CamK k = make_camk(cam);
   return launch_ppc_backward(ctx, d_color, d_depth, d_spp, rt, k, make_lensk(lens, k), *pp, *comp, d_grad_out,
                              d_grad_color, d_grad_lens, (hipStream_t)stream);

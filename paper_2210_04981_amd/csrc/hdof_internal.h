@@ -73,6 +73,8 @@ struct hdof_ctx {
   // post-filter scratch
   Buf pp_pack, pp_tile, pp_rad, pp_taps;
   int pp_taps_n = 0;  // tap count the table currently holds
+  int pp_taps_blades = 0;
+  float pp_taps_rot = 0.0f, pp_taps_sa = 0.0f;  // and the aperture it was built for
   // adjoint scratch: CoC per unit aperture, tile / radius arg pixels, block partials
   Buf ppb_args, ppb_partial;
   // variance history (previous frame) and its reprojection into this frame
@@ -181,9 +183,15 @@ __device__ inline V3 pixel_dir(const CamK& k, int x, int y) {
             fmaf(sy, k.u.z, fmaf(sx, k.r.z, k.w.z))};
 }
 
-// signed CoC diameter in pixels: A (1/S1 - 1/z) s_px
+#define HDOF_MAX_BLADES 16
+
+// signed CoC diameter in pixels: A (1/S1 - 1/z) s_px; the aperture's
+// silhouette (blades 0: disk, else a regular polygon whose first vertex is
+// at rot_ht half turns) and spherical aberration sa
 struct LensK {
   float f, A, S1, invS1, coc_scale;  // coc_scale = A * s_px
+  int blades;
+  float rot_ht, sa;
 };
 inline LensK make_lensk(const hdof_lens* l, const CamK& k) {
   LensK q;
@@ -192,6 +200,9 @@ inline LensK make_lensk(const hdof_lens* l, const CamK& k) {
   q.S1 = l->focus_distance;
   q.invS1 = 1.0f / l->focus_distance;
   q.coc_scale = l->aperture * k.spx;
+  q.blades = l->blades;
+  q.rot_ht = (float)((double)l->rotation / 3.14159265358979323846);
+  q.sa = l->sa;
   return q;
 }
 __device__ inline float coc_px(const LensK& l, float z) { return l.coc_scale * (l.invS1 - 1.0f / z); }
@@ -232,18 +243,43 @@ __device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint
   o1 = c1;
 }
 
-// thin-lens ray for sample j of pixel (x, y); pinhole when A == 0
+// thin-lens ray for sample j of pixel (x, y); pinhole when A == 0.  Disk:
+// radius A/2, polar sqrt(u0), 2 pi u1.  Regular B-gon inscribed in it: the
+// fan triangle k = floor(B u0) (integer arithmetic on u0's 24 bits, so the
+// choice is exact) and in it sqrt(f) (V_k + u1 (V_k+1 - V_k)), f = B u0 - k.
+// w (nullable): the sample's spherical-aberration weight
+// max(0, 1 + sa (2 rho^2 - 1)), rho = |lens point| / (A/2).
 __device__ inline void lens_ray(const CamK& k, const LensK& l, int x, int y, uint32_t j, uint32_t view,
-                                uint32_t seed, uint32_t frame, V3& O, V3& D) {
+                                uint32_t seed, uint32_t frame, V3& O, V3& D, float* w = nullptr) {
   V3 v = pixel_dir(k, x, y);
   uint64_t w0, w1;
   philox4x64_10((uint64_t)y * (uint64_t)k.W + (uint64_t)x, j, view, 0, seed, frame, w0, w1);
-  float u0 = (float)(uint32_t)(w0 >> 40) * (1.0f / 16777216.0f);
+  const uint32_t m0 = (uint32_t)(w0 >> 40);
   float u1 = (float)(uint32_t)(w1 >> 40) * (1.0f / 16777216.0f);
-  float rho = 0.5f * l.A * sqrtf(u0);
-  float s, c;
-  sincospif(2.0f * u1, &s, &c);
-  float lx = rho * c, ly = rho * s;
+  float lx, ly;
+  const float a = 0.5f * l.A;
+  if (l.blades >= 3) {
+    const uint32_t mb = m0 * (uint32_t)l.blades;
+    const int kk = (int)(mb >> 24);
+    const float sq = a * sqrtf((float)(mb & 0xFFFFFFu) * (1.0f / 16777216.0f));
+    const float step = 2.0f / (float)l.blades;
+    float s0, c0, s1, c1;
+    sincospif(fmaf((float)kk, step, l.rot_ht), &s0, &c0);
+    sincospif(fmaf((float)(kk + 1), step, l.rot_ht), &s1, &c1);
+    lx = sq * fmaf(u1, c1 - c0, c0);
+    ly = sq * fmaf(u1, s1 - s0, s0);
+  } else {
+    float u0 = (float)m0 * (1.0f / 16777216.0f);
+    float rho = a * sqrtf(u0);
+    float s, c;
+    sincospif(2.0f * u1, &s, &c);
+    lx = rho * c;
+    ly = rho * s;
+  }
+  if (w) {
+    const float r2 = a > 0.0f ? fmaf(lx, lx, ly * ly) / (a * a) : 0.0f;
+    *w = fmaxf(0.0f, fmaf(l.sa, fmaf(2.0f, r2, -1.0f), 1.0f));
+  }
   V3 lv = V3{fmaf(ly, k.u.x, lx * k.r.x), fmaf(ly, k.u.y, lx * k.r.y), fmaf(ly, k.u.z, lx * k.r.z)};
   O = k.e + lv;
   D = V3{fmaf(l.S1, v.x, -lv.x), fmaf(l.S1, v.y, -lv.y), fmaf(l.S1, v.z, -lv.z)};

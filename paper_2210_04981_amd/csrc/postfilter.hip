@@ -44,13 +44,41 @@ __global__ __launch_bounds__(256) void k_pp_pack(const float* __restrict__ color
 }
 
 // golden-angle taps u_k = sqrt((k - 0.5)/n) (cos k g, sin k g), g = pi (3 - sqrt 5),
-// evaluated in double and stored as (ux, uy, |u|, 0)
-__global__ void k_pp_taps(int n, float4* __restrict__ taps) {
+// evaluated in double and stored as (ux, uy, |u|, omega).  A polygonal
+// aperture (blades >= 3, first vertex at rot radians) moves each tap
+// radially onto the polygon, u' = u P(angle), P its boundary radius at
+// circumradius 1, keeping |u| (the tap's gauge distance in the polygonal
+// CoC); omega = max(0, 1 + sa (2 |u'|^2 - 1)) is the tap's aberration weight.
+__global__ void k_pp_taps(int n, int blades, double rot, float sa, float4* __restrict__ taps) {
   int k = threadIdx.x + 1;
   if (k > n) return;
-  const double g = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+  const double pi = 3.14159265358979323846;
+  const double g = pi * (3.0 - sqrt(5.0));
   double rr = sqrt((k - 0.5) / n);
-  taps[k - 1] = make_float4((float)(rr * cos(k * g)), (float)(rr * sin(k * g)), (float)rr, 0.0f);
+  double sc = 1.0;
+  if (blades >= 3) {
+    const double sector = 2.0 * pi / blades;
+    double a = fmod(k * g - rot, sector);
+    if (a < 0.0) a += sector;
+    sc = cos(pi / blades) / cos(a - pi / blades);
+  }
+  const double r2 = rr * sc;
+  const double om = fmax(0.0, 1.0 + (double)sa * (2.0 * r2 * r2 - 1.0));
+  taps[k - 1] = make_float4((float)(r2 * cos(k * g)), (float)(r2 * sin(k * g)), (float)rr, (float)om);
+}
+
+// (re)build the context's tap table when the tap count or the aperture changed
+void pp_taps_ensure(hdof_ctx* ctx, int n, const LensK& l, hipStream_t st) {
+  const int blades = l.blades >= 3 ? l.blades : 0;
+  if (ctx->pp_taps_n == n && ctx->pp_taps_blades == blades && ctx->pp_taps_rot == l.rot_ht &&
+      ctx->pp_taps_sa == l.sa)
+    return;
+  hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, n, blades, (double)l.rot_ht * 3.14159265358979323846,
+                     l.sa, (float4*)ctx->pp_taps.p);
+  ctx->pp_taps_n = n;
+  ctx->pp_taps_blades = blades;
+  ctx->pp_taps_rot = l.rot_ht;
+  ctx->pp_taps_sa = l.sa;
 }
 
 __global__ void k_pp_dilate(const float* __restrict__ tile_r, int TW, int TH, int K, float r_cap,
@@ -94,8 +122,9 @@ struct GatherAcc {
   }
   // one tap: bilinear (rgb, c) from the four texels with weights
   // (w00, w10, w01, w11), d = 0.5 - R |u|
+  // om: the tap's aberration weight (1: the disk's uniform weights)
   __device__ __forceinline__ void tap(float w00, float w10, float w01, float w11, float d, const float4& v00,
-                                      const float4& v10, const float4& v01, const float4& v11) {
+                                      const float4& v10, const float4& v01, const float4& v11, float om = 1.0f) {
     const float sr = fmaf(w11, v11.x, fmaf(w01, v01.x, fmaf(w10, v10.x, w00 * v00.x)));
     const float sg = fmaf(w11, v11.y, fmaf(w01, v01.y, fmaf(w10, v10.y, w00 * v00.y)));
     const float sb = fmaf(w11, v11.z, fmaf(w01, v01.z, fmaf(w10, v10.z, w00 * v00.z)));
@@ -103,7 +132,7 @@ struct GatherAcc {
     const float aq = fabsf(cq);
     const float tk = clamp01(fmaf(cq, inv_ramp, ncpr));
     const float reff2 = fmaf(-tk, fmaxf(0.0f, aq - ap), aq);
-    const float a = clamp01(fmaf(reff2, 0.5f, d));
+    const float a = clamp01(fmaf(reff2, 0.5f, d)) * om;
     const float wt = a * __builtin_amdgcn_rcpf(fmaxf(cq * cq, 1.0f));
     ar = fmaf(wt, sr, ar);
     ag = fmaf(wt, sg, ag);
@@ -216,7 +245,7 @@ __device__ __forceinline__ void stage_store(float4* __restrict__ dst, TapRec* __
 // The tap loop of one block.  Groups are always full: a wave whose tap of
 // the group lies past n_taps stages tap n_taps - 1 again, and that slot's
 // distance term is -1e30 so its coverage, and with it its weight, is 0.
-template <bool INTERIOR>
+template <bool INTERIOR, bool SA>
 __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], TapRec (*rec)[PPG_G],
                                             const float4* __restrict__ pack, const float4* __restrict__ taps,
                                             int n_taps, float R, int x0, int y0, int W, int H, int wave, int lane,
@@ -249,9 +278,10 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
       for (int jj = 0; jj < PPG_G; ++jj) {
         const int j = gi * PPG_G + jj;
         const float d = j < n_taps ? 0.5f - R * uz[4 * j] : -1e30f;
+        const float om = SA ? uz[4 * min(j, n_taps - 1) + 1] : 1.0f;
         const float4* a = src + jj * PPG_TAPSZ;
         const TapRec t = rec[b][jj];
-        g.tap(t.w00, t.w10, t.w01, t.w11, d, a[0], a[1], a[PPG_STRIDE], a[PPG_STRIDE + 1]);
+        g.tap(t.w00, t.w10, t.w01, t.w11, d, a[0], a[1], a[PPG_STRIDE], a[PPG_STRIDE + 1], om);
       }
     }
     if (more) stage_store(stg[b ^ 1] + wave * PPG_TAPSZ, &rec[b ^ 1][wave], st, sl, lane);
@@ -322,8 +352,9 @@ __device__ __forceinline__ float block_dilated_radius(const float* __restrict__ 
 }
 
 // 16-pixel tiles.  The block first reduces its tile's dilated radius from
-// the per-tile maxima; FUSE applies the composite to the result.
-template <bool FUSE>
+// the per-tile maxima; FUSE applies the composite to the result; SA weights
+// the taps by the lens's spherical aberration (the table's fourth entry).
+template <bool FUSE, bool SA>
 __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ tile_r,
                                                      int K, float r_cap, const float4* __restrict__ taps, int n_taps,
                                                      int W, int H, float inv_ramp, float* __restrict__ out, FuseK fz) {
@@ -354,9 +385,9 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   g.init(cp4, R, n_taps, inv_ramp);
   const int lofs = ly * PPG_STRIDE + lx;
   if (interior)
-    gather_taps<true>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
+    gather_taps<true, SA>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
   else
-    gather_taps<false>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
+    gather_taps<false, SA>(stg, rec, pack, taps, n_taps, R, x0, y0, W, H, wave, lane, lofs, inside, g);
   if (inside) {
     const float iw = 1.0f / g.ws;
     pp_emit<FUSE>(out, fz, N, p, cp4, g.ar * iw, g.ag * iw, g.ab * iw);
@@ -385,7 +416,7 @@ __global__ __launch_bounds__(256) void k_pp_gather_any(const float4* __restrict_
       const float ax = ox - fx, ay = oy - fy, bx = 1.0f - ax, by = 1.0f - ay;
       float4 v00, v10, v01, v11;
       texels_clamped(pack, W, H, x + (int)fx, y + (int)fy, v00, v10, v01, v11);
-      g.tap(bx * by, ax * by, bx * ay, ax * ay, 0.5f - R * u.z, v00, v10, v01, v11);
+      g.tap(bx * by, ax * by, bx * ay, ax * ay, 0.5f - R * u.z, v00, v10, v01, v11, u.w);
     }
   }
   g.store(out, N, p);
@@ -439,11 +470,12 @@ __global__ __launch_bounds__(256) void k_pp_spec(const float4* __restrict__ pack
   // are all issued before its sums (a tap past the end accepts nothing)
   for (int j0 = sub; j0 < n_taps; j0 += 16) {
     float4 v[4][4];
-    float wb[4][4], d[4];
+    float wb[4][4], d[4], om[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = min(j0 + 4 * q, n_taps - 1);
       const float4 u = taps[j];
+      om[q] = u.w;
       const float ox = R * u.x, oy = R * u.y;
       const float fx = floorf(ox), fy = floorf(oy);
       const float ax = ox - fx, ay = oy - fy, bxw = 1.0f - ax, byw = 1.0f - ay;
@@ -463,7 +495,8 @@ __global__ __launch_bounds__(256) void k_pp_spec(const float4* __restrict__ pack
       v[q][3] = make_float4(ys[i11], 0.0f, 0.0f, pack[i11].w);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) g.tap(wb[q][0], wb[q][1], wb[q][2], wb[q][3], d[q], v[q][0], v[q][1], v[q][2], v[q][3]);
+    for (int q = 0; q < 4; ++q)
+      g.tap(wb[q][0], wb[q][1], wb[q][2], wb[q][3], d[q], v[q][0], v[q][1], v[q][2], v[q][3], om[q]);
   }
   float ar = g.ar, ws = g.ws;
   ar += __shfl_xor(ar, 1);
@@ -886,10 +919,7 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
   if ((s = hdof_ensure(ctx->pp_tile, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_rad, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
-  if (ctx->pp_taps_n != pp.n_taps) {  // the table depends on the tap count only
-    hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
-    ctx->pp_taps_n = pp.n_taps;
-  }
+  pp_taps_ensure(ctx, pp.n_taps, l, st);
   if (!packed)
     hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
                        (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
@@ -898,16 +928,19 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
                        TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
   hdof_prof_mark(ctx, 8, st);
   if (t == 16) {
+    const bool sa = l.sa != 0.0f;
     FuseK fz{};
     if (fuse) {
       fz = FuseK{fuse->spp, fuse->rt.c_near, fuse->rt.c_far, fuse->rt.hit_ratio, 1.0f / fuse->cp.h_t,
                  fuse->cp.rt_override, fuse->out, fuse->pps,
                  fuse->pps && fuse->cp.spec_y > 0.0f ? 1.0f / fuse->cp.spec_y : 0.0f};
-      hipLaunchKernelGGL(k_pp_gather16<true>, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+      auto kern = sa ? k_pp_gather16<true, true> : k_pp_gather16<true, false>;
+      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                          (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     } else {
-      hipLaunchKernelGGL(k_pp_gather16<false>, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+      auto kern = sa ? k_pp_gather16<false, true> : k_pp_gather16<false, false>;
+      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                          (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     }
@@ -939,17 +972,13 @@ hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp,
 
 hdof_status launch_pp_spec(hdof_ctx* ctx, const float* ys, const uint8_t* spp, const CamK& k, const LensK& l,
                            const hdof_pp_params& pp, float* out, hipStream_t st) {
-  (void)l;
   const int W = k.W, H = k.H, t = pp.tile;
   const int K = (int)ceil((double)pp.r_cap / t);
   if (!ctx->pp_pack.p || !ctx->pp_tile.p || (t != 16 && !ctx->pp_rad.p))
     return hdof_set_error(HDOF_ERR_INVALID_ARG, "specular post-filter before the frame's post-filter preparation");
   hdof_status s;
   if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
-  if (ctx->pp_taps_n != pp.n_taps) {
-    hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
-    ctx->pp_taps_n = pp.n_taps;
-  }
+  pp_taps_ensure(ctx, pp.n_taps, l, st);
   hipLaunchKernelGGL(k_pp_spec, dim3(cdiv(W, 8) * cdiv(H, 8)), dim3(256), 0, st, (const float4*)ctx->pp_pack.p, ys,
                      spp, (const float*)ctx->pp_tile.p, (const float*)ctx->pp_rad.p, t, K, pp.r_cap,
                      (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, 1.0f / pp.bg_ramp_px, out);
@@ -974,10 +1003,7 @@ hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* 
   if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->ppb_args, sizeof(int) * 2 * (size_t)TW * TH)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->ppb_partial, sizeof(float2) * (size_t)nblk)) != HDOF_OK) return s;
-  if (ctx->pp_taps_n != pp.n_taps) {
-    hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, (float4*)ctx->pp_taps.p);
-    ctx->pp_taps_n = pp.n_taps;
-  }
+  pp_taps_ensure(ctx, pp.n_taps, l, st);
   int* tile_arg = (int*)ctx->ppb_args.p;
   int* rad_arg = tile_arg + (size_t)TW * TH;
   hipLaunchKernelGGL(k_ppb_pack, dim3(nblk), dim3(256), 0, st, color, depth, k, l, t, (float4*)ctx->pp_pack.p,

@@ -579,23 +579,29 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   float Pw = 0.f, spx_ = 0.f, spy_ = 0.f, spz_ = 0.f, scn = 0.f, scf = 0.f;
   long o = (long)offsets[p] + (ebase ? *ebase : 0);
   if (o < 0 || o + s > (long)cap) s = 0;  // inconsistent offsets: nothing was traced here
+  // spherical aberration: every ray weighs its lens sample's weight (the
+  // sample regenerated from its counters); 1 for sa = 0
+  const bool weighted = l.sa != 0.0f;
+  float Sw = 0.f;
   if (s > 0) {
     for (int j = 0; j < s; ++j) {
       long e = o + j;
       float R = ray_col[e], G = ray_col[cap + e], B = ray_col[2 * cap + e];
       const float zj = ray_z[e];
       float c = coc_px(l, zj);
-      float w = clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
-      float wf = 1.0f - w;
+      float om = 1.0f;
+      V3 O, D;
+      if (FARPOS || weighted) lens_ray(k, l, p % k.W, p / k.W, (uint32_t)j, view, seed, frame, O, D, &om);
+      float w = om * clamp01(fmaf(-c, 0.35355339059327376f, 0.5f));
+      float wf = om - w;
       if (FARPOS && zj < HDOF_ZMAX) {
-        V3 O, D;
-        lens_ray(k, l, p % k.W, p / k.W, (uint32_t)j, view, seed, frame, O, D);
         const float t = zj * l.invS1;
         Pw += wf;
         spx_ = fmaf(wf, fmaf(t, D.x, O.x), spx_);
         spy_ = fmaf(wf, fmaf(t, D.y, O.y), spy_);
         spz_ = fmaf(wf, fmaf(t, D.z, O.z), spz_);
       }
+      Sw += om;
       Nw += w;
       Fw += wf;
       scn = fmaf(w, fabsf(c), scn);
@@ -607,12 +613,12 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
       sfg = fmaf(wf, G, sfg);
       sfb = fmaf(wf, B, sfb);
       float Y = fmaf(0.2126f, R, fmaf(0.7152f, G, 0.0722f * B));
-      sy += Y;
-      sy2 = fmaf(Y, Y, sy2);
+      sy = fmaf(om, Y, sy);
+      sy2 = fmaf(om * Y, Y, sy2);
     }
   }
   const float in_ = Nw > 0.f ? 1.0f / Nw : 0.f, if_ = Fw > 0.f ? 1.0f / Fw : 0.f;
-  const float is = s > 0 ? 1.0f / (float)s : 0.f;
+  const float is = Sw > 0.f ? 1.0f / Sw : 0.f;
   cn[p] = snr * in_;
   cn[N + p] = sng * in_;
   cn[2 * (size_t)N + p] = snb * in_;

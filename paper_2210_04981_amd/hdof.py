@@ -36,7 +36,8 @@ class Camera(C.Structure):
 
 
 class Lens(C.Structure):
-    _fields_ = [("focal_length", C.c_float), ("aperture", C.c_float), ("focus_distance", C.c_float)]
+    _fields_ = [("focal_length", C.c_float), ("aperture", C.c_float), ("focus_distance", C.c_float),
+                ("blades", C.c_int32), ("rotation", C.c_float), ("sa", C.c_float)]
 
 
 class Light(C.Structure):
@@ -201,8 +202,8 @@ def camera(eye, right, up, fwd, tan_half_fov_x, width, height) -> Camera:
     return Camera(F3(*eye), F3(*right), F3(*up), F3(*fwd), float(tan_half_fov_x), int(width), int(height))
 
 
-def lens(focal_length, aperture, focus_distance) -> Lens:
-    return Lens(float(focal_length), float(aperture), float(focus_distance))
+def lens(focal_length, aperture, focus_distance, blades=0, rotation=0.0, sa=0.0) -> Lens:
+    return Lens(float(focal_length), float(aperture), float(focus_distance), int(blades), float(rotation), float(sa))
 
 
 def light(pos, intensity, ambient) -> Light:
@@ -568,7 +569,8 @@ def camera_of(c) -> Camera:
 
 
 def lens_of(l) -> Lens:
-    return lens(l.focal_length, l.aperture, l.focus_distance)
+    return lens(l.focal_length, l.aperture, l.focus_distance, getattr(l, "blades", 0), getattr(l, "rotation", 0.0),
+                getattr(l, "sa", 0.0))
 
 
 def light_of(l) -> Light:
