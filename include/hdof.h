@@ -465,11 +465,22 @@ void hdof_batch_destroy(hdof_batch* batch);
 /* Launch shape of the persistent thin-lens trace (performance only: results
  * do not depend on it).  blocks_per_cu in [1, 32]; refill in [1, 64]: idle
  * lanes of a wave that trigger a refill from the queue (64 = batches of 64
- * rays); segments in [1, 8]: queue segments, one per XCD group.  Defaults
- * {10, 64, 8}: ten two-wave blocks per CU is the trace kernel's register-
+ * rays); segments in [1, 8]: queue segments, one per XCD group; wave 0 or 1:
+ * 1 walks the 64 rays of a batch of consecutive queue entries as one wave
+ * (one node sequence, the union of their paths; refill is then unused), 0
+ * traverses each lane's ray on its own and refills idle lanes; overlap 0
+ * or 1: 1 runs hdof_frame's post-filter gather on a second stream of the
+ * context beside the mask, trace and reconstruction (it needs only the
+ * G-buffer) and applies the composite once both are done, the results
+ * being the same as with 0; overlap_ray_quantum >= 1: while overlapped, the
+ * trace keeps one block per CU for every overlap_ray_quantum rays of the
+ * frame (at least one, at most blocks_per_cu; the count is read on the
+ * device, the other blocks return at once), so a light trace leaves CUs to
+ * the gather and a heavy one keeps them.  Defaults {10, 64, 8, 0, 1,
+ * 150000}: ten two-wave blocks per CU is the trace kernel's register-
  * limited residency (5 waves per SIMD), so every block starts at once. */
 typedef struct {
-  int32_t blocks_per_cu, refill, segments;
+  int32_t blocks_per_cu, refill, segments, wave, overlap, overlap_ray_quantum;
 } hdof_tuning;
 hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* tuning);
 hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
@@ -505,7 +516,11 @@ hdof_status hdof_postfilter_composite_backward(hdof_ctx* ctx, const float* d_col
  * reduction, variance update, temporal and spatial reconstruction (0 when
  * both are disabled),
  * post-filter preparation (pack, tile radius, taps), post-filter gather,
- * composite. */
+ * composite.  With the overlapped frame (tuning overlap = 1) the
+ * gather is timed on its own stream from its start to its end, while the
+ * preparation stage runs from the end of the reconstruction to the start
+ * of the composite (the specular gather, then the wait for the post-filter
+ * gather), so the stages then add up to more than the frame. */
 #define HDOF_PROFILE_STAGES 10
 
 /* Start recording stage events in every following hdof_frame call (events

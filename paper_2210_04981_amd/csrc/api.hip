@@ -191,8 +191,15 @@ extern "C" hdof_status hdof_create(int device, hdof_ctx** out) {
   }
   e = hipMemset(c->d_counters, 0, 6 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->d_flags, 0, sizeof(int));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
+    if (c->ev_join) hipEventDestroy(c->ev_join);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->side) hipStreamDestroy(c->side);
+    hipFree(c->d_counters);
     hipFree(c->d_flags);
     delete c;
     return hdof_set_error(HDOF_ERR_HIP, "init: %s", hipGetErrorString(e));
@@ -223,6 +230,9 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
   buf_free(ctx->b_totals);
   if (ctx->b_views_host) hipHostFree(ctx->b_views_host);
   if (ctx->b_views_done) hipEventDestroy(ctx->b_views_done);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->side) hipStreamDestroy(ctx->side);
   if (ctx->d_flags) hipFree(ctx->d_flags);
   if (ctx->d_counters) hipFree(ctx->d_counters);
   delete ctx;
@@ -634,7 +644,10 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   // tile radii, the gather applies the composite (the filtered colour is
   // stored only when the caller keeps it)
   const bool fused = params->pp.tile == 16;
-  if (fused) {
+  // overlapped frame: the gather on the context's second stream beside the
+  // mask, trace and reconstruction, the composite after both
+  const bool ovl = ctx->tune.overlap != 0;
+  if (fused && !ovl) {
     pp = u.pp;
   } else {
     TRY(pick_buf(u.pp, ctx->f_pp, 12 * N, &pp));
@@ -683,11 +696,32 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
       TRY(hdof_ensure(ctx->rec_valid[i], N));
     }
   }
+  TRY(hdof_ensure(ctx->work_counter, sizeof(int) * 8 * HDOF_SEG_STRIDE));
+  // the tap table is written on the frame's stream before the fork, so the
+  // gathers of both streams read it complete
+  if (ovl) TRY(postfilter_reserve(ctx, k, l, params->pp, st));
   ctx->prof_in_frame = true;
   hdof_prof_mark(ctx, 0, st);
-  TRY(hdof_ensure(ctx->work_counter, sizeof(int) * 8 * HDOF_SEG_STRIDE));
   hdof_status s = launch_gbuffer(ctx, scene, k, l, li, gb, st, pack, tile_r);
   hdof_prof_mark(ctx, 1, st);
+  bool forked = false;
+  if (s == HDOF_OK && ovl) {
+    hipError_t e = hipEventRecord(ctx->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+    if (e != hipSuccess) {
+      s = hdof_set_error(HDOF_ERR_HIP, "overlapped frame fork: %s", hipGetErrorString(e));
+    } else {
+      forked = true;
+      // mark 8 on the side stream (inside), then the gather's end
+      s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, ctx->side, fused);
+      hdof_prof_mark(ctx, HDOF_PROF_GATHER_END, ctx->side);
+      e = hipEventRecord(ctx->ev_join, ctx->side);
+      if (e != hipSuccess) {
+        forked = false;
+        if (s == HDOF_OK) s = hdof_set_error(HDOF_ERR_HIP, "overlapped frame join: %s", hipGetErrorString(e));
+      }
+    }
+  }
   // the mask's final pass also fills the ray queue (queue stage empty)
   if (s == HDOF_OK)
     s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st,
@@ -696,9 +730,13 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   // (variance stage empty)
   VarFuse vf;
   if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf);
-  if (s == HDOF_OK)
+  if (s == HDOF_OK) {
+    // beside the gather the trace keeps blocks in proportion to its rays
+    ctx->trace_ray_quantum = ovl ? ctx->tune.overlap_ray_quantum : 0;
     s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt_tr,
                      nullptr, nullptr, far_pos, st, &vf, true, coc_nf);  // marks 3, 4
+    ctx->trace_ray_quantum = 0;
+  }
   if (params->recon.enable || spatial) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
   if (s == HDOF_OK && params->recon.enable)
     s = launch_recon(ctx, k, prev ? &pk : nullptr, gb.depth, spp, far_pos, rt_tr, params->recon.alpha, st);
@@ -708,7 +746,20 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
                        params->recon.enable ? (const float*)ctx->rec_hist[ctx->rec_cur].p + 3 * N : nullptr, coc_nf,
                        nullptr, true, params->spatial, rt.c_near, rt.c_far, st, true);
   hdof_prof_mark(ctx, 7, st);
-  if (fused) {
+  if (ovl) {
+    // 16-pixel tiles: the specular gather reads the G-buffer's packed texels
+    // and runs before the join; other tiles: the side stream's pack
+    if (s == HDOF_OK && spec_on && fused) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);
+    if (forked) {
+      const hipError_t e = hipStreamWaitEvent(st, ctx->ev_join, 0);
+      if (e != hipSuccess && s == HDOF_OK)
+        s = hdof_set_error(HDOF_ERR_HIP, "overlapped frame join: %s", hipGetErrorString(e));
+    }
+    if (s == HDOF_OK && spec_on && !fused) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);
+    hdof_prof_mark(ctx, 9, st);
+    if (s == HDOF_OK)
+      s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st, pps);
+  } else if (fused) {
     // the G-buffer wrote the packed texels and tile radii the specular gather reads
     if (s == HDOF_OK && spec_on) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);
     const PostFuse pf{spp, rt, params->comp, d_out, pps};
@@ -731,14 +782,14 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
 // ---------------------------------------------------------------------------
 void hdof_prof_mark(hdof_ctx* ctx, int i, hipStream_t st) {
   if (!ctx->prof_on || !ctx->prof_in_frame) return;
-  const size_t base = (size_t)ctx->prof_frames * (HDOF_PROFILE_STAGES + 1), idx = base + i;
-  while (ctx->prof_events.size() <= idx) {
+  const size_t base = (size_t)ctx->prof_frames * HDOF_PROF_SLOTS, idx = base + i;
+  while (ctx->prof_events.size() < base + HDOF_PROF_SLOTS) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     ctx->prof_events.push_back(e);
   }
-  if (ctx->prof_set.size() < base + HDOF_PROFILE_STAGES + 1) ctx->prof_set.resize(base + HDOF_PROFILE_STAGES + 1, 0);
-  if (i == 0) std::fill(ctx->prof_set.begin() + base, ctx->prof_set.begin() + base + HDOF_PROFILE_STAGES + 1, 0);
+  if (ctx->prof_set.size() < base + HDOF_PROF_SLOTS) ctx->prof_set.resize(base + HDOF_PROF_SLOTS, 0);
+  if (i == 0) std::fill(ctx->prof_set.begin() + base, ctx->prof_set.begin() + base + HDOF_PROF_SLOTS, 0);
   if (hipEventRecord(ctx->prof_events[idx], st) == hipSuccess) ctx->prof_set[idx] = 1;
 }
 
@@ -756,14 +807,22 @@ extern "C" hdof_status hdof_profile_end(hdof_ctx* ctx, float* ms_out, int32_t* n
   const int S = HDOF_PROFILE_STAGES;
   for (int i = 0; i < S; ++i) ms_out[i] = 0.0f;
   // stage i runs from mark i to the next recorded mark; a stage whose
-  // start mark was not recorded (it had no work) counts 0
+  // start mark was not recorded (it had no work) counts 0.  An overlapped
+  // gather (its end recorded) runs from its mark to its end, and the
+  // stage before it on the frame's stream ends at the composite's mark.
+  const int G = 8;  // the post-filter gather's stage
   for (int f = 0; f < ctx->prof_frames; ++f) {
-    const size_t base = (size_t)f * (S + 1);
+    const size_t base = (size_t)f * HDOF_PROF_SLOTS;
+    const bool ovl = ctx->prof_set[base + HDOF_PROF_GATHER_END] != 0;
     for (int i = 0; i < S; ++i) {
       if (!ctx->prof_set[base + i]) continue;
       int j = i + 1;
-      while (j <= S && !ctx->prof_set[base + j]) ++j;
-      if (j > S) continue;
+      if (ovl && i == G) {
+        j = HDOF_PROF_GATHER_END;
+      } else {
+        while (j <= S && (!ctx->prof_set[base + j] || (ovl && j == G))) ++j;
+        if (j > S) continue;
+      }
       float ms = 0.0f;
       HDOF_HIP(hipEventElapsedTime(&ms, ctx->prof_events[base + i], ctx->prof_events[base + j]));
       ms_out[i] += ms;
@@ -809,6 +868,9 @@ extern "C" hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* t) {
   REQUIRE(t->blocks_per_cu >= 1 && t->blocks_per_cu <= 32, "blocks_per_cu must be in [1, 32]");
   REQUIRE(t->refill >= 1 && t->refill <= 64, "refill must be in [1, 64]");
   REQUIRE(t->segments >= 1 && t->segments <= 8, "segments must be in [1, 8]");
+  REQUIRE(t->wave == 0 || t->wave == 1, "wave must be 0 or 1");
+  REQUIRE(t->overlap == 0 || t->overlap == 1, "overlap must be 0 or 1");
+  REQUIRE(t->overlap_ray_quantum >= 1, "overlap_ray_quantum must be at least 1");
   ctx->tune = *t;
   return HDOF_OK;
 }

@@ -98,7 +98,9 @@ struct hdof_ctx {
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp, f_spec, f_pps;
   // persistent-trace launch shape (performance only)
-  hdof_tuning tune = {HDOF_DEFAULT_BPC, 64, 8};
+  hdof_tuning tune = {HDOF_DEFAULT_BPC, 64, 8, 0, 1, 150000};
+  // the trace's ray quantum while a frame overlaps it with the gather (0: all blocks)
+  int trace_ray_quantum = 0;
   // batched form: per-view intermediates, view table (device + pinned host)
   Buf b_arena, b_views, b_totals;
   void* b_views_host = nullptr;
@@ -107,7 +109,12 @@ struct hdof_ctx {
   // traversal work counters (rays, node visits, triangle tests) x (G-buffer, trace)
   bool count_on = false;
   unsigned long long* d_counters = nullptr;
-  // stage profiling: HDOF_PROFILE_STAGES + 1 events per profiled frame
+  // overlapped frame: the post-filter gather's stream, forked from the
+  // frame's stream after the G-buffer and joined before the composite
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // stage profiling: HDOF_PROF_SLOTS events per profiled frame (the stage
+  // marks, then the end of an overlapped gather)
   bool prof_on = false, prof_in_frame = false;
   int prof_frames = 0;
   std::vector<hipEvent_t> prof_events;
@@ -115,6 +122,10 @@ struct hdof_ctx {
 };
 
 // record stage boundary `i` of the current profiled frame (no-op when off)
+// per profiled frame: marks 0..HDOF_PROFILE_STAGES, then the end of an
+// overlapped post-filter gather (recorded on its own stream)
+#define HDOF_PROF_SLOTS (HDOF_PROFILE_STAGES + 2)
+#define HDOF_PROF_GATHER_END (HDOF_PROFILE_STAGES + 1)
 void hdof_prof_mark(hdof_ctx* ctx, int i, hipStream_t st);
 
 // ---------------------------------------------------------------------------
@@ -355,6 +366,10 @@ struct PostFuse {
   const float* pps;  // nullable: post-filtered specular luminance (the specular bokeh rule)
 };
 // packed: pack and per-tile radius already written (by the G-buffer)
+// the post-filter's scratch and tap table for this image and lens, on st
+// (a frame that runs the gather on another stream calls it before forking)
+hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, const hdof_pp_params& pp,
+                               hipStream_t st);
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
                               bool packed = false, const PostFuse* fuse = nullptr);

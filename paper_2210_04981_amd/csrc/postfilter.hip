@@ -300,6 +300,22 @@ struct FuseK {
   float inv_sy;      // 1 / spec_y, 0: no specular bokeh rule
 };
 
+// The composite's blend of one channel (paper, Composite): the traced
+// colour crt = h C_tn + (1 - h) C_tf, the near rule nu, the focus-zone
+// weight phi, the far blend beta and the specular weight sig.  Every
+// product that meets a sum is an explicit fmaf, so the fused gather
+// epilogue and the separate composite kernel round alike.
+__device__ __forceinline__ float traced_mix(float h, float cn, float cf) { return fmaf(h, cn, (1.0f - h) * cf); }
+
+__device__ __forceinline__ float composite_mix(float col, float cpp, float crt, float phi, float nu, float rho,
+                                               float beta, float sig) {
+  const float cnear = fmaf(sig, cpp - crt, crt);
+  const float v_near = fmaf(rho, cnear, (1.0f - rho) * cpp);
+  const float v_far = fmaf(beta, crt, (1.0f - beta) * cpp);
+  const float oof = fmaf(nu, v_near, (1.0f - nu) * v_far);
+  return fmaf(phi, oof, (1.0f - phi) * col);
+}
+
 __device__ __forceinline__ void composite_px(const FuseK& fz, size_t N, size_t p, const float4& cp4, float pr,
                                              float pg, float pb) {
   const float c = cp4.w;
@@ -313,10 +329,8 @@ __device__ __forceinline__ void composite_px(const FuseK& fz, size_t N, size_t p
   const float col[3] = {cp4.x, cp4.y, cp4.z}, cpp[3] = {pr, pg, pb};
   for (int q = 0; q < 3; ++q) {
     const size_t i = (size_t)q * N + p;
-    const float crt = traced ? h * fz.cn[i] + (1.0f - h) * fz.cf[i] : 0.0f;
-    const float cnear = fmaf(sig, cpp[q] - crt, crt);
-    const float oof = nu * (rho * cnear + (1.0f - rho) * cpp[q]) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp[q]);
-    float o = (1.0f - phi) * col[q] + phi * oof;
+    const float crt = traced ? traced_mix(h, fz.cn[i], fz.cf[i]) : 0.0f;
+    float o = composite_mix(col[q], cpp[q], crt, phi, nu, rho, beta, sig);
     if (fz.rt_override && traced) o = crt;
     fz.out[i] = o;
   }
@@ -528,11 +542,9 @@ __global__ void k_composite(const float* __restrict__ color, const float* __rest
   const float sig = (pps && traced && inv_sy > 0.0f) ? clamp01(pps[p] * inv_sy) : 0.0f;
   for (int q = 0; q < 3; ++q) {
     size_t i = (size_t)q * N + p;
-    const float crt = traced ? h * cn[i] + (1.0f - h) * cf[i] : 0.0f;
+    const float crt = traced ? traced_mix(h, cn[i], cf[i]) : 0.0f;
     const float cpp = phi > 0.0f ? pp[i] : 0.0f;
-    const float cnear = fmaf(sig, cpp - crt, crt);
-    float oof = nu * (rho * cnear + (1.0f - rho) * cpp) + (1.0f - nu) * (beta * crt + (1.0f - beta) * cpp);
-    float o = (1.0f - phi) * color[i] + phi * oof;
+    float o = composite_mix(color[i], cpp, crt, phi, nu, rho, beta, sig);
     if (rt_override && traced) o = crt;
     out[i] = o;
   }
@@ -907,19 +919,27 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
+hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, const hdof_pp_params& pp,
+                               hipStream_t st) {
+  const int t = pp.tile;
+  const size_t N = (size_t)k.W * k.H, NT = (size_t)cdiv(k.W, t) * cdiv(k.H, t);
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->pp_pack, sizeof(float4) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->pp_tile, sizeof(float) * NT)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->pp_rad, sizeof(float) * NT)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
+  pp_taps_ensure(ctx, pp.n_taps, l, st);
+  return HDOF_OK;
+}
+
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st, bool packed,
                               const PostFuse* fuse) {
   const int W = k.W, H = k.H, t = pp.tile;
-  const size_t N = (size_t)W * H;
   const int TW = cdiv(W, t), TH = cdiv(H, t);
   const int K = (int)ceil((double)pp.r_cap / t);
   hdof_status s;
-  if ((s = hdof_ensure(ctx->pp_pack, sizeof(float4) * N)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->pp_tile, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->pp_rad, sizeof(float) * (size_t)TW * TH)) != HDOF_OK) return s;
-  if ((s = hdof_ensure(ctx->pp_taps, sizeof(float4) * 256)) != HDOF_OK) return s;
-  pp_taps_ensure(ctx, pp.n_taps, l, st);
+  if ((s = postfilter_reserve(ctx, k, l, pp, st)) != HDOF_OK) return s;
   if (!packed)
     hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
                        (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);

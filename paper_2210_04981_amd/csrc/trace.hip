@@ -444,12 +444,85 @@ struct TraceArgs {
   int* flags;
   unsigned long long* counters;
   int refill, segments;
+  int ray_quantum, n_cu, bpc;  // ray_quantum > 0: blocks kept per CU = ceil(rays / ray_quantum) in [1, bpc]
   ViewK v0;                // the view of a plain frame
   const ViewK* views;      // batch: device table of views
   const int* entry_base;   // batch: first queue entry of each view
   int n_views;
 };
 
+// The ray of queue entry ee of a segment ending at hi: its pixel from the
+// queue, its sample index from the pixel's first entry, the lens sample
+// from the view's counters.  False for an entry past hi or a corrupt pixel
+// index.  pxb (batch): the first batch pixel of each view.
+template <bool BATCH>
+__device__ inline bool entry_ray(const TraceArgs& A, const int* pxb, int ee, int hi, Ray& r, float& S1) {
+  const int g = ee < hi ? A.queue[ee] : -1;
+  bool ok;
+  int p, j;
+  const ViewK* vk = &A.v0;
+  if (BATCH) {
+    // view of batch pixel g: last view whose first pixel is <= g
+    int v = 0;
+    for (int step = HDOF_MAX_VIEWS / 2; step >= 1; step >>= 1)
+      if (v + step < A.n_views && pxb[v + step] <= g) v += step;
+    vk = &A.views[v];
+    p = g - pxb[v];
+    ok = g >= 0 && p < vk->k.W * vk->k.H;
+    j = ok ? ee - A.entry_base[v] - A.offsets[g] : 0;
+  } else {
+    p = g;
+    ok = g >= 0 && g < A.v0.k.W * A.v0.k.H;
+    j = ok ? ee - A.offsets[g] : 0;
+  }
+  if (!ok) return false;
+  const CamK k = vk->k;
+  const LensK l = vk->l;
+  V3 O, D;
+  lens_ray(k, l, p % k.W, p / k.W, (uint32_t)j, vk->view, vk->seed, vk->frame, O, D);
+  r = make_ray(O, D);
+  S1 = l.S1;
+  return true;
+}
+
+// Shade the closest hit of a finished ray and store entry e's result.
+template <bool COUNT>
+__device__ inline void store_ray(const TraceArgs& A, const Ray& r, const Best& b, float S1, int e, const Work& wk) {
+  float z = HDOF_ZMAX;
+  V3 L = V3{0.0f, 0.0f, 0.0f};
+  if (b.tri >= 0) {
+    V3 n, a;
+    float ys;
+    shade(A.tris, A.albedo, A.spec, A.li, r, b, L, n, a, ys);
+    z = b.t * S1;
+  }
+  A.ray_col[e] = L.x;
+  A.ray_col[A.cap + e] = L.y;
+  A.ray_col[2 * A.cap + e] = L.z;
+  A.ray_z[e] = z;
+  if (A.ray_id) A.ray_id[e] = b.tri >= 0 ? b.id : -1;
+  if (COUNT) {
+    atomicAdd(&A.counters[3], 1ull);
+    atomicAdd(&A.counters[4], (unsigned long long)wk.visits);
+    atomicAdd(&A.counters[5], (unsigned long long)wk.tests);
+  }
+}
+
+// Whether this block of the persistent trace takes part: with a ray
+// quantum (a frame overlapping the trace with the post-filter gather) only
+// ceil(total / ray_quantum) blocks per CU, at least one and at most the
+// grid's, so a light trace leaves the CUs to the gather; the first blocks
+// are kept, so every queue segment keeps its blocks.
+__device__ inline bool keep_block(const TraceArgs& A, int total) {
+  if (A.ray_quantum <= 0) return true;
+  const long per_cu = min((long)A.bpc, max(1L, ((long)total + A.ray_quantum - 1) / A.ray_quantum));
+  return (long)blockIdx.x < per_cu * A.n_cu;
+}
+
+// Entries handed out: per queue segment (one per XCD, the block's
+// blockIdx.x mod segments) an atomic counter of entries taken; a wave whose
+// segment runs dry moves on to the next and stops once it has found every
+// segment dry.
 template <bool COUNT, bool BATCH>
 __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_trace(TraceArgs A) {
   __shared__ int stk_all[HDOF_LDS_STACK * HDOF_TRACE_BLOCK];
@@ -467,6 +540,7 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
     if (blockIdx.x == 0 && t == 0) atomicOr(A.flags, HDOF_FLAG_CAPACITY);
     total = (int)A.cap;
   }
+  if (!keep_block(A, total)) return;
   const int nseg = A.segments;
   const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   bool active = false, drained = false;
@@ -490,31 +564,7 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
       }
       if (!active) {
         const int ee = base + __popcll(idle & lt_mask);
-        const int g = ee < hi ? A.queue[ee] : -1;
-        bool ok;
-        int p, j;
-        const ViewK* vk = &A.v0;
-        if (BATCH) {
-          // view of batch pixel g: last view whose first pixel is <= g
-          int v = 0;
-          for (int step = HDOF_MAX_VIEWS / 2; step >= 1; step >>= 1)
-            if (v + step < A.n_views && pxb[v + step] <= g) v += step;
-          vk = &A.views[v];
-          p = g - pxb[v];
-          ok = g >= 0 && p < vk->k.W * vk->k.H;
-          j = ok ? ee - A.entry_base[v] - A.offsets[g] : 0;
-        } else {
-          p = g;
-          ok = g >= 0 && g < A.v0.k.W * A.v0.k.H;
-          j = ok ? ee - A.offsets[g] : 0;
-        }
-        if (ok) {
-          const CamK k = vk->k;
-          const LensK l = vk->l;
-          V3 O, D;
-          lens_ray(k, l, p % k.W, p / k.W, (uint32_t)j, vk->view, vk->seed, vk->frame, O, D);
-          r = make_ray(O, D);
-          S1 = l.S1;
+        if (entry_ray<BATCH>(A, pxb, ee, hi, r, S1)) {
           trav_init(s);
           e = ee;
           steps = 0;
@@ -533,26 +583,53 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
       done = true;
     }
     if (done) {
-      float z = HDOF_ZMAX;
-      V3 L = V3{0.0f, 0.0f, 0.0f};
-      if (s.b.tri >= 0) {
-        V3 n, a;
-        float ys;
-        shade(A.tris, A.albedo, A.spec, A.li, r, s.b, L, n, a, ys);
-        z = s.b.t * S1;
-      }
-      A.ray_col[e] = L.x;
-      A.ray_col[A.cap + e] = L.y;
-      A.ray_col[2 * A.cap + e] = L.z;
-      A.ray_z[e] = z;
-      if (A.ray_id) A.ray_id[e] = s.b.tri >= 0 ? s.b.id : -1;
-      if (COUNT) {
-        atomicAdd(&A.counters[3], 1ull);
-        atomicAdd(&A.counters[4], (unsigned long long)wk.visits);
-        atomicAdd(&A.counters[5], (unsigned long long)wk.tests);
-      }
+      store_ray<COUNT>(A, r, s.b, S1, e, wk);
       active = false;
     }
+  }
+}
+
+// Wave-coherent form: a wave takes 64 consecutive entries of its segment at
+// a time (the samples of a few neighbouring pixels, whose rays differ by
+// their lens offsets) and walks the union of their paths with wave-uniform
+// node loads (traverse_wave), then shades and stores them; no per-lane
+// refill and no LDS stack.  Same hand-out of entries as k_trace, so the
+// same results.
+template <bool COUNT, bool BATCH>
+__global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_trace_wave(TraceArgs A) {
+  __shared__ int pxb[HDOF_MAX_VIEWS + 1];
+  const int t = threadIdx.x, lane = t & 63;
+  if (BATCH) {
+    for (int v = t; v < A.n_views; v += HDOF_TRACE_BLOCK) pxb[v] = A.views[v].px_base;
+    __syncthreads();
+  }
+  int total = *A.total_p;
+  if (total < 0) total = 0;
+  if ((size_t)total > A.cap) {
+    if (blockIdx.x == 0 && t == 0) atomicOr(A.flags, HDOF_FLAG_CAPACITY);
+    total = (int)A.cap;
+  }
+  if (!keep_block(A, total)) return;
+  const int nseg = A.segments;
+  int seg = blockIdx.x % nseg, tried = 0;
+  while (tried < nseg) {
+    const int lo = (int)((long)total * seg / nseg), hi = (int)((long)total * (seg + 1) / nseg);
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&A.counter[seg * HDOF_SEG_STRIDE], 64);
+    base = __shfl(base, 0) + lo;
+    if (base >= hi) {  // this segment is used up: go on to the next one
+      seg = seg + 1 == nseg ? 0 : seg + 1;
+      ++tried;
+      continue;
+    }
+    const int e = base + lane;
+    Ray r;
+    float S1 = A.v0.l.S1;
+    const bool live = entry_ray<BATCH>(A, pxb, e, hi, r, S1);
+    if (!live) r = make_ray(V3{0.0f, 0.0f, 0.0f}, V3{0.0f, 0.0f, 1.0f});
+    Work wk{0, 0};
+    const Best b = traverse_wave<COUNT>(A.nodes, A.tris, A.n_nodes, r, live, A.flags, wk);
+    if (live) store_ray<COUNT>(A, r, b, S1, e, wk);
   }
 }
 
@@ -678,10 +755,12 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 template <bool BATCH>
 void launch_trace_kernel(hdof_ctx* ctx, const TraceArgs& A, hipStream_t st) {
   const int grid = ctx->n_cu * ctx->tune.blocks_per_cu;
-  if (ctx->count_on)
-    hipLaunchKernelGGL((k_trace<true, BATCH>), dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, A);
+  void (*kern)(TraceArgs);
+  if (ctx->tune.wave)
+    kern = ctx->count_on ? k_trace_wave<true, BATCH> : k_trace_wave<false, BATCH>;
   else
-    hipLaunchKernelGGL((k_trace<false, BATCH>), dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, A);
+    kern = ctx->count_on ? k_trace<true, BATCH> : k_trace<false, BATCH>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(HDOF_TRACE_BLOCK), 0, st, A);
 }
 
 __global__ void k_zero_f(float* __restrict__ a, int n) {
@@ -705,6 +784,9 @@ TraceArgs base_args(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, size_
   A.counters = ctx->d_counters;
   A.refill = ctx->tune.refill;
   A.segments = ctx->tune.segments;
+  A.ray_quantum = ctx->trace_ray_quantum;
+  A.n_cu = ctx->n_cu;
+  A.bpc = ctx->tune.blocks_per_cu;
   return A;
 }
 

@@ -94,7 +94,8 @@ class View(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("refill", C.c_int32), ("segments", C.c_int32)]
+    _fields_ = [("blocks_per_cu", C.c_int32), ("refill", C.c_int32), ("segments", C.c_int32), ("wave", C.c_int32),
+                ("overlap", C.c_int32), ("overlap_ray_quantum", C.c_int32)]
 
 
 MAX_VIEWS = 64
@@ -683,15 +684,17 @@ class Batch:
             pass
 
 
-def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8) -> None:
-    t = Tuning(int(blocks_per_cu), int(refill), int(segments))
+def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8, wave=0, overlap=1,
+                    overlap_ray_quantum=150000) -> None:
+    t = Tuning(int(blocks_per_cu), int(refill), int(segments), int(wave), int(overlap), int(overlap_ray_quantum))
     _check(_lib.hdof_set_tuning(ctx.handle, C.byref(t)), "hdof_set_tuning")
 
 
 def hdof_get_tuning(ctx: Context) -> dict:
     t = Tuning()
     _check(_lib.hdof_get_tuning(ctx.handle, C.byref(t)), "hdof_get_tuning")
-    return dict(blocks_per_cu=t.blocks_per_cu, refill=t.refill, segments=t.segments)
+    return dict(blocks_per_cu=t.blocks_per_cu, refill=t.refill, segments=t.segments, wave=t.wave,
+                overlap=t.overlap, overlap_ray_quantum=t.overlap_ray_quantum)
 
 
 # ----------------------------------------------------------------------------

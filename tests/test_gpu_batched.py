@@ -92,10 +92,12 @@ def test_tuning_does_not_change_results(hd, ctx, room):
     v = (hd.camera_of(cfg.camera), hd.lens_of(cfg.lens), 0, 0, 0)
     base = _plain(hd, ctx, room, cfg, v).clone()
     for t in [dict(blocks_per_cu=1, refill=64, segments=1), dict(blocks_per_cu=4, refill=16, segments=3),
-              dict(blocks_per_cu=32, refill=1, segments=8)]:
+              dict(blocks_per_cu=32, refill=1, segments=8), dict(blocks_per_cu=10, segments=8, wave=1),
+              dict(blocks_per_cu=2, segments=5, wave=1)]:
         hd.hdof_set_tuning(ctx, **t)
         out = _plain(hd, ctx, room, cfg, v)
         torch.cuda.synchronize()
         assert torch.equal(out, base), t
     hd.hdof_set_tuning(ctx)
-    assert hd.hdof_get_tuning(ctx) == dict(blocks_per_cu=10, refill=64, segments=8)
+    assert hd.hdof_get_tuning(ctx) == dict(blocks_per_cu=10, refill=64, segments=8, wave=0, overlap=1,
+                                           overlap_ray_quantum=150000)

@@ -1,0 +1,152 @@
+"""The overlapped frame (the post-filter gather on the context's second
+stream beside the mask, trace and reconstruction; the composite after both)
+against the single-stream frame: bitwise equal kept planes and outputs, for
+16- and 8-pixel tiles, the specular rule, and temporal plus spatial
+reconstruction along a camera path; the stage profile of an overlapped
+frame times the gather on its own stream."""
+import pytest
+import torch
+
+import scenegen as sg
+from gpu_common import DEV, print_case, to_dev, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    from paper_2210_04981_amd import hdof
+    return hdof
+
+
+@pytest.fixture(scope="module")
+def ctx(hd):
+    c = hd.Context(0)
+    yield c
+    hd.hdof_set_tuning(c)
+    c.close()
+
+
+def _run(hd, ctx, sc, cfg, params, cams, lens, light, spec_y, ovl):
+    """Frames along cams, single stream (ovl 0) or overlapped with ray
+    quantum ovl; (out, kept planes) per frame."""
+    hd.hdof_set_tuning(ctx, overlap=int(ovl > 0), overlap_ray_quantum=max(ovl, 1))
+    hd.hdof_history_reset(ctx)
+    hd.hdof_recon_history_reset(ctx)
+    H, W = cfg.camera.height, cfg.camera.width
+    res = []
+    for t, cam in enumerate(cams):
+        k = hd.FrameKeep.empty(H, W)
+        if spec_y > 0:
+            k.gb = hd.GBuffer.empty(H, W, spec=True)
+        k.pp = torch.empty(3, H, W, device=DEV)
+        out = torch.empty(3, H, W, device=DEV)
+        hd.hdof_frame(ctx, sc, cam, cams[t - 1] if t else None, lens, light, params, frame=t, out=out, keep=k)
+        res.append((out, k))
+    torch.cuda.synchronize()
+    ctx.sync()
+    return res
+
+
+def _same(hd, ctx, cfg, params, lens, a, b, ovl_b):
+    """Frames a (single stream) and b (overlapped with ray quantum ovl_b):
+    every kept plane and the output bitwise equal (the 16-pixel gather's
+    fused composite and the separate composite kernel round alike), and b's
+    output bitwise equal to the separate composite of its kept planes."""
+    cam = hd.camera_of(cfg.camera)
+    for t, ((oa, ka), (ob, kb)) in enumerate(zip(a, b)):
+        for name in ("c_near", "c_far", "hit_ratio", "lum_m1", "lum_m2"):
+            assert torch.equal(getattr(ka.rt, name), getattr(kb.rt, name)), (t, name)
+        assert torch.equal(ka.spp, kb.spp) and torch.equal(ka.gb.color, kb.gb.color)
+        assert torch.equal(ka.pp, kb.pp), t
+        pps = None
+        if params.comp.spec_y > 0:
+            _, pps = hd.hdof_postfilter_specular(ctx, kb.gb.color, kb.gb.depth, kb.gb.spec, kb.spp, cam, lens,
+                                                 params.pp)
+        comp = hd.hdof_composite(ctx, kb.gb.color, kb.pp, kb.gb.depth, kb.spp, kb.rt, cam, lens, params.comp,
+                                 pp_spec=pps)
+        torch.cuda.synchronize()
+        assert torch.equal(ob, comp), (t, ovl_b)
+        assert torch.equal(oa, ob), (t, ovl_b, (oa - ob).abs().max().item())
+
+
+@pytest.mark.parametrize("tile,spec_y", [(16, 0.0), (8, 0.0), (16, 0.3), (8, 0.3)])
+def test_overlapped_frame_equals_single_stream(hd, ctx, tile, spec_y):
+    print_case(f"overlap tile {tile} spec_y {spec_y}")
+    W, H = 320, 180
+    glossy = spec_y > 0
+    scene = sg.glossy_living_room_scene(0) if glossy else sg.living_room_scene(0)
+    cfg = sg.config_1080p(W, H)
+    cfg.pp.tile = tile
+    sc = upload_scene(hd, ctx, scene)
+    if glossy:
+        hd.hdof_scene_set_specular(sc, to_dev(scene.spec))
+    params = hd.frame_params_of(cfg)
+    params.comp.spec_y = spec_y
+    cams = [hd.camera_of(cfg.camera)]
+    lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    ref = _run(hd, ctx, sc, cfg, params, cams, lens, light, spec_y, 0)
+    for ovl in (150000, 1, 10 ** 9, 20000):  # default, all blocks, one per CU, in between
+        _same(hd, ctx, cfg, params, lens, ref, _run(hd, ctx, sc, cfg, params, cams, lens, light, spec_y, ovl), ovl)
+    assert (ref[0][0] - ref[0][1].gb.color).abs().max().item() > 0.05  # depth of field changed the image
+    sc.close()
+
+
+def test_overlapped_frame_with_reconstruction(hd, ctx):
+    """Temporal and spatial reconstruction over four frames of a camera
+    path: the overlapped frames equal the single-stream ones."""
+    print_case("overlap temporal+spatial")
+    W, H = 320, 180
+    cfg = sg.config_temporal(W, H)
+    cfg.mask.spp_max = 8
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    params = hd.frame_params_of(cfg)
+    params.spatial.enable, params.spatial.n_taps, params.spatial.r_cap, params.spatial.v_clamp = 1, 24, 64.0, 0.01
+    params.recon.enable, params.recon.alpha = 1, 0.2
+    cams = [hd.camera_of(sg.temporal_camera(t, W, H)) for t in range(4)]
+    lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    ref = _run(hd, ctx, sc, cfg, params, cams, lens, light, 0.0, 0)
+    b = _run(hd, ctx, sc, cfg, params, cams, lens, light, 0.0, 150000)
+    for t, ((oa, ka), (ob, kb)) in enumerate(zip(ref, b)):
+        for name in ("c_near", "c_far", "hit_ratio"):
+            assert torch.equal(getattr(ka.rt, name), getattr(kb.rt, name)), (t, name)
+        assert torch.equal(ka.pp, kb.pp), t
+        assert torch.equal(oa, ob), (t, (oa - ob).abs().max().item())
+    sc.close()
+
+
+def test_overlapped_frame_profile(hd, ctx):
+    """Profiled overlapped frames: every stage that ran has a positive
+    duration, the gather's is its own stream's, and the frame's stream
+    stages (all but the gather) fit in the frame."""
+    print_case("overlap profile")
+    W, H = 640, 360
+    cfg = sg.config_1080p(W, H)
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    params = hd.frame_params_of(cfg)
+    cam, lens, light = hd.camera_of(cfg.camera), hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    out = torch.empty(3, H, W, device=DEV)
+    hd.hdof_set_tuning(ctx)  # overlapped by default
+    assert hd.hdof_get_tuning(ctx)["overlap"] == 1
+    hd.hdof_history_reset(ctx)
+    for _ in range(2):
+        hd.hdof_frame(ctx, sc, cam, None, lens, light, params, out=out)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    hd.hdof_profile_begin(ctx)
+    a.record()
+    for _ in range(5):
+        hd.hdof_frame(ctx, sc, cam, None, lens, light, params, out=out)
+    b.record()
+    st, n = hd.hdof_profile_end(ctx)
+    torch.cuda.synchronize()
+    frame_ms = a.elapsed_time(b) / 5
+    assert n == 5
+    assert all(v >= 0 for v in st.values()), st
+    for k in ("gbuffer", "ray_mask", "trace", "rt_reduce", "pp_gather", "composite"):
+        assert st[k] > 0, (k, st)
+    main = sum(v for k, v in st.items() if k != "pp_gather")
+    assert main <= frame_ms * 1.05 + 0.01, (main, frame_ms, st)
+    assert st["pp_gather"] <= frame_ms * 1.05 + 0.01, (st["pp_gather"], frame_ms)
+    hd.hdof_set_tuning(ctx)
+    sc.close()

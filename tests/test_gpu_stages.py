@@ -197,9 +197,13 @@ def test_frame_with_scaled_mask_tile(hd, ctx):
     sc.close()
 
 
-@pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_small"])
-def test_trace_matches_oracle(hd, ctx, which):
-    print_case(f"trace {which}")
+@pytest.mark.parametrize("which,wave", [("tiny", 0), ("tiny_strong", 0), ("room_small", 0), ("tiny_strong", 1),
+                                        ("room_small", 1)])
+def test_trace_matches_oracle(hd, ctx, which, wave):
+    """Both traversal forms of the persistent trace (per-lane with refill,
+    and wave-coherent batches of 64 entries) against the oracle."""
+    print_case(f"trace {which} wave {wave}")
+    hd.hdof_set_tuning(ctx, wave=wave)
     if which == "room_small":
         scene, cfg = sg.living_room_scene(0), sg.config_1080p(320, 180)
     else:
@@ -249,6 +253,7 @@ def test_trace_matches_oracle(hd, ctx, which):
     assert np.max(np.abs(g["c_near"] - ref["c_near"])[:, strong], initial=0) < COL_TOL
     untraced = spp == 0
     assert np.all(g["hit_ratio"][untraced] == 0) and np.all(g["c_near"][:, untraced] == 0)
+    hd.hdof_set_tuning(ctx)
     sc.close()
 
 
