@@ -2,16 +2,19 @@
 
 A step is one hdof_frame over the 1920x1080 procedural living room (~200k
 triangles, f = 50 mm, f/1.4, focus 2 m, 0-8 spp): G-buffer, ray mask,
-thin-lens trace, variance update, post-filter, composite.  The scene's BVH
-is built once before timing (reported separately).  Inputs are resident in
-HBM when the timed region starts.
+thin-lens trace, variance update, post-filter, composite, with the library's
+default tuning (the post-filter gather on a second stream beside the mask
+and trace).  The scene's BVH is built once before timing (reported
+separately).  Inputs are resident in HBM when the timed region starts.
 
 Prints one JSON line (the driver's contract).  `value` / `ms_per_step` come
 from the timed steps with events only around the whole region; a second
 pass over the same number of steps records HIP events between the stages
-(on the frame's stream, by the library) for the per-stage times and the
-`roofline` of the dominant kernel.  `cpu_baseline` is the FP64 oracle on
-the host cores (one full frame).
+(on the streams the kernels run on, by the library) for the per-stage times
+and the `roofline` of the dominant kernel.  `single_stream` repeats both
+passes with the overlap off: the frame time and each kernel's time without
+another kernel beside it.  `cpu_baseline` is the FP64 oracle on the host
+cores (one full frame).
 """
 from __future__ import annotations
 
@@ -121,6 +124,18 @@ def main():
     stage_ms, nf = hdof.hdof_profile_end(ctx)
     profiled_ms = ep0.elapsed_time(ep1) / args.steps
     ctx.sync()
+    tuning = hdof.hdof_get_tuning(ctx)
+
+    # the same frames on one stream: each kernel alone
+    print("[bench] single-stream pass", file=sys.stderr, flush=True)
+    hdof.hdof_set_tuning(ctx, **{**tuning, "overlap": 0})
+    single_ms = _time_ms(lambda: step(0), args.steps, stream)
+    hdof.hdof_profile_begin(ctx)
+    for i in range(args.steps):
+        step(i)
+    stage_single, _ = hdof.hdof_profile_end(ctx)
+    hdof.hdof_set_tuning(ctx, **tuning)
+    ctx.sync()
 
     # one extra frame with the counting traversal variants: node visits and
     # triangle tests per ray (not part of the timed region)
@@ -141,7 +156,11 @@ def main():
         "gbuffer": (work["gbuffer_visits"] / max(work["gbuffer_rays"], 1), work["gbuffer_tests"] / max(work["gbuffer_rays"], 1)),
         "trace": (work["trace_visits"] / max(work["trace_rays"], 1), work["trace_tests"] / max(work["trace_rays"], 1)),
     }
-    roofline = roofline_for(dom, stage_ms[dom], N, rays, per_ray)
+    form = "overlapped" if tuning["overlap"] else "single_stream"
+    roofline = roofline_for(dom, stage_ms[dom], N, rays, per_ray, form)
+    dom1 = max(stage_single, key=stage_single.get)
+    single = {"frame_ms": round(single_ms, 4), "stage_ms": {k: round(v, 4) for k, v in stage_single.items()},
+              "roofline": roofline_for(dom1, stage_single[dom1], N, rays, per_ray, "single_stream")}
 
     res = {
         "metric": METRIC,
@@ -173,6 +192,8 @@ def main():
         "profiled_frames": nf,
         "bvh": {"build_ms_host_timed": round(bvh_ms, 2), **stats},
         "roofline": roofline,
+        "tuning": tuning,
+        "single_stream": single,
         "paper_context": "143 fps hybrid on GeForce RTX 2080 Ti, The Modern Living Room (context only)",
     }
     if not args.no_forms:
@@ -546,15 +567,18 @@ OPS_NODE, OPS_TRI, OPS_RAY, OPS_PHILOX, OPS_TAP = 38, 45, 150, 250, 30
 
 # measured HBM traffic per launch of a kernel: rocprofv3 FETCH_SIZE and
 # WRITE_SIZE summaries under profiles/, valid only while the kernel source
-# they were taken on is unchanged
-TRAFFIC_FILES = {"pp_gather": "profiles/pp_gather_1080p_living_room_traffic.txt"}
+# they were taken on is unchanged; per stage and frame form (the overlapped
+# frame's gather writes the filtered colour, the single-stream frame's
+# gather applies the composite)
+TRAFFIC_FILES = {("pp_gather", "overlapped"): "profiles/pp_gather_1080p_living_room_traffic.txt",
+                 ("pp_gather", "single_stream"): "profiles/pp_gather_fused_1080p_living_room_traffic.txt"}
 
 
-def traffic_for(stage):
+def traffic_for(stage, form):
     """HBM bytes per launch from the committed counter summary, or None when
     there is none or the kernel source has changed since."""
     import hashlib
-    path = TRAFFIC_FILES.get(stage)
+    path = TRAFFIC_FILES.get((stage, form))
     if path is None or not os.path.exists(os.path.join(ROOT, path)):
         return None
     kv = {}
@@ -570,7 +594,7 @@ def traffic_for(stage):
     return int(float(kv["traffic_bytes_per_dispatch"]))
 
 
-def roofline_for(stage, ms, n_px, rays, per_ray):
+def roofline_for(stage, ms, n_px, rays, per_ray, form):
     """Roofline entry of the dominant stage.  Traversal and gather stages are
     reported against the VALU peak with their algorithmic lane-op counts per
     unit (node visits and triangle tests measured by the counting pass);
@@ -580,7 +604,7 @@ def roofline_for(stage, ms, n_px, rays, per_ray):
         b = HBM_BYTES_PER_PX[stage] * n_px
         ach = b / sec / 1e9
         return {"kernel": stage, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(stage)}
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(stage, form)}
     if stage == "pp_gather":
         ops = n_px * 48 * OPS_TAP
     elif stage == "gbuffer":
@@ -591,7 +615,7 @@ def roofline_for(stage, ms, n_px, rays, per_ray):
         ops = max(rays, 1) * (v * OPS_NODE + t * OPS_TRI + OPS_RAY + OPS_PHILOX)
     ach = ops / sec / 1e12
     return {"kernel": stage, "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "Tlane-op/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic_for(stage)}
+            "unit": "Tlane-op/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": traffic_for(stage, form)}
 
 
 def cpu_baseline(cfg, scene):
