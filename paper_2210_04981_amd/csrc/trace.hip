@@ -8,7 +8,7 @@
 // Triangles: watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013),
 // ties broken towards the lowest input triangle index.
 //
-// G-buffer: 16x16-pixel blocks, each wave a 16x4 strip (coherent primary
+// G-buffer: 16x16-pixel blocks, each wave an 8x8 quadrant (coherent primary
 // rays); blocks remapped so each XCD works on a contiguous band of the image
 // and keeps its part of the BVH in its own L2.
 // Thin-lens trace: queue of (pixel, sample) entries built from the mask's
@@ -211,7 +211,7 @@ __device__ inline Best traverse(const float4* __restrict__ nodes, const float4* 
 }
 
 // Wave-coherent traversal: the lanes of a wave walk one node sequence, the
-// union of their own paths (primary rays of a 16x4 pixel strip are
+// union of their own paths (primary rays of an 8x8 pixel quadrant are
 // coherent).  Node records and leaf triangles are then wave-uniform loads,
 // served by the scalar data cache instead of 64 vector fetches per node;
 // the node stack is one VGPR holding entry i in lane i; a lane tests the
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
   const int lb = xcd_block(blockIdx.x, bx_n * by_n);
   const int bx = lb % bx_n, by = lb / bx_n;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int x = bx * 16 + (lane & 15), y = by * 16 + wave * 4 + (lane >> 4);
+  const int x = bx * 16 + (wave & 1) * 8 + (lane & 7), y = by * 16 + (wave >> 1) * 8 + (lane >> 3);
   const bool live = x < k.W && y < k.H;
   V3 v = pixel_dir(k, live ? x : 0, live ? y : 0);
   Ray r = make_ray(k.e, V3{l.S1 * v.x, l.S1 * v.y, l.S1 * v.z});
