@@ -465,10 +465,13 @@ void hdof_batch_destroy(hdof_batch* batch);
 /* Launch shape of the persistent thin-lens trace (performance only: results
  * do not depend on it).  blocks_per_cu in [1, 32]; refill in [1, 64]: idle
  * lanes of a wave that trigger a refill from the queue (64 = batches of 64
- * rays); segments in [1, 8]: queue segments, one per XCD group; wave 0 or 1:
- * 1 walks the 64 rays of a batch of consecutive queue entries as one wave
- * (one node sequence, the union of their paths; refill is then unused), 0
- * traverses each lane's ray on its own and refills idle lanes; overlap 0
+ * rays); segments in [1, 8]: queue segments, one per XCD group; wave 0, 1
+ * or 2: 1 walks the 64 rays of a batch of consecutive queue entries as one
+ * wave (one node sequence, the union of their paths, with wave-uniform node
+ * loads; refill is then unused), 0 traverses each lane's ray on its own and
+ * refills idle lanes, 2 takes 1 for scenes of at least HDOF_WAVE_AUTO_TRIS
+ * triangles (whose tree and triangles far exceed an XCD's L2, so 64 lane
+ * fetches per node cost more than a longer shared walk) and 0 below; overlap 0
  * or 1: 1 runs hdof_frame's post-filter gather on a second stream of the
  * context beside the mask, trace and reconstruction (it needs only the
  * G-buffer) and applies the composite once both are done, the results
@@ -476,9 +479,10 @@ void hdof_batch_destroy(hdof_batch* batch);
  * trace keeps one block per CU for every overlap_ray_quantum rays of the
  * frame (at least one, at most blocks_per_cu; the count is read on the
  * device, the other blocks return at once), so a light trace leaves CUs to
- * the gather and a heavy one keeps them.  Defaults {10, 64, 8, 0, 1,
+ * the gather and a heavy one keeps them.  Defaults {10, 64, 8, 2, 1,
  * 150000}: ten two-wave blocks per CU is the trace kernel's register-
  * limited residency (5 waves per SIMD), so every block starts at once. */
+#define HDOF_WAVE_AUTO_TRIS (1 << 19)
 typedef struct {
   int32_t blocks_per_cu, refill, segments, wave, overlap, overlap_ray_quantum;
 } hdof_tuning;

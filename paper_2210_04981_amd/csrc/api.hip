@@ -868,7 +868,7 @@ extern "C" hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* t) {
   REQUIRE(t->blocks_per_cu >= 1 && t->blocks_per_cu <= 32, "blocks_per_cu must be in [1, 32]");
   REQUIRE(t->refill >= 1 && t->refill <= 64, "refill must be in [1, 64]");
   REQUIRE(t->segments >= 1 && t->segments <= 8, "segments must be in [1, 8]");
-  REQUIRE(t->wave == 0 || t->wave == 1, "wave must be 0 or 1");
+  REQUIRE(t->wave >= 0 && t->wave <= 2, "wave must be 0, 1 or 2");
   REQUIRE(t->overlap == 0 || t->overlap == 1, "overlap must be 0 or 1");
   REQUIRE(t->overlap_ray_quantum >= 1, "overlap_ray_quantum must be at least 1");
   ctx->tune = *t;

@@ -756,7 +756,9 @@ template <bool BATCH>
 void launch_trace_kernel(hdof_ctx* ctx, const TraceArgs& A, hipStream_t st) {
   const int grid = ctx->n_cu * ctx->tune.blocks_per_cu;
   void (*kern)(TraceArgs);
-  if (ctx->tune.wave)
+  // automatic form: by the scene's triangle count (n_nodes + 1 for the binary tree)
+  const bool wave = ctx->tune.wave == 1 || (ctx->tune.wave == 2 && A.n_nodes + 1 >= HDOF_WAVE_AUTO_TRIS);
+  if (wave)
     kern = ctx->count_on ? k_trace_wave<true, BATCH> : k_trace_wave<false, BATCH>;
   else
     kern = ctx->count_on ? k_trace<true, BATCH> : k_trace<false, BATCH>;
