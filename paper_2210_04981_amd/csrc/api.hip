@@ -712,8 +712,14 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
       s = hdof_set_error(HDOF_ERR_HIP, "overlapped frame fork: %s", hipGetErrorString(e));
     } else {
       forked = true;
-      // mark 8 on the side stream (inside), then the gather's end
-      s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, ctx->side, fused);
+      // mark 8 on the side stream (inside), then the gather's end; with
+      // 16-pixel tiles its epilogue writes every pixel's output by the
+      // untraced pixels' rule, and the composite after the join rewrites
+      // only the traced pixels
+      hdof_rt_bufs none;
+      memset(&none, 0, sizeof none);
+      const PostFuse pu{nullptr, none, params->comp, d_out, nullptr, true};
+      s = launch_postfilter(ctx, gb.color, gb.depth, k, l, params->pp, pp, ctx->side, fused, fused ? &pu : nullptr);
       hdof_prof_mark(ctx, HDOF_PROF_GATHER_END, ctx->side);
       e = hipEventRecord(ctx->ev_join, ctx->side);
       if (e != hipSuccess) {
@@ -758,7 +764,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
     if (s == HDOF_OK && spec_on && !fused) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);
     hdof_prof_mark(ctx, 9, st);
     if (s == HDOF_OK)
-      s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st, pps);
+      s = launch_composite(ctx, gb.color, pp, gb.depth, spp, rt, k, l, params->comp, d_out, st, pps, fused);
   } else if (fused) {
     // the G-buffer wrote the packed texels and tile radii the specular gather reads
     if (s == HDOF_OK && spec_on) s = launch_pp_spec(ctx, gb.spec, spp, k, l, params->pp, pps, st);

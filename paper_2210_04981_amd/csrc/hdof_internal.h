@@ -364,12 +364,16 @@ struct PostFuse {
   hdof_composite_params cp;
   float* out;
   const float* pps;  // nullable: post-filtered specular luminance (the specular bokeh rule)
+  // 16-pixel tiles: the epilogue applies the untraced pixels' rule to every
+  // pixel and reads none of spp, rt, pps (the trace may still be writing
+  // them); a sparse composite then rewrites the traced pixels
+  bool untraced_only;
 };
-// packed: pack and per-tile radius already written (by the G-buffer)
 // the post-filter's scratch and tap table for this image and lens, on st
 // (a frame that runs the gather on another stream calls it before forking)
 hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, const hdof_pp_params& pp,
                                hipStream_t st);
+// packed: pack and per-tile radius already written (by the G-buffer)
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
                               bool packed = false, const PostFuse* fuse = nullptr);
@@ -377,10 +381,12 @@ hdof_status launch_ppc_backward(hdof_ctx* ctx, const float* color, const float* 
                                 hdof_rt_bufs rt, const CamK& k, const LensK& l, const hdof_pp_params& pp,
                                 const hdof_composite_params& cp, const float* grad_out, float* grad_color,
                                 float* grad_lens, hipStream_t st);
+// sparse: only the traced pixels (spp > 0) are written; the others already
+// hold the untraced rule's result (the overlapped frame's gather epilogue)
 hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
                              const uint8_t* spp, hdof_rt_bufs rt, const CamK& k, const LensK& l,
                              const hdof_composite_params& cp, float* out, hipStream_t st,
-                             const float* pps = nullptr);
+                             const float* pps = nullptr, bool sparse = false);
 // the post-filtered specular luminance of the traced pixels (all pixels when
 // spp is NULL); reads the frame's post-filter preparation (packed CoC, tile
 // radii, taps), so it follows the G-buffer's packing or launch_postfilter
