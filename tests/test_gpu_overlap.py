@@ -3,7 +3,8 @@ stream beside the mask, trace and reconstruction; the composite after both)
 against the single-stream frame: bitwise equal kept planes and outputs, for
 16- and 8-pixel tiles, the specular rule, and temporal plus spatial
 reconstruction along a camera path; the stage profile of an overlapped
-frame times the gather on its own stream."""
+frame times the gather on its own stream; an overlapped frame captured into
+a HIP graph replays to the eager result."""
 import pytest
 import torch
 
@@ -149,4 +150,43 @@ def test_overlapped_frame_profile(hd, ctx):
     assert main <= frame_ms * 1.05 + 0.01, (main, frame_ms, st)
     assert st["pp_gather"] <= frame_ms * 1.05 + 0.01, (st["pp_gather"], frame_ms)
     hd.hdof_set_tuning(ctx)
+    sc.close()
+
+
+def test_overlapped_frame_in_a_graph(hd, ctx):
+    """A frame captured into a HIP graph (torch.cuda.graph) with the overlap
+    on: the fork to the context's second stream and the join are captured
+    with it.  Three replays, with other eager frames and synchronisations
+    between them, each equal the eager frame bitwise."""
+    print_case("overlap graph capture")
+    W, H = 320, 180
+    cfg = sg.config_1080p(W, H)
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    params = hd.frame_params_of(cfg)
+    cam, lens, light = hd.camera_of(cfg.camera), hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    other = hd.camera_of(sg.temporal_camera(5, W, H))
+    hd.hdof_set_tuning(ctx)
+    assert hd.hdof_get_tuning(ctx)["overlap"] == 1
+    out_e = torch.empty(3, H, W, device=DEV)
+    out_g = torch.empty(3, H, W, device=DEV)
+    hd.hdof_frame(ctx, sc, cam, None, lens, light, params, frame=0, out=out_e)
+    hd.hdof_frame(ctx, sc, cam, None, lens, light, params, frame=0, out=out_g)  # every buffer in place
+    torch.cuda.synchronize()
+    ctx.sync()
+    assert torch.equal(out_e, out_g)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=s):
+        hd.hdof_frame(ctx, sc, cam, None, lens, light, params, frame=0, out=out_g)
+    scratch = torch.empty(3, H, W, device=DEV)
+    for rep in range(3):
+        out_g.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, out_e), rep
+        hd.hdof_frame(ctx, sc, other, None, lens, light, params, frame=rep + 1, out=scratch)
+        torch.cuda.synchronize()
+        assert not torch.equal(scratch, out_e)
+    ctx.sync()
+    del g
     sc.close()
