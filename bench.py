@@ -126,6 +126,18 @@ def main():
     ctx.sync()
     tuning = hdof.hdof_get_tuning(ctx)
 
+    # per-frame times (events around each frame): median, p10, p90
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i, (a, b) in enumerate(evs):
+        a.record(stream)
+        step(i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per_frame = sorted(a.elapsed_time(b) for a, b in evs)
+
+    def pct(q):
+        return round(per_frame[min(len(per_frame) - 1, int(q * len(per_frame)))], 4)
+
     # the same frames on one stream: each kernel alone
     print("[bench] single-stream pass", file=sys.stderr, flush=True)
     hdof.hdof_set_tuning(ctx, **{**tuning, "overlap": 0})
@@ -180,6 +192,7 @@ def main():
                    "focus_m": cfg.lens.focus_distance, "spp_max": cfg.mask.spp_max, "mask_tile": cfg.mask.tile,
                    "pp_taps": cfg.pp.n_taps, "parallelism": "single_gpu"},
         "frame_ms": round(ms_per_step, 4),
+        "frame_ms_p10_p50_p90": [pct(0.1), pct(0.5), pct(0.9)],
         "wall_ms_per_step": round(wall_ms / args.steps, 4),
         "profiled_ms_per_step": round(profiled_ms, 4),
         "traced_rays_per_frame": rays,
@@ -619,15 +632,43 @@ def roofline_for(stage, ms, n_px, rays, per_ray, form):
 
 
 def cpu_baseline(cfg, scene):
-    """The FP64 oracle as it stands on the host cores: one full 1080p frame."""
+    """The FP64 oracle as it stands on the host cores: one full 1080p frame
+    of the living room (the reported value), plus the 64x64 tiny
+    configuration on all threads and on one, and frame 0 of the ~1M-triangle
+    temporal configuration at 1080p."""
     import oracle
+    import scenegen as sg
+    cores = oracle.threads()
     osc = oracle.Scene(scene.verts, scene.albedo)
     t0 = time.perf_counter()
     fr = oracle.frame(osc, cfg)
     sec = time.perf_counter() - t0
-    return {"value": round(1.0 / sec, 4), "unit": "frames/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"one full 1920x1080 frame ({int(fr['mask']['total'])} traced rays), {sec:.2f} s",
-            "frame_ms": round(sec * 1e3, 1)}
+    rays = int(fr["mask"]["total"])
+    res = {"value": round(1.0 / sec, 4), "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "sample": f"one full 1920x1080 frame ({rays} traced rays), {sec:.2f} s",
+           "frame_ms": round(sec * 1e3, 1), "traced_mrays_per_s_incl_frame": round(rays / sec / 1e6, 3)}
+    tiny = sg.tiny_scene(0)
+    tcfg = sg.config_tiny()
+    tsc = oracle.Scene(tiny.verts, tiny.albedo)
+    t_ms = {}
+    for label, n in (("all_cores", cores), ("1_thread", 1)):
+        oracle.set_threads(n)
+        oracle.frame(tsc, tcfg)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            oracle.frame(tsc, tcfg)
+        t_ms[label] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+    oracle.set_threads(cores)
+    res["tiny_64x64"] = {"frame_ms_all_cores": t_ms["all_cores"], "frame_ms_1_thread": t_ms["1_thread"]}
+    big = sg.temporal_scene(1)
+    bcfg = sg.config_temporal()
+    bsc = oracle.Scene(big.verts, big.albedo)
+    t0 = time.perf_counter()
+    fb = oracle.frame(bsc, bcfg)
+    bsec = time.perf_counter() - t0
+    res["temporal_frame0_1080p"] = {"frame_ms": round(bsec * 1e3, 1), "n_tris": big.n_tris,
+                                    "traced_rays": int(fb["mask"]["total"])}
+    return res
 
 
 if __name__ == "__main__":
