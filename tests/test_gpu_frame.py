@@ -98,11 +98,17 @@ def keep_normal_diff(g, gb):
     return g["normal"] - gb["normal"]
 
 
-@pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_320x180"])
+@pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_320x180", "room_1080p"])
 def test_frame_matches_oracle(hd, ctx, which):
+    """room_1080p is the benchmark's workload at its full size, in the launch
+    configuration the benchmark times (default tuning: the gather overlapped
+    with the trace), compared with the oracle's full frame at every pixel."""
     print_case(f"frame {which}")
+    hd.hdof_set_tuning(ctx)
     if which == "room_320x180":
         scene, cfg = sg.living_room_scene(0), sg.config_1080p(320, 180)
+    elif which == "room_1080p":
+        scene, cfg = sg.living_room_scene(0), sg.config_1080p()
     else:
         scene = sg.tiny_scene(0)
         cfg = sg.config_tiny() if which == "tiny" else sg.config_tiny(aperture_override=0.2)
