@@ -51,7 +51,10 @@ __global__ __launch_bounds__(256) void k_pp_pack(const float* __restrict__ color
 // CoC); omega = max(0, 1 + sa (2 |u'|^2 - 1)) is the tap's aberration weight.
 __global__ void k_pp_taps(int n, int blades, double rot, float sa, float4* __restrict__ taps) {
   int k = threadIdx.x + 1;
-  if (k > n) return;
+  if (k > n) {  // the table's unused entries are zero (gathers read whole groups of taps)
+    taps[k - 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   const double pi = 3.14159265358979323846;
   const double g = pi * (3.0 - sqrt(5.0));
   double rr = sqrt((k - 0.5) / n);
@@ -198,12 +201,12 @@ struct StageLane {
   bool last;          // slot 4 holds a footprint texel of its own
 };
 
-// Texels and record of tap j (wave-uniform, < n_taps) for the block at (x0, y0).
+// Texels and record of the tap with table entry u (wave-uniform) for the
+// block at (x0, y0).
 template <bool INTERIOR>
-__device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, const float4* __restrict__ taps, int j,
-                                            float R, int x0, int y0, int W, int H, const StageLane& sl) {
+__device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, const float4 u, float R, int x0,
+                                            int y0, int W, int H, const StageLane& sl) {
   Stage st;
-  const float4 u = taps[j];
   const float ox = R * u.x, oy = R * u.y;
   const float fx = floorf(ox), fy = floorf(oy);
   const float ax = ox - fx, ay = oy - fy, bx = 1.0f - ax, by = 1.0f - ay;
@@ -243,8 +246,9 @@ __device__ __forceinline__ void stage_store(float4* __restrict__ dst, TapRec* __
 }
 
 // The tap loop of one block.  Groups are always full: a wave whose tap of
-// the group lies past n_taps stages tap n_taps - 1 again, and that slot's
-// distance term is -1e30 so its coverage, and with it its weight, is 0.
+// the group lies past n_taps stages the table's zero entry (the footprint
+// at the block's corner), and that slot's distance term is -1e30 so its
+// coverage, and with it its weight, is 0.
 template <bool INTERIOR, bool SA>
 __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], TapRec (*rec)[PPG_G],
                                             const float4* __restrict__ pack, const float4* __restrict__ taps,
@@ -261,30 +265,55 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
   }
   sl.last = lane < PPG_TEX - 4 * 64;
   const int ng = (n_taps + PPG_G - 1) / PPG_G;
+  // The table entries of a group (four taps, 64 contiguous bytes of the
+  // 256-entry table whose unused entries are zero) are read together right
+  // after the group's barrier: the staging wave takes its own tap's offset
+  // from them, the gather the taps' radii |u| and weights.  A scalar load's
+  // wait also drains the LDS reads in flight, so no table read is left
+  // inside the tap loop.
+  // (four named values and value selects: an indexed array would live in
+  // scratch memory)
+  float4 c0 = taps[0], c1 = taps[1], c2 = taps[2], c3 = taps[3];
   {
-    const Stage st = stage_load<INTERIOR>(pack, taps, min(wave, n_taps - 1), R, x0, y0, W, H, sl);
+    const float4 u = wave == 0 ? c0 : wave == 1 ? c1 : wave == 2 ? c2 : c3;
+    const Stage st = stage_load<INTERIOR>(pack, u, R, x0, y0, W, H, sl);
     stage_store(stg[0] + wave * PPG_TAPSZ, &rec[0][wave], st, sl, lane);
   }
-  const float* __restrict__ uz = reinterpret_cast<const float*>(taps) + 2;
   for (int gi = 0; gi < ng; ++gi) {
     __syncthreads();
     const int b = gi & 1;
     const bool more = gi + 1 < ng;
     Stage st;
-    if (more) st = stage_load<INTERIOR>(pack, taps, min((gi + 1) * PPG_G + wave, n_taps - 1), R, x0, y0, W, H, sl);
+    float4 n0, n1, n2, n3;
+    if (more) {
+      const float4* tg = taps + (gi + 1) * PPG_G;
+      n0 = tg[0];
+      n1 = tg[1];
+      n2 = tg[2];
+      n3 = tg[3];
+      const float4 u = wave == 0 ? n0 : wave == 1 ? n1 : wave == 2 ? n2 : n3;
+      st = stage_load<INTERIOR>(pack, u, R, x0, y0, W, H, sl);
+    }
     if (inside) {
       const float4* src = stg[b] + lofs;
+      const float uz[PPG_G] = {c0.z, c1.z, c2.z, c3.z}, uw[PPG_G] = {c0.w, c1.w, c2.w, c3.w};
 #pragma unroll
       for (int jj = 0; jj < PPG_G; ++jj) {
-        const int j = gi * PPG_G + jj;
-        const float d = j < n_taps ? 0.5f - R * uz[4 * j] : -1e30f;
-        const float om = SA ? uz[4 * min(j, n_taps - 1) + 1] : 1.0f;
+        const bool valid = gi * PPG_G + jj < n_taps;
+        const float d = valid ? 0.5f - R * uz[jj] : -1e30f;
+        const float om = SA && valid ? uw[jj] : 1.0f;
         const float4* a = src + jj * PPG_TAPSZ;
         const TapRec t = rec[b][jj];
         g.tap(t.w00, t.w10, t.w01, t.w11, d, a[0], a[1], a[PPG_STRIDE], a[PPG_STRIDE + 1], om);
       }
     }
-    if (more) stage_store(stg[b ^ 1] + wave * PPG_TAPSZ, &rec[b ^ 1][wave], st, sl, lane);
+    if (more) {
+      stage_store(stg[b ^ 1] + wave * PPG_TAPSZ, &rec[b ^ 1][wave], st, sl, lane);
+      c0 = n0;
+      c1 = n1;
+      c2 = n2;
+      c3 = n3;
+    }
   }
 }
 
