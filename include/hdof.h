@@ -480,7 +480,7 @@ void hdof_batch_destroy(hdof_batch* batch);
  * frame (at least one, at most blocks_per_cu; the count is read on the
  * device, the other blocks return at once), so a light trace leaves CUs to
  * the gather and a heavy one keeps them.  Defaults {10, 64, 8, 2, 1,
- * 125000}: ten two-wave blocks per CU is the trace kernel's register-
+ * 150000}: ten two-wave blocks per CU is the trace kernel's register-
  * limited residency (5 waves per SIMD), so every block starts at once. */
 #define HDOF_WAVE_AUTO_TRIS (1 << 19)
 typedef struct {

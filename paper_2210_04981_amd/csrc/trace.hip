@@ -131,7 +131,7 @@ struct Work {
 // Traversal state of one ray between steps.
 struct Trav {
   Best b;
-  unsigned cur;  // internal node to enter next
+  unsigned cur;  // entry to visit next: an internal node, or a leaf code (leaf bit set)
   int sp;        // stack depth
 };
 
@@ -141,73 +141,67 @@ __device__ inline void trav_init(Trav& s) {
   s.sp = 0;
 }
 
-// One step: enter node s.cur, test both child boxes, test leaf children at
-// once, continue into the nearer internal child and push the farther one,
-// or pop.  Returns true when the stack is empty (traversal finished).
+// Per-lane traversal in two kinds of step.  A box step enters the lane's
+// current entry, an internal node: of its two children whose boxes the ray
+// reaches within the closest hit so far, the nearer (internal node or
+// leaf) becomes the entry and the farther is pushed; with neither, the
+// entry is popped.  A leaf step tests the entry's triangles and pops.  The
+// caller takes box steps until the entry is a leaf, so the lanes of a wave
+// test their leaves together; testing a leaf child as soon as it is met
+// costs the whole wave its triangle loop in nearly every box step, since
+// some lane nearly always meets one.
+template <int BLOCK>
+__device__ inline void trav_push(int* __restrict__ stk, int* __restrict__ spill, Trav& s, unsigned code,
+                                 int* __restrict__ flags) {
+  if (s.sp < HDOF_LDS_STACK) {
+    stk[s.sp * BLOCK] = (int)code;
+    ++s.sp;
+  } else if (s.sp < HDOF_LDS_STACK + HDOF_SPILL_STACK) {
+    spill[s.sp - HDOF_LDS_STACK] = (int)code;
+    ++s.sp;
+  } else {
+    atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
+  }
+}
+
+// Pop the next entry; true when the stack is empty (the ray is done).
+template <int BLOCK>
+__device__ inline bool trav_pop(const int* __restrict__ stk, const int* __restrict__ spill, Trav& s) {
+  if (s.sp == 0) return true;
+  --s.sp;
+  s.cur = (unsigned)(s.sp < HDOF_LDS_STACK ? stk[s.sp * BLOCK] : spill[s.sp - HDOF_LDS_STACK]);
+  return false;
+}
+
 template <int BLOCK, bool COUNT>
-__device__ inline bool trav_step(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                 const Ray& r, int* __restrict__ stk, int* __restrict__ spill, Trav& s,
-                                 int* __restrict__ flags, Work& wk) {
+__device__ inline bool box_step(const float4* __restrict__ nodes, const Ray& r, int* __restrict__ stk,
+                                int* __restrict__ spill, Trav& s, int* __restrict__ flags, Work& wk) {
   if (COUNT) wk.visits++;
   const float4* nd = nodes + 4 * (size_t)s.cur;
-  float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+  const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
   float t0, t1;
-  bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, s.b.t, t0);
-  bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, s.b.t, t1);
-  unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
-  if (h0 && (c0 & HDOF_LEAF_BIT)) {
-    test_leaf(r, tris, c0, s.b);
-    if (COUNT) wk.tests += (int)((c0 >> 27) & 0xF) + 1;
-    h0 = false;
-  }
-  if (h1 && (c1 & HDOF_LEAF_BIT)) {
-    test_leaf(r, tris, c1, s.b);
-    if (COUNT) wk.tests += (int)((c1 >> 27) & 0xF) + 1;
-    h1 = false;
-  }
+  const bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, s.b.t, t0);
+  const bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, s.b.t, t1);
+  const unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
   if (h0 && h1) {
-    unsigned nearc = t0 <= t1 ? c0 : c1;
-    unsigned farc = t0 <= t1 ? c1 : c0;
-    if (s.sp < HDOF_LDS_STACK) {
-      stk[s.sp * BLOCK] = (int)farc;
-      ++s.sp;
-    } else if (s.sp < HDOF_LDS_STACK + HDOF_SPILL_STACK) {
-      spill[s.sp - HDOF_LDS_STACK] = (int)farc;
-      ++s.sp;
-    } else {
-      atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
-    }
-    s.cur = nearc;
+    trav_push<BLOCK>(stk, spill, s, t0 <= t1 ? c1 : c0, flags);
+    s.cur = t0 <= t1 ? c0 : c1;
   } else if (h0) {
     s.cur = c0;
   } else if (h1) {
     s.cur = c1;
   } else {
-    if (s.sp == 0) return true;
-    --s.sp;
-    s.cur = (unsigned)(s.sp < HDOF_LDS_STACK ? stk[s.sp * BLOCK] : spill[s.sp - HDOF_LDS_STACK]);
+    return trav_pop<BLOCK>(stk, spill, s);
   }
   return false;
 }
 
-// Whole traversal of one ray.  Each internal node is entered at most once
-// per ray, so more than n_nodes steps means a malformed tree: the ray stops
-// and raises the device flag instead of looping.
 template <int BLOCK, bool COUNT>
-__device__ inline Best traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                int n_nodes, const Ray& r, int* __restrict__ stk, int* __restrict__ flags,
-                                Work& wk) {
-  int spill[HDOF_SPILL_STACK];
-  Trav s;
-  trav_init(s);
-  for (int steps = 0;; ++steps) {
-    if (steps > n_nodes) {
-      atomicOr(flags, HDOF_FLAG_STACK_OVERFLOW);
-      break;
-    }
-    if (trav_step<BLOCK, COUNT>(nodes, tris, r, stk, spill, s, flags, wk)) break;
-  }
-  return s.b;
+__device__ inline bool leaf_step(const float4* __restrict__ tris, const Ray& r, const int* __restrict__ stk,
+                                 const int* __restrict__ spill, Trav& s, Work& wk) {
+  test_leaf(r, tris, s.cur, s.b);
+  if (COUNT) wk.tests += (int)((s.cur >> 27) & 0xF) + 1;
+  return trav_pop<BLOCK>(stk, spill, s);
 }
 
 // Wave-coherent traversal: the lanes of a wave walk one node sequence, the
@@ -577,11 +571,22 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
       if (drained) break;  // nothing left to hand out: an idle lane is done
       continue;
     }
-    bool done = trav_step<HDOF_TRACE_BLOCK, COUNT>(A.nodes, A.tris, r, stk, spill, s, A.flags, wk);
-    if (++steps > A.n_nodes) {
-      atomicOr(A.flags, HDOF_FLAG_STACK_OVERFLOW);
-      done = true;
+    // box steps until the entry is a leaf (each internal node is entered at
+    // most once per ray, so more than n_nodes of them means a malformed tree:
+    // the ray stops and raises the device flag), then the leaf step
+    bool done = false;
+    while (!(s.cur & HDOF_LEAF_BIT)) {
+      if (++steps > A.n_nodes) {
+        atomicOr(A.flags, HDOF_FLAG_STACK_OVERFLOW);
+        done = true;
+        break;
+      }
+      if (box_step<HDOF_TRACE_BLOCK, COUNT>(A.nodes, r, stk, spill, s, A.flags, wk)) {
+        done = true;
+        break;
+      }
     }
+    if (!done) done = leaf_step<HDOF_TRACE_BLOCK, COUNT>(A.tris, r, stk, spill, s, wk);
     if (done) {
       store_ray<COUNT>(A, r, s.b, S1, e, wk);
       active = false;
