@@ -174,6 +174,9 @@ struct TapRec {
 #define PPG_STRIDE 17           // LDS row stride of a staged footprint, in texels
 #endif
 #define PPG_TAPSZ (PPG_SIDE * PPG_STRIDE)
+#ifndef PPG_BUFS
+#define PPG_BUFS 2              // LDS ring: 2 = double-buffered groups, 1 = one group and a second barrier
+#endif
 
 // 16-pixel tiles: one 16x16 block per tile, blocks in XCD-contiguous order;
 // the gather radius R and with it every tap's footprint offset and bilinear
@@ -281,7 +284,7 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
   }
   for (int gi = 0; gi < ng; ++gi) {
     __syncthreads();
-    const int b = gi & 1;
+    const int b = PPG_BUFS == 2 ? gi & 1 : 0;
     const bool more = gi + 1 < ng;
     Stage st;
     float4 n0, n1, n2, n3;
@@ -308,7 +311,9 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
       }
     }
     if (more) {
-      stage_store(stg[b ^ 1] + wave * PPG_TAPSZ, &rec[b ^ 1][wave], st, sl, lane);
+      if (PPG_BUFS == 1) __syncthreads();  // every wave has read the group the next one overwrites
+      stage_store(stg[PPG_BUFS == 2 ? b ^ 1 : 0] + wave * PPG_TAPSZ, &rec[PPG_BUFS == 2 ? b ^ 1 : 0][wave], st, sl,
+                  lane);
       c0 = n0;
       c1 = n1;
       c2 = n2;
@@ -408,8 +413,8 @@ template <int FUSE, bool SA>
 __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ tile_r,
                                                      int K, float r_cap, const float4* __restrict__ taps, int n_taps,
                                                      int W, int H, float inv_ramp, float* __restrict__ out, FuseK fz) {
-  __shared__ float4 stg[2][PPG_G * PPG_TAPSZ];
-  __shared__ TapRec rec[2][PPG_G];
+  __shared__ float4 stg[PPG_BUFS][PPG_G * PPG_TAPSZ];
+  __shared__ TapRec rec[PPG_BUFS][PPG_G];
   __shared__ float wred[4];
   const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
   const int tile = xcd_block(blockIdx.x, TW * TH);
