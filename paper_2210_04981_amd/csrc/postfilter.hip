@@ -204,6 +204,16 @@ struct StageLane {
   bool last;          // slot 4 holds a footprint texel of its own
 };
 
+// word 3 of a raw buffer resource on gfx9 (32-bit data format, no swizzle)
+#define HDOF_BUFFER_WORD3 0x00020000
+
+__device__ __forceinline__ float4 buffer_texel(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, soff, 0);
+  float4 f;
+  __builtin_memcpy(&f, &v, sizeof f);
+  return f;
+}
+
 // Texels and record of the tap with table entry u (wave-uniform) for the
 // block at (x0, y0).
 template <bool INTERIOR>
@@ -220,12 +230,18 @@ __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, con
   const int gx0 = x0 + __builtin_amdgcn_readfirstlane((int)fx);
   const int gy0 = y0 + __builtin_amdgcn_readfirstlane((int)fy);
   if (INTERIOR) {
-    const char* base = reinterpret_cast<const char*>(pack) + (size_t)(gy0 * W + gx0) * 16;
-    st.v0 = *reinterpret_cast<const float4*>(base + sl.so[0]);
-    st.v1 = *reinterpret_cast<const float4*>(base + sl.so[1]);
-    st.v2 = *reinterpret_cast<const float4*>(base + sl.so[2]);
-    st.v3 = *reinterpret_cast<const float4*>(base + sl.so[3]);
-    st.v4 = *reinterpret_cast<const float4*>(base + sl.so[4]);
+    // buffer loads: the footprint corner's byte offset as the scalar
+    // offset, each lane's texel offset as the vector one (no per-lane 64-bit
+    // address arithmetic; the resource spans the image, which interior
+    // blocks require to be under 2 GiB)
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float4*>(pack), (short)0, W * H * 16, HDOF_BUFFER_WORD3);
+    const int corner = __builtin_amdgcn_readfirstlane((gy0 * W + gx0) * 16);
+    st.v0 = buffer_texel(rs, sl.so[0], corner);
+    st.v1 = buffer_texel(rs, sl.so[1], corner);
+    st.v2 = buffer_texel(rs, sl.so[2], corner);
+    st.v3 = buffer_texel(rs, sl.so[3], corner);
+    st.v4 = buffer_texel(rs, sl.so[4], corner);
   } else {
 #define PPG_CLAMPED(s) pack[(size_t)clampi(gy0 + sl.sr[s], 0, H - 1) * W + clampi(gx0 + sl.sc[s], 0, W - 1)]
     st.v0 = PPG_CLAMPED(0);
@@ -274,12 +290,12 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
   // from them, the gather the taps' radii |u| and weights.  A scalar load's
   // wait also drains the LDS reads in flight, so no table read is left
   // inside the tap loop.
-  // (four named values and value selects: an indexed array would live in
-  // scratch memory)
+  // (four named values, and the wave's own entry read by its own scalar
+  // load: an indexed array of them would live in scratch memory, and value
+  // selects among them cost 14 vector instructions per group)
   float4 c0 = taps[0], c1 = taps[1], c2 = taps[2], c3 = taps[3];
   {
-    const float4 u = wave == 0 ? c0 : wave == 1 ? c1 : wave == 2 ? c2 : c3;
-    const Stage st = stage_load<INTERIOR>(pack, u, R, x0, y0, W, H, sl);
+    const Stage st = stage_load<INTERIOR>(pack, taps[wave], R, x0, y0, W, H, sl);
     stage_store(stg[0] + wave * PPG_TAPSZ, &rec[0][wave], st, sl, lane);
   }
   for (int gi = 0; gi < ng; ++gi) {
@@ -294,8 +310,7 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
       n1 = tg[1];
       n2 = tg[2];
       n3 = tg[3];
-      const float4 u = wave == 0 ? n0 : wave == 1 ? n1 : wave == 2 ? n2 : n3;
-      st = stage_load<INTERIOR>(pack, u, R, x0, y0, W, H, sl);
+      st = stage_load<INTERIOR>(pack, tg[wave], R, x0, y0, W, H, sl);
     }
     if (inside) {
       const float4* src = stg[b] + lofs;
@@ -434,7 +449,8 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
     return;
   }
   const int E = (int)ceilf(R);
-  const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H;
+  const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H &&
+                        (long long)W * H * 16 < (1ll << 31);
   const float4 cp4 = inside ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f);
   GatherAcc g;
   g.init(cp4, R, n_taps, inv_ramp);
