@@ -269,8 +269,9 @@ def _mixed_depth(H, W, cell, seed):
 @pytest.mark.parametrize("which", ["tiny_strong", "room_small", "uniform_big_coc", "room_640",
                                    "mixed_radius_t16", "uniform_r30_t16"])
 def test_postfilter_matches_oracle(hd, ctx, which):
-    """Tiles of 16 take the LDS window for ceil(R) <= 23 and direct reads
-    (interior and clamped) beyond; tiles of 8 take the per-lane form."""
+    """Tiles of 16 stage each tap's 17x17 footprint in LDS (interior blocks
+    through buffer loads, border blocks clamped to the edge); tiles of 8
+    take the per-lane form."""
     print_case(f"postfilter {which}")
     if which == "tiny_strong":
         scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.2)
