@@ -4,7 +4,9 @@ A step is one hdof_frame over the 1920x1080 procedural living room (~200k
 triangles, f = 50 mm, f/1.4, focus 2 m, 0-8 spp): G-buffer, ray mask,
 thin-lens trace, variance update, post-filter, composite, with the library's
 default tuning (the post-filter gather on a second stream beside the mask
-and trace).  The scene's BVH is built once before timing (reported
+and trace).  The frames keep only the mask's counts and the ray total (for
+the ray statistics), as a caller after the image alone would; one frame
+keeping every intermediate feeds the adjoint form.  The scene's BVH is built once before timing (reported
 separately).  Inputs are resident in HBM when the timed region starts.
 
 Prints one JSON line (the driver's contract).  `value` / `ms_per_step` come
@@ -83,7 +85,9 @@ def main():
     H, W = cfg.camera.height, cfg.camera.width
     cam, lens, light = hdof.camera_of(cfg.camera), hdof.lens_of(cfg.lens), hdof.light_of(cfg.light)
     params = hdof.frame_params_of(cfg)
-    keep = hdof.FrameKeep.empty(H, W)
+    # the timed frames keep only the mask's counts and ray total (for the
+    # ray statistics), as a caller that wants the image alone would
+    keep = counts_keep(hdof, H, W)
     out = torch.empty(3, H, W, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -210,8 +214,12 @@ def main():
         "paper_context": "143 fps hybrid on GeForce RTX 2080 Ti, The Modern Living Room (context only)",
     }
     if not args.no_forms:
+        # one frame keeping every intermediate: the adjoint's inputs
+        full = hdof.FrameKeep.empty(H, W)
+        hdof.hdof_frame(ctx, sc, cam, None, lens, light, params, seed=cfg.seed, frame=0, view=0, out=out, keep=full,
+                        stream=stream)
         res["forms"] = {"batched": bench_batched(hdof, ctx, sc, ms_per_step),
-                        "backward": bench_backward(hdof, ctx, sc, cfg, keep, ms_per_step),
+                        "backward": bench_backward(hdof, ctx, sc, cfg, full, ms_per_step),
                         "focus_fit": bench_focus_fit(hdof, ctx, sc, cfg, ms_per_step),
                         "temporal": bench_temporal(hdof, ctx),
                         "scaled_mask": bench_scaled_mask(hdof, ctx, sc, cfg, ms_per_step, rays),
@@ -299,7 +307,7 @@ def bench_scaled_mask(hdof, ctx, sc, cfg, plain_ms, plain_rays, steps=50):
     cam, lens, light = hdof.camera_of(cfg.camera), hdof.lens_of(cfg.lens), hdof.light_of(cfg.light)
     params = hdof.frame_params_of(cfg)
     params.mask.tile = 0
-    keep = hdof.FrameKeep.empty(H, W)
+    keep = counts_keep(hdof, H, W)
     out = torch.empty(3, H, W, device="cuda")
 
     def step():
@@ -327,6 +335,15 @@ def bench_scaled_mask(hdof, ctx, sc, cfg, plain_ms, plain_rays, steps=50):
             "tile_in_force": tile, "frame_ms": round(ms, 4), "frame_ms_fixed_tile_8": round(plain_ms, 4),
             "traced_rays": rays, "traced_rays_fixed_tile_8": plain_rays,
             "ray_mask_ms": round(stage["ray_mask"], 4), "trace_ms": round(stage["trace"], 4)}
+
+
+def counts_keep(hdof, H, W):
+    """Kept planes of a frame for its ray statistics only: the mask's
+    per-pixel counts, their offsets and the ray total."""
+    import torch
+    return hdof.FrameKeep(spp=torch.empty(H, W, dtype=torch.uint8, device="cuda"),
+                          offsets=torch.empty(H, W, dtype=torch.int32, device="cuda"),
+                          total=torch.empty(1, dtype=torch.int32, device="cuda"))
 
 
 def _time_ms(fn, reps, stream):
@@ -512,7 +529,7 @@ def bench_temporal(hdof, ctx, frames=60):
     cams = [hdof.camera_of(sg.temporal_camera(t, W, H)) for t in range(frames)]
     lens, light = hdof.lens_of(cfg.lens), hdof.light_of(cfg.light)
     params = hdof.frame_params_of(cfg)
-    keep = hdof.FrameKeep.empty(H, W)
+    keep = counts_keep(hdof, H, W)
     out = torch.empty(3, H, W, device="cuda")
     totals = torch.zeros(frames, dtype=torch.int32, device="cuda")
 

@@ -736,6 +736,10 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   // (variance stage empty)
   VarFuse vf;
   if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf);
+  // only the composite reads the trace planes, and only at traced pixels,
+  // unless the caller keeps them or a reconstruction stage reads them
+  vf.sparse_rt = !u.rt.c_near && !u.rt.c_far && !u.rt.hit_ratio && !u.rt.lum_m1 && !u.rt.lum_m2 &&
+                 !params->recon.enable && !spatial;
   if (s == HDOF_OK) {
     // beside the gather the trace keeps blocks in proportion to its rays
     ctx->trace_ray_quantum = ovl ? ctx->tune.overlap_ray_quantum : 0;

@@ -327,6 +327,10 @@ struct VarFuse {
   float *m1, *m2;
   uint8_t* fl;
   float* hz;
+  // untraced pixels leave the trace planes (near, far, hit ratio, luminance
+  // moments) unwritten: a frame whose caller keeps none of them and whose
+  // later stages read them only where the pixel was traced
+  int sparse_rt;
 };
 // checks the frame's reprojection, reserves the history and marks it
 // written (as launch_var_update does before its launch)

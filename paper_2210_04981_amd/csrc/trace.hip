@@ -701,16 +701,18 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   }
   const float in_ = Nw > 0.f ? 1.0f / Nw : 0.f, if_ = Fw > 0.f ? 1.0f / Fw : 0.f;
   const float is = Sw > 0.f ? 1.0f / Sw : 0.f;
-  cn[p] = snr * in_;
-  cn[N + p] = sng * in_;
-  cn[2 * (size_t)N + p] = snb * in_;
-  cf[p] = sfr * if_;
-  cf[N + p] = sfg * if_;
-  cf[2 * (size_t)N + p] = sfb * if_;
   const float ybar = sy * is, y2bar = sy2 * is;
-  h[p] = Nw * is;
-  m1[p] = ybar;
-  m2[p] = y2bar;
+  if (!(VAR && vf.sparse_rt) || spp[p] > 0) {
+    cn[p] = snr * in_;
+    cn[N + p] = sng * in_;
+    cn[2 * (size_t)N + p] = snb * in_;
+    cf[p] = sfr * if_;
+    cf[N + p] = sfg * if_;
+    cf[2 * (size_t)N + p] = sfb * if_;
+    h[p] = Nw * is;
+    m1[p] = ybar;
+    m2[p] = y2bar;
+  }
   if (VAR) {
     float a1 = vf.rm1[p], a2 = vf.rm2[p];
     uint8_t f = vf.rfl[p];

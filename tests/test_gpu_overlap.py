@@ -190,3 +190,35 @@ def test_overlapped_frame_in_a_graph(hd, ctx):
     ctx.sync()
     del g
     sc.close()
+
+
+@pytest.mark.parametrize("overlap", [1, 0])
+def test_frame_without_kept_planes(hd, ctx, overlap):
+    """Without kept trace planes (and no reconstruction) the reduction
+    writes the trace planes only at traced pixels; the frame's output and
+    its variance history are the same as with every plane kept, over frames
+    that carry the history."""
+    print_case(f"frame without kept planes, overlap {overlap}")
+    W, H = 320, 180
+    cfg = sg.config_1080p(W, H)
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    params = hd.frame_params_of(cfg)
+    lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    cams = [hd.camera_of(sg.temporal_camera(t, W, H)) for t in range(3)]
+    hd.hdof_set_tuning(ctx, overlap=overlap)
+    outs = {}
+    for kept in (True, False):
+        hd.hdof_history_reset(ctx)
+        res = []
+        for t, cam in enumerate(cams):
+            out = torch.empty(3, H, W, device=DEV)
+            k = hd.FrameKeep.empty(H, W) if kept else None
+            hd.hdof_frame(ctx, sc, cam, cams[t - 1] if t else None, lens, light, params, frame=t, out=out, keep=k)
+            res.append(out)
+        torch.cuda.synchronize()
+        ctx.sync()
+        outs[kept] = res
+    for t in range(len(cams)):
+        assert torch.equal(outs[True][t], outs[False][t]), t
+    hd.hdof_set_tuning(ctx)
+    sc.close()
