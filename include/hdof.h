@@ -476,11 +476,11 @@ void hdof_batch_destroy(hdof_batch* batch);
  * context beside the mask, trace and reconstruction (it needs only the
  * G-buffer) and applies the composite once both are done, the results
  * being the same as with 0; overlap_ray_quantum >= 1: while overlapped, the
- * trace keeps one block per CU for every overlap_ray_quantum rays of the
- * frame (at least one, at most blocks_per_cu; the count is read on the
- * device, the other blocks return at once), so a light trace leaves CUs to
- * the gather and a heavy one keeps them.  Defaults {10, 64, 8, 2, 1,
- * 150000}: ten two-wave blocks per CU is the trace kernel's register-
+ * trace keeps, on average, one block per CU for every overlap_ray_quantum
+ * rays of the frame (at least one per CU, at most blocks_per_cu; the count
+ * is read on the device, the other blocks return at once), so a light
+ * trace leaves CUs to the gather and a heavy one keeps them.  Defaults {10, 64, 8, 2, 1,
+ * 140000}: ten two-wave blocks per CU is the trace kernel's register-
  * limited residency (5 waves per SIMD), so every block starts at once. */
 #define HDOF_WAVE_AUTO_TRIS (1 << 19)
 typedef struct {

@@ -504,13 +504,14 @@ __device__ inline void store_ray(const TraceArgs& A, const Ray& r, const Best& b
 
 // Whether this block of the persistent trace takes part: with a ray
 // quantum (a frame overlapping the trace with the post-filter gather) only
-// ceil(total / ray_quantum) blocks per CU, at least one and at most the
-// grid's, so a light trace leaves the CUs to the gather; the first blocks
+// the first ceil(total * n_cu / ray_quantum) blocks, one block per CU for
+// every ray_quantum rays on average (at least one per CU, at most the
+// grid), so a light trace leaves the CUs to the gather; the first blocks
 // are kept, so every queue segment keeps its blocks.
 __device__ inline bool keep_block(const TraceArgs& A, int total) {
   if (A.ray_quantum <= 0) return true;
-  const long per_cu = min((long)A.bpc, max(1L, ((long)total + A.ray_quantum - 1) / A.ray_quantum));
-  return (long)blockIdx.x < per_cu * A.n_cu;
+  const long kept = ((long)total * A.n_cu + A.ray_quantum - 1) / A.ray_quantum;
+  return (long)blockIdx.x < min((long)A.bpc * A.n_cu, max((long)A.n_cu, kept));
 }
 
 // Entries handed out: per queue segment (one per XCD, the block's

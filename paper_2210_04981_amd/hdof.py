@@ -685,7 +685,7 @@ class Batch:
 
 
 def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8, wave=2, overlap=1,
-                    overlap_ray_quantum=150000) -> None:
+                    overlap_ray_quantum=140000) -> None:
     t = Tuning(int(blocks_per_cu), int(refill), int(segments), int(wave), int(overlap), int(overlap_ray_quantum))
     _check(_lib.hdof_set_tuning(ctx.handle, C.byref(t)), "hdof_set_tuning")
 

@@ -87,7 +87,7 @@ def test_overlapped_frame_equals_single_stream(hd, ctx, tile, spec_y):
     cams = [hd.camera_of(cfg.camera)]
     lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
     ref = _run(hd, ctx, sc, cfg, params, cams, lens, light, spec_y, 0)
-    for ovl in (150000, 1, 10 ** 9, 20000):  # default, all blocks, one per CU, in between
+    for ovl in (140000, 1, 10 ** 9, 20000):  # default, all blocks, one per CU, in between
         _same(hd, ctx, cfg, params, lens, ref, _run(hd, ctx, sc, cfg, params, cams, lens, light, spec_y, ovl), ovl)
     assert (ref[0][0] - ref[0][1].gb.color).abs().max().item() > 0.05  # depth of field changed the image
     sc.close()
@@ -107,7 +107,7 @@ def test_overlapped_frame_with_reconstruction(hd, ctx):
     cams = [hd.camera_of(sg.temporal_camera(t, W, H)) for t in range(4)]
     lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
     ref = _run(hd, ctx, sc, cfg, params, cams, lens, light, 0.0, 0)
-    b = _run(hd, ctx, sc, cfg, params, cams, lens, light, 0.0, 150000)
+    b = _run(hd, ctx, sc, cfg, params, cams, lens, light, 0.0, 140000)
     for t, ((oa, ka), (ob, kb)) in enumerate(zip(ref, b)):
         for name in ("c_near", "c_far", "hit_ratio"):
             assert torch.equal(getattr(ka.rt, name), getattr(kb.rt, name)), (t, name)
