@@ -660,7 +660,8 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   int s = spp[p];
   float Nw = 0.f, Fw = 0.f, snr = 0.f, sng = 0.f, snb = 0.f, sfr = 0.f, sfg = 0.f, sfb = 0.f, sy = 0.f, sy2 = 0.f;
   float Pw = 0.f, spx_ = 0.f, spy_ = 0.f, spz_ = 0.f, scn = 0.f, scf = 0.f;
-  long o = (long)offsets[p] + (ebase ? *ebase : 0);
+  // untraced pixels (most of them) do not read their offset
+  const long o = s > 0 ? (long)offsets[p] + (ebase ? *ebase : 0) : 0;
   if (o < 0 || o + s > (long)cap) s = 0;  // inconsistent offsets: nothing was traced here
   // spherical aberration: every ray weighs its lens sample's weight (the
   // sample regenerated from its counters); 1 for sa = 0
