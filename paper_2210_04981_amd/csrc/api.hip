@@ -216,7 +216,7 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->mask_tile_dil, &ctx->mask_xpref, &ctx->mask_rowsum, &ctx->mask_ybase, &ctx->mask_auto,
                 &ctx->pp_pack, &ctx->pp_tile, &ctx->pp_rad, &ctx->pp_taps, &ctx->hist_m1,
                 &ctx->hist_m2, &ctx->hist_flags, &ctx->hist_z, &ctx->rep_m1, &ctx->rep_m2,
-                &ctx->rep_flags, &ctx->f_depth, &ctx->f_normal, &ctx->f_albedo, &ctx->f_color,
+                &ctx->rep_flags, &ctx->rep_z, &ctx->f_depth, &ctx->f_normal, &ctx->f_albedo, &ctx->f_color,
                 &ctx->f_triid, &ctx->f_spp, &ctx->f_offsets, &ctx->f_total, &ctx->f_cn, &ctx->f_cf,
                 &ctx->f_h, &ctx->f_m1, &ctx->f_m2, &ctx->f_pp, &ctx->f_spec, &ctx->f_pps, &ctx->rec_hist[0], &ctx->rec_hist[1],
                 &ctx->rec_valid[0], &ctx->rec_valid[1], &ctx->rec_farpos, &ctx->sp_levels, &ctx->sp_taps,
@@ -735,7 +735,7 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   // the trace's per-pixel reduction also updates the variance history
   // (variance stage empty)
   VarFuse vf;
-  if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf);
+  if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf, true);
   // only the composite reads the trace planes, and only at traced pixels,
   // unless the caller keeps them or a reconstruction stage reads them
   vf.sparse_rt = !u.rt.c_near && !u.rt.c_far && !u.rt.hit_ratio && !u.rt.lum_m1 && !u.rt.lum_m2 &&
@@ -746,6 +746,8 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
     s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt_tr,
                      nullptr, nullptr, far_pos, st, &vf, true, coc_nf);  // marks 3, 4
     ctx->trace_ray_quantum = 0;
+    // the reduction updated the history in the reprojected planes
+    if (s == HDOF_OK) history_swap(ctx);
   }
   if (params->recon.enable || spatial) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
   if (s == HDOF_OK && params->recon.enable)
@@ -981,6 +983,7 @@ static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params,
   TRY(hdof_ensure(ctx->rep_m1, sizeof(float) * L.max_px));
   TRY(hdof_ensure(ctx->rep_m2, sizeof(float) * L.max_px));
   TRY(hdof_ensure(ctx->rep_flags, L.max_px));
+  TRY(hdof_ensure(ctx->rep_z, sizeof(float) * L.max_px));
   const int pt = params->pp.tile;
   const size_t ptiles = (size_t)((L.max_w + pt - 1) / pt + 1) * (size_t)((L.max_h + pt - 1) / pt + 1);
   TRY(hdof_ensure(ctx->pp_pack, 16 * (size_t)L.max_px));

@@ -83,7 +83,7 @@ struct hdof_ctx {
   Buf hist_m1, hist_m2, hist_flags, hist_z;
   int rep_w = 0, rep_h = 0;
   bool rep_valid = false;
-  Buf rep_m1, rep_m2, rep_flags;
+  Buf rep_m1, rep_m2, rep_flags, rep_z;
   // temporal reconstruction of the traced colours: ping-pong history of
   // 9 planes (premultiplied near rgb, near hit ratio, premultiplied far rgb,
   // far-path hit ratio, depth) + valid bytes, and the frame's far positions
@@ -331,10 +331,18 @@ struct VarFuse {
   // moments) unwritten: a frame whose caller keeps none of them and whose
   // later stages read them only where the pixel was traced
   int sparse_rt;
+  // the history is updated in the reprojected planes themselves (m1, m2, fl
+  // are rm1, rm2, rfl): traced pixels only, the depth already there; the
+  // frame then swaps the reprojected and the history planes
+  int in_place;
 };
 // checks the frame's reprojection, reserves the history and marks it
 // written (as launch_var_update does before its launch)
-hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const float* depth, VarFuse* vf);
+hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const float* depth, VarFuse* vf,
+                               bool in_place = false);
+// the frame's in-place history update: the reprojected planes become the
+// history (after the reduction that updated them is enqueued)
+void history_swap(hdof_ctx* ctx);
 hdof_status launch_trace(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                          const LightK& li, int spp_max, const uint8_t* spp, const int32_t* offsets,
                          const int32_t* total, uint32_t seed, uint32_t frame, uint32_t view,

@@ -15,6 +15,8 @@
 // maximum R and picks the tile edge (4 below 16 px, 8 below 32 px, else
 // 16: about R / 2), and the later passes read it from device memory, so the
 // choice never reaches the host.
+#include <utility>
+
 #include "hdof_internal.h"
 
 #define MT 16          // pixels per block edge
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
                                                     const float* __restrict__ normal, CamK k, MaskK mk,
                                                     HistIn hi, float* __restrict__ rep_m1,
                                                     float* __restrict__ rep_m2,
-                                                    uint8_t* __restrict__ rep_flags,
+                                                    uint8_t* __restrict__ rep_flags, float* __restrict__ rep_z,
                                                     int* __restrict__ tile_max, MaskAuto au) {
   // (depth, nx, ny, nz) of one pixel per float4; all extents compile-time
   constexpr int AP = GR + 1, NIN = MT + 2 * AP;
@@ -176,6 +178,7 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
     rep_m1[p] = a1;
     rep_m2[p] = a2;
     rep_flags[p] = fl;
+    rep_z[p] = depth[p];  // the history depth, should these planes become the history
     float m = fmaxf(gz * mk.inv_tz, fmaxf(gn * mk.inv_tn, V * mk.inv_tv));
     if (m >= 1.0f) s_raw = (int)ceilf(fminf(m, (float)mk.spp_max));
     if (mk.tile == 0) rc = 0.5f * fabsf(mk.coc_scale * (mk.inv_s1 - 1.0f / depth[p]));
@@ -409,6 +412,7 @@ hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp
   if ((s = hdof_ensure(ctx->mask_auto, sizeof(float) * (blocks + 1))) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->rep_m1, sizeof(float) * N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->rep_m2, sizeof(float) * N)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->rep_z, sizeof(float) * N)) != HDOF_OK) return s;
   return hdof_ensure(ctx->rep_flags, N);
 }
 
@@ -469,10 +473,11 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
     float* r1 = (float*)ctx->rep_m1.p;
     float* r2 = (float*)ctx->rep_m2.p;
     uint8_t* rf = (uint8_t*)ctx->rep_flags.p;
+    float* rz = (float*)ctx->rep_z.p;
     int* tm = (int*)ctx->mask_tile.p;
     switch (gr) {
 #define CASE(R) \
-  case R: hipLaunchKernelGGL(k_mask_score<R>, g, b, 0, st, depth, normal, k, mk, hi, r1, r2, rf, tm, au); break;
+  case R: hipLaunchKernelGGL(k_mask_score<R>, g, b, 0, st, depth, normal, k, mk, hi, r1, r2, rf, rz, tm, au); break;
       CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
 #undef CASE
       default: return hdof_set_error(HDOF_ERR_INVALID_ARG, "Gaussian radius %d above %d", gr, MAX_GR);
@@ -496,12 +501,20 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   return HDOF_OK;
 }
 
-hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const float* depth, VarFuse* vf) {
+hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const float* depth, VarFuse* vf,
+                               bool in_place) {
   const size_t N = (size_t)k.W * k.H;
   hdof_status s;
   if (!ctx->rep_valid || ctx->rep_w != k.W || ctx->rep_h != k.H)
     return hdof_set_error(HDOF_ERR_INVALID_ARG,
                           "variance update without a ray mask of the same frame size");
+  if (in_place) {
+    float* r1 = (float*)ctx->rep_m1.p;
+    float* r2 = (float*)ctx->rep_m2.p;
+    uint8_t* rf = (uint8_t*)ctx->rep_flags.p;
+    *vf = VarFuse{alpha, depth, r1, r2, rf, r1, r2, rf, (float*)ctx->rep_z.p, 0, 1};
+    return HDOF_OK;
+  }
   if ((s = hdof_ensure(ctx->hist_m1, sizeof(float) * N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->hist_m2, sizeof(float) * N)) != HDOF_OK) return s;
   if ((s = hdof_ensure(ctx->hist_flags, N)) != HDOF_OK) return s;
@@ -513,6 +526,17 @@ hdof_status var_update_prepare(hdof_ctx* ctx, const CamK& k, float alpha, const 
   ctx->hist_h = k.H;
   ctx->hist_any = true;
   return HDOF_OK;
+}
+
+void history_swap(hdof_ctx* ctx) {
+  std::swap(ctx->hist_m1, ctx->rep_m1);
+  std::swap(ctx->hist_m2, ctx->rep_m2);
+  std::swap(ctx->hist_flags, ctx->rep_flags);
+  std::swap(ctx->hist_z, ctx->rep_z);
+  ctx->hist_w = ctx->rep_w;
+  ctx->hist_h = ctx->rep_h;
+  ctx->hist_any = true;
+  ctx->rep_valid = false;  // these planes now hold the old history, no reprojection
 }
 
 hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,

@@ -715,7 +715,7 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
     m1[p] = ybar;
     m2[p] = y2bar;
   }
-  if (VAR) {
+  if (VAR && !(vf.in_place && spp[p] == 0)) {  // in place: an untraced pixel's history is already there
     float a1 = vf.rm1[p], a2 = vf.rm2[p];
     uint8_t f = vf.rfl[p];
     if (spp[p] > 0) {
@@ -732,7 +732,7 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
     vf.m1[p] = a1;
     vf.m2[p] = a2;
     vf.fl[p] = f;
-    vf.hz[p] = vf.depth[p];
+    if (!vf.in_place) vf.hz[p] = vf.depth[p];
   }
   if (FARPOS) {
     const float ip = Pw > 0.f ? 1.0f / Pw : 0.f;
