@@ -75,6 +75,23 @@ __device__ inline bool box_hit(const Ray& r, float lox, float hix, float loy, fl
   return tmin <= tmx * 1.0000004f;
 }
 
+// The same test when the signs of the ray's direction are known: (nx, ny,
+// nz) are the box's planes the ray enters through and (fx, fy, fz) those it
+// leaves through, so the per-axis min and max of box_hit are decided in
+// advance.  For a box with lo <= hi on every axis the entry and exit
+// distances equal box_hit's bit for bit (an fma with a fixed multiplier and
+// addend is monotonic in its first operand).
+__device__ inline bool box_hit_signed(const Ray& r, float nx, float fx, float ny, float fy, float nz, float fz,
+                                      float tmax, float& tnear) {
+  const float tx0 = fmaf(nx, r.inv.x, r.oinv.x), tx1 = fmaf(fx, r.inv.x, r.oinv.x);
+  const float ty0 = fmaf(ny, r.inv.y, r.oinv.y), ty1 = fmaf(fy, r.inv.y, r.oinv.y);
+  const float tz0 = fmaf(nz, r.inv.z, r.oinv.z), tz1 = fmaf(fz, r.inv.z, r.oinv.z);
+  const float tmin = fmaxf(fmaxf(tx0, ty0), fmaxf(tz0, 0.0f));
+  const float tmx = fminf(fminf(tx1, ty1), fminf(tz1, tmax));
+  tnear = tmin;
+  return tmin <= tmx * 1.0000004f;
+}
+
 struct Best {
   float t;
   int tri;   // leaf-order index, -1 = none
@@ -214,10 +231,18 @@ __device__ inline bool leaf_step(const float4* __restrict__ tris, const Ray& r, 
 // children the one the wave's first lane reaches first is entered first.
 // Each node is entered at most once per wave, so more than n_nodes steps
 // raises the device flag and stops.
-template <bool COUNT>
+// FLIP >= 0: every live lane's direction has the signs FLIP gives (bit k
+// set: axis k negative), so each slab's entry and exit planes are known at
+// compile time (one copy of the loop per sign octant) and the box test
+// needs no per-lane min and max of the two slab distances.  FLIP < 0: the
+// general test.
+template <bool COUNT, int FLIP>
 __device__ inline Best traverse_wave(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                      int n_nodes, const Ray& r, bool live, int* __restrict__ flags, Work& wk) {
-  Best b = Best{INFINITY, -1, 0x7fffffff};
+  // a lane without a ray starts with a negative closest-hit distance: every
+  // box test then fails for it (entry distances are >= 0), so its results
+  // need no masking
+  Best b = Best{live ? INFINITY : -1.0f, -1, 0x7fffffff};
   const int lane = (int)(threadIdx.x & 63);
   int stackv = 0;  // entry i in lane i
   int sp = 0;
@@ -231,10 +256,19 @@ __device__ inline Best traverse_wave(const float4* __restrict__ nodes, const flo
     const float4* nd = nodes + 4 * (size_t)cur;
     const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
     float t0, t1;
-    const bool h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0) & live;
-    const bool h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1) & live;
+    bool h0, h1;
+    if (FLIP >= 0) {
+      constexpr bool fx = (FLIP & 1) != 0, fy = (FLIP & 2) != 0, fz = (FLIP & 4) != 0;
+      h0 = box_hit_signed(r, fx ? n0.y : n0.x, fx ? n0.x : n0.y, fy ? n0.w : n0.z, fy ? n0.z : n0.w,
+                          fz ? n2.y : n2.x, fz ? n2.x : n2.y, b.t, t0);
+      h1 = box_hit_signed(r, fx ? n1.y : n1.x, fx ? n1.x : n1.y, fy ? n1.w : n1.z, fy ? n1.z : n1.w,
+                          fz ? n2.w : n2.z, fz ? n2.z : n2.w, b.t, t1);
+    } else {
+      h0 = box_hit(r, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, b.t, t0);
+      h1 = box_hit(r, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, b.t, t1);
+    }
     const unsigned c0 = __float_as_uint(n3.x), c1 = __float_as_uint(n3.y);
-    const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
+    const unsigned long long m0 = __builtin_amdgcn_ballot_w64(h0), m1 = __builtin_amdgcn_ballot_w64(h1);
     const bool l0 = (c0 & HDOF_LEAF_BIT) != 0, l1 = (c1 & HDOF_LEAF_BIT) != 0;
     if (l0 && m0 != 0ull) {
       if (h0) {
@@ -270,6 +304,31 @@ __device__ inline Best traverse_wave(const float4* __restrict__ nodes, const flo
     }
   }
   return b;
+}
+
+// The wave's traversal: the signed form when the live lanes' directions
+// share their signs on every axis (nearly every wave of pixel-adjacent
+// rays), else the general one.  Both return the same closest hit.
+template <bool COUNT>
+__device__ inline Best traverse_wave_any(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                         int n_nodes, const Ray& r, bool live, int* __restrict__ flags, Work& wk) {
+  const unsigned long long lm = __ballot(live);
+  const unsigned long long sx = __ballot(live && signbit(r.inv.x)), sy = __ballot(live && signbit(r.inv.y)),
+                           sz = __ballot(live && signbit(r.inv.z));
+  if ((sx == 0ull || sx == lm) && (sy == 0ull || sy == lm) && (sz == 0ull || sz == lm)) {
+    const int flip = (sx != 0ull ? 1 : 0) | (sy != 0ull ? 2 : 0) | (sz != 0ull ? 4 : 0);
+    switch (flip) {
+      case 0: return traverse_wave<COUNT, 0>(nodes, tris, n_nodes, r, live, flags, wk);
+      case 1: return traverse_wave<COUNT, 1>(nodes, tris, n_nodes, r, live, flags, wk);
+      case 2: return traverse_wave<COUNT, 2>(nodes, tris, n_nodes, r, live, flags, wk);
+      case 3: return traverse_wave<COUNT, 3>(nodes, tris, n_nodes, r, live, flags, wk);
+      case 4: return traverse_wave<COUNT, 4>(nodes, tris, n_nodes, r, live, flags, wk);
+      case 5: return traverse_wave<COUNT, 5>(nodes, tris, n_nodes, r, live, flags, wk);
+      case 6: return traverse_wave<COUNT, 6>(nodes, tris, n_nodes, r, live, flags, wk);
+      default: return traverse_wave<COUNT, 7>(nodes, tris, n_nodes, r, live, flags, wk);
+    }
+  }
+  return traverse_wave<COUNT, -1>(nodes, tris, n_nodes, r, live, flags, wk);
 }
 
 // Two-sided Lambertian face normal + point light, no shadow ray; with a
@@ -338,7 +397,7 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
   V3 v = pixel_dir(k, live ? x : 0, live ? y : 0);
   Ray r = make_ray(k.e, V3{l.S1 * v.x, l.S1 * v.y, l.S1 * v.z});
   Work wk{0, 0};
-  Best b = traverse_wave<COUNT>(nodes, tris, n_nodes, r, live, flags, wk);
+  Best b = traverse_wave_any<COUNT>(nodes, tris, n_nodes, r, live, flags, wk);
   float rr = 0.0f;
   if (live) {
     if (COUNT) {
@@ -598,7 +657,7 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
 // Wave-coherent form: a wave takes 64 consecutive entries of its segment at
 // a time (the samples of a few neighbouring pixels, whose rays differ by
 // their lens offsets) and walks the union of their paths with wave-uniform
-// node loads (traverse_wave), then shades and stores them; no per-lane
+// node loads (traverse_wave_any), then shades and stores them; no per-lane
 // refill and no LDS stack.  Same hand-out of entries as k_trace, so the
 // same results.
 template <bool COUNT, bool BATCH>
@@ -634,7 +693,7 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
     const bool live = entry_ray<BATCH>(A, pxb, e, hi, r, S1);
     if (!live) r = make_ray(V3{0.0f, 0.0f, 0.0f}, V3{0.0f, 0.0f, 1.0f});
     Work wk{0, 0};
-    const Best b = traverse_wave<COUNT>(A.nodes, A.tris, A.n_nodes, r, live, A.flags, wk);
+    const Best b = traverse_wave_any<COUNT>(A.nodes, A.tris, A.n_nodes, r, live, A.flags, wk);
     if (live) store_ray<COUNT>(A, r, b, S1, e, wk);
   }
 }
