@@ -5,9 +5,11 @@
 //   CoC radius.
 // k_pp_dilate: gather radius per tile = min(r_cap, max radius over the tiles
 //   within ceil(r_cap / tile) tiles).
-// k_pp_gather16 / k_pp_gather_any: golden-angle taps, four float4 texels per
-//   tap (16-pixel tiles: staged per tap group in LDS), weights recomputed per
-//   tap, nothing stored but the result.
+// k_pp_gather16q / k_pp_gather16 / k_pp_gather_any: golden-angle taps,
+//   bilinear float4 texels, weights recomputed per tap, nothing stored but
+//   the result.  16-pixel tiles stage each tap's footprint in LDS: one wave
+//   per tile gathering 2x2 pixel quads (k_pp_gather16q), or, beside the
+//   trace in the overlapped frame, four waves per tile (k_pp_gather16).
 // k_composite: focus zone / near / far rules, one pass over the pixels.
 #include "hdof_internal.h"
 
@@ -112,7 +114,10 @@ __global__ void k_pp_dilate(const float* __restrict__ tile_r, int TW, int TH, in
 struct GatherAcc {
   float ap, ncpr, inv_ramp;  // |c_p|, -c_p / ramp, 1 / ramp
   float ar, ag, ab, ws;
+  // (no implicit contraction of a product into a sum here or in tap(): the
+  // gather's forms inline these into different code and must round alike)
   __device__ __forceinline__ void init(const float4& cp4, float R, int n_taps, float inv_ramp_) {
+#pragma clang fp contract(off)
     inv_ramp = inv_ramp_;
     ap = fabsf(cp4.w);
     ncpr = -cp4.w * inv_ramp;
@@ -128,6 +133,7 @@ struct GatherAcc {
   // om: the tap's aberration weight (1: the disk's uniform weights)
   __device__ __forceinline__ void tap(float w00, float w10, float w01, float w11, float d, const float4& v00,
                                       const float4& v10, const float4& v01, const float4& v11, float om = 1.0f) {
+#pragma clang fp contract(off)
     const float sr = fmaf(w11, v11.x, fmaf(w01, v01.x, fmaf(w10, v10.x, w00 * v00.x)));
     const float sg = fmaf(w11, v11.y, fmaf(w01, v01.y, fmaf(w10, v10.y, w00 * v00.y)));
     const float sb = fmaf(w11, v11.z, fmaf(w01, v01.z, fmaf(w10, v10.z, w00 * v00.z)));
@@ -219,6 +225,7 @@ __device__ __forceinline__ float4 buffer_texel(__amdgpu_buffer_rsrc_t rs, unsign
 template <bool INTERIOR>
 __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, const float4 u, float R, int x0,
                                             int y0, int W, int H, const StageLane& sl) {
+#pragma clang fp contract(off)
   Stage st;
   const float ox = R * u.x, oy = R * u.y;
   const float fx = floorf(ox), fy = floorf(oy);
@@ -254,13 +261,17 @@ __device__ __forceinline__ Stage stage_load(const float4* __restrict__ pack, con
   return st;
 }
 
-__device__ __forceinline__ void stage_store(float4* __restrict__ dst, TapRec* __restrict__ rdst, const Stage& st,
-                                            const StageLane& sl, int lane) {
+__device__ __forceinline__ void stage_store_texels(float4* __restrict__ dst, const Stage& st, const StageLane& sl) {
   dst[sl.lo[0]] = st.v0;
   dst[sl.lo[1]] = st.v1;
   dst[sl.lo[2]] = st.v2;
   dst[sl.lo[3]] = st.v3;
   if (sl.last) dst[sl.lo[4]] = st.v4;
+}
+
+__device__ __forceinline__ void stage_store(float4* __restrict__ dst, TapRec* __restrict__ rdst, const Stage& st,
+                                            const StageLane& sl, int lane) {
+  stage_store_texels(dst, st, sl);
   if (lane == 0) *rdst = st.tr;
 }
 
@@ -318,7 +329,7 @@ __device__ __forceinline__ void gather_taps(float4 (*stg)[PPG_G * PPG_TAPSZ], Ta
 #pragma unroll
       for (int jj = 0; jj < PPG_G; ++jj) {
         const bool valid = gi * PPG_G + jj < n_taps;
-        const float d = valid ? 0.5f - R * uz[jj] : -1e30f;
+        const float d = valid ? fmaf(-R, uz[jj], 0.5f) : -1e30f;
         const float om = SA && valid ? uw[jj] : 1.0f;
         const float4* a = src + jj * PPG_TAPSZ;
         const TapRec t = rec[b][jj];
@@ -462,6 +473,149 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   if (inside) {
     const float iw = 1.0f / g.ws;
     pp_emit<FUSE>(out, fz, N, p, cp4, g.ar * iw, g.ag * iw, g.ab * iw);
+  }
+}
+
+// The gather radius of tile (tx, ty) reduced by one wave (uniform result).
+__device__ __forceinline__ float wave_dilated_radius(const float* __restrict__ tile_r, int TW, int TH, int tx,
+                                                     int ty, int K, float r_cap) {
+  const int D = 2 * K + 1, lane = threadIdx.x & 63;
+  float m = 0.0f;
+  for (int i = lane; i < D * D; i += 64) {
+    const int yy = ty - K + i / D, xx = tx - K + i % D;
+    if (yy >= 0 && yy < TH && xx >= 0 && xx < TW) m = fmaxf(m, tile_r[yy * TW + xx]);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  return fminf(r_cap, m);
+}
+
+// Orders a wave's LDS stores before its later LDS loads (and its earlier
+// loads before its later stores) across lanes: every LDS access in flight
+// completes and the compiler moves none across.  No other wave takes part.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The tap loop of one wave whose lanes gather 2x2 pixel quads of one tile;
+// per tap a lane reads the 3x3 staged texels its four bilinear footprints
+// cover.  Software-pipelined over a two-buffer LDS ring: iteration t stores
+// tap t + 1's texels (loaded during iteration t - 1, so a whole gather has
+// covered their latency), issues tap t + 2's loads, and gathers tap t.
+// Table entries are read two taps ahead; past the last tap the last one is
+// staged again (unused), so nothing is carried on a conditional path.
+template <bool INTERIOR, bool SA>
+__device__ __forceinline__ void gather_taps_quad(float4 (*stg)[PPG_TAPSZ], const float4* __restrict__ pack,
+                                                 const float4* __restrict__ taps, int n_taps, float R, int x0,
+                                                 int y0, int W, int H, int lane, int lofs, GatherAcc (&g)[4]) {
+  StageLane sl;
+#pragma unroll
+  for (int s = 0; s < PPG_SLOTS; ++s) {
+    const int idx = s * 64 + lane < PPG_TEX ? s * 64 + lane : s * 64 + lane - 64;
+    sl.sr[s] = idx / PPG_SIDE;
+    sl.sc[s] = idx - sl.sr[s] * PPG_SIDE;
+    sl.so[s] = (unsigned)(sl.sr[s] * W + sl.sc[s]) * 16u;
+    sl.lo[s] = sl.sr[s] * PPG_STRIDE + sl.sc[s];
+  }
+  sl.last = lane < PPG_TEX - 4 * 64;
+  const int last = n_taps - 1;
+  const float4 e0 = taps[0];
+  float4 e1 = taps[last < 1 ? last : 1], e2 = taps[last < 2 ? last : 2];
+  TapRec tr;
+  {
+    const Stage s0 = stage_load<INTERIOR>(pack, e0, R, x0, y0, W, H, sl);
+    stage_store_texels(stg[0], s0, sl);
+    tr = s0.tr;
+  }
+  float uz = e0.z, uw = e0.w;
+  Stage sn = stage_load<INTERIOR>(pack, e1, R, x0, y0, W, H, sl);  // tap 1 (in flight)
+  for (int t = 0; t < n_taps; ++t) {
+    wave_lds_sync();  // tap t's texels stored; tap t - 1's reads done
+    const int b = t & 1;
+    stage_store_texels(stg[b ^ 1], sn, sl);  // tap t + 1
+    const TapRec trn = sn.tr;
+    const float unz = e1.z, unw = e1.w;
+    sn = stage_load<INTERIOR>(pack, e2, R, x0, y0, W, H, sl);  // tap t + 2
+    e1 = e2;
+    e2 = taps[t + 3 < last ? t + 3 : last];
+    {
+      const float4* a = stg[b] + lofs;
+      const float4 v00 = a[0], v10 = a[1], v20 = a[2];
+      const float4 v01 = a[PPG_STRIDE], v11 = a[PPG_STRIDE + 1], v21 = a[PPG_STRIDE + 2];
+      const float4 v02 = a[2 * PPG_STRIDE], v12 = a[2 * PPG_STRIDE + 1], v22 = a[2 * PPG_STRIDE + 2];
+      const float d = fmaf(-R, uz, 0.5f);
+      const float om = SA ? uw : 1.0f;
+      g[0].tap(tr.w00, tr.w10, tr.w01, tr.w11, d, v00, v10, v01, v11, om);
+      g[1].tap(tr.w00, tr.w10, tr.w01, tr.w11, d, v10, v20, v11, v21, om);
+      g[2].tap(tr.w00, tr.w10, tr.w01, tr.w11, d, v01, v11, v02, v12, om);
+      g[3].tap(tr.w00, tr.w10, tr.w01, tr.w11, d, v11, v21, v12, v22, om);
+    }
+    tr = trn;
+    uz = unz;
+    uw = unw;
+  }
+}
+
+// 16-pixel tiles, one wave per tile (the quad form): lane l gathers the
+// 2x2 quad at (2 (l mod 8), 2 (l div 8)) of its tile, so per tap a tile
+// reads 2.25 staged texels per pixel from LDS instead of 4, and each wave
+// stages its own taps into its own ring (no barrier between waves).  A
+// block holds four neighbouring tiles, so it frees as much LDS at a time
+// as the four-wave form does (a kernel running beside it, such as the ray
+// mask, needs whole blocks' worth).  Same arithmetic, in the same tap
+// order, as k_pp_gather16, so the same results bit for bit.
+template <int FUSE, bool SA>
+__global__ __launch_bounds__(256) void k_pp_gather16q(const float4* __restrict__ pack,
+                                                      const float* __restrict__ tile_r, int K, float r_cap,
+                                                      const float4* __restrict__ taps, int n_taps, int W, int H,
+                                                      float inv_ramp, float* __restrict__ out, FuseK fz) {
+  __shared__ float4 stg[4][2][PPG_TAPSZ];
+  const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = xcd_block(blockIdx.x, (TW * TH + 3) >> 2) * 4 + wave;
+  if (tile >= TW * TH) return;
+  const int x0 = (tile % TW) * 16, y0 = (tile / TW) * 16;
+  const int lane = threadIdx.x & 63;
+  const int qx = (lane & 7) * 2, qy = (lane >> 3) * 2;
+  const size_t N = (size_t)W * H;
+  const float R = wave_dilated_radius(tile_r, TW, TH, tile % TW, tile / TW, K, r_cap);
+  if (!(R > 0.0f)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int x = x0 + qx + (q & 1), y = y0 + qy + (q >> 1);
+      if (x < W && y < H) {
+        const size_t p = (size_t)y * W + x;
+        const float4 c = pack[p];
+        pp_emit<FUSE>(out, fz, N, p, c, c.x, c.y, c.z);
+      }
+    }
+    return;
+  }
+  const int E = (int)ceilf(R);
+  const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H &&
+                        (long long)W * H * 16 < (1ll << 31);
+  GatherAcc g[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int x = x0 + qx + (q & 1), y = y0 + qy + (q >> 1);
+    const float4 cp4 = x < W && y < H ? pack[(size_t)y * W + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    g[q].init(cp4, R, n_taps, inv_ramp);
+  }
+  const int lofs = qy * PPG_STRIDE + qx;
+  if (interior)
+    gather_taps_quad<true, SA>(stg[wave], pack, taps, n_taps, R, x0, y0, W, H, lane, lofs, g);
+  else
+    gather_taps_quad<false, SA>(stg[wave], pack, taps, n_taps, R, x0, y0, W, H, lane, lofs, g);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int x = x0 + qx + (q & 1), y = y0 + qy + (q >> 1);
+    if (x < W && y < H) {
+      const size_t p = (size_t)y * W + x;
+      const float4 cp4 = pack[p];
+      const float iw = 1.0f / g[q].ws;
+      pp_emit<FUSE>(out, fz, N, p, cp4, g[q].ar * iw, g[q].ag * iw, g[q].ab * iw);
+    }
   }
 }
 
@@ -1030,6 +1184,8 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
     FuseK fz{};
     if (fuse && fuse->untraced_only) {
       fz.out = fuse->out;
+      // beside the trace (the overlapped frame) the four-wave form: the quad
+      // form finishes sooner but takes the trace's issue slots on the way
       auto kern = sa ? k_pp_gather16<2, true> : k_pp_gather16<2, false>;
       hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                          (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
@@ -1038,13 +1194,13 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
       fz = FuseK{fuse->spp, fuse->rt.c_near, fuse->rt.c_far, fuse->rt.hit_ratio, 1.0f / fuse->cp.h_t,
                  fuse->cp.rt_override, fuse->out, fuse->pps,
                  fuse->pps && fuse->cp.spec_y > 0.0f ? 1.0f / fuse->cp.spec_y : 0.0f};
-      auto kern = sa ? k_pp_gather16<1, true> : k_pp_gather16<1, false>;
-      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+      auto kern = sa ? k_pp_gather16q<1, true> : k_pp_gather16q<1, false>;
+      hipLaunchKernelGGL(kern, dim3((TW * TH + 3) / 4), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                          (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     } else {
-      auto kern = sa ? k_pp_gather16<0, true> : k_pp_gather16<0, false>;
-      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
+      auto kern = sa ? k_pp_gather16q<0, true> : k_pp_gather16q<0, false>;
+      hipLaunchKernelGGL(kern, dim3((TW * TH + 3) / 4), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
                          (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     }
