@@ -596,11 +596,12 @@ __global__ __launch_bounds__(256) void k_pp_gather16q(const float4* __restrict__
   const bool interior = x0 - E - 1 >= 0 && x0 + 16 + E < W && y0 - E - 1 >= 0 && y0 + 16 + E < H &&
                         (long long)W * H * 16 < (1ll << 31);
   GatherAcc g[4];
+  float4 cp[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int x = x0 + qx + (q & 1), y = y0 + qy + (q >> 1);
-    const float4 cp4 = x < W && y < H ? pack[(size_t)y * W + x] : make_float4(0.f, 0.f, 0.f, 0.f);
-    g[q].init(cp4, R, n_taps, inv_ramp);
+    cp[q] = x < W && y < H ? pack[(size_t)y * W + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    g[q].init(cp[q], R, n_taps, inv_ramp);
   }
   const int lofs = qy * PPG_STRIDE + qx;
   if (interior)
@@ -612,9 +613,8 @@ __global__ __launch_bounds__(256) void k_pp_gather16q(const float4* __restrict__
     const int x = x0 + qx + (q & 1), y = y0 + qy + (q >> 1);
     if (x < W && y < H) {
       const size_t p = (size_t)y * W + x;
-      const float4 cp4 = pack[p];
       const float iw = 1.0f / g[q].ws;
-      pp_emit<FUSE>(out, fz, N, p, cp4, g[q].ar * iw, g[q].ag * iw, g[q].ab * iw);
+      pp_emit<FUSE>(out, fz, N, p, cp[q], g[q].ar * iw, g[q].ag * iw, g[q].ab * iw);
     }
   }
 }
