@@ -71,7 +71,7 @@ def lib():
         L.or_trace.argtypes = [P, P, i32, i32, P, P, P, P, i64, P, u64, u64, u64,
                                P, P, P, P, i64, P, P, P, P, P, P, P, P]
         L.or_sp_level.argtypes = [i32, i32, P, P, P, P, P, P, f64, i32, P]
-        L.or_spatial.argtypes = [i32, i32, P, P, P, P, P, P, P, i32, f64, f64, P, P, P]
+        L.or_spatial.argtypes = [i32, i32, P, P, P, P, P, P, P, i32, f64, f64, P, P, P, P]
         L.or_recon.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, f64, P, P, P, P, P, P]
         L.or_var_reproject.argtypes = [P, i32, i32, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
         L.or_var_update.argtypes = [i32, i32, P, P, P, P, P, P, f64, P, P, P, P, P]
@@ -489,19 +489,23 @@ def sp_level(spp, c_near, c_far, hit, hit_acc, coc_nf, r_cap: float, level: int)
 
 def spatial(spp, c_near, c_far, hit, hit_acc, coc_nf, V, n_taps=24, r_cap=64.0, v_clamp=0.01) -> dict:
     """Spatial reconstruction of the near and far traced colours (paper,
-    Reconstruction, last paragraph): returns c_near, c_far and `cond`, the
-    conditioning of each output on the acceptance weights (near, far).
+    Reconstruction, last paragraph): returns c_near, c_far, `amb` (per
+    pixel: 1 = level decision within relative 1e-5 of a level boundary,
+    2 = a tap coordinate within its rounding band of a pixel boundary) and
+    `cond`, the sensitivity of each output (near, far) to errors in the
+    acceptances of the taps on or near the acceptance ramp.
     `hit_acc` None: the latest hit ratio stands for the accumulated one; `V`
     None: no variance estimate (full weight)."""
     sp = _i32(spp)
     H, W = sp.shape
     cno, cfo = np.zeros((3, H, W)), np.zeros((3, H, W))
     cond = np.zeros((2, H, W))
+    amb = np.zeros((H, W), np.int32)
     lib().or_spatial(W, H, _p(sp), _p(_f64(c_near)), _p(_f64(c_far)), _p(_f64(hit)),
                      _p(None if hit_acc is None else _f64(hit_acc)), _p(_f64(coc_nf)),
                      _p(None if V is None else _f64(V)), int(n_taps), float(r_cap), float(v_clamp),
-                     _p(cno), _p(cfo), _p(cond))
-    return dict(c_near=cno, c_far=cfo, cond=cond)
+                     _p(cno), _p(cfo), _p(amb), _p(cond))
+    return dict(c_near=cno, c_far=cfo, amb=amb, cond=cond)
 
 
 def history_variance(hist: dict) -> np.ndarray:

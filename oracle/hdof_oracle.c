@@ -1001,17 +1001,25 @@ void or_recon(const double* cam, int W, int H, const double* z, const int* spp,
 /*   C_tn(p) when the denominator is 0; G_f alike with the far sums.         */
 /*   lambda = clamp(V_p / v_clamp, 0, 1), 1 where V_p = +inf or no variance  */
 /*   is given; C_tn' = C_tn + lambda (G_n - C_tn), C_tf' alike.             */
-/* Untraced pixels are copied.  cond (nullable, 2 planes): lambda times the */
-/* weight the taps reach (accepted or not, with the centre) over the weight */
-/* they accept, near and far: an error e in every acceptance moves the      */
-/* output by at most e cond times the colour range (0 where untraced).      */
-/* The level and the tap pixels are integers decided by floating point: they */
-/* are taken in single precision, in the order of the kernel's arithmetic    */
-/* (r_p = min(r_cap, 0.5 fma(H, cbar_n, (1 - H) cbar_f)), spacing = r_p *   */
-/* float(sqrt(pi / N)), tap coordinate fma(r_p, float(u), x + 0.5)), so both */
-/* sides pick the same pixels; the weights and sums are double.             */
+/* Untraced pixels are copied.                                               */
+/* Ambiguity (amb, nullable, per pixel; 0 where untraced): the level and the */
+/* tap pixels are integers decided by floating point.  Bit 1: the spacing   */
+/* r_p sqrt(pi/N) lies within relative OR_EPS of a level boundary 2^m       */
+/* (m = 1..OR_SP_LMAX).  Bit 2: a tap coordinate v = x + 0.5 + r_p u lies   */
+/* within OR_EPS + 2^-20 (|x + 0.5| + |r_p u|) of an integer.  The band     */
+/* grows with the operands because a single-precision evaluation of v      */
+/* rounds at up to 2^-24 |v| (6e-5 px at v = 1000) on top of the roundings  */
+/* of r_p and u; 2^-20 is sixteen such units.                              */
+/* cond (nullable, 2 planes: near, far): the sensitivity of each output to  */
+/* errors in the acceptances.  A tap whose argument rho/kappa - d + 0.5     */
+/* lies within OR_SP_DA of the ramp [0, 1] (inside it, or near an end) can  */
+/* move; one clear of it cannot.  cond = lambda (sum of the weights Bn_k of */
+/* such taps) / (the accepted near weight s_p h_p + sum a_k Bn_k), far      */
+/* alike; an error e in every such acceptance moves the output by at most   */
+/* e cond max_k |An_k / Bn_k - G_n| (0 where untraced).                     */
 /* ------------------------------------------------------------------------- */
 #define OR_SP_LMAX 5
+#define OR_SP_DA 1.0e-3
 
 typedef struct {
   int W, H;
@@ -1024,13 +1032,6 @@ static double sp_radius(const sp_in_t* I, size_t q) {
   double Hq = I->hacc ? I->hacc[q] : I->h[q];
   size_t N = (size_t)I->W * I->H;
   return mind(I->r_cap, 0.5 * (Hq * I->coc[q] + (1.0 - Hq) * I->coc[N + q]));
-}
-
-/* the same radius in single precision (for the integer decisions only) */
-static float sp_radius_f(const sp_in_t* I, size_t q) {
-  float Hq = (float)(I->hacc ? I->hacc[q] : I->h[q]);
-  size_t N = (size_t)I->W * I->H;
-  return fminf((float)I->r_cap, 0.5f * fmaf(Hq, (float)I->coc[q], (1.0f - Hq) * (float)I->coc[N + q]));
 }
 
 /* the sums of level-L texel (i, j): o[0..2] An, o[3] Bn, o[4..6] Af, o[7] Bf,
@@ -1069,9 +1070,15 @@ void or_sp_level(int W, int H, const int* spp, const double* cn, const double* c
     }
 }
 
+/* v within band of an integer */
+static int sp_near_int(double v, double band) {
+  double f = floor(v);
+  return v - f < band || f + 1.0 - v < band;
+}
+
 void or_spatial(int W, int H, const int* spp, const double* cn, const double* cf, const double* h,
                 const double* hacc, const double* coc, const double* V, int n_taps, double r_cap,
-                double v_clamp, double* cn_out, double* cf_out, double* cond) {
+                double v_clamp, double* cn_out, double* cf_out, int* amb, double* cond) {
   sp_in_t I = {W, H, spp, cn, cf, h, hacc, coc, r_cap};
   size_t N = (size_t)W * H;
   const double g = OR_PI * (3.0 - sqrt(5.0));
@@ -1079,31 +1086,37 @@ void or_spatial(int W, int H, const int* spp, const double* cn, const double* cf
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
       size_t p = (size_t)y * W + x;
+      int am = 0;
       for (int c = 0; c < 3; ++c) { cn_out[c * N + p] = cn[c * N + p]; cf_out[c * N + p] = cf[c * N + p]; }
-      if (spp[p] <= 0) continue;
+      if (cond) cond[p] = cond[N + p] = 0.0;
+      if (spp[p] <= 0) { if (amb) amb[p] = 0; continue; }
       double rp = sp_radius(&I, p);
-      float rpf = sp_radius_f(&I, p);
-      float spacing = rpf * (float)sqrt(OR_PI / n_taps);
+      double spacing = rp * sqrt(OR_PI / n_taps);
       int L = 0;
-      if (spacing >= 1.0f) L = (int)floor(log2((double)spacing));
+      if (spacing >= 1.0) L = (int)floor(log2(spacing));
       if (L > OR_SP_LMAX) L = OR_SP_LMAX;
+      for (int m = 1; m <= OR_SP_LMAX; ++m)
+        if (fabs(spacing - (double)(1 << m)) < OR_EPS * (double)(1 << m)) am |= 1;
       double sn = spp[p] * h[p], sf = spp[p] * (1.0 - h[p]);
-      double An[3], Af[3], Bn = sn, Bf = sf, Tn = sn, Tf = sf;
+      double An[3], Af[3], Bn = sn, Bf = sf, Sn = 0.0, Sf = 0.0;
       for (int c = 0; c < 3; ++c) { An[c] = sn * cn[c * N + p]; Af[c] = sf * cf[c * N + p]; }
       for (int k = 1; k <= n_taps; ++k) {
         double rr = sqrt((k - 0.5) / n_taps);
-        float ux = (float)(rr * cos(k * g)), uy = (float)(rr * sin(k * g));
-        float fx = fmaf(rpf, ux, (float)x + 0.5f), fy = fmaf(rpf, uy, (float)y + 0.5f);
-        int px = clampi((int)floorf(fx), 0, W - 1), py = clampi((int)floorf(fy), 0, H - 1);
+        double ux = rr * cos(k * g), uy = rr * sin(k * g);
+        double fx = x + 0.5 + rp * ux, fy = y + 0.5 + rp * uy;
+        if (sp_near_int(fx, OR_EPS + ldexp(fabs(x + 0.5) + fabs(rp * ux), -20)) ||
+            sp_near_int(fy, OR_EPS + ldexp(fabs(y + 0.5) + fabs(rp * uy), -20)))
+          am |= 2;
+        int px = clampi((int)floor(fx), 0, W - 1), py = clampi((int)floor(fy), 0, H - 1);
         double o[10];
         sp_texel(&I, L, px >> L, py >> L, o);
         if (o[9] <= 0.0) continue;
-        double a = clampd(o[8] / o[9] - rp * rr + 0.5, 0.0, 1.0);
+        double arg = o[8] / o[9] - rp * rr + 0.5;
+        double a = clampd(arg, 0.0, 1.0);
         for (int c = 0; c < 3; ++c) { An[c] += a * o[c]; Af[c] += a * o[4 + c]; }
         Bn += a * o[3];
         Bf += a * o[7];
-        Tn += o[3];
-        Tf += o[7];
+        if (arg > -OR_SP_DA && arg < 1.0 + OR_SP_DA) { Sn += o[3]; Sf += o[7]; }
       }
       double lam = 1.0;
       if (V && !isinf(V[p])) lam = clampd(V[p] / v_clamp, 0.0, 1.0);
@@ -1114,9 +1127,10 @@ void or_spatial(int W, int H, const int* spp, const double* cn, const double* cf
         cf_out[c * N + p] = cf[c * N + p] + lam * (Gf - cf[c * N + p]);
       }
       if (cond) {
-        cond[p] = Bn > 0.0 ? lam * Tn / Bn : 0.0;
-        cond[N + p] = Bf > 0.0 ? lam * Tf / Bf : 0.0;
+        cond[p] = Bn > 0.0 ? lam * Sn / Bn : 0.0;
+        cond[N + p] = Bf > 0.0 ? lam * Sf / Bf : 0.0;
       }
+      if (amb) amb[p] = am;
     }
 }
 

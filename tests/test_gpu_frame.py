@@ -5,7 +5,6 @@ changes the stages downstream of it; the comparison therefore excludes the
 footprint of pixels whose GPU and oracle inputs actually differ, after
 checking that each such difference is one the oracle flagged.
 """
-import math
 
 import numpy as np
 import pytest
@@ -13,11 +12,9 @@ import torch
 
 import oracle
 import scenegen as sg
-from gpu_common import DEV, chebyshev_dilate, excl_cumsum, f32, print_case, tile_footprint, to_dev, upload_scene
+from gpu_common import COL_TOL, compare_frame, excl_cumsum, print_case, run_frame, to_dev, upload_scene
 
 pytestmark = pytest.mark.gpu
-
-COL_TOL = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -33,69 +30,9 @@ def ctx(hd):
     c.close()
 
 
-def run_frame(hd, ctx, sc, cfg, prev=None, frame=0, view=0):
-    H, W = cfg.camera.height, cfg.camera.width
-    keep = hd.FrameKeep.empty(H, W)
-    out = hd.hdof_frame(ctx, sc, hd.camera_of(cfg.camera), hd.camera_of(prev) if prev is not None else None,
-                        hd.lens_of(cfg.lens), hd.light_of(cfg.light), hd.frame_params_of(cfg), seed=cfg.seed,
-                        frame=frame, view=view, keep=keep)
-    torch.cuda.synchronize()
-    ctx.sync()
-    g = dict(out=out.cpu().numpy().astype(np.float64), spp=keep.spp.cpu().numpy().astype(np.int64),
-             offsets=keep.offsets.cpu().numpy().astype(np.int64), total=int(keep.total.item()),
-             tri_id=keep.gb.tri_id.cpu().numpy(), color=keep.gb.color.cpu().numpy().astype(np.float64),
-             depth=keep.gb.depth.cpu().numpy().astype(np.float64), pp=keep.pp.cpu().numpy().astype(np.float64),
-             normal=keep.gb.normal.cpu().numpy().astype(np.float64))
-    for k in ("c_near", "c_far", "hit_ratio", "lum_m1", "lum_m2"):
-        g[k] = getattr(keep.rt, k).cpu().numpy().astype(np.float64)
-    return g
-
-
-def compare_frame(g, ref, cfg):
-    gb = ref["gbuffer"]
-    H, W = gb["depth"].shape
-    # 1. G-buffer: differences only where the oracle flags them
-    diff_id = g["tri_id"] != gb["tri_id"]
-    assert not (diff_id & (gb["amb"] == 0)).any()
-    same = ~diff_id
-    # a legitimately different hit matters downstream only where it changes
-    # the G-buffer values (neighbouring coplanar faces of one object do not)
-    dz = np.abs(g["depth"] - gb["depth"]) / np.maximum(gb["depth"], 1e-6)
-    dc = np.max(np.abs(g["color"] - gb["color"]), axis=0)
-    diff_gb = diff_id & ((dz > 1e-5) | (dc > 2e-4))
-    # neighbours of such a pixel see a different normal only if the faces differ
-    diff_n = diff_id & (np.max(np.abs(keep_normal_diff(g, gb)), axis=0) > 1e-4)
-    assert np.max(np.abs(g["color"] - gb["color"])[:, same], initial=0) < COL_TOL
-    # 2. mask, outside the stencil + tile footprint of differing G-buffer pixels
-    mp = cfg.mask
-    gr = int(math.floor(3 * mp.sigma + 0.5))
-    foot_mask = tile_footprint(chebyshev_dilate(diff_gb | diff_n, gr + 1), mp.tile, mp.dilate)
-    lo, hi = ref["mask"]["spp_lo"], ref["mask"]["spp_hi"]
-    s = g["spp"]
-    ok = ~foot_mask
-    assert np.all((s >= lo) & (s <= hi) | foot_mask)
-    assert np.array_equal(g["offsets"], excl_cumsum(s)) and g["total"] == s.sum()
-    # 3. trace: pixels with equal counts and unambiguous rays trace the same rays
-    rt = ref["rt"]
-    tr_ok = (s == ref["spp"]) & (rt["px_amb"] == 0)
-    h = g["hit_ratio"]
-    assert np.max(np.abs(h - rt["hit_ratio"])[tr_ok], initial=0) < 1e-4
-    crt_g = h * g["c_near"] + (1 - h) * g["c_far"]
-    crt_r = rt["hit_ratio"] * rt["c_near"] + (1 - rt["hit_ratio"]) * rt["c_far"]
-    assert np.max(np.abs(crt_g - crt_r)[:, tr_ok], initial=0) < COL_TOL
-    # 4. post-filter outside the gather footprint of differing G-buffer pixels
-    pp = cfg.pp
-    K = math.ceil(pp.r_cap / pp.tile)
-    foot_pp = chebyshev_dilate(diff_gb, int(pp.r_cap) + 2) | tile_footprint(diff_gb, pp.tile, K)
-    assert np.max(np.abs(g["pp"] - ref["pp"])[:, ~foot_pp], initial=0) < COL_TOL
-    # 5. composite where every input agrees
-    comp_ok = same & ~foot_pp & tr_ok
-    assert np.max(np.abs(g["out"] - ref["out"])[:, comp_ok], initial=0) < COL_TOL
-    return dict(diff_id=int(diff_id.sum()), diff_gb=int(diff_gb.sum()), compared=float(comp_ok.mean()))
-
-
-def keep_normal_diff(g, gb):
-    return g["normal"] - gb["normal"]
+# fraction of the image compared at the full bar (the rest lies in the
+# stencil or gather footprint of a legitimately different G-buffer hit)
+MIN_COMPARED = {"tiny": 0.9, "tiny_strong": 0.9, "room_320x180": 0.9, "room_1080p": 0.9}
 
 
 @pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_320x180", "room_1080p"])
@@ -118,7 +55,7 @@ def test_frame_matches_oracle(hd, ctx, which):
     ref = oracle.frame(oracle.Scene(scene.verts, scene.albedo), cfg)
     info = compare_frame(g, ref, cfg)
     print(info)
-    assert info["compared"] > 0.3, info
+    assert info["compared"] >= MIN_COMPARED[which], info
     sc.close()
 
 

@@ -6,15 +6,21 @@ hit ratio and a variance plane, an empty mask, 1920x1080) and on a real
 frame's trace, and its place in hdof_frame (alone and after the temporal
 reconstruction).
 
-Bars: the level and tap pixels are decided in single precision on both
-sides (identical).  A traced pixel's output is a ratio of acceptance-weighted
-sums; where the taps it accepts carry a small part of the weight they reach
-(say a pure far pixel whose near taps are barely accepted), an error e in
-the acceptances moves it by up to e * cond * (colour range), cond = reached
-over accepted weight, which the oracle reports.  The bar is
-1e-4 + EPS_A * cond * range, EPS_A = 3e-5 for the single-precision radii,
-their texel sums (up to 1024 pixels) and tap distances; untraced pixels are
-copied bit for bit."""
+Bars.  The level and the tap pixels are integers that floating point
+decides: the oracle takes them in double and flags a pixel whose spacing
+lies within relative 1e-5 of a level boundary or whose tap coordinate lies
+within its rounding band of a pixel boundary; flagged pixels are left out
+(a pixel's output depends on its own decisions only).  Every other traced
+pixel is compared at the 1e-3 linear-colour bar, except the ill-conditioned
+ones, which are counted apart: a pixel's output is a ratio of
+acceptance-weighted sums, and where the taps on the acceptance ramp carry
+most of the weight it accepts (cond, reported by the oracle), the
+single-precision acceptance arguments' rounding (at most EPS_A = r_cap
+2^-19: the texel mean radii, sums of up to 1024 radii, and the tap
+distances) can move it by EPS_A * cond * range.  Pixels where that bound
+exceeds half the bar are reported separately, must be under 1 % of the
+traced pixels, and are held to that bound.  Untraced pixels are copied
+bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -25,8 +31,12 @@ from gpu_common import f32, print_case, to_dev, upload_scene
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-4
-EPS_A = 3e-5
+TOL = 1e-3  # linear colour, absolute
+ILL_FRAC = 0.01
+
+
+def eps_a(r_cap: float) -> float:
+    return r_cap * 2.0 ** -19
 
 
 @pytest.fixture(scope="module")
@@ -61,19 +71,28 @@ def _run_oracle(inp, n_taps, r_cap, use_hacc, use_var, v_clamp=0.01):
                           f32(inp["variance"]) if use_var else None, n_taps, r_cap, v_clamp)
 
 
-def _compare(inp, g, ref, name):
+def _compare(inp, g, ref, name, r_cap):
     traced = inp["spp"] > 0
+    amb = ref["amb"] != 0
+    stats = {}
     for i, (k, gk) in enumerate(zip(("c_near", "c_far"), g)):
         rng = float(np.max(inp[k])) if traced.any() else 0.0
-        tol = TOL + EPS_A * ref["cond"][i] * rng
-        d = np.abs(gk - ref[k])
-        bad = (d > tol[None]) & traced[None]
-        well = traced & (ref["cond"][i] <= 2.0)
-        print(f"{name} {k}: max err {d[:, traced].max(initial=0):.2e}, well-conditioned "
-              f"{d[:, well].max(initial=0):.2e} over {well.sum()} of {traced.sum()} px", flush=True)
-        assert not bad.any(), (name, k, d[bad].max(), ref["cond"][i][bad.any(0)].min())
+        bound = eps_a(r_cap) * ref["cond"][i] * rng
+        ill = traced & ~amb & (bound > 0.5 * TOL)
+        well = traced & ~amb & ~ill
+        d = np.abs(gk - ref[k]).max(axis=0)
+        print(f"{name} {k}: traced {traced.sum()}, flagged {(traced & amb).sum()}, ill-conditioned {ill.sum()}; "
+              f"max err {d[well].max(initial=0):.2e} (bar {TOL:.0e}), ill-conditioned max err "
+              f"{d[ill].max(initial=0):.2e} (bound {(bound[ill] + 1e-4).max(initial=0):.2e})", flush=True)
+        assert d[well].max(initial=0) <= TOL, (name, k, d[well].max())
+        assert np.all(d[ill] <= bound[ill] + 1e-4), (name, k)
+        assert ill.sum() <= ILL_FRAC * max(traced.sum(), 1), (name, k, ill.sum(), traced.sum())
         # untraced pixels: bit-exact copies
         assert np.array_equal(gk[:, ~traced], inp[k].astype(np.float64)[:, ~traced]), (name, k)
+        stats[k] = (well.sum(), traced.sum())
+    if traced.sum() >= 100:
+        assert (traced & amb).sum() <= 0.25 * traced.sum(), (name, (traced & amb).sum(), traced.sum())
+    return stats
 
 
 CASES = [
@@ -94,7 +113,7 @@ def test_spatial_stage_matches_oracle(hd, ctx, case):
     inp = sg.spatial_inputs(H, W, seed, cov, cmax)
     ref = _run_oracle(inp, n_taps, r_cap, use_hacc, use_var)
     g = _run_gpu(hd, ctx, inp, n_taps, r_cap, use_hacc, use_var)
-    _compare(inp, g, ref, name)
+    _compare(inp, g, ref, name, r_cap)
     if name == "empty_mask":
         assert not (inp["spp"] > 0).any()
     else:
@@ -106,9 +125,9 @@ def test_spatial_levels_are_all_reached(hd, ctx):
     """The seeded cases above reach every level: with 4 taps and radii up to
     150 px the spacing r sqrt(pi/4) spans 0 .. 133 px."""
     inp = sg.spatial_inputs(256, 320, 3, 0.4, 300.0)
-    hacc = inp["hit_acc"].astype(np.float32)
-    r = np.minimum(np.float32(200.0), np.float32(0.5) * (hacc * inp["coc_nf"][0] + (1 - hacc) * inp["coc_nf"][1]))
-    sp = r * np.float32(np.sqrt(np.pi / 4))
+    hacc = inp["hit_acc"].astype(np.float64)
+    r = np.minimum(200.0, 0.5 * (hacc * inp["coc_nf"][0] + (1 - hacc) * inp["coc_nf"][1]))
+    sp = r * np.sqrt(np.pi / 4)
     L = np.clip(np.floor(np.log2(np.maximum(sp, 1e-30))), 0, 5)[inp["spp"] > 0]
     assert set(np.unique(L).astype(int)) == {0, 1, 2, 3, 4, 5}
 
@@ -119,7 +138,7 @@ def test_spatial_full_size(hd, ctx):
     inp = sg.spatial_inputs(1080, 1920, 11, 0.055, 150.0)
     ref = _run_oracle(inp, 24, 64.0, True, True)
     g = _run_gpu(hd, ctx, inp, 24, 64.0, True, True)
-    _compare(inp, g, ref, "1080p")
+    _compare(inp, g, ref, "1080p", 64.0)
 
 
 def test_coc_averages_match_oracle(hd, ctx):
@@ -165,7 +184,7 @@ def test_spatial_on_a_real_trace(hd, ctx):
     for n_taps in (24, 48):
         ref = _run_oracle(inp, n_taps, 64.0, False, True)
         g = _run_gpu(hd, ctx, inp, n_taps, 64.0, False, True)
-        _compare(inp, g, ref, f"frame n{n_taps}")
+        _compare(inp, g, ref, f"frame n{n_taps}", 64.0)
 
 
 def _hist_variance(hd, ctx, H, W):

@@ -206,3 +206,48 @@ def test_frame_applies_spatial_after_the_trace(orc):
     assert np.array_equal(on["rt"]["c_near"], ref["c_near"])
     assert np.array_equal(on["rt"]["c_far"], ref["c_far"])
     assert not np.array_equal(on["rt"]["c_near"], rt["c_near"])
+
+
+def test_ambiguity_flags_and_conditioning(orc):
+    """The oracle's flags of the integer decisions and its conditioning
+    figure, on the one-tap cases worked by hand above.
+
+    Level: with one tap the spacing is r_p sqrt(pi); r_p = 4 / sqrt(pi)
+    puts it on the level-2 boundary (flag 1), 0.1 % away it is clear.
+    Tap coordinate: r_p = -0.5 / u_x puts the tap's x on 4.0 (flag 2); the
+    band is 1e-5 + 2^-20 (|x + 0.5| + |r_p u_x|), so an offset of 1e-4 px
+    is flagged at x ~ 1000 but not at x = 4.
+    Conditioning: a tap whose acceptance sits on the ramp (a = 1/4) counts
+    its near weight 2 over the accepted 2 + 2/4: 0.8; a fully accepted tap
+    (argument 4.8) counts nothing."""
+    g = math.pi * (3 - math.sqrt(5))
+    ux, uy = math.sqrt(0.5) * math.cos(g), math.sqrt(0.5) * math.sin(g)
+
+    def one(x, y, r_p, W=8, H=8, r_q=5.0):
+        spp, cn, cf, h, coc = _blank(W, H)
+        _put(spp, cn, cf, h, coc, x, y, 2, 1.0, 0.0, r_near=r_p)
+        tx = min(max(math.floor(x + 0.5 + r_p * ux), 0), W - 1)
+        ty = min(max(math.floor(y + 0.5 + r_p * uy), 0), H - 1)
+        if (tx, ty) != (x, y):
+            _put(spp, cn, cf, h, coc, tx, ty, 2, 1.0, 1.0, r_near=r_q)
+        return orc.spatial(spp, cn, cf, h, None, coc, None, n_taps=1, r_cap=64.0)
+
+    r_lvl = 4.0 / math.sqrt(math.pi)
+    assert one(4, 4, r_lvl)["amb"][4, 4] & 1
+    assert not one(4, 4, r_lvl * 1.001)["amb"][4, 4] & 1
+    r_tap = -0.5 / ux
+    assert abs(4.5 + r_tap * uy - round(4.5 + r_tap * uy)) > 0.01
+    assert one(4, 4, r_tap)["amb"][4, 4] & 2
+    assert one(4, 4, r_tap * 1.01)["amb"][4, 4] == 0
+    # 1e-4 px from a pixel boundary: flagged far from the origin, clear near it
+    W = 1100
+    r_far = (1000.0 - 1e-4 - 1000.5) / ux
+    assert 1000.5 + r_far * ux < 1000.0 and one(1000, 4, r_far, W=W)["amb"][4, 1000] & 2
+    r_near = (4.0 - 1e-4 - 4.5) / ux
+    assert one(4, 4, r_near)["amb"][4, 4] == 0
+    # conditioning of the near output
+    out = one(4, 4, 1.0, r_q=math.sqrt(0.5) - 0.25)
+    assert abs(out["cond"][0, 4, 4] - 0.8) < 1e-12 and abs(out["c_near"][0, 4, 4] - 0.2) < 1e-12
+    assert one(4, 4, 1.0, r_q=5.0)["cond"][0, 4, 4] == 0.0
+    # untraced pixels carry neither flags nor conditioning
+    assert out["amb"][0, 0] == 0 and out["cond"][:, 0, 0].max() == 0.0
