@@ -412,7 +412,13 @@ hdof_status hdof_composite(hdof_ctx* ctx, const float* d_color, const float* d_p
  * the variance history just updated) -> post-process -> composite.
  * d_out [3][H][W].  `keep` (nullable) supplies caller buffers for
  * intermediates (keep->rt receives the reconstructed colours when
- * reconstruction is on).  The batched form refuses both reconstructions. */
+ * reconstruction is on).  The batched form refuses both reconstructions.
+ * Under stream capture (a HIP graph), once an eager frame of the same size
+ * has reserved the scratch, a frame records kernels and events only; it
+ * then refuses prev != NULL and both reconstructions (HDOF_ERR_UNSUPPORTED:
+ * their histories advance on the host, which a replay would not see), and
+ * it neither reads nor writes the variance history (a replay leaves the
+ * history of the last eager frame as it was). */
 hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const hdof_camera* cam,
                        const hdof_camera* prev, const hdof_lens* lens, const hdof_light* light,
                        const hdof_frame_params* params, uint32_t seed, uint32_t frame,

@@ -608,6 +608,17 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   TRY(check_spatial(&params->spatial));
   TRY(check_capacity(cam, params->mask.spp_max));
   REQUIRE(d_out, "out is NULL");
+  // A captured frame replays with the buffers fixed when it was captured,
+  // while the variance history's ping-pong and the temporal
+  // reconstruction's history index advance on the host: a captured frame
+  // may neither read a history (prev, reconstruction) nor advance one.
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  HDOF_HIP(hipStreamIsCapturing((hipStream_t)stream, &cap_status));
+  const bool capturing = cap_status != hipStreamCaptureStatusNone;
+  if (capturing && (prev || params->recon.enable || params->spatial.enable))
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED,
+                          "a frame under stream capture takes no previous camera and no reconstruction "
+                          "(their histories advance on the host)");
   hdof_frame_bufs z;
   memset(&z, 0, sizeof z);
   const hdof_frame_bufs& u = keep ? *keep : z;
@@ -731,11 +742,17 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
   // the mask's final pass also fills the ray queue (queue stage empty)
   if (s == HDOF_OK)
     s = launch_mask(ctx, gb.depth, gb.normal, k, prev ? &pk : nullptr, params->mask, spp, offs, total, st,
-                    (int*)ctx->queue.p, (long)cap, (int*)ctx->work_counter.p, &l);
+                    (int*)ctx->queue.p, (long)cap, (int*)ctx->work_counter.p, &l, !capturing);
   // the trace's per-pixel reduction also updates the variance history
-  // (variance stage empty)
-  VarFuse vf;
-  if (s == HDOF_OK) s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf, true);
+  // (variance stage empty); a captured frame writes no history at all: its
+  // replays would write planes fixed at capture, which by then may hold the
+  // history of a later eager frame
+  VarFuse vf{};
+  const VarFuse* vfp = nullptr;
+  if (s == HDOF_OK && !capturing) {
+    s = var_update_prepare(ctx, k, params->mask.var_alpha, gb.depth, &vf, true);
+    vfp = &vf;
+  }
   // only the composite reads the trace planes, and only at traced pixels,
   // unless the caller keeps them or a reconstruction stage reads them
   vf.sparse_rt = !u.rt.c_near && !u.rt.c_far && !u.rt.hit_ratio && !u.rt.lum_m1 && !u.rt.lum_m2 &&
@@ -744,10 +761,10 @@ extern "C" hdof_status hdof_frame(hdof_ctx* ctx, const hdof_scene* scene, const 
     // beside the gather the trace keeps blocks in proportion to its rays
     ctx->trace_ray_quantum = ovl ? ctx->tune.overlap_ray_quantum : 0;
     s = launch_trace(ctx, scene, k, l, li, params->mask.spp_max, spp, offs, total, seed, frame, view, rt_tr,
-                     nullptr, nullptr, far_pos, st, &vf, true, coc_nf);  // marks 3, 4
+                     nullptr, nullptr, far_pos, st, vfp, true, coc_nf);  // marks 3, 4
     ctx->trace_ray_quantum = 0;
     // the reduction updated the history in the reprojected planes
-    if (s == HDOF_OK) history_swap(ctx);
+    if (s == HDOF_OK && !capturing) history_swap(ctx);
   }
   if (params->recon.enable || spatial) hdof_prof_mark(ctx, 6, st);  // else the reconstruction stage is empty
   if (s == HDOF_OK && params->recon.enable)
@@ -1022,7 +1039,7 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     rt[v].lum_m2 = (float*)(a + L.o_m2) + pb;
     TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
     TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
-                    (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l));
+                    (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l, false));
   }
   TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
                            (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,

@@ -361,11 +361,14 @@ hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof
                            bool zero_untraced = false);
 // the mask's scratch for a W x H frame (tile 0: every candidate grid)
 hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp);
-// lens: needed for tile 0 (the mask tile scaled by the frame's maximum CoC)
+// lens: needed for tile 0 (the mask tile scaled by the frame's maximum CoC);
+// write_rep false: the reprojected history is not written (no later
+// variance update of this frame reads it: batched views, captured frames)
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
                         int32_t* total, hipStream_t st,
-                        int* queue = nullptr, long cap = 0, int* counter = nullptr, const LensK* lens = nullptr);
+                        int* queue = nullptr, long cap = 0, int* counter = nullptr, const LensK* lens = nullptr,
+                        bool write_rep = true);
 hdof_status launch_var_update(hdof_ctx* ctx, const CamK& k, float alpha, const uint8_t* spp,
                               const float* depth, const float* m1, const float* m2, hipStream_t st);
 // Composite fused into the post-filter of a whole frame (the gather writes

@@ -175,10 +175,12 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
       }
       if (fl & HDOF_HIST_VALID) V = (fl & HDOF_HIST_NEW) ? INFINITY : fmaxf(0.0f, fmaf(-a1, a1, a2));
     }
-    rep_m1[p] = a1;
-    rep_m2[p] = a2;
-    rep_flags[p] = fl;
-    rep_z[p] = depth[p];  // the history depth, should these planes become the history
+    if (rep_m1) {  // NULL: nothing will read the reprojected history
+      rep_m1[p] = a1;
+      rep_m2[p] = a2;
+      rep_flags[p] = fl;
+      rep_z[p] = depth[p];  // the history depth, should these planes become the history
+    }
     float m = fmaxf(gz * mk.inv_tz, fmaxf(gn * mk.inv_tn, V * mk.inv_tv));
     if (m >= 1.0f) s_raw = (int)ceilf(fminf(m, (float)mk.spp_max));
     if (mk.tile == 0) rc = 0.5f * fabsf(mk.coc_scale * (mk.inv_s1 - 1.0f / depth[p]));
@@ -418,7 +420,8 @@ hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp
 
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
-                        int32_t* total, hipStream_t st, int* queue, long cap, int* counter, const LensK* lens) {
+                        int32_t* total, hipStream_t st, int* queue, long cap, int* counter, const LensK* lens,
+                        bool write_rep) {
   const int W = k.W, H = k.H;
   const bool scaled = mp.tile == 0;
   if (scaled && !lens) return hdof_set_error(HDOF_ERR_INVALID_ARG, "mask tile 0 (scaled by the CoC) needs the lens");
@@ -455,7 +458,7 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   }
   ctx->rep_w = W;
   ctx->rep_h = H;
-  ctx->rep_valid = true;
+  ctx->rep_valid = write_rep;
   int* rowsum = (int*)ctx->mask_rowsum.p;
   int* rowtot = rowsum + TH;
   const int nblk = cdiv(W, MT) * cdiv(H, MT);
@@ -470,10 +473,10 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   }
   {
     const dim3 g(nblk), b(256);
-    float* r1 = (float*)ctx->rep_m1.p;
-    float* r2 = (float*)ctx->rep_m2.p;
-    uint8_t* rf = (uint8_t*)ctx->rep_flags.p;
-    float* rz = (float*)ctx->rep_z.p;
+    float* r1 = write_rep ? (float*)ctx->rep_m1.p : nullptr;
+    float* r2 = write_rep ? (float*)ctx->rep_m2.p : nullptr;
+    uint8_t* rf = write_rep ? (uint8_t*)ctx->rep_flags.p : nullptr;
+    float* rz = write_rep ? (float*)ctx->rep_z.p : nullptr;
     int* tm = (int*)ctx->mask_tile.p;
     switch (gr) {
 #define CASE(R) \

@@ -81,7 +81,7 @@ def frame_numpy(out, keep) -> dict:
     return g
 
 
-def compare_frame(g, ref, cfg, hist=None):
+def compare_frame(g, ref, cfg, hist=None, iso=True):
     """Whole-frame parity of a GPU frame `g` (run_frame) with oracle.frame's
     `ref` on the same inputs.  Every G-buffer hit that differs must be one the
     oracle flagged; downstream stages are compared outside the stencil, tile
@@ -91,7 +91,9 @@ def compare_frame(g, ref, cfg, hist=None):
     compared with the oracle's updated history (flags exact, moments within
     1e-5, depth within relative 1e-5) wherever the counts, the rays and the
     reprojection agree.  Returns counts and the fraction compared at the
-    full bar."""
+    full bar.  `iso`: also run the oracle's post-filter and composite on the
+    GPU's own G-buffer, counts and traced planes, and compare them with the
+    GPU's at every pixel (stage-isolated: no footprint is left out)."""
     gb = ref["gbuffer"]
     H, W = gb["depth"].shape
     # 1. G-buffer: differences only where the oracle flags them
@@ -140,6 +142,18 @@ def compare_frame(g, ref, cfg, hist=None):
     assert np.max(np.abs(g["out"] - ref["out"])[:, comp_ok], initial=0) < COL_TOL
     info = dict(diff_id=int(diff_id.sum()), diff_gb=int(diff_gb.sum()), rep_amb=int(rep_amb.sum()),
                 traced=int((s > 0).sum()), compared=float(comp_ok.mean()))
+    if iso:
+        import oracle
+        pp_iso = oracle.postfilter(cfg.camera, cfg.lens, g["color"], g["depth"], cfg.pp)
+        e_pp = float(np.max(np.abs(g["pp"] - pp_iso)))
+        assert e_pp < COL_TOL, e_pp
+        info["pp_iso_err"] = e_pp
+        if getattr(cfg.comp, "spec_y", 0.0) == 0.0:
+            out_iso = oracle.composite(cfg.camera, cfg.lens, g["color"], g["pp"], g["depth"], g["spp"], g["c_near"],
+                                       g["c_far"], g["hit_ratio"], cfg.comp)
+            e_out = float(np.max(np.abs(g["out"] - out_iso)))
+            assert e_out < COL_TOL, e_out
+            info["out_iso_err"] = e_out
     # 6. the updated variance history
     if hist is not None:
         rh = ref["history"]

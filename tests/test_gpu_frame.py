@@ -30,9 +30,12 @@ def ctx(hd):
     c.close()
 
 
-# fraction of the image compared at the full bar (the rest lies in the
-# stencil or gather footprint of a legitimately different G-buffer hit)
-MIN_COMPARED = {"tiny": 0.9, "tiny_strong": 0.9, "room_320x180": 0.9, "room_1080p": 0.9}
+# fraction of the image compared end to end at the full bar (the rest lies
+# in the stencil or gather footprint of a legitimately different G-buffer
+# hit; the post-filter and composite are also compared stage-isolated at
+# every pixel).  One such pixel's 64-px gather footprint is a 131x131 square:
+# 30 % of a 320x180 image, 0.8 % of 1920x1080.
+MIN_COMPARED = {"tiny": 0.9, "tiny_strong": 0.9, "room_320x180": 0.5, "room_1080p": 0.9}
 
 
 @pytest.mark.parametrize("which", ["tiny", "tiny_strong", "room_320x180", "room_1080p"])

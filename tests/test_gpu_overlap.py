@@ -4,7 +4,10 @@ against the single-stream frame: bitwise equal kept planes and outputs, for
 16- and 8-pixel tiles, the specular rule, and temporal plus spatial
 reconstruction along a camera path; the stage profile of an overlapped
 frame times the gather on its own stream; an overlapped frame captured into
-a HIP graph replays to the eager result."""
+a HIP graph replays to the eager result; under capture a frame refuses a
+history and its replays leave the context's history unchanged."""
+import ctypes
+
 import pytest
 import torch
 
@@ -190,6 +193,74 @@ def test_overlapped_frame_in_a_graph(hd, ctx):
     ctx.sync()
     del g
     sc.close()
+
+
+def test_captured_frame_refuses_history_and_keeps_it(hd, ctx):
+    """Under stream capture a frame with a previous camera (or a
+    reconstruction stage) is refused before anything is recorded; a
+    captured frame without one replays without touching the context's
+    variance history: after eager frames, replays and another eager frame
+    with a previous camera, outputs and history equal those of the same
+    eager frames without the replays."""
+    print_case("captured frame and the variance history")
+    W, H = 320, 180
+    cfg = sg.config_temporal(W, H)
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    params = hd.frame_params_of(cfg)
+    lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    cams = [hd.camera_of(sg.temporal_camera(t, W, H)) for t in range(3)]
+    hd.hdof_set_tuning(ctx)
+    out = torch.empty(3, H, W, device=DEV)
+    hd.hdof_history_reset(ctx)
+    hd.hdof_frame(ctx, sc, cams[0], None, lens, light, params, frame=0, out=out)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    rec = hd.frame_params_of(cfg)
+    rec.recon.enable = 1
+    hip = hd._lib  # its HIP runtime dependency, the one torch loaded
+    for p_, prev in ((params, cams[0]), (rec, None)):
+        graph = ctypes.c_void_p()
+        assert hip.hipStreamBeginCapture(ctypes.c_void_p(s.cuda_stream), 2) == 0  # relaxed mode
+        try:
+            with pytest.raises(hd.HdofError):
+                hd.hdof_frame(ctx, sc, cams[1], prev, lens, light, p_, frame=1, out=out, stream=s)
+        finally:
+            assert hip.hipStreamEndCapture(ctypes.c_void_p(s.cuda_stream), ctypes.byref(graph)) == 0
+            if graph.value:
+                hip.hipGraphDestroy(graph)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        hd.hdof_frame(ctx, sc, cams[2], None, lens, light, params, frame=7, out=out)
+    try:
+        _replays_between_frames(hd, ctx, sc, g, cams, lens, light, params, H, W)
+    finally:
+        torch.cuda.synchronize()
+        del g
+    ctx.sync()
+    sc.close()
+
+
+def _replays_between_frames(hd, ctx, sc, g, cams, lens, light, params, H, W):
+    res = {}
+    for replays in (0, 2):
+        hd.hdof_history_reset(ctx)
+        o = []
+        for t in range(3):
+            ot = torch.empty(3, H, W, device=DEV)
+            hd.hdof_frame(ctx, sc, cams[t], cams[t - 1] if t else None, lens, light, params, frame=t, out=ot)
+            torch.cuda.synchronize()
+            for _ in range(replays):
+                g.replay()
+                torch.cuda.synchronize()
+            o.append(ot)
+        h = hd.hdof_history_save(ctx, H, W)
+        torch.cuda.synchronize()
+        res[replays] = (o, h)
+    for t in range(3):
+        assert torch.equal(res[0][0][t], res[2][0][t]), t
+    for k in ("lum_m1", "lum_m2", "flags", "depth"):
+        assert torch.equal(res[0][1][k], res[2][1][k]), k
 
 
 @pytest.mark.parametrize("overlap", [1, 0])
