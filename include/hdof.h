@@ -377,6 +377,26 @@ hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, const float* d_
                             const hdof_camera* cam, const hdof_lens* lens,
                             const hdof_pp_params* params, float* d_out, hdof_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * post-filter as hdof_postfilter, same kernels and same results bit for bit,
+ * with its scratch (tap table, tile radii, dilated radii, packed texels) in
+ * one file-scope device array of HDOF_POSTFILTER_NOALLOC_BYTES that every
+ * device the library runs on holds from the library's first context on that
+ * device until the process ends.  It calls no hipMalloc, hipFree or
+ * allocating routine; the caller still owns d_color, d_depth and d_out.
+ * Images above HDOF_POSTFILTER_NOALLOC_MAX_PX pixels (2560 x 1440) are
+ * refused with HDOF_ERR_CAPACITY before any launch; other arguments are
+ * checked as for hdof_postfilter.  Every call on one device shares that
+ * device's array: calls whose work overlaps on one device (two streams, two
+ * contexts, two threads) race; a call rewrites everything it reads, so
+ * nothing needs clearing between calls. */
+#define HDOF_POSTFILTER_NOALLOC_MAX_PX 3686400
+#define HDOF_POSTFILTER_NOALLOC_BYTES (4096u + 2u * 954624u + 16u * HDOF_POSTFILTER_NOALLOC_MAX_PX) /* 58.1 MiB */
+hdof_status hdof_postfilter_noalloc(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                                    const hdof_camera* cam, const hdof_lens* lens,
+                                    const hdof_pp_params* params, float* d_out, hdof_stream stream);
+
 /* The post-filter plus the post-filtered specular luminance (paper,
  * Composite: the specular component's intensity in the post-process colour):
  * hdof_postfilter on d_color into d_out, and the same gather (radius, taps,

@@ -204,6 +204,12 @@ extern "C" hdof_status hdof_create(int device, hdof_ctx** out) {
     delete c;
     return hdof_set_error(HDOF_ERR_HIP, "init: %s", hipGetErrorString(e));
   }
+  // the no-alloc post-filter's scratch address on this device (current now)
+  const hdof_status ns = postfilter_noalloc_init(device, &c->noalloc_scratch);
+  if (ns != HDOF_OK) {
+    hdof_destroy(c);
+    return ns;
+  }
   *out = c;
   return HDOF_OK;
 }
@@ -543,6 +549,19 @@ extern "C" hdof_status hdof_postfilter(hdof_ctx* ctx, const float* d_color, cons
   TRY(check_pp(params));
   CamK k = make_camk(cam);
   return launch_postfilter(ctx, d_color, d_depth, k, make_lensk(lens, k), *params, d_out, (hipStream_t)stream);
+}
+
+extern "C" hdof_status hdof_postfilter_noalloc(hdof_ctx* ctx, const float* d_color, const float* d_depth,
+                                               const hdof_camera* cam, const hdof_lens* lens,
+                                               const hdof_pp_params* params, float* d_out, hdof_stream stream) {
+  TRY(check_ctx(ctx));
+  REQUIRE(d_color && d_depth && d_out, "color, depth and out must be non-NULL");
+  TRY(check_camera(cam, "current"));
+  TRY(check_lens(lens));
+  TRY(check_pp(params));
+  CamK k = make_camk(cam);
+  return launch_postfilter_noalloc(ctx, d_color, d_depth, k, make_lensk(lens, k), *params, d_out,
+                                   (hipStream_t)stream);
 }
 
 extern "C" hdof_status hdof_postfilter_specular(hdof_ctx* ctx, const float* d_color, const float* d_depth,

@@ -72,6 +72,9 @@ struct hdof_ctx {
   Buf mask_auto;  // tile 0: per-score-block CoC radius maxima + the chosen tile edge
   // post-filter scratch
   Buf pp_pack, pp_tile, pp_rad, pp_taps;
+  // the no-alloc post-filter's scratch on this context's device (the
+  // address hipGetSymbolAddress gave for the library's file-scope array)
+  void* noalloc_scratch = nullptr;
   int pp_taps_n = 0;  // tap count the table currently holds
   int pp_taps_blades = 0;
   float pp_taps_rot = 0.0f, pp_taps_sa = 0.0f;  // and the aperture it was built for
@@ -389,6 +392,11 @@ struct PostFuse {
 hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, const hdof_pp_params& pp,
                                hipStream_t st);
 // packed: pack and per-tile radius already written (by the G-buffer)
+// the no-alloc post-filter: the scratch address on the current device
+// (looked up once per device), and the launch into it
+hdof_status postfilter_noalloc_init(int device, void** out);
+hdof_status launch_postfilter_noalloc(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
+                                      const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st);
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
                               bool packed = false, const PostFuse* fuse = nullptr);

@@ -13,6 +13,8 @@
 // k_composite: focus zone / near / far rules, one pass over the pixels.
 #include "hdof_internal.h"
 
+#include <mutex>
+
 namespace {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -1164,20 +1166,28 @@ hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, con
   return HDOF_OK;
 }
 
-hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
-                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st, bool packed,
-                              const PostFuse* fuse) {
+namespace {
+
+// where one post-filter call keeps its intermediates
+struct PPScratch {
+  float4* pack;   // packed texels (rgb, signed CoC), one per pixel
+  float* tile;    // per-tile maximum CoC radius
+  float* rad;     // dilated tile radius (tiles other than 16 px)
+  float4* taps;   // tap table, 256 entries
+};
+
+hdof_status postfilter_run(hdof_ctx* ctx, const PPScratch& S, const float* color, const float* depth,
+                           const CamK& k, const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
+                           bool packed, const PostFuse* fuse) {
   const int W = k.W, H = k.H, t = pp.tile;
   const int TW = cdiv(W, t), TH = cdiv(H, t);
   const int K = (int)ceil((double)pp.r_cap / t);
-  hdof_status s;
-  if ((s = postfilter_reserve(ctx, k, l, pp, st)) != HDOF_OK) return s;
   if (!packed)
     hipLaunchKernelGGL(k_pp_pack, dim3(cdiv(W, 16) * cdiv(H, 16)), dim3(256), 0, st, color, depth, k, l, t,
-                       (float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p);
+                       S.pack, S.tile);
   if (t != 16)
-    hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)ctx->pp_tile.p, TW,
-                       TH, K, pp.r_cap, (float*)ctx->pp_rad.p);
+    hipLaunchKernelGGL(k_pp_dilate, dim3(cdiv(TW, 64), TH), dim3(64), 0, st, (const float*)S.tile, TW,
+                       TH, K, pp.r_cap, S.rad);
   hdof_prof_mark(ctx, 8, st);
   if (t == 16) {
     const bool sa = l.sa != 0.0f;
@@ -1187,27 +1197,27 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
       // beside the trace (the overlapped frame) the four-wave form: the quad
       // form finishes sooner but takes the trace's issue slots on the way
       auto kern = sa ? k_pp_gather16<2, true> : k_pp_gather16<2, false>;
-      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
-                         (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
+      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)S.pack,
+                         (const float*)S.tile, K, pp.r_cap, (const float4*)S.taps, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     } else if (fuse) {
       fz = FuseK{fuse->spp, fuse->rt.c_near, fuse->rt.c_far, fuse->rt.hit_ratio, 1.0f / fuse->cp.h_t,
                  fuse->cp.rt_override, fuse->out, fuse->pps,
                  fuse->pps && fuse->cp.spec_y > 0.0f ? 1.0f / fuse->cp.spec_y : 0.0f};
       auto kern = sa ? k_pp_gather16q<1, true> : k_pp_gather16q<1, false>;
-      hipLaunchKernelGGL(kern, dim3((TW * TH + 3) / 4), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
-                         (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
+      hipLaunchKernelGGL(kern, dim3((TW * TH + 3) / 4), dim3(256), 0, st, (const float4*)S.pack,
+                         (const float*)S.tile, K, pp.r_cap, (const float4*)S.taps, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     } else {
       auto kern = sa ? k_pp_gather16q<0, true> : k_pp_gather16q<0, false>;
-      hipLaunchKernelGGL(kern, dim3((TW * TH + 3) / 4), dim3(256), 0, st, (const float4*)ctx->pp_pack.p,
-                         (const float*)ctx->pp_tile.p, K, pp.r_cap, (const float4*)ctx->pp_taps.p, pp.n_taps, W, H,
+      hipLaunchKernelGGL(kern, dim3((TW * TH + 3) / 4), dim3(256), 0, st, (const float4*)S.pack,
+                         (const float*)S.tile, K, pp.r_cap, (const float4*)S.taps, pp.n_taps, W, H,
                          1.0f / pp.bg_ramp_px, out, fz);
     }
   } else {
     hipLaunchKernelGGL(k_pp_gather_any, dim3(cdiv(W, 16), cdiv(H, 16)), dim3(256), 0, st,
-                       (const float4*)ctx->pp_pack.p, (const float*)ctx->pp_rad.p,
-                       (const float4*)ctx->pp_taps.p, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
+                       (const float4*)S.pack, (const float*)S.rad,
+                       (const float4*)S.taps, pp.n_taps, W, H, t, 1.0f / pp.bg_ramp_px, out);
     if (fuse && !fuse->untraced_only) {
       HDOF_HIP(hipGetLastError());
       return launch_composite(ctx, color, out, depth, fuse->spp, fuse->rt, k, l, fuse->cp, fuse->out, st,
@@ -1216,6 +1226,75 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
   }
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
+}
+
+}  // namespace
+
+hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
+                              const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st, bool packed,
+                              const PostFuse* fuse) {
+  hdof_status s;
+  if ((s = postfilter_reserve(ctx, k, l, pp, st)) != HDOF_OK) return s;
+  const PPScratch S{(float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p, (float*)ctx->pp_rad.p, (float4*)ctx->pp_taps.p};
+  return postfilter_run(ctx, S, color, depth, k, l, pp, out, st, packed, fuse);
+}
+
+// ---------------------------------------------------------------------------
+// The post-filter without allocation: its intermediates live in `scratch`,
+// one file-scope device array per device (tap table, tile radii, dilated
+// tile radii, packed texels), sized for images of up to
+// HDOF_POSTFILTER_NOALLOC_MAX_PX pixels.  In host code `scratch` names a
+// host-side stand-in, never device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device when the library's first context on it is created.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t NA_TAPS_BYTES = 256 * sizeof(float4);
+// tile radii at the smallest tile (4 px) of any W x H <= the maximum with
+// W, H <= 16384: ceil(W/4) ceil(H/4) <= N/16 + (W + H)/4 + 1
+constexpr size_t NA_TILES = (size_t)HDOF_POSTFILTER_NOALLOC_MAX_PX / 16 + 8193;
+constexpr size_t NA_TILE_BYTES = (NA_TILES * sizeof(float) + 255) / 256 * 256;
+constexpr size_t NA_BYTES = NA_TAPS_BYTES + 2 * NA_TILE_BYTES + sizeof(float4) * (size_t)HDOF_POSTFILTER_NOALLOC_MAX_PX;
+static_assert(NA_BYTES == (size_t)HDOF_POSTFILTER_NOALLOC_BYTES, "header size of the no-alloc scratch");
+constexpr int NA_MAX_DEVICES = 64;
+
+std::mutex na_mu;
+void* na_ptr[NA_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+hdof_status postfilter_noalloc_init(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= NA_MAX_DEVICES)
+    return hdof_set_error(HDOF_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", device, NA_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(na_mu);
+  if (!na_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return hdof_set_error(HDOF_ERR_HIP, "no-alloc scratch address on device %d: %s", device, hipGetErrorString(e));
+    na_ptr[device] = p;
+  }
+  *out = na_ptr[device];
+  return HDOF_OK;
+}
+
+hdof_status launch_postfilter_noalloc(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
+                                      const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st) {
+  if ((size_t)k.W * (size_t)k.H > (size_t)HDOF_POSTFILTER_NOALLOC_MAX_PX)
+    return hdof_set_error(HDOF_ERR_CAPACITY, "%dx%d exceeds the no-alloc post-filter's %d pixels", k.W, k.H,
+                          HDOF_POSTFILTER_NOALLOC_MAX_PX);
+  unsigned char* base = (unsigned char*)ctx->noalloc_scratch;
+  if (!base) return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the context holds no no-alloc scratch");
+  const PPScratch S{(float4*)(base + NA_TAPS_BYTES + 2 * NA_TILE_BYTES), (float*)(base + NA_TAPS_BYTES),
+                    (float*)(base + NA_TAPS_BYTES + NA_TILE_BYTES), (float4*)base};
+  // the tap table is rebuilt every call: the array keeps whatever the last
+  // call on this device left in it
+  const int blades = l.blades >= 3 ? l.blades : 0;
+  hipLaunchKernelGGL(k_pp_taps, dim3(1), dim3(256), 0, st, pp.n_taps, blades,
+                     (double)l.rot_ht * 3.14159265358979323846, l.sa, S.taps);
+  return postfilter_run(ctx, S, color, depth, k, l, pp, out, st, false, nullptr);
 }
 
 hdof_status launch_composite(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,

@@ -99,6 +99,7 @@ class Tuning(C.Structure):
 
 
 MAX_VIEWS = 64
+POSTFILTER_NOALLOC_MAX_PX = 3686400  # HDOF_POSTFILTER_NOALLOC_MAX_PX
 
 
 class SceneInfo(C.Structure):
@@ -133,6 +134,7 @@ _PROTOS = {
     "hdof_history_save": (_S, [P, P, P, P, P, P]),
     "hdof_history_reset": (_S, [P]),
     "hdof_postfilter": (_S, [P, P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(PPParams), P, P]),
+    "hdof_postfilter_noalloc": (_S, [P, P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(PPParams), P, P]),
     "hdof_composite": (_S, [P, P, P, P, P, RTBufs, C.POINTER(Camera), C.POINTER(Lens),
                             C.POINTER(CompositeParams), P, P, P]),
     "hdof_postfilter_specular": (_S, [P, P, P, P, P, C.POINTER(Camera), C.POINTER(Lens), C.POINTER(PPParams),
@@ -486,6 +488,18 @@ def hdof_postfilter(ctx: Context, color, depth, cam: Camera, lns: Lens, pp: PPPa
     _check(_lib.hdof_postfilter(ctx.handle, _ptr(color, torch.float32, 3 * n, "color"),
                                 _ptr(depth, torch.float32, n, "depth"), C.byref(cam), C.byref(lns), C.byref(pp),
                                 _ptr(out, torch.float32, 3 * n, "out"), _stream(stream)), "hdof_postfilter")
+    return out
+
+
+def hdof_postfilter_noalloc(ctx: Context, color, depth, cam: Camera, lns: Lens, pp: PPParams, out,
+                            stream=None):
+    """hdof_postfilter with the library's fixed device scratch (no device
+    allocation in the call); `out` is required."""
+    n = _npx(cam)
+    _check(_lib.hdof_postfilter_noalloc(ctx.handle, _ptr(color, torch.float32, 3 * n, "color"),
+                                        _ptr(depth, torch.float32, n, "depth"), C.byref(cam), C.byref(lns),
+                                        C.byref(pp), _ptr(out, torch.float32, 3 * n, "out"), _stream(stream)),
+           "hdof_postfilter_noalloc")
     return out
 
 
