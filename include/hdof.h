@@ -515,6 +515,36 @@ typedef struct {
 hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* tuning);
 hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
 
+/* The library's autotuner of the launch shape (the spec batched
+ * form's "tile and queue sizes chosen by a project-written autotuner"; the
+ * paper has none).  It times the caller's workload -- hdof_frame on
+ * views[0] with no previous camera when n_views = 1, hdof_frame_batched on
+ * all views otherwise -- on `stream` under candidate tunings (coordinate
+ * descent from the defaults over blocks_per_cu, refill, segments, wave,
+ * and for single frames overlap and overlap_ray_quantum; a change is kept
+ * when it is at least 0.5 % faster; each candidate is the median of
+ * several timed runs), sets the fastest on the context and returns it in
+ * *out.  The workload's outputs (views[v].d_out) are written, and for a
+ * single frame the context's variance history is replaced (every timed
+ * frame is a first frame).  cache_path (nullable): a JSON-lines file, one
+ * object per workload class keyed by the device's architecture, its CU
+ * count and the class (image sizes, spp_max, tiles, the scene's triangle
+ * count as a power of two, view count, optional stages); an entry for the
+ * class is applied without timing unless force != 0, and a search writes
+ * (or replaces) its entry.  Not under stream capture
+ * (HDOF_ERR_UNSUPPORTED); not thread-safe per context or per cache file. */
+typedef struct {
+  char key[256];        /* the workload class */
+  float best_ms;        /* per run of the workload under the chosen tuning */
+  float default_ms;     /* per run under the defaults (as cached, for cache hits) */
+  int32_t candidates;   /* tunings timed (0: taken from the cache) */
+  int32_t from_cache;
+} hdof_autotune_report;
+hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
+                          const hdof_frame_params* params, int32_t n_views, const hdof_view* views,
+                          const char* cache_path, int32_t force, hdof_tuning* out,
+                          hdof_autotune_report* report, hdof_stream stream);
+
 /* ---------------------------------------------------------------------- */
 /* Differentiable form                                                      */
 /* ---------------------------------------------------------------------- */

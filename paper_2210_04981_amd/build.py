@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libhdof.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "bvh.hip", "trace.hip", "mask.hip", "postfilter.hip", "recon.hip", "spatial.hip"]
+SOURCES = ["api.hip", "bvh.hip", "trace.hip", "mask.hip", "postfilter.hip", "recon.hip", "spatial.hip",
+           "autotune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

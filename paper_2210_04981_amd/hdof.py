@@ -98,6 +98,11 @@ class Tuning(C.Structure):
                 ("overlap", C.c_int32), ("overlap_ray_quantum", C.c_int32)]
 
 
+class AutotuneReport(C.Structure):
+    _fields_ = [("key", C.c_char * 256), ("best_ms", C.c_float), ("default_ms", C.c_float),
+                ("candidates", C.c_int32), ("from_cache", C.c_int32)]
+
+
 MAX_VIEWS = 64
 POSTFILTER_NOALLOC_MAX_PX = 3686400  # HDOF_POSTFILTER_NOALLOC_MAX_PX
 
@@ -151,6 +156,8 @@ _PROTOS = {
     "hdof_batch_destroy": (None, [P]),
     "hdof_set_tuning": (_S, [P, C.POINTER(Tuning)]),
     "hdof_get_tuning": (_S, [P, C.POINTER(Tuning)]),
+    "hdof_autotune": (_S, [P, P, C.POINTER(Light), C.POINTER(FrameParams), _i32, C.POINTER(View), C.c_char_p, _i32,
+                           C.POINTER(Tuning), C.POINTER(AutotuneReport), P]),
     "hdof_postfilter_composite_backward": (_S, [P, P, P, P, RTBufs, C.POINTER(Camera), C.POINTER(Lens),
                                                 C.POINTER(PPParams), C.POINTER(CompositeParams), P, P, P, P]),
     "hdof_counters_begin": (_S, [P]),
@@ -702,6 +709,27 @@ def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8, wave=
                     overlap_ray_quantum=140000) -> None:
     t = Tuning(int(blocks_per_cu), int(refill), int(segments), int(wave), int(overlap), int(overlap_ray_quantum))
     _check(_lib.hdof_set_tuning(ctx.handle, C.byref(t)), "hdof_set_tuning")
+
+
+def hdof_autotune(ctx: Context, scene: Scene, lit: Light, params: FrameParams, views, outs=None,
+                  cache_path: str | None = None, force: bool = False, stream=None) -> tuple[dict, dict]:
+    """Search (or load from `cache_path`) the fastest launch shape for the
+    workload: one view = hdof_frame, several = hdof_frame_batched; `views`
+    as for hdof_frame_batched.  Returns (tuning, report); the tuning is set
+    on the context."""
+    if outs is None:
+        outs = [torch.empty(3, v[0].height, v[0].width, dtype=torch.float32, device="cuda") for v in views]
+    arr = _views(views, outs)
+    t = Tuning()
+    rep = AutotuneReport()
+    _check(_lib.hdof_autotune(ctx.handle, scene.handle, C.byref(lit), C.byref(params), len(views), arr,
+                              None if cache_path is None else str(cache_path).encode(), int(bool(force)),
+                              C.byref(t), C.byref(rep), _stream(stream)), "hdof_autotune")
+    tuning = dict(blocks_per_cu=t.blocks_per_cu, refill=t.refill, segments=t.segments, wave=t.wave,
+                  overlap=t.overlap, overlap_ray_quantum=t.overlap_ray_quantum)
+    report = dict(key=rep.key.decode(), best_ms=rep.best_ms, default_ms=rep.default_ms,
+                  candidates=rep.candidates, from_cache=bool(rep.from_cache))
+    return tuning, report
 
 
 def hdof_get_tuning(ctx: Context) -> dict:

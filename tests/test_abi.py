@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(hd):
 def test_struct_layout_matches_header(hd, tmp_path):
     structs = ["hdof_camera", "hdof_lens", "hdof_light", "hdof_mask_params", "hdof_pp_params",
                "hdof_composite_params", "hdof_frame_params", "hdof_gbuffer_bufs", "hdof_rt_bufs",
-               "hdof_frame_bufs", "hdof_scene_info", "hdof_view", "hdof_tuning"]
+               "hdof_frame_bufs", "hdof_scene_info", "hdof_view", "hdof_tuning", "hdof_autotune_report"]
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "hdof.h"\nint main(void){\n' +
                    "".join(f'printf("%zu\\n", sizeof({s}));\n' for s in structs) + "return 0;}\n")
@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(hd, tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     py = [hd.Camera, hd.Lens, hd.Light, hd.MaskParams, hd.PPParams, hd.CompositeParams, hd.FrameParams,
-          hd.GBufferBufs, hd.RTBufs, hd.FrameBufs, hd.SceneInfo, hd.View, hd.Tuning]
+          hd.GBufferBufs, hd.RTBufs, hd.FrameBufs, hd.SceneInfo, hd.View, hd.Tuning, hd.AutotuneReport]
     assert sizes == [C.sizeof(t) for t in py]
 
 
@@ -78,6 +78,11 @@ def test_null_arguments_rejected(hd):
                                       None, None, None) == INVALID
     assert L.hdof_scene_set_specular(None, None, None) == INVALID
     assert L.hdof_history_reset(None) == INVALID
+    assert L.hdof_postfilter_noalloc(None, None, None, C.byref(cam), C.byref(lns), C.byref(pp), None, None) == INVALID
+    fp = hd.FrameParams()
+    t = hd.Tuning()
+    assert L.hdof_autotune(None, None, C.byref(lit), C.byref(fp), 1, None, None, 0, C.byref(t), None,
+                           None) == INVALID
     h = C.c_void_p()
     assert L.hdof_build_bvh(None, None, None, 1, C.byref(h), None) == INVALID
     L.hdof_destroy(None)

@@ -1,0 +1,94 @@
+"""GPU tests of the library's autotuner of the launch shape: it searches,
+keeps a shape no slower than the defaults it timed, sets it on the context,
+writes a JSON-lines cache entry keyed by architecture, CU count and
+workload class that a second call applies without timing, and (the knobs
+being scheduling only) frames under the tuned shape equal frames under the
+defaults bit for bit; the batched form is tuned as a batch."""
+import json
+
+import pytest
+import torch
+
+import scenegen as sg
+from gpu_common import print_case, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    from paper_2210_04981_amd import hdof
+    return hdof
+
+
+@pytest.fixture(scope="module")
+def ctx(hd):
+    c = hd.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def room(hd, ctx):
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    yield sc
+    sc.close()
+
+
+def test_autotune_frame_and_cache(hd, ctx, room, tmp_path):
+    print_case("autotune a 640x360 frame")
+    cfg = sg.config_1080p(640, 360)
+    params = hd.frame_params_of(cfg)
+    light = hd.light_of(cfg.light)
+    view = (hd.camera_of(cfg.camera), hd.lens_of(cfg.lens), 0, 0, 0)
+    hd.hdof_set_tuning(ctx)
+    ref = hd.hdof_frame(ctx, room, view[0], None, view[1], light, params).clone()
+    cache = tmp_path / "autotune.jsonl"
+    tuning, rep = hd.hdof_autotune(ctx, room, light, params, [view], cache_path=cache)
+    print(tuning, rep, flush=True)
+    assert rep["candidates"] > 8 and not rep["from_cache"]
+    assert 0 < rep["best_ms"] <= rep["default_ms"]
+    assert rep["key"].startswith("gfx950|") and "frame 640x360 spp8" in rep["key"]
+    assert hd.hdof_get_tuning(ctx) == tuning
+    out = hd.hdof_frame(ctx, room, view[0], None, view[1], light, params)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    lines = [json.loads(l) for l in cache.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0]["key"] == rep["key"]
+    assert {k: lines[0][k] for k in tuning} == tuning
+    # a second call applies the cached entry without timing
+    hd.hdof_set_tuning(ctx)
+    t2, rep2 = hd.hdof_autotune(ctx, room, light, params, [view], cache_path=cache)
+    assert rep2["from_cache"] and rep2["candidates"] == 0 and t2 == tuning
+    assert hd.hdof_get_tuning(ctx) == tuning
+    # another class gets its own entry; forcing searches again
+    cfg2 = sg.config_1080p(320, 180)
+    view2 = (hd.camera_of(cfg2.camera), hd.lens_of(cfg2.lens), 0, 0, 0)
+    _, rep3 = hd.hdof_autotune(ctx, room, light, hd.frame_params_of(cfg2), [view2], cache_path=cache)
+    assert not rep3["from_cache"] and rep3["key"] != rep["key"]
+    _, rep4 = hd.hdof_autotune(ctx, room, light, params, [view], cache_path=cache, force=True)
+    assert not rep4["from_cache"] and rep4["candidates"] > 8
+    keys = [json.loads(l)["key"] for l in cache.read_text().splitlines()]
+    assert sorted(keys) == sorted({rep["key"], rep3["key"]})
+    hd.hdof_set_tuning(ctx)
+
+
+def test_autotune_batch(hd, ctx, room):
+    print_case("autotune a 3-view batch")
+    cfg = sg.config_1080p()
+    views = []
+    for v, (w, h) in enumerate([(320, 180), (256, 144), (160, 90)]):
+        cam = sg.look_camera((0.05 * v, 0.0, 0.0), 3.0 * v, w, h)
+        views.append((hd.camera_of(cam), hd.lens_of(sg.lens_fnumber(0.05, 2.0, 1.5 + v)), 5, 1, v))
+    params, light = hd.frame_params_of(cfg), hd.light_of(cfg.light)
+    hd.hdof_set_tuning(ctx)
+    ref = [o.clone() for o in hd.hdof_frame_batched(ctx, room, light, params, views)]
+    tuning, rep = hd.hdof_autotune(ctx, room, light, params, views)
+    print(tuning, rep, flush=True)
+    assert "batch 3 views" in rep["key"] and rep["candidates"] > 4
+    assert rep["best_ms"] <= rep["default_ms"]
+    outs = hd.hdof_frame_batched(ctx, room, light, params, views)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, ref):
+        assert torch.equal(a, b)
+    hd.hdof_set_tuning(ctx)
