@@ -468,8 +468,11 @@ typedef struct {
  * batched.
  * Every view's G-buffer, mask, post-filter and composite (one launch each),
  * one device-side scan of the per-view ray totals, ONE queue over all views
- * and ONE persistent thin-lens trace launch for the whole batch.  No
- * variance history (each view is a first frame).  1 <= n_views <=
+ * and ONE persistent thin-lens trace launch for the whole batch.  With
+ * 16-pixel post-filter tiles and the tuning's overlap on, every view's
+ * gather runs on the context's second stream beside the masks and the
+ * trace (as in hdof_frame), the composite after both.  No variance history
+ * (each view is a first frame).  1 <= n_views <=
  * HDOF_MAX_VIEWS; all views share the scene, light and parameters. */
 hdof_status hdof_frame_batched(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
                                const hdof_frame_params* params, int32_t n_views,

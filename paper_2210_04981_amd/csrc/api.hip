@@ -229,6 +229,7 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->sp_cn, &ctx->sp_cf, &ctx->sp_coc};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->b_view_ready) hipEventDestroy(e);
   buf_free(ctx->ppb_args);
   buf_free(ctx->ppb_partial);
   buf_free(ctx->b_arena);
@@ -933,13 +934,24 @@ extern "C" hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* t) {
 // ---------------------------------------------------------------------------
 // batched form
 // ---------------------------------------------------------------------------
+// the overlapped batch hands its views' gathers to the second stream in
+// this many chunks
+#ifndef HDOF_BATCH_FORKS
+#define HDOF_BATCH_FORKS 4
+#endif
+
 struct BatchLayout {
   int n;
   long npx, max_px;
   int max_w, max_h;
   BatchView hv[HDOF_MAX_VIEWS];
-  // byte offsets of each concatenated plane set in the arena
-  size_t o_depth, o_normal, o_albedo, o_color, o_tri, o_spp, o_offs, o_cn, o_cf, o_h, o_m1, o_m2, o_pp, total;
+  // first 16-pixel post-filter tile of each view in the concatenated tile radii
+  long tile_base[HDOF_MAX_VIEWS];
+  long ntiles;
+  // byte offsets of each concatenated plane set in the arena (o_pack, o_ptile:
+  // every view's packed texels and tile radii, for the overlapped batch)
+  size_t o_depth, o_normal, o_albedo, o_color, o_tri, o_spp, o_offs, o_cn, o_cf, o_h, o_m1, o_m2, o_pp, o_pack,
+      o_ptile, total;
 };
 
 static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
@@ -969,6 +981,7 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
   L.npx = 0;
   L.max_px = 0;
   L.max_w = L.max_h = 0;
+  L.ntiles = 0;
   for (int v = 0; v < n_views; ++v) {
     TRY(check_camera(&views[v].cam, "view"));
     TRY(check_lens(&views[v].lens));
@@ -979,6 +992,8 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
     L.hv[v] = BatchView{k, make_lensk(&views[v].lens, k), views[v].seed, views[v].frame, views[v].view, (int)L.npx};
     long n = (long)k.W * k.H;
     L.npx += n;
+    L.tile_base[v] = L.ntiles;
+    L.ntiles += (long)((k.W + 15) / 16) * ((k.H + 15) / 16);
     if (n > L.max_px) L.max_px = n;
     if (k.W > L.max_w) L.max_w = k.W;
     if (k.H > L.max_h) L.max_h = k.H;
@@ -1003,6 +1018,9 @@ static hdof_status batch_check(hdof_ctx* ctx, const hdof_scene* scene, const hdo
   L.o_m1 = carve(4);
   L.o_m2 = carve(4);
   L.o_pp = carve(12);
+  L.o_pack = carve(16);
+  L.o_ptile = off;
+  off += ((size_t)L.ntiles * sizeof(float) + 255) & ~(size_t)255;
   L.total = off;
   return HDOF_OK;
 }
@@ -1026,6 +1044,11 @@ static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params,
   TRY(hdof_ensure(ctx->pp_tile, sizeof(float) * ptiles));
   TRY(hdof_ensure(ctx->pp_rad, sizeof(float) * ptiles));
   TRY(hdof_ensure(ctx->pp_taps, 16 * 256));
+  while ((int)ctx->b_view_ready.size() < L.n) {
+    hipEvent_t e;
+    HDOF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->b_view_ready.push_back(e);
+  }
   return HDOF_OK;
 }
 
@@ -1041,6 +1064,16 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
   HDOF_HIP(hipMemcpyAsync(ctx->b_views.p, table_host, batch_view_bytes() * L.n, hipMemcpyHostToDevice, st));
   LightK li = make_lightk(light);
   hdof_rt_bufs rt[HDOF_MAX_VIEWS];
+  // overlapped batch (16-pixel post-filter tiles, overlap on): every view's
+  // G-buffer packs its texels and tile radii, and that view's gather then
+  // runs on the context's second stream beside the later views' G-buffers,
+  // the masks and the one trace, writing its untraced pixels' composite;
+  // after the join a sparse composite rewrites each view's traced pixels --
+  // the overlapped frame's order, view by view
+  const bool ovl = ctx->tune.overlap != 0 && params->pp.tile == 16;
+  float4* packs = (float4*)(a + L.o_pack);
+  float* ptiles = (float*)(a + L.o_ptile);
+  if (ovl) TRY(postfilter_reserve(ctx, L.hv[0].k, L.hv[0].l, params->pp, st));  // tap table, before the fork
   for (int v = 0; v < L.n; ++v) {
     const BatchView& bv = L.hv[v];
     const size_t pb = (size_t)bv.px_base;
@@ -1056,13 +1089,34 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     rt[v].hit_ratio = (float*)(a + L.o_h) + pb;
     rt[v].lum_m1 = (float*)(a + L.o_m1) + pb;
     rt[v].lum_m2 = (float*)(a + L.o_m2) + pb;
-    TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
+    if (ovl) {
+      TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st, packs + pb, ptiles + L.tile_base[v]));
+      // the second stream takes the views in HDOF_BATCH_FORKS chunks: each
+      // cross-stream dependency costs a replayed graph tens of microseconds
+      const int chunk = (L.n + HDOF_BATCH_FORKS - 1) / HDOF_BATCH_FORKS;
+      if ((v + 1) % chunk == 0 || v == L.n - 1) {
+        HDOF_HIP(hipEventRecord(ctx->b_view_ready[v], st));
+        HDOF_HIP(hipStreamWaitEvent(ctx->side, ctx->b_view_ready[v], 0));
+        hdof_rt_bufs none;
+        memset(&none, 0, sizeof none);
+        for (int u = v - (v % chunk); u <= v; ++u) {
+          const size_t ub = (size_t)L.hv[u].px_base;
+          const PostFuse pu{nullptr, none, params->comp, views[u].d_out, nullptr, true};
+          TRY(launch_postfilter_packed(ctx, packs + ub, ptiles + L.tile_base[u], L.hv[u].k, L.hv[u].l,
+                                       params->pp, (float*)(a + L.o_pp) + 3 * ub, ctx->side, &pu));
+        }
+      }
+    } else {
+      TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
+    }
     TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
                     (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l, false));
   }
+  if (ovl) HDOF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
   TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
                            (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,
                            st));
+  if (ovl) HDOF_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
   for (int v = 0; v < L.n; ++v) {
     const BatchView& bv = L.hv[v];
     const size_t pb = (size_t)bv.px_base;
@@ -1070,7 +1124,10 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     float* depth = (float*)(a + L.o_depth) + pb;
     float* pp = (float*)(a + L.o_pp) + 3 * pb;
     const uint8_t* spp = (const uint8_t*)(a + L.o_spp) + pb;
-    if (params->pp.tile == 16) {  // composite in the gather's epilogue, as in hdof_frame
+    if (ovl) {
+      TRY(launch_composite(ctx, color, pp, depth, spp, rt[v], bv.k, bv.l, params->comp, views[v].d_out, st,
+                           nullptr, true));
+    } else if (params->pp.tile == 16) {  // composite in the gather's epilogue, as in hdof_frame
       const PostFuse pf{spp, rt[v], params->comp, views[v].d_out};
       TRY(launch_postfilter(ctx, color, depth, bv.k, bv.l, params->pp, nullptr, st, false, &pf));
     } else {

@@ -223,8 +223,8 @@ extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, con
   if (s == HDOF_OK) s = time_tuning(w, best, warm, reps, ev.data(), &best_ms);
   rep.default_ms = best_ms;
   rep.candidates = 1;
-  // candidate values per knob; the batched form runs on one stream (overlap
-  // and its quantum do not apply)
+  // candidate values per knob (the batched form keeps every trace block: the
+  // ray quantum applies to single frames only)
   static const int bpc_v[] = {4, 6, 8, 10, 12, 16};
   static const int refill_v[] = {16, 32, 64};
   static const int seg_v[] = {1, 2, 4, 8};
@@ -238,7 +238,7 @@ extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, con
     bool frame_only;
   };
   const Knob knobs[] = {{&hdof_tuning::wave, wave_v, 2, false},
-                        {&hdof_tuning::overlap, ovl_v, 2, true},
+                        {&hdof_tuning::overlap, ovl_v, 2, false},
                         {&hdof_tuning::overlap_ray_quantum, quantum_v, 7, true},
                         {&hdof_tuning::blocks_per_cu, bpc_v, 6, false},
                         {&hdof_tuning::segments, seg_v, 4, false},

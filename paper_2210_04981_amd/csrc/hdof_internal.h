@@ -109,6 +109,9 @@ struct hdof_ctx {
   void* b_views_host = nullptr;
   size_t b_views_host_bytes = 0;
   hipEvent_t b_views_done = nullptr;
+  // overlapped batch: one event per view, recorded after its G-buffer (its
+  // gather on the second stream waits for it)
+  std::vector<hipEvent_t> b_view_ready;
   // traversal work counters (rays, node visits, triangle tests) x (G-buffer, trace)
   bool count_on = false;
   unsigned long long* d_counters = nullptr;
@@ -391,12 +394,18 @@ struct PostFuse {
 // (a frame that runs the gather on another stream calls it before forking)
 hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, const hdof_pp_params& pp,
                                hipStream_t st);
-// packed: pack and per-tile radius already written (by the G-buffer)
 // the no-alloc post-filter: the scratch address on the current device
 // (looked up once per device), and the launch into it
 hdof_status postfilter_noalloc_init(int device, void** out);
 hdof_status launch_postfilter_noalloc(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                                       const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st);
+// the 16-pixel-tile gather over texels a G-buffer packed into `pack` with
+// its tile radii in `tile_r` (the batched form: one pack per view); the
+// context's tap table must already hold this tap count and aperture
+hdof_status launch_postfilter_packed(hdof_ctx* ctx, const float4* pack, const float* tile_r, const CamK& k,
+                                     const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
+                                     const PostFuse* fuse);
+// packed: pack and per-tile radius already written (by the G-buffer)
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
                               bool packed = false, const PostFuse* fuse = nullptr);
