@@ -520,15 +520,21 @@ def bench_focus_fit(hdof, ctx, sc, cfg, plain_ms, steps=200):
     outs = [torch.empty(3, H, W, device="cuda") for _ in cams]
     Ad = torch.tensor(float(A), device="cuda")
 
-    def loss_at(S1, untraced_only):
+    def loss_at(S1, untraced_only, tgt=None, n_taps=None):
+        tgt = targets if tgt is None else tgt
+        ppx, prm = pp, params
+        if n_taps is not None:
+            ppx = hdof.pp_params(n_taps, cfg.pp.tile, cfg.pp.r_cap, cfg.pp.bg_ramp_px)
+            prm = hdof.frame_params_of(cfg)
+            prm.pp.n_taps = n_taps
         s_now = float(S1.detach())
         loss = None
         for t, cam in enumerate(cams):
-            hdof.hdof_frame(ctx, sc, cam, None, hdof.lens(f, A, s_now), light, params, seed=cfg.seed, frame=t,
+            hdof.hdof_frame(ctx, sc, cam, None, hdof.lens(f, A, s_now), light, prm, seed=cfg.seed, frame=t,
                             view=0, out=outs[t], keep=keeps[t], stream=stream)
             k = keeps[t]
-            o = hdof.HybridDoFPost.apply(k.gb.color, S1, Ad, k.gb.depth, k.spp, k.rt, cam, f, pp, cp, ctx)
-            d2 = (o - targets[t]) ** 2
+            o = hdof.HybridDoFPost.apply(k.gb.color, S1, Ad, k.gb.depth, k.spp, k.rt, cam, f, ppx, cp, ctx)
+            d2 = (o - tgt[t]) ** 2
             if untraced_only:
                 d2 = d2 * (k.spp == 0).to(d2.dtype)
             term = d2.sum()
@@ -559,9 +565,33 @@ def bench_focus_fit(hdof, ctx, sc, cfg, plain_ms, steps=200):
                 "ms_per_step": round(sec * 1e3 / steps, 3),
                 "ms_per_step_over_plain_frames": round(sec * 1e3 / steps / (8 * plain_ms), 3)}
 
+    def curve(n_taps):
+        with torch.no_grad():
+            return [[s1, round(float(loss_at(torch.tensor(s1, device="cuda"), True, n_taps=n_taps)), 1)]
+                    for s1 in (1.6, 1.8, 2.0, 2.05, 2.2, 2.5, 3.0, 3.5)]
+
+    def self_consistent(n_taps, s0, n=100):
+        """Target = the hybrid frame itself at S1 = 2 (same frames, seeds and
+        taps), post-filtered pixels: the loss is 0 at S1 = 2 exactly."""
+        prm = hdof.frame_params_of(cfg)
+        prm.pp.n_taps = n_taps
+        tgt = [hdof.hdof_frame(ctx, sc, cam, None, hdof.lens(f, A, 2.0), light, prm, seed=cfg.seed, frame=t,
+                               stream=stream).clone() for t, cam in enumerate(cams)]
+        S1 = torch.tensor(s0, device="cuda", requires_grad=True)
+        opt = torch.optim.Adam([S1], lr=0.02)
+        for _ in range(n):
+            opt.zero_grad()
+            loss = loss_at(S1, True, tgt=tgt, n_taps=n_taps)
+            loss.backward()
+            opt.step()
+        return {"n_taps": n_taps, "from": s0, "steps": n, "final_S1": round(float(S1.detach()), 4),
+                "final_loss": round(float(loss.detach()), 3)}
+
     return {"workload": "8 frames 1920x1080 (temporal camera path 0-7, living room), f/1.4; target = full ray "
                         "tracing at 16 spp and S1 = 2 m; Adam lr 0.02 from S1 = 3 m, 200 steps",
-            "all_pixels": fit(False), "post_filtered_pixels": fit(True)}
+            "all_pixels": fit(False), "post_filtered_pixels": fit(True),
+            "loss_curve_post_filtered": {"taps_48": curve(48), "taps_256": curve(256)},
+            "self_consistent": [self_consistent(256, 2.3), self_consistent(256, 3.0), self_consistent(48, 2.3)]}
 
 
 def bench_temporal(hdof, ctx, frames=60):
@@ -590,6 +620,11 @@ def bench_temporal(hdof, ctx, frames=60):
     keep = counts_keep(hdof, H, W)
     out = torch.empty(3, H, W, device="cuda")
     totals = torch.zeros(frames, dtype=torch.int32, device="cuda")
+    # the launch shape the autotuner picks for this workload class (timed on
+    # the path's first frame), restored afterwards
+    prior = hdof.hdof_get_tuning(ctx)
+    tuned, rep = hdof.hdof_autotune(ctx, sc, light, params, [(cams[0], lens, cfg.seed, 0, 0)], outs=[out],
+                                    stream=stream)
 
     def run(record=None):
         for t in range(frames):
@@ -603,7 +638,9 @@ def bench_temporal(hdof, ctx, frames=60):
     st = slice(10, frames)
     res = {"workload": f"{frames}-frame path (dolly 1 cm + yaw 0.2 deg per frame), 1920x1080, "
                        f"{scene.n_tris} triangles, f/1.4, focus 1.5 m, 0-16 spp, variance history",
-           "bvh_build_ms_host_timed": round(bvh_ms, 2), "bvh": sc.stats()}
+           "bvh_build_ms_host_timed": round(bvh_ms, 2), "bvh": sc.stats(),
+           "autotune": {"tuning": tuned, "tuned_ms": round(rep["best_ms"], 4), "default_ms": round(rep["default_ms"], 4),
+                        "candidates": rep["candidates"]}}
     runs = (("plain", 0, 0), ("reconstructed", 1, 0), ("reconstructed_spatial", 1, 1))
     for name, recon, spatial in runs:
         params.recon.enable, params.recon.alpha = recon, 0.2
@@ -633,6 +670,7 @@ def bench_temporal(hdof, ctx, frames=60):
                             frame=t, view=0, out=out, keep=keep, stream=stream)
         stage, nf = hdof.hdof_profile_end(ctx)
         res[name]["stage_ms"] = {k: round(v, 4) for k, v in stage.items()}
+    hdof.hdof_set_tuning(ctx, **prior)
     sc.close()
     return res
 

@@ -499,8 +499,9 @@ void hdof_batch_destroy(hdof_batch* batch);
  * wave (one node sequence, the union of their paths, with wave-uniform node
  * loads; refill is then unused), 0 traverses each lane's ray on its own and
  * refills idle lanes, 2 takes 1 for scenes of at least HDOF_WAVE_AUTO_TRIS
- * triangles (whose tree and triangles far exceed an XCD's L2, so 64 lane
- * fetches per node cost more than a longer shared walk) and 0 below; overlap 0
+ * triangles and 0 below (the per-lane form is the faster one on the 200k-
+ * and the 1M-triangle scenes measured; the wave form remains for callers
+ * and the autotuner to try); overlap 0
  * or 1: 1 runs hdof_frame's post-filter gather on a second stream of the
  * context beside the mask, trace and reconstruction (it needs only the
  * G-buffer) and applies the composite once both are done, the results
@@ -508,9 +509,9 @@ void hdof_batch_destroy(hdof_batch* batch);
  * trace keeps, on average, one block per CU for every overlap_ray_quantum
  * rays of the frame (at least one per CU, at most blocks_per_cu; the count
  * is read on the device, the other blocks return at once), so a light
- * trace leaves CUs to the gather and a heavy one keeps them.  Defaults {10, 64, 8, 2, 1,
- * 140000}: ten two-wave blocks per CU is the trace kernel's register-
- * limited residency (5 waves per SIMD), so every block starts at once. */
+ * trace leaves CUs to the gather and a heavy one keeps them.  Defaults {10, 64, 8, 0, 1,
+ * 140000}: ten two-wave blocks per CU (more are slower: the trace is bound
+ * by its per-CU cache working set and latency, not by resident waves). */
 #define HDOF_WAVE_AUTO_TRIS (1 << 19)
 typedef struct {
   int32_t blocks_per_cu, refill, segments, wave, overlap, overlap_ray_quantum;

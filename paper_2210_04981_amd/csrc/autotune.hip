@@ -213,7 +213,7 @@ extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, con
       return hdof_set_error(HDOF_ERR_HIP, "autotune events: %s", hipGetErrorString(he));
     }
   }
-  const hdof_tuning defaults = {HDOF_DEFAULT_BPC, 64, 8, 2, 1, 140000};
+  const hdof_tuning defaults = {HDOF_DEFAULT_BPC, 64, 8, 0, 1, 140000};
   hdof_tuning best = defaults;
   float best_ms = 0.0f;
   hdof_status s = HDOF_OK;

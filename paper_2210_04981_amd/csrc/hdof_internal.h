@@ -101,7 +101,7 @@ struct hdof_ctx {
   Buf f_depth, f_normal, f_albedo, f_color, f_triid, f_spp, f_offsets, f_total;
   Buf f_cn, f_cf, f_h, f_m1, f_m2, f_pp, f_spec, f_pps;
   // persistent-trace launch shape (performance only)
-  hdof_tuning tune = {HDOF_DEFAULT_BPC, 64, 8, 2, 1, 140000};
+  hdof_tuning tune = {HDOF_DEFAULT_BPC, 64, 8, 0, 1, 140000};
   // the trace's ray quantum while a frame overlaps it with the gather (0: all blocks)
   int trace_ray_quantum = 0;
   // batched form: per-view intermediates, view table (device + pinned host)

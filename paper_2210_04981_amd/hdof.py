@@ -705,7 +705,7 @@ class Batch:
             pass
 
 
-def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8, wave=2, overlap=1,
+def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8, wave=0, overlap=1,
                     overlap_ray_quantum=140000) -> None:
     t = Tuning(int(blocks_per_cu), int(refill), int(segments), int(wave), int(overlap), int(overlap_ray_quantum))
     _check(_lib.hdof_set_tuning(ctx.handle, C.byref(t)), "hdof_set_tuning")

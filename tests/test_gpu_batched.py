@@ -137,5 +137,5 @@ def test_tuning_does_not_change_results(hd, ctx, room):
         torch.cuda.synchronize()
         assert torch.equal(out, base), t
     hd.hdof_set_tuning(ctx)
-    assert hd.hdof_get_tuning(ctx) == dict(blocks_per_cu=10, refill=64, segments=8, wave=2, overlap=1,
+    assert hd.hdof_get_tuning(ctx) == dict(blocks_per_cu=10, refill=64, segments=8, wave=0, overlap=1,
                                            overlap_ray_quantum=140000)
