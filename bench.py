@@ -47,8 +47,13 @@ def parse():
     ap.add_argument("--settle-ms", type=float, default=150.0,
                     help="wall time of frames run before the warm-up so the GPU clocks leave their idle ramp")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--overlap", type=int, choices=(0, 1), default=None,
+                    help="force the frame's overlap knob (profiling a kernel alone or beside the gather); "
+                         "default: the autotuner's choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and backward timings")
+    ap.add_argument("--forms", default="batched,backward,focus_fit,temporal,scaled_mask,specular,aperture",
+                    help="comma-separated forms to run (profiling one of them)")
     ap.add_argument("--scene-seed", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (a counter calibration "
@@ -120,6 +125,8 @@ def main():
         tuned, rep = hdof.hdof_autotune(ctx, sc, light, params, [view], outs=[out], stream=stream)
         autotune = {"tuning": tuned, "tuned_ms": round(rep["best_ms"], 4), "default_ms": round(rep["default_ms"], 4),
                     "candidates": rep["candidates"], "key": rep["key"]}
+    if args.overlap is not None:
+        hdof.hdof_set_tuning(ctx, **{**hdof.hdof_get_tuning(ctx), "overlap": args.overlap})
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -245,13 +252,14 @@ def main():
         full = hdof.FrameKeep.empty(H, W)
         hdof.hdof_frame(ctx, sc, cam, None, lens, light, params, seed=cfg.seed, frame=0, view=0, out=out, keep=full,
                         stream=stream)
-        res["forms"] = {"batched": bench_batched(hdof, ctx, sc, ms_per_step),
-                        "backward": bench_backward(hdof, ctx, sc, cfg, full, ms_per_step),
-                        "focus_fit": bench_focus_fit(hdof, ctx, sc, cfg, ms_per_step),
-                        "temporal": bench_temporal(hdof, ctx),
-                        "scaled_mask": bench_scaled_mask(hdof, ctx, sc, cfg, ms_per_step, rays),
-                        "specular": bench_specular(hdof, ctx, cfg),
-                        "aperture": bench_aperture(hdof, ctx, sc, cfg, ms_per_step)}
+        forms = {"batched": lambda: bench_batched(hdof, ctx, sc, ms_per_step),
+                 "backward": lambda: bench_backward(hdof, ctx, sc, cfg, full, ms_per_step),
+                 "focus_fit": lambda: bench_focus_fit(hdof, ctx, sc, cfg, ms_per_step),
+                 "temporal": lambda: bench_temporal(hdof, ctx),
+                 "scaled_mask": lambda: bench_scaled_mask(hdof, ctx, sc, cfg, ms_per_step, rays),
+                 "specular": lambda: bench_specular(hdof, ctx, cfg),
+                 "aperture": lambda: bench_aperture(hdof, ctx, sc, cfg, ms_per_step)}
+        res["forms"] = {name: forms[name]() for name in args.forms.split(",") if name}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, scene)
     print(json.dumps(res), flush=True)

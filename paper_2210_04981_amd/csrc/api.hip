@@ -229,7 +229,8 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->sp_cn, &ctx->sp_cf, &ctx->sp_coc};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
-  for (hipEvent_t e : ctx->b_view_ready) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->b_chunk_ready)
+    if (e) hipEventDestroy(e);
   buf_free(ctx->ppb_args);
   buf_free(ctx->ppb_partial);
   buf_free(ctx->b_arena);
@@ -934,11 +935,14 @@ extern "C" hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* t) {
 // ---------------------------------------------------------------------------
 // batched form
 // ---------------------------------------------------------------------------
-// the overlapped batch hands its views' gathers to the second stream in
-// this many chunks
-#ifndef HDOF_BATCH_FORKS
-#define HDOF_BATCH_FORKS 4
+
+// the overlapped batch's views in this many chunks (G-buffer launches and
+// forks to the second stream); 32 views, eager / replayed graph: 1 chunk
+// 11.3 / 11.2 ms, 4 chunks 11.2 / 12.4 ms
+#ifndef HDOF_BATCH_CHUNKS
+#define HDOF_BATCH_CHUNKS 1
 #endif
+static_assert(HDOF_BATCH_CHUNKS >= 1 && HDOF_BATCH_CHUNKS <= 8, "one event per chunk");
 
 struct BatchLayout {
   int n;
@@ -1044,11 +1048,8 @@ static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params,
   TRY(hdof_ensure(ctx->pp_tile, sizeof(float) * ptiles));
   TRY(hdof_ensure(ctx->pp_rad, sizeof(float) * ptiles));
   TRY(hdof_ensure(ctx->pp_taps, 16 * 256));
-  while ((int)ctx->b_view_ready.size() < L.n) {
-    hipEvent_t e;
-    HDOF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ctx->b_view_ready.push_back(e);
-  }
+  for (hipEvent_t& e : ctx->b_chunk_ready)
+    if (!e) HDOF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return HDOF_OK;
 }
 
@@ -1064,55 +1065,69 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
   HDOF_HIP(hipMemcpyAsync(ctx->b_views.p, table_host, batch_view_bytes() * L.n, hipMemcpyHostToDevice, st));
   LightK li = make_lightk(light);
   hdof_rt_bufs rt[HDOF_MAX_VIEWS];
-  // overlapped batch (16-pixel post-filter tiles, overlap on): every view's
-  // G-buffer packs its texels and tile radii, and that view's gather then
-  // runs on the context's second stream beside the later views' G-buffers,
-  // the masks and the one trace, writing its untraced pixels' composite;
-  // after the join a sparse composite rewrites each view's traced pixels --
-  // the overlapped frame's order, view by view
+  // overlapped batch (16-pixel post-filter tiles, overlap on): one G-buffer
+  // launch over all views (packing texels and tile radii), then the views'
+  // gathers on the context's second stream beside the masks and the one
+  // trace, each writing its untraced pixels' composite; after the join a
+  // sparse composite rewrites each view's traced pixels -- the overlapped
+  // frame's order over the whole batch
   const bool ovl = ctx->tune.overlap != 0 && params->pp.tile == 16;
   float4* packs = (float4*)(a + L.o_pack);
   float* ptiles = (float*)(a + L.o_ptile);
-  if (ovl) TRY(postfilter_reserve(ctx, L.hv[0].k, L.hv[0].l, params->pp, st));  // tap table, before the fork
   for (int v = 0; v < L.n; ++v) {
-    const BatchView& bv = L.hv[v];
-    const size_t pb = (size_t)bv.px_base;
-    hdof_gbuffer_bufs gb;
-    gb.depth = (float*)(a + L.o_depth) + pb;
-    gb.normal = (float*)(a + L.o_normal) + 3 * pb;
-    gb.albedo = (float*)(a + L.o_albedo) + 3 * pb;
-    gb.color = (float*)(a + L.o_color) + 3 * pb;
-    gb.tri_id = (int32_t*)(a + L.o_tri) + pb;
-    gb.spec = nullptr;
+    const size_t pb = (size_t)L.hv[v].px_base;
     rt[v].c_near = (float*)(a + L.o_cn) + 3 * pb;
     rt[v].c_far = (float*)(a + L.o_cf) + 3 * pb;
     rt[v].hit_ratio = (float*)(a + L.o_h) + pb;
     rt[v].lum_m1 = (float*)(a + L.o_m1) + pb;
     rt[v].lum_m2 = (float*)(a + L.o_m2) + pb;
-    if (ovl) {
-      TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st, packs + pb, ptiles + L.tile_base[v]));
-      // the second stream takes the views in HDOF_BATCH_FORKS chunks: each
-      // cross-stream dependency costs a replayed graph tens of microseconds
-      const int chunk = (L.n + HDOF_BATCH_FORKS - 1) / HDOF_BATCH_FORKS;
-      if ((v + 1) % chunk == 0 || v == L.n - 1) {
-        HDOF_HIP(hipEventRecord(ctx->b_view_ready[v], st));
-        HDOF_HIP(hipStreamWaitEvent(ctx->side, ctx->b_view_ready[v], 0));
-        hdof_rt_bufs none;
-        memset(&none, 0, sizeof none);
-        for (int u = v - (v % chunk); u <= v; ++u) {
-          const size_t ub = (size_t)L.hv[u].px_base;
-          const PostFuse pu{nullptr, none, params->comp, views[u].d_out, nullptr, true};
-          TRY(launch_postfilter_packed(ctx, packs + ub, ptiles + L.tile_base[u], L.hv[u].k, L.hv[u].l,
-                                       params->pp, (float*)(a + L.o_pp) + 3 * ub, ctx->side, &pu));
-        }
+  }
+  hdof_gbuffer_bufs gball;
+  gball.depth = (float*)(a + L.o_depth);
+  gball.normal = (float*)(a + L.o_normal);
+  gball.albedo = (float*)(a + L.o_albedo);
+  gball.color = (float*)(a + L.o_color);
+  gball.tri_id = (int32_t*)(a + L.o_tri);
+  gball.spec = nullptr;
+  if (ovl) {
+    TRY(postfilter_reserve(ctx, L.hv[0].k, L.hv[0].l, params->pp, st));  // tap table, before the fork
+    // the views in HDOF_BATCH_CHUNKS chunks: one G-buffer launch per chunk,
+    // then the chunk's gathers on the second stream, beside the next
+    // chunk's G-buffers (a replayed graph pays tens of microseconds per
+    // cross-stream dependency, so not one per view)
+    const int chunk = (L.n + HDOF_BATCH_CHUNKS - 1) / HDOF_BATCH_CHUNKS;
+    hdof_rt_bufs none;
+    memset(&none, 0, sizeof none);
+    for (int v0 = 0, c = 0; v0 < L.n; v0 += chunk, ++c) {
+      const int v1 = std::min(L.n, v0 + chunk);
+      TRY(launch_gbuffer_batched(ctx, scene, li, v1 - v0, L.hv + v0,
+                                 (const char*)ctx->b_views.p + batch_view_bytes() * v0, gball, packs,
+                                 ptiles + L.tile_base[v0], st));
+      HDOF_HIP(hipEventRecord(ctx->b_chunk_ready[c], st));
+      HDOF_HIP(hipStreamWaitEvent(ctx->side, ctx->b_chunk_ready[c], 0));
+      for (int v = v0; v < v1; ++v) {
+        const size_t pb = (size_t)L.hv[v].px_base;
+        const PostFuse pu{nullptr, none, params->comp, views[v].d_out, nullptr, true};
+        TRY(launch_postfilter_packed(ctx, packs + pb, ptiles + L.tile_base[v], L.hv[v].k, L.hv[v].l, params->pp,
+                                     (float*)(a + L.o_pp) + 3 * pb, ctx->side, &pu));
       }
-    } else {
-      TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
     }
+    HDOF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+  }
+  for (int v = 0; v < L.n; ++v) {
+    const BatchView& bv = L.hv[v];
+    const size_t pb = (size_t)bv.px_base;
+    hdof_gbuffer_bufs gb;
+    gb.depth = gball.depth + pb;
+    gb.normal = gball.normal + 3 * pb;
+    gb.albedo = gball.albedo + 3 * pb;
+    gb.color = gball.color + 3 * pb;
+    gb.tri_id = gball.tri_id + pb;
+    gb.spec = nullptr;
+    if (!ovl) TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
     TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
                     (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l, false));
   }
-  if (ovl) HDOF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
   TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
                            (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,
                            st));

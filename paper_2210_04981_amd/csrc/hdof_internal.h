@@ -109,9 +109,7 @@ struct hdof_ctx {
   void* b_views_host = nullptr;
   size_t b_views_host_bytes = 0;
   hipEvent_t b_views_done = nullptr;
-  // overlapped batch: one event per view, recorded after its G-buffer (its
-  // gather on the second stream waits for it)
-  std::vector<hipEvent_t> b_view_ready;
+  hipEvent_t b_chunk_ready[8] = {};  // overlapped batch: a chunk's G-buffers done
   // traversal work counters (rays, node visits, triangle tests) x (G-buffer, trace)
   bool count_on = false;
   unsigned long long* d_counters = nullptr;
@@ -316,6 +314,12 @@ struct BatchView {
   uint32_t seed, frame, view;
   int px_base;  // first pixel of the view in the batch's concatenated planes
 };
+// every view's G-buffer in one launch (packed texels and 16-pixel tile
+// radii too): planes concatenated per view from its px_base, tile radii from
+// the view's first 16x16 block; views_dev is the device copy of hviews
+hdof_status launch_gbuffer_batched(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, int n_views,
+                                   const BatchView* hviews, const void* views_dev, hdof_gbuffer_bufs out,
+                                   float4* pack, float* tile_r, hipStream_t st);
 hdof_status reserve_trace(hdof_ctx* ctx, size_t cap, bool own_depth);
 hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, int spp_max,
                                  int n_views, const BatchView* hviews, const void* views_dev,

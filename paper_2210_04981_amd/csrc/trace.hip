@@ -375,21 +375,18 @@ __device__ inline void shade(const float4* __restrict__ tris, const float* __res
 // packed texel (shaded rgb, signed CoC of the stored depth) and the block's
 // maximum CoC radius, the block being the post-filter tile.
 // spec_out (nullable): the specular luminance plane.
+// One 16x16-pixel block lb of the image of camera k (its outputs planar
+// [C][H][W] from the given pointers).
 template <bool COUNT, bool PACK>
-__global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ nodes,
-                                                 const float4* __restrict__ tris, int n_nodes,
-                                                 const float* __restrict__ albedo,
-                                                 const float2* __restrict__ spec, float* __restrict__ spec_out,
-                                                 CamK k, LensK l,
-                                                 LightK li, float* __restrict__ depth,
-                                                 float* __restrict__ normal, float* __restrict__ alb_out,
-                                                 float* __restrict__ color, int* __restrict__ tri_id,
-                                                 int* __restrict__ flags,
-                                                 unsigned long long* __restrict__ counters,
-                                                 float4* __restrict__ pack, float* __restrict__ tile_r) {
+__device__ inline void gbuffer_block(const float4* __restrict__ nodes, const float4* __restrict__ tris, int n_nodes,
+                                     const float* __restrict__ albedo, const float2* __restrict__ spec,
+                                     float* __restrict__ spec_out, const CamK& k, const LensK& l, const LightK& li,
+                                     int lb, float* __restrict__ depth, float* __restrict__ normal,
+                                     float* __restrict__ alb_out, float* __restrict__ color, int* __restrict__ tri_id,
+                                     int* __restrict__ flags, unsigned long long* __restrict__ counters,
+                                     float4* __restrict__ pack, float* __restrict__ tile_r) {
   __shared__ float wmax[4];
-  const int bx_n = (k.W + 15) >> 4, by_n = (k.H + 15) >> 4;
-  const int lb = xcd_block(blockIdx.x, bx_n * by_n);
+  const int bx_n = (k.W + 15) >> 4;
   const int bx = lb % bx_n, by = lb / bx_n;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int x = bx * 16 + (wave & 1) * 8 + (lane & 7), y = by * 16 + (wave >> 1) * 8 + (lane >> 3);
@@ -443,6 +440,23 @@ __global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ node
     __syncthreads();
     if (t == 0) tile_r[lb] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
   }
+}
+
+template <bool COUNT, bool PACK>
+__global__ __launch_bounds__(256) void k_gbuffer(const float4* __restrict__ nodes,
+                                                 const float4* __restrict__ tris, int n_nodes,
+                                                 const float* __restrict__ albedo,
+                                                 const float2* __restrict__ spec, float* __restrict__ spec_out,
+                                                 CamK k, LensK l,
+                                                 LightK li, float* __restrict__ depth,
+                                                 float* __restrict__ normal, float* __restrict__ alb_out,
+                                                 float* __restrict__ color, int* __restrict__ tri_id,
+                                                 int* __restrict__ flags,
+                                                 unsigned long long* __restrict__ counters,
+                                                 float4* __restrict__ pack, float* __restrict__ tile_r) {
+  const int nb = ((k.W + 15) >> 4) * ((k.H + 15) >> 4);
+  gbuffer_block<COUNT, PACK>(nodes, tris, n_nodes, albedo, spec, spec_out, k, l, li, xcd_block(blockIdx.x, nb),
+                             depth, normal, alb_out, color, tri_id, flags, counters, pack, tile_r);
 }
 
 // queue entries: pixel index repeated spp times at its offset; also resets
@@ -559,6 +573,35 @@ __device__ inline void store_ray(const TraceArgs& A, const Ray& r, const Best& b
     atomicAdd(&A.counters[4], (unsigned long long)wk.visits);
     atomicAdd(&A.counters[5], (unsigned long long)wk.tests);
   }
+}
+
+// The G-buffers of a batch in one launch (packed texels and tile radii
+// too): the launch's blocks, in XCD-contiguous order over the whole batch,
+// are the views' 16x16-pixel blocks one view after another; blk_base[v] is
+// view v's first block (blk_base[n] the total), which is also its first
+// post-filter tile.  A view's planes start at its first batch pixel.
+struct GbBatch {
+  int n;
+  int blk_base[HDOF_MAX_VIEWS + 1];
+};
+
+__global__ __launch_bounds__(256) void k_gbuffer_batch(const float4* __restrict__ nodes,
+                                                       const float4* __restrict__ tris, int n_nodes,
+                                                       const float* __restrict__ albedo, LightK li,
+                                                       const ViewK* __restrict__ views, GbBatch gbb,
+                                                       float* __restrict__ depth, float* __restrict__ normal,
+                                                       float* __restrict__ alb_out, float* __restrict__ color,
+                                                       int* __restrict__ tri_id, int* __restrict__ flags,
+                                                       float4* __restrict__ pack, float* __restrict__ tile_r) {
+  const int g = xcd_block(blockIdx.x, gbb.blk_base[gbb.n]);
+  int v = 0;  // last view whose first block is <= g
+  for (int step = HDOF_MAX_VIEWS / 2; step >= 1; step >>= 1)
+    if (v + step < gbb.n && gbb.blk_base[v + step] <= g) v += step;
+  const ViewK& vk = views[v];
+  const size_t pb = (size_t)vk.px_base;
+  gbuffer_block<false, true>(nodes, tris, n_nodes, albedo, nullptr, nullptr, vk.k, vk.l, li, g - gbb.blk_base[v],
+                             depth + pb, normal + 3 * pb, alb_out + 3 * pb, color + 3 * pb, tri_id + pb, flags,
+                             nullptr, pack + pb, tile_r + gbb.blk_base[v]);
 }
 
 // Whether this block of the persistent trace takes part: with a ray
@@ -873,6 +916,22 @@ hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, c
   // a Lambertian scene has no specular part: its plane is 0
   if (!sc->spec && out.spec) hipLaunchKernelGGL(k_zero_f, dim3(cdiv(k.W * k.H, 256)), dim3(256), 0, st, out.spec,
                                                 k.W * k.H);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+hdof_status launch_gbuffer_batched(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, int n_views,
+                                   const BatchView* hviews, const void* views_dev, hdof_gbuffer_bufs out,
+                                   float4* pack, float* tile_r, hipStream_t st) {
+  GbBatch gbb;
+  gbb.n = n_views;
+  gbb.blk_base[0] = 0;
+  for (int v = 0; v < n_views; ++v)
+    gbb.blk_base[v + 1] = gbb.blk_base[v] + cdiv(hviews[v].k.W, 16) * cdiv(hviews[v].k.H, 16);
+  for (int v = n_views + 1; v <= HDOF_MAX_VIEWS; ++v) gbb.blk_base[v] = gbb.blk_base[n_views];
+  hipLaunchKernelGGL(k_gbuffer_batch, dim3(gbb.blk_base[n_views]), dim3(256), 0, st, sc->nodes, sc->tris,
+                     sc->n_nodes, sc->albedo, li, (const ViewK*)views_dev, gbb, out.depth, out.normal, out.albedo,
+                     out.color, out.tri_id, ctx->d_flags, pack, tile_r);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }

@@ -104,3 +104,39 @@ def test_tuning_rejects_out_of_range(hd, ctx, kw):
     assert ei.value.status == INVALID_ARG
     assert next(iter(kw)) in str(ei.value)
     assert hd.hdof_get_tuning(ctx) == before  # a refused tuning changes nothing
+
+
+def test_queue_capacity_guard(hd, ctx):
+    """The trace's capacity guard, forced from the host: counts of 2 rays per
+    pixel against spp_max = 1 make the ray total (2N) exceed the queue's
+    capacity (N entries).  The queue fill drops entries past the capacity,
+    the trace clamps its total to it and raises the device flag, the
+    reduction leaves the pixels whose rays lie past it untraced; hdof_sync
+    reports HDOF_ERR_CAPACITY once and clears the flag.  The pixels whose
+    rays fit are traced exactly as with a large enough capacity."""
+    print_case("queue capacity guard")
+    scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.2)
+    sc = upload_scene(hd, ctx, scene)
+    H = W = 64
+    N = H * W
+    spp = torch.full((H, W), 2, dtype=torch.uint8, device=DEV)
+    offs = (torch.arange(N, dtype=torch.int32, device=DEV) * 2).view(H, W)
+    total = torch.tensor([2 * N], dtype=torch.int32, device=DEV)
+    args = (hd.camera_of(cfg.camera), hd.lens_of(cfg.lens), hd.light_of(cfg.light))
+    ok = hd.hdof_trace_thin_lens(ctx, sc, *args, 2, spp, offs, total, seed=3)
+    torch.cuda.synchronize()
+    ctx.sync()
+    ref = ok.c_near.clone(), ok.hit_ratio.clone()
+    over = hd.hdof_trace_thin_lens(ctx, sc, *args, 1, spp, offs, total, seed=3)
+    torch.cuda.synchronize()
+    with pytest.raises(hd.HdofError) as ei:
+        ctx.sync()
+    assert ei.value.status == 4  # HDOF_ERR_CAPACITY
+    ctx.sync()  # the flag was cleared
+    fit = torch.zeros(N, dtype=torch.bool, device=DEV)
+    fit[: N // 2] = True  # pixel p's rays are entries 2p, 2p + 1 < N
+    fit = fit.view(H, W)
+    assert torch.equal(over.c_near[:, fit], ref[0][:, fit])
+    assert torch.equal(over.hit_ratio[fit], ref[1][fit])
+    assert torch.all(over.hit_ratio[~fit] == 0) and torch.all(over.c_near[:, ~fit] == 0)
+    sc.close()
