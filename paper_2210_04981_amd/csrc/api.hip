@@ -229,8 +229,6 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
                 &ctx->sp_cn, &ctx->sp_cf, &ctx->sp_coc};
   for (Buf* b : all) buf_free(*b);
   for (hipEvent_t e : ctx->prof_events) hipEventDestroy(e);
-  for (hipEvent_t e : ctx->b_chunk_ready)
-    if (e) hipEventDestroy(e);
   buf_free(ctx->ppb_args);
   buf_free(ctx->ppb_partial);
   buf_free(ctx->b_arena);
@@ -936,14 +934,6 @@ extern "C" hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* t) {
 // batched form
 // ---------------------------------------------------------------------------
 
-// the overlapped batch's views in this many chunks (G-buffer launches and
-// forks to the second stream); 32 views, eager / replayed graph: 1 chunk
-// 11.3 / 11.2 ms, 4 chunks 11.2 / 12.4 ms
-#ifndef HDOF_BATCH_CHUNKS
-#define HDOF_BATCH_CHUNKS 1
-#endif
-static_assert(HDOF_BATCH_CHUNKS >= 1 && HDOF_BATCH_CHUNKS <= 8, "one event per chunk");
-
 struct BatchLayout {
   int n;
   long npx, max_px;
@@ -1048,8 +1038,6 @@ static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params,
   TRY(hdof_ensure(ctx->pp_tile, sizeof(float) * ptiles));
   TRY(hdof_ensure(ctx->pp_rad, sizeof(float) * ptiles));
   TRY(hdof_ensure(ctx->pp_taps, 16 * 256));
-  for (hipEvent_t& e : ctx->b_chunk_ready)
-    if (!e) HDOF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return HDOF_OK;
 }
 
@@ -1089,29 +1077,19 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
   gball.color = (float*)(a + L.o_color);
   gball.tri_id = (int32_t*)(a + L.o_tri);
   gball.spec = nullptr;
+  float* outs[HDOF_MAX_VIEWS];
+  for (int v = 0; v < L.n; ++v) outs[v] = views[v].d_out;
   if (ovl) {
     TRY(postfilter_reserve(ctx, L.hv[0].k, L.hv[0].l, params->pp, st));  // tap table, before the fork
-    // the views in HDOF_BATCH_CHUNKS chunks: one G-buffer launch per chunk,
-    // then the chunk's gathers on the second stream, beside the next
-    // chunk's G-buffers (a replayed graph pays tens of microseconds per
-    // cross-stream dependency, so not one per view)
-    const int chunk = (L.n + HDOF_BATCH_CHUNKS - 1) / HDOF_BATCH_CHUNKS;
-    hdof_rt_bufs none;
-    memset(&none, 0, sizeof none);
-    for (int v0 = 0, c = 0; v0 < L.n; v0 += chunk, ++c) {
-      const int v1 = std::min(L.n, v0 + chunk);
-      TRY(launch_gbuffer_batched(ctx, scene, li, v1 - v0, L.hv + v0,
-                                 (const char*)ctx->b_views.p + batch_view_bytes() * v0, gball, packs,
-                                 ptiles + L.tile_base[v0], st));
-      HDOF_HIP(hipEventRecord(ctx->b_chunk_ready[c], st));
-      HDOF_HIP(hipStreamWaitEvent(ctx->side, ctx->b_chunk_ready[c], 0));
-      for (int v = v0; v < v1; ++v) {
-        const size_t pb = (size_t)L.hv[v].px_base;
-        const PostFuse pu{nullptr, none, params->comp, views[v].d_out, nullptr, true};
-        TRY(launch_postfilter_packed(ctx, packs + pb, ptiles + L.tile_base[v], L.hv[v].k, L.hv[v].l, params->pp,
-                                     (float*)(a + L.o_pp) + 3 * pb, ctx->side, &pu));
-      }
-    }
+    // one fork after the G-buffer: a replayed graph pays tens of
+    // microseconds per cross-stream dependency (forking per view, or per
+    // chunk of views after its G-buffers, was slower replayed: 32 views,
+    // 4 chunks 12.4 ms against 11.2)
+    TRY(launch_gbuffer_batched(ctx, scene, li, L.n, L.hv, ctx->b_views.p, gball, packs, ptiles, st));
+    HDOF_HIP(hipEventRecord(ctx->ev_fork, st));
+    HDOF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    TRY(launch_postfilter_batched(ctx, packs, ptiles, L.n, L.hv, ctx->b_views.p, outs, params->pp,
+                                  (float*)(a + L.o_pp), ctx->side));
     HDOF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
   }
   for (int v = 0; v < L.n; ++v) {
@@ -1131,18 +1109,20 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
   TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
                            (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,
                            st));
-  if (ovl) HDOF_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-  for (int v = 0; v < L.n; ++v) {
+  if (ovl) {
+    HDOF_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    TRY(launch_composite_traced_batched(ctx, (const float*)(a + L.o_color), (const float*)(a + L.o_pp),
+                                        (const float*)(a + L.o_depth), (const uint8_t*)(a + L.o_spp), rt[0], L.n,
+                                        L.hv, ctx->b_views.p, outs, params->comp, st));
+  }
+  for (int v = 0; v < L.n && !ovl; ++v) {
     const BatchView& bv = L.hv[v];
     const size_t pb = (size_t)bv.px_base;
     float* color = (float*)(a + L.o_color) + 3 * pb;
     float* depth = (float*)(a + L.o_depth) + pb;
     float* pp = (float*)(a + L.o_pp) + 3 * pb;
     const uint8_t* spp = (const uint8_t*)(a + L.o_spp) + pb;
-    if (ovl) {
-      TRY(launch_composite(ctx, color, pp, depth, spp, rt[v], bv.k, bv.l, params->comp, views[v].d_out, st,
-                           nullptr, true));
-    } else if (params->pp.tile == 16) {  // composite in the gather's epilogue, as in hdof_frame
+    if (params->pp.tile == 16) {  // composite in the gather's epilogue, as in hdof_frame
       const PostFuse pf{spp, rt[v], params->comp, views[v].d_out};
       TRY(launch_postfilter(ctx, color, depth, bv.k, bv.l, params->pp, nullptr, st, false, &pf));
     } else {

@@ -109,7 +109,6 @@ struct hdof_ctx {
   void* b_views_host = nullptr;
   size_t b_views_host_bytes = 0;
   hipEvent_t b_views_done = nullptr;
-  hipEvent_t b_chunk_ready[8] = {};  // overlapped batch: a chunk's G-buffers done
   // traversal work counters (rays, node visits, triangle tests) x (G-buffer, trace)
   bool count_on = false;
   unsigned long long* d_counters = nullptr;
@@ -161,6 +160,15 @@ __device__ inline V3 cross3(V3 a, V3 b) {
 }
 __device__ inline float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 __device__ inline float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// the view of unit g (a block or a tile) of a launch over a batch's views:
+// the last view whose first unit base[v] is <= g (base ascending, base[0] 0)
+__device__ inline int batch_view_of(const int* base, int n, int g) {
+  int v = 0;
+  for (int step = 32; step >= 1; step >>= 1)
+    if (v + step < n && base[v + step] <= g) v += step;
+  return v;
+}
 
 // logical block index so that XCD x (blocks dispatched round-robin over 8
 // XCDs) processes one contiguous range of logical blocks
@@ -409,6 +417,18 @@ hdof_status launch_postfilter_noalloc(hdof_ctx* ctx, const float* color, const f
 hdof_status launch_postfilter_packed(hdof_ctx* ctx, const float4* pack, const float* tile_r, const CamK& k,
                                      const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
                                      const PostFuse* fuse);
+// the batched form's gathers over every view in one launch (16-pixel
+// tiles; each view's pixels by the composite's untraced rule into outs[v],
+// its filtered colour into pp_out from its px_base), and its traced pixels'
+// composite in one launch; planes concatenated per view from px_base, tile
+// radii from the view's first tile; views_dev is the device copy of hviews
+hdof_status launch_postfilter_batched(hdof_ctx* ctx, const float4* pack, const float* tile_r, int n_views,
+                                      const BatchView* hviews, const void* views_dev, float* const* outs,
+                                      const hdof_pp_params& pp, float* pp_out, hipStream_t st);
+hdof_status launch_composite_traced_batched(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
+                                            const uint8_t* spp, hdof_rt_bufs rt, int n_views,
+                                            const BatchView* hviews, const void* views_dev, float* const* outs,
+                                            const hdof_composite_params& cp, hipStream_t st);
 // packed: pack and per-tile radius already written (by the G-buffer)
 hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                               const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,

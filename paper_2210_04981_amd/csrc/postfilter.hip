@@ -438,14 +438,12 @@ __device__ __forceinline__ float block_dilated_radius(const float* __restrict__ 
 // later); SA weights the taps by the lens's spherical aberration (the
 // table's fourth entry).
 template <int FUSE, bool SA>
-__global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ tile_r,
-                                                     int K, float r_cap, const float4* __restrict__ taps, int n_taps,
-                                                     int W, int H, float inv_ramp, float* __restrict__ out, FuseK fz) {
-  __shared__ float4 stg[PPG_BUFS][PPG_G * PPG_TAPSZ];
-  __shared__ TapRec rec[PPG_BUFS][PPG_G];
-  __shared__ float wred[4];
+__device__ __forceinline__ void gather16_tile(float4 (*stg)[PPG_G * PPG_TAPSZ], TapRec (*rec)[PPG_G], float* wred,
+                                              const float4* __restrict__ pack, const float* __restrict__ tile_r,
+                                              int K, float r_cap, const float4* __restrict__ taps, int n_taps, int W,
+                                              int H, float inv_ramp, float* __restrict__ out, const FuseK& fz,
+                                              int tile) {
   const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
-  const int tile = xcd_block(blockIdx.x, TW * TH);
   const int x0 = (tile % TW) * 16, y0 = (tile / TW) * 16;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -476,6 +474,49 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
     const float iw = 1.0f / g.ws;
     pp_emit<FUSE>(out, fz, N, p, cp4, g.ar * iw, g.ag * iw, g.ab * iw);
   }
+}
+
+template <int FUSE, bool SA>
+__global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ tile_r,
+                                                     int K, float r_cap, const float4* __restrict__ taps, int n_taps,
+                                                     int W, int H, float inv_ramp, float* __restrict__ out, FuseK fz) {
+  __shared__ float4 stg[PPG_BUFS][PPG_G * PPG_TAPSZ];
+  __shared__ TapRec rec[PPG_BUFS][PPG_G];
+  __shared__ float wred[4];
+  const int tile = xcd_block(blockIdx.x, ((W + 15) >> 4) * ((H + 15) >> 4));
+  gather16_tile<FUSE, SA>(stg, rec, wred, pack, tile_r, K, r_cap, taps, n_taps, W, H, inv_ramp, out, fz, tile);
+}
+
+// The batched form's gathers and traced pixels' composites, one launch
+// each over every view: a block finds its view by a binary search over the
+// views' first tiles (first 256-pixel blocks for the composite); a view's
+// planes start at its px_base and its tile radii at its first tile.
+struct PPBatch {
+  int n;
+  int tile_base[HDOF_MAX_VIEWS + 1];  // [n]: all tiles
+  int blk_base[HDOF_MAX_VIEWS + 1];   // [n]: all 256-pixel blocks
+  float* out[HDOF_MAX_VIEWS];
+};
+
+// FUSE 2 only (the overlapped form: every pixel by the untraced pixels'
+// rule; `pp_out` receives the filtered colour)
+template <bool SA>
+__global__ __launch_bounds__(256) void k_pp_gather16_batch(const float4* __restrict__ pack,
+                                                           const float* __restrict__ tile_r, int K, float r_cap,
+                                                           const float4* __restrict__ taps, int n_taps,
+                                                           float inv_ramp, float* __restrict__ pp_out,
+                                                           const BatchView* __restrict__ views, PPBatch b) {
+  __shared__ float4 stg[PPG_BUFS][PPG_G * PPG_TAPSZ];
+  __shared__ TapRec rec[PPG_BUFS][PPG_G];
+  __shared__ float wred[4];
+  const int g = xcd_block(blockIdx.x, b.tile_base[b.n]);
+  const int v = batch_view_of(b.tile_base, b.n, g);
+  const int W = views[v].k.W, H = views[v].k.H;
+  const size_t pb = (size_t)views[v].px_base;
+  FuseK fz{};
+  fz.out = b.out[v];
+  gather16_tile<2, SA>(stg, rec, wred, pack + pb, tile_r + b.tile_base[v], K, r_cap, taps, n_taps, W, H, inv_ramp,
+                       pp_out + 3 * pb, fz, g - b.tile_base[v]);
 }
 
 // The gather radius of tile (tx, ty) reduced by one wave (uniform result).
@@ -782,6 +823,28 @@ __global__ void k_composite(CompK a) {
 __global__ void k_composite_traced(CompK a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < a.N && a.spp[p] > 0) composite_at(a, p);
+}
+
+// every view's traced pixels in one launch; `a` holds the first view's
+// planes (all views' planes are concatenated from their px_base)
+__global__ void k_composite_traced_batch(CompK a, const BatchView* __restrict__ views, PPBatch b) {
+  const int v = batch_view_of(b.blk_base, b.n, blockIdx.x);
+  const int N = views[v].k.W * views[v].k.H;
+  const int p = (blockIdx.x - b.blk_base[v]) * blockDim.x + threadIdx.x;
+  const size_t pb = (size_t)views[v].px_base;
+  if (p >= N || a.spp[pb + p] == 0) return;
+  CompK c = a;
+  c.color += 3 * pb;
+  c.pp += 3 * pb;
+  c.depth += pb;
+  c.spp += pb;
+  c.cn += 3 * pb;
+  c.cf += 3 * pb;
+  c.hr += pb;
+  c.l = views[v].l;
+  c.N = N;
+  c.out = b.out[v];
+  composite_at(c, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -1237,6 +1300,47 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
   if ((s = postfilter_reserve(ctx, k, l, pp, st)) != HDOF_OK) return s;
   const PPScratch S{(float4*)ctx->pp_pack.p, (float*)ctx->pp_tile.p, (float*)ctx->pp_rad.p, (float4*)ctx->pp_taps.p};
   return postfilter_run(ctx, S, color, depth, k, l, pp, out, st, packed, fuse);
+}
+
+hdof_status launch_postfilter_batched(hdof_ctx* ctx, const float4* pack, const float* tile_r, int n_views,
+                                      const BatchView* hviews, const void* views_dev, float* const* outs,
+                                      const hdof_pp_params& pp, float* pp_out, hipStream_t st) {
+  if (pp.tile != 16) return hdof_set_error(HDOF_ERR_INVALID_ARG, "batched gather: 16-pixel tiles only");
+  PPBatch b{};
+  b.n = n_views;
+  const bool sa = hviews[0].l.sa != 0.0f;
+  for (int v = 0; v < n_views; ++v) {
+    if ((hviews[v].l.sa != 0.0f) != sa)
+      return hdof_set_error(HDOF_ERR_UNSUPPORTED, "batched gather: one spherical aberration for every view");
+    b.tile_base[v + 1] = b.tile_base[v] + cdiv(hviews[v].k.W, 16) * cdiv(hviews[v].k.H, 16);
+    b.out[v] = outs[v];
+  }
+  const int K = (int)ceil((double)pp.r_cap / 16);
+  auto kern = sa ? k_pp_gather16_batch<true> : k_pp_gather16_batch<false>;
+  hipLaunchKernelGGL(kern, dim3(b.tile_base[n_views]), dim3(256), 0, st, pack, tile_r, K, pp.r_cap,
+                     (const float4*)ctx->pp_taps.p, pp.n_taps, 1.0f / pp.bg_ramp_px, pp_out,
+                     (const BatchView*)views_dev, b);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+hdof_status launch_composite_traced_batched(hdof_ctx* ctx, const float* color, const float* pp, const float* depth,
+                                            const uint8_t* spp, hdof_rt_bufs rt, int n_views,
+                                            const BatchView* hviews, const void* views_dev, float* const* outs,
+                                            const hdof_composite_params& cp, hipStream_t st) {
+  (void)ctx;
+  PPBatch b{};
+  b.n = n_views;
+  for (int v = 0; v < n_views; ++v) {
+    b.blk_base[v + 1] = b.blk_base[v] + cdiv(hviews[v].k.W * hviews[v].k.H, 256);
+    b.out[v] = outs[v];
+  }
+  const CompK a{color, pp, depth, spp, rt.c_near, rt.c_far, rt.hit_ratio, hviews[0].l, 0, 1.0f / cp.h_t,
+                cp.rt_override, nullptr, 0.0f, nullptr};
+  hipLaunchKernelGGL(k_composite_traced_batch, dim3(b.blk_base[n_views]), dim3(256), 0, st, a,
+                     (const BatchView*)views_dev, b);
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
 }
 
 hdof_status launch_postfilter_packed(hdof_ctx* ctx, const float4* pack, const float* tile_r, const CamK& k,

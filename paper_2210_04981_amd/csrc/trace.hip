@@ -486,12 +486,7 @@ __global__ void k_queue_fill(const uint8_t* __restrict__ spp, const int* __restr
 // wave takes work from its own segment first, so each XCD's L2 holds the
 // part of the BVH its rays touch, then moves on to the other segments.
 // Every wave exits once all segments are drained and its lanes are idle.
-struct ViewK {
-  CamK k;
-  LensK l;
-  uint32_t seed, frame, view;
-  int px_base;  // first pixel of the view in the batch
-};
+using ViewK = BatchView;  // the device copy of a batch's view table
 
 struct TraceArgs {
   const float4* nodes;
@@ -594,9 +589,7 @@ __global__ __launch_bounds__(256) void k_gbuffer_batch(const float4* __restrict_
                                                        int* __restrict__ tri_id, int* __restrict__ flags,
                                                        float4* __restrict__ pack, float* __restrict__ tile_r) {
   const int g = xcd_block(blockIdx.x, gbb.blk_base[gbb.n]);
-  int v = 0;  // last view whose first block is <= g
-  for (int step = HDOF_MAX_VIEWS / 2; step >= 1; step >>= 1)
-    if (v + step < gbb.n && gbb.blk_base[v + step] <= g) v += step;
+  const int v = batch_view_of(gbb.blk_base, gbb.n, g);
   const ViewK& vk = views[v];
   const size_t pb = (size_t)vk.px_base;
   gbuffer_block<false, true>(nodes, tris, n_nodes, albedo, nullptr, nullptr, vk.k, vk.l, li, g - gbb.blk_base[v],
@@ -751,14 +744,14 @@ __global__ __launch_bounds__(HDOF_TRACE_BLOCK, HDOF_TRACE_WAVES_PER_EU) void k_t
 // coc_nf (nullable, 2 planes): the average CoC size of the near rays and of
 // the far rays, sum w |c| / sum w and sum (1 - w) |c| / sum (1 - w).
 template <bool FARPOS, bool VAR>
-__global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
-                            const int* __restrict__ ebase, const float* __restrict__ ray_col,
-                            const float* __restrict__ ray_z, size_t cap, LensK l, float* __restrict__ cn,
-                            float* __restrict__ cf, float* __restrict__ h, float* __restrict__ m1,
-                            float* __restrict__ m2, CamK k, uint32_t seed, uint32_t frame, uint32_t view,
-                            float* __restrict__ far_pos, VarFuse vf, float* __restrict__ coc_nf) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
+__device__ __forceinline__ void rt_reduce_px(int p, const uint8_t* __restrict__ spp, const int* __restrict__ offsets,
+                                             int N, const int* __restrict__ ebase, const float* __restrict__ ray_col,
+                                             const float* __restrict__ ray_z, size_t cap, const LensK& l,
+                                             float* __restrict__ cn, float* __restrict__ cf, float* __restrict__ h,
+                                             float* __restrict__ m1, float* __restrict__ m2, const CamK& k,
+                                             uint32_t seed, uint32_t frame, uint32_t view,
+                                             float* __restrict__ far_pos, const VarFuse& vf,
+                                             float* __restrict__ coc_nf) {
   int s = spp[p];
   float Nw = 0.f, Fw = 0.f, snr = 0.f, sng = 0.f, snb = 0.f, sfr = 0.f, sfg = 0.f, sfb = 0.f, sy = 0.f, sy2 = 0.f;
   float Pw = 0.f, spx_ = 0.f, spy_ = 0.f, spz_ = 0.f, scn = 0.f, scf = 0.f;
@@ -806,7 +799,7 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
   const float in_ = Nw > 0.f ? 1.0f / Nw : 0.f, if_ = Fw > 0.f ? 1.0f / Fw : 0.f;
   const float is = Sw > 0.f ? 1.0f / Sw : 0.f;
   const float ybar = sy * is, y2bar = sy2 * is;
-  if (!(VAR && vf.sparse_rt) || spp[p] > 0) {
+  if (!vf.sparse_rt || spp[p] > 0) {
     cn[p] = snr * in_;
     cn[N + p] = sng * in_;
     cn[2 * (size_t)N + p] = snb * in_;
@@ -847,6 +840,60 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
     coc_nf[p] = scn * in_;
     coc_nf[N + p] = scf * if_;
   }
+}
+
+template <bool FARPOS, bool VAR>
+__global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restrict__ offsets, int N,
+                            const int* __restrict__ ebase, const float* __restrict__ ray_col,
+                            const float* __restrict__ ray_z, size_t cap, LensK l, float* __restrict__ cn,
+                            float* __restrict__ cf, float* __restrict__ h, float* __restrict__ m1,
+                            float* __restrict__ m2, CamK k, uint32_t seed, uint32_t frame, uint32_t view,
+                            float* __restrict__ far_pos, VarFuse vf, float* __restrict__ coc_nf) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  rt_reduce_px<FARPOS, VAR>(p, spp, offsets, N, ebase, ray_col, ray_z, cap, l, cn, cf, h, m1, m2, k, seed, frame,
+                            view, far_pos, vf, coc_nf);
+}
+
+// The batched form's queue fill and reduction, one launch each over every
+// view: blocks of 256 pixels, view v's from blk_base[v] (blk_base[n] the
+// total), its pixels from its px_base and its queue entries from ebase[v].
+struct PxBatch {
+  int n;
+  int blk_base[HDOF_MAX_VIEWS + 1];
+};
+
+__global__ void k_queue_fill_batch(const uint8_t* __restrict__ spp, const int* __restrict__ offsets,
+                                   const ViewK* __restrict__ views, PxBatch b, const int* __restrict__ ebase,
+                                   long cap, int* __restrict__ queue, int* __restrict__ counter) {
+  const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gp < 8 * HDOF_SEG_STRIDE) counter[gp] = 0;
+  const int v = batch_view_of(b.blk_base, b.n, blockIdx.x);
+  const int N = views[v].k.W * views[v].k.H, pb = views[v].px_base;
+  const int p = (blockIdx.x - b.blk_base[v]) * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int s = spp[pb + p];
+  const long o = (long)offsets[pb + p] + ebase[v];
+  for (int j = 0; j < s; ++j)
+    if (o + j >= 0 && o + j < cap) queue[o + j] = pb + p;
+}
+
+// the trace planes are written at traced pixels only (the composite reads
+// them nowhere else)
+__global__ void k_rt_reduce_batch(const uint8_t* __restrict__ spp, const int* __restrict__ offsets,
+                                  const ViewK* __restrict__ views, PxBatch b, const int* __restrict__ ebase,
+                                  const float* __restrict__ ray_col, const float* __restrict__ ray_z, size_t cap,
+                                  float* __restrict__ cn, float* __restrict__ cf, float* __restrict__ h,
+                                  float* __restrict__ m1, float* __restrict__ m2) {
+  const int v = batch_view_of(b.blk_base, b.n, blockIdx.x);
+  const int N = views[v].k.W * views[v].k.H;
+  const size_t pb = (size_t)views[v].px_base;
+  const int p = (blockIdx.x - b.blk_base[v]) * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  VarFuse vf{};
+  vf.sparse_rt = 1;
+  rt_reduce_px<false, false>(p, spp + pb, offsets + pb, N, ebase + v, ray_col, ray_z, cap, views[v].l, cn + 3 * pb,
+                             cf + 3 * pb, h + pb, m1 + pb, m2 + pb, views[v].k, 0u, 0u, 0u, nullptr, vf, nullptr);
 }
 
 // batch: first queue entry of each view and the batch total
@@ -992,12 +1039,13 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
   const size_t cap = (size_t)npx * (size_t)spp_max;
   hdof_status s;
   if ((s = reserve_trace(ctx, cap, true)) != HDOF_OK) return s;
+  PxBatch pxb{};
+  pxb.n = n_views;
+  for (int v = 0; v < n_views; ++v) pxb.blk_base[v + 1] = pxb.blk_base[v] + cdiv(hviews[v].k.W * hviews[v].k.H, 256);
   hipLaunchKernelGGL(k_view_scan, dim3(1), dim3(64), 0, st, totals, n_views, ebase, grand);
-  for (int v = 0; v < n_views; ++v) {
-    const int N = hviews[v].k.W * hviews[v].k.H, pb = hviews[v].px_base;
-    hipLaunchKernelGGL(k_queue_fill, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb, N,
-                       (const int*)(ebase + v), pb, (long)cap, (int*)ctx->queue.p, (int*)ctx->work_counter.p);
-  }
+  hipLaunchKernelGGL(k_queue_fill_batch, dim3(pxb.blk_base[n_views]), dim3(256), 0, st, spp, offsets,
+                     (const ViewK*)views_dev, pxb, (const int*)ebase, (long)cap, (int*)ctx->queue.p,
+                     (int*)ctx->work_counter.p);
   TraceArgs A = base_args(ctx, sc, li, cap);
   A.offsets = offsets;
   A.total_p = grand;
@@ -1008,14 +1056,10 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
   A.n_views = n_views;
   A.v0 = ViewK{hviews[0].k, hviews[0].l, 0, 0, 0, 0};
   launch_trace_kernel<true>(ctx, A, st);
-  for (int v = 0; v < n_views; ++v) {
-    const int N = hviews[v].k.W * hviews[v].k.H, pb = hviews[v].px_base;
-    auto red = k_rt_reduce<false, false>;
-    hipLaunchKernelGGL(red, dim3(cdiv(N, 256)), dim3(256), 0, st, spp + pb, offsets + pb,
-                       N, (const int*)(ebase + v), (const float*)ctx->ray_col.p, (const float*)ctx->ray_z.p, cap,
-                       hviews[v].l, rt[v].c_near, rt[v].c_far, rt[v].hit_ratio, rt[v].lum_m1, rt[v].lum_m2,
-                       hviews[v].k, 0u, 0u, 0u, (float*)nullptr, VarFuse{}, (float*)nullptr);
-  }
+  hipLaunchKernelGGL(k_rt_reduce_batch, dim3(pxb.blk_base[n_views]), dim3(256), 0, st, spp, offsets,
+                     (const ViewK*)views_dev, pxb, (const int*)ebase, (const float*)ctx->ray_col.p,
+                     (const float*)ctx->ray_z.p, cap, rt->c_near, rt->c_far, rt->hit_ratio, rt->lum_m1,
+                     rt->lum_m2);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
