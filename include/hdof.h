@@ -519,9 +519,8 @@ typedef struct {
 hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* tuning);
 hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
 
-/* The library's autotuner of the launch shape (the spec batched
- * form's "tile and queue sizes chosen by a project-written autotuner"; the
- * paper has none).  It times the caller's workload -- hdof_frame on
+/* The library's autotuner of the launch shape (not in the paper: its tile
+ * and queue sizes are scheduling choices of this implementation).  It times the caller's workload -- hdof_frame on
  * views[0] with no previous camera when n_views = 1, hdof_frame_batched on
  * all views otherwise -- on `stream` under candidate tunings (coordinate
  * descent from the defaults over blocks_per_cu, refill, segments, wave,
