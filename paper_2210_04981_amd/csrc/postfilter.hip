@@ -894,19 +894,37 @@ __global__ __launch_bounds__(256) void k_ppb_pack(const float* __restrict__ colo
   red[tid] = r;
   redi[tid] = idx;
   __syncthreads();
+  // the largest radius of each tile and its lowest pixel index: first along
+  // each tile row (the row's first thread), then over the tile's rows
   const int tx = tid & 15, ty = tid >> 4;
+  __shared__ float rowm[256];
+  __shared__ int rowi[256];
+  if ((tx % tile) == 0) {
+    float m = -1.0f;
+    int mi = 0x7fffffff;
+    for (int dx = 0; dx < tile; ++dx) {
+      const float v = red[ty * 16 + tx + dx];
+      const int vi = redi[ty * 16 + tx + dx];
+      if (v > m || (v == m && vi < mi)) {
+        m = v;
+        mi = vi;
+      }
+    }
+    rowm[tid] = m;
+    rowi[tid] = mi;
+  }
+  __syncthreads();
   if ((tx % tile) == 0 && (ty % tile) == 0 && x < k.W && y < k.H) {
     float m = -1.0f;
     int mi = 0x7fffffff;
-    for (int dy = 0; dy < tile; ++dy)
-      for (int dx = 0; dx < tile; ++dx) {
-        float v = red[(ty + dy) * 16 + tx + dx];
-        int vi = redi[(ty + dy) * 16 + tx + dx];
-        if (v > m || (v == m && vi < mi)) {
-          m = v;
-          mi = vi;
-        }
+    for (int dy = 0; dy < tile; ++dy) {
+      const float v = rowm[(ty + dy) * 16 + tx];
+      const int vi = rowi[(ty + dy) * 16 + tx];
+      if (v > m || (v == m && vi < mi)) {
+        m = v;
+        mi = vi;
       }
+    }
     const int TW = (k.W + tile - 1) / tile;
     tile_r[(y / tile) * TW + x / tile] = m;
     tile_arg[(y / tile) * TW + x / tile] = mi;
@@ -943,7 +961,9 @@ __global__ void k_fill_f(float* __restrict__ p, size_t n, float v) {
   if (i < n) p[i] = v;
 }
 
-#define PPB_WIN_E 23                     // largest ceil(R) accumulated in one LDS window per block
+#ifndef PPB_WIN_E
+#define PPB_WIN_E 21                     // largest ceil(R) accumulated in one LDS window per block
+#endif
 #define PPB_WIN (17 + 2 * PPB_WIN_E)     // window side at that radius
 #define PPB_FOOT (PPG_SIDE * PPG_SIDE)   // one tap's 17x17 footprint
 
@@ -957,6 +977,76 @@ __device__ __forceinline__ TapGeo tap_geo(float R, float4 u) {
   const float ox = R * u.x, oy = R * u.y;
   const float fx = floorf(ox), fy = floorf(oy);
   return TapGeo{(int)fx, (int)fy, ox - fx, oy - fy};
+}
+
+// The forward-mode gather's taps of one pixel (value, d/dS1, d/dA).  SLOPE:
+// the tile radius R moves with S1 and A, so every sample moves with it and
+// its spatial slopes enter the derivatives.
+template <bool SLOPE>
+__device__ __forceinline__ void fwd_taps(const float4* __restrict__ pack, const float4* __restrict__ taps, int ntap,
+                                         int n_taps, int W, int H, int x, int y, const D3& R, const D3& cpv,
+                                         const D3& rp, float dcs, float inv_A, float inv_ramp, D3& nr, D3& ng,
+                                         D3& nb, D3& den) {
+  if (ntap <= 0) return;
+  // each tap's texels are requested one tap ahead, so their latency overlaps
+  // the previous tap's arithmetic (the last tap's are requested twice)
+  float4 v00, v10, v01, v11;
+  {
+    const TapGeo t0 = tap_geo(R.v, taps[0]);
+    texels_clamped(pack, W, H, x + t0.ix, y + t0.iy, v00, v10, v01, v11);
+  }
+  for (int kk = 0; kk < ntap; ++kk) {
+    const float4 u = taps[kk];
+    const TapGeo tg = tap_geo(R.v, u);
+    const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
+    float4 n00, n10, n01, n11;
+    {
+      const TapGeo tn = tap_geo(R.v, taps[kk + 1 < ntap ? kk + 1 : kk]);
+      texels_clamped(pack, W, H, x + tn.ix, y + tn.iy, n00, n10, n01, n11);
+    }
+    const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
+    // samples, their spatial slopes, and their motion with R
+    const float dxs = u.x * R.s, dxa = u.x * R.a, dys = u.y * R.s, dya = u.y * R.a;
+#define SAMPLE(c)                                                                                   \
+  const float s_##c = w00 * v00.c + w10 * v10.c + w01 * v01.c + w11 * v11.c;                        \
+  const float sx_##c = SLOPE ? by * (v10.c - v00.c) + ay * (v11.c - v01.c) : 0.f;                    \
+  const float sy_##c = SLOPE ? bx * (v01.c - v00.c) + ax * (v11.c - v10.c) : 0.f;
+    SAMPLE(x) SAMPLE(y) SAMPLE(z) SAMPLE(w)
+#undef SAMPLE
+    const D3 cq = SLOPE ? dk(s_w, dcs + sx_w * dxs + sy_w * dys, s_w * inv_A + sx_w * dxa + sy_w * dya)
+                        : dk(s_w, dcs, s_w * inv_A);
+    const D3 rq = 0.5f * dabs(cq);
+    const D3 tk = dclamp(inv_ramp * (cq - cpv), 0.f, 1.f);
+    const D3 dpos = dmaxc(rq - rp, 0.f);
+    const D3 reff = rq - tk * dpos;
+    const D3 a = dclamp(reff - u.z * R + dc(0.5f), 0.f, 1.f);
+    const D3 rq5 = dmaxc(rq, 0.5f);
+    const D3 w = dquot(a * ((1.0f / (float)n_taps) * (R * R)), rq5 * rq5);
+    if (SLOPE) {
+      nr = nr + w * dk(s_x, sx_x * dxs + sy_x * dys, sx_x * dxa + sy_x * dya);
+      ng = ng + w * dk(s_y, sx_y * dxs + sy_y * dys, sx_y * dxa + sy_y * dya);
+      nb = nb + w * dk(s_z, sx_z * dxs + sy_z * dys, sx_z * dxa + sy_z * dya);
+    } else {
+      nr = nr + s_x * w;
+      ng = ng + s_y * w;
+      nb = nb + s_z * w;
+    }
+    den = den + w;
+    v00 = n00;
+    v10 = n10;
+    v01 = n01;
+    v11 = n11;
+  }
+}
+
+// The CoCs (w) of the four clamp-to-edge texels of the bilinear footprint
+// whose corner is (xa, ya), in the order 00, 10, 01, 11.
+__device__ __forceinline__ float4 cocs_clamped(const float4* __restrict__ pack, int W, int H, int xa, int ya) {
+  const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
+  const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
+  const float* pw = (const float*)pack + 3;
+  return make_float4(pw[4 * ((size_t)ya_ * W + xa_)], pw[4 * ((size_t)ya_ * W + xb_)],
+                     pw[4 * ((size_t)yb_ * W + xa_)], pw[4 * ((size_t)yb_ * W + xb_)]);
 }
 
 // Adjoint of post-filter + composite.  Pass 1 per pixel: the gather again in
@@ -1035,34 +1125,12 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
       R = dk(R.v, sg * dcs, sg * cm * inv_A);
     }
     D3 nr = w0 * dc(cp4.x), ng = w0 * dc(cp4.y), nb = w0 * dc(cp4.z), den = w0;
-    for (int kk = 0; kk < ntap; ++kk) {
-      const float4 u = taps[kk];
-      const TapGeo tg = tap_geo(R.v, u);
-      const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
-      float4 v00, v10, v01, v11;
-      texels_clamped(pack, W, H, x + tg.ix, y + tg.iy, v00, v10, v01, v11);
-      const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
-      // samples, their spatial slopes, and their motion with R
-      const float dxs = u.x * R.s, dxa = u.x * R.a, dys = u.y * R.s, dya = u.y * R.a;
-#define SAMPLE(c)                                                                       \
-  const float s_##c = w00 * v00.c + w10 * v10.c + w01 * v01.c + w11 * v11.c;            \
-  const float sx_##c = by * (v10.c - v00.c) + ay * (v11.c - v01.c);                      \
-  const float sy_##c = bx * (v01.c - v00.c) + ax * (v11.c - v10.c);
-      SAMPLE(x) SAMPLE(y) SAMPLE(z) SAMPLE(w)
-#undef SAMPLE
-      const D3 cq = dk(s_w, dcs + sx_w * dxs + sy_w * dys, s_w * inv_A + sx_w * dxa + sy_w * dya);
-      const D3 rq = 0.5f * dabs(cq);
-      const D3 tk = dclamp(inv_ramp * (cq - cpv), 0.f, 1.f);
-      const D3 dpos = dmaxc(rq - rp, 0.f);
-      const D3 reff = rq - tk * dpos;
-      const D3 a = dclamp(reff - u.z * R + dc(0.5f), 0.f, 1.f);
-      const D3 rq5 = dmaxc(rq, 0.5f);
-      const D3 w = dquot(a * ((1.0f / (float)n_taps) * (R * R)), rq5 * rq5);
-      nr = nr + w * dk(s_x, sx_x * dxs + sy_x * dys, sx_x * dxa + sy_x * dya);
-      ng = ng + w * dk(s_y, sx_y * dxs + sy_y * dys, sx_y * dxa + sy_y * dya);
-      nb = nb + w * dk(s_z, sx_z * dxs + sy_z * dys, sx_z * dxa + sy_z * dya);
-      den = den + w;
-    }
+    // a tile radius at the cap does not move with S1 or A: the samples stay
+    // put and their spatial slopes drop out
+    if (R.s != 0.0f || R.a != 0.0f)
+      fwd_taps<true>(pack, taps, ntap, n_taps, W, H, x, y, R, cpv, rp, dcs, inv_A, inv_ramp, nr, ng, nb, den);
+    else
+      fwd_taps<false>(pack, taps, ntap, n_taps, W, H, x, y, R, cpv, rp, dcs, inv_A, inv_ramp, nr, ng, nb, den);
     // composite backward per channel; post-filter transpose for the colour
     const float gq[3] = {g[p], g[N + p], g[2 * N + p]};
     const D3 num[3] = {nr, ng, nb};
@@ -1091,15 +1159,24 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
     // per tap: every pixel posts gpp * weight, then footprint texel (r, q)
     // collects the posts of pixels (r - dy, q - dx) with the block-uniform
     // bilinear weight of corner (dx, dy)
+    // each tap's texel CoCs are requested one tap ahead (see fwd_taps)
+    float4 cw = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (scat && ntap > 0) {
+      const TapGeo t0 = tap_geo(Rv, taps[0]);
+      cw = cocs_clamped(pack, W, H, x + t0.ix, y + t0.iy);
+    }
     for (int kk = 0; kk < ntap; ++kk) {
       const float4 u = taps[kk];
       const TapGeo tg = tap_geo(Rv, u);
       const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
+      float4 cwn = cw;
+      if (scat && kk + 1 < ntap) {
+        const TapGeo tn = tap_geo(Rv, taps[kk + 1]);
+        cwn = cocs_clamped(pack, W, H, x + tn.ix, y + tn.iy);
+      }
       float4 post = make_float4(0.f, 0.f, 0.f, 0.f);
       if (scat) {
-        float4 v00, v10, v01, v11;
-        texels_clamped(pack, W, H, x + tg.ix, y + tg.iy, v00, v10, v01, v11);
-        const float cq = bx * by * v00.w + ax * by * v10.w + bx * ay * v01.w + ax * ay * v11.w;
+        const float cq = bx * by * cw.x + ax * by * cw.y + bx * ay * cw.z + ax * ay * cw.w;
         const float rq = 0.5f * fabsf(cq);
         const float tk = clamp01((cq - cp4.w) * inv_ramp);
         const float a = clamp01(rq - tk * fmaxf(0.f, rq - rpv) - Rv * u.z + 0.5f);
@@ -1107,6 +1184,7 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
         const float wv = a * area * __builtin_amdgcn_rcpf(rq5 * rq5);
         post = make_float4(gpp[0] * wv, gpp[1] * wv, gpp[2] * wv, 0.f);
       }
+      cw = cwn;
       float4* kb = posts[kk & 1];
       kb[ly * 16 + lx] = post;
       __syncthreads();
