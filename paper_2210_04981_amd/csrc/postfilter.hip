@@ -966,6 +966,7 @@ __global__ void k_fill_f(float* __restrict__ p, size_t n, float v) {
 #endif
 #define PPB_WIN (17 + 2 * PPB_WIN_E)     // window side at that radius
 #define PPB_FOOT (PPG_SIDE * PPG_SIDE)   // one tap's 17x17 footprint
+#define PPB_PAD 18                       // the posts' 16x16 grid with a zero border
 
 // Sample geometry of tap u at radius R relative to a pixel's texel grid: the
 // footprint corner offset (floor R u) and the bilinear fractions.
@@ -977,6 +978,18 @@ __device__ __forceinline__ TapGeo tap_geo(float R, float4 u) {
   const float ox = R * u.x, oy = R * u.y;
   const float fx = floorf(ox), fy = floorf(oy);
   return TapGeo{(int)fx, (int)fy, ox - fx, oy - fy};
+}
+
+// texels_clamped with 32-bit byte offsets (images below 2^28 pixels)
+__device__ __forceinline__ void texels_clamped32(const float4* __restrict__ pack, int W, int H, int xa, int ya,
+                                                 float4& v00, float4& v10, float4& v01, float4& v11) {
+  const unsigned xa_ = (unsigned)clampi(xa, 0, W - 1), xb_ = (unsigned)clampi(xa + 1, 0, W - 1);
+  const unsigned ya_ = (unsigned)clampi(ya, 0, H - 1) * (unsigned)W, yb_ = (unsigned)clampi(ya + 1, 0, H - 1) * (unsigned)W;
+  const char* pb = (const char*)pack;
+  v00 = *(const float4*)(pb + ((ya_ + xa_) << 4));
+  v10 = *(const float4*)(pb + ((ya_ + xb_) << 4));
+  v01 = *(const float4*)(pb + ((yb_ + xa_) << 4));
+  v11 = *(const float4*)(pb + ((yb_ + xb_) << 4));
 }
 
 // The forward-mode gather's taps of one pixel (value, d/dS1, d/dA).  SLOPE:
@@ -993,7 +1006,7 @@ __device__ __forceinline__ void fwd_taps(const float4* __restrict__ pack, const 
   float4 v00, v10, v01, v11;
   {
     const TapGeo t0 = tap_geo(R.v, taps[0]);
-    texels_clamped(pack, W, H, x + t0.ix, y + t0.iy, v00, v10, v01, v11);
+    texels_clamped32(pack, W, H, x + t0.ix, y + t0.iy, v00, v10, v01, v11);
   }
   for (int kk = 0; kk < ntap; ++kk) {
     const float4 u = taps[kk];
@@ -1002,7 +1015,7 @@ __device__ __forceinline__ void fwd_taps(const float4* __restrict__ pack, const 
     float4 n00, n10, n01, n11;
     {
       const TapGeo tn = tap_geo(R.v, taps[kk + 1 < ntap ? kk + 1 : kk]);
-      texels_clamped(pack, W, H, x + tn.ix, y + tn.iy, n00, n10, n01, n11);
+      texels_clamped32(pack, W, H, x + tn.ix, y + tn.iy, n00, n10, n01, n11);
     }
     const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
     // samples, their spatial slopes, and their motion with R
@@ -1040,13 +1053,44 @@ __device__ __forceinline__ void fwd_taps(const float4* __restrict__ pack, const 
 }
 
 // The CoCs (w) of the four clamp-to-edge texels of the bilinear footprint
-// whose corner is (xa, ya), in the order 00, 10, 01, 11.
+// whose corner is (xa, ya), in the order 00, 10, 01, 11 (images below 2^28
+// pixels: 32-bit byte offsets).
 __device__ __forceinline__ float4 cocs_clamped(const float4* __restrict__ pack, int W, int H, int xa, int ya) {
-  const int xa_ = clampi(xa, 0, W - 1), xb_ = clampi(xa + 1, 0, W - 1);
-  const int ya_ = clampi(ya, 0, H - 1), yb_ = clampi(ya + 1, 0, H - 1);
-  const float* pw = (const float*)pack + 3;
-  return make_float4(pw[4 * ((size_t)ya_ * W + xa_)], pw[4 * ((size_t)ya_ * W + xb_)],
-                     pw[4 * ((size_t)yb_ * W + xa_)], pw[4 * ((size_t)yb_ * W + xb_)]);
+  const unsigned xa_ = (unsigned)clampi(xa, 0, W - 1), xb_ = (unsigned)clampi(xa + 1, 0, W - 1);
+  const unsigned ya_ = (unsigned)clampi(ya, 0, H - 1) * (unsigned)W, yb_ = (unsigned)clampi(ya + 1, 0, H - 1) * (unsigned)W;
+  const char* pw = (const char*)pack + 12;
+  return make_float4(*(const float*)(pw + ((ya_ + xa_) << 4)), *(const float*)(pw + ((ya_ + xb_) << 4)),
+                     *(const float*)(pw + ((yb_ + xa_) << 4)), *(const float*)(pw + ((yb_ + xb_) << 4)));
+}
+
+// Footprint texel t = (r, q) of one tap collects the posts of pixels
+// (r - dy, q - dx) with the block-uniform bilinear weight of corner (dx, dy);
+// kb is the padded post grid (zero border), so no bounds checks.  MODE 1:
+// added to the block's LDS window; MODE 2: added to the image (clamped to
+// the edge) with global atomics.
+template <int MODE>
+__device__ __forceinline__ void foot_texel(const float4* kb, int t, float w00, float w10, float w01, float w11,
+                                           const TapGeo& tg, int E, int wd, float* acc, float* __restrict__ gcol,
+                                           int x0, int y0, int W, int H, size_t N) {
+  const int r = t / PPG_SIDE, q = t - r * PPG_SIDE;
+  const float4* b = kb + r * PPB_PAD + q;  // padded (r - dy + 1, q - dx + 1) = b[(1 - dy) PPB_PAD + 1 - dx]
+  const float4 k00 = b[PPB_PAD + 1], k01 = b[PPB_PAD], k10 = b[1], k11 = b[0];
+  float3 v;
+  v.x = fmaf(w11, k11.x, fmaf(w01, k10.x, fmaf(w10, k01.x, w00 * k00.x)));
+  v.y = fmaf(w11, k11.y, fmaf(w01, k10.y, fmaf(w10, k01.y, w00 * k00.y)));
+  v.z = fmaf(w11, k11.z, fmaf(w01, k10.z, fmaf(w10, k01.z, w00 * k00.z)));
+  if (MODE == 1) {
+    float* wp = acc + (tg.iy + E + r) * wd + tg.ix + E + q;
+    wp[0] += v.x;
+    wp[wd * wd] += v.y;
+    wp[2 * wd * wd] += v.z;
+  } else if (v.x != 0.f || v.y != 0.f || v.z != 0.f) {
+    // footprint texel (r, q) is image texel (y0 + iy + r, x0 + ix + q), clamped to the edge
+    const size_t gi = (size_t)clampi(y0 + tg.iy + r, 0, H - 1) * W + clampi(x0 + tg.ix + q, 0, W - 1);
+    atomicAdd(&gcol[gi], v.x);
+    atomicAdd(&gcol[N + gi], v.y);
+    atomicAdd(&gcol[2 * N + gi], v.z);
+  }
 }
 
 // Adjoint of post-filter + composite.  Pass 1 per pixel: the gather again in
@@ -1070,8 +1114,9 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
     const float* __restrict__ hr, float inv_ht, int rt_override, const float* __restrict__ g,
     float* __restrict__ gcol, float2* __restrict__ partial) {
   __shared__ float acc[UNI ? 3 * PPB_WIN * PPB_WIN : 1];
-  __shared__ float4 posts[UNI ? 2 : 1][UNI ? 256 : 1];
-  __shared__ float2 red[256];
+  // two buffers of the 16x16 pixels' posts, each with a zero border (18x18)
+  __shared__ float4 posts[UNI ? 2 : 1][UNI ? PPB_PAD * PPB_PAD : 128];
+  float2* red = (float2*)&posts[0][0];  // the partials' reduction, after pass 2
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int TWb = (W + 15) >> 4, THb = (H + 15) >> 4;
   const int blk = UNI ? xcd_block(blockIdx.x, TWb * THb) : blockIdx.x;
@@ -1094,8 +1139,10 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
   int mode = 0;
   if (UNI && Rv > 0.0f) mode = E <= PPB_WIN_E ? 1 : 2;
   const int wd = 17 + 2 * E;
-  if (UNI && mode == 1) {
+  if (UNI && mode == 1)
     for (int i = tid; i < 3 * wd * wd; i += 256) acc[i] = 0.0f;
+  if (UNI && mode != 0) {
+    for (int i = tid; i < 2 * PPB_PAD * PPB_PAD; i += 256) (&posts[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
   }
   const int ntap = Rv > 0.0f ? n_taps : 0;
@@ -1186,35 +1233,16 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
       }
       cw = cwn;
       float4* kb = posts[kk & 1];
-      kb[ly * 16 + lx] = post;
+      kb[(ly + 1) * PPB_PAD + lx + 1] = post;
       __syncthreads();
-      for (int t = tid; t < PPB_FOOT; t += 256) {
-        const int r = t / PPG_SIDE, q = t - r * PPG_SIDE;
-        float3 v = make_float3(0.f, 0.f, 0.f);
-#define PPB_POST(dy, dx, wgt)                                                     \
-  if (r - dy >= 0 && r - dy < 16 && q - dx >= 0 && q - dx < 16) {                \
-    const float4 k4 = kb[(r - dy) * 16 + q - dx];                                 \
-    v.x = fmaf(wgt, k4.x, v.x);                                                   \
-    v.y = fmaf(wgt, k4.y, v.y);                                                   \
-    v.z = fmaf(wgt, k4.z, v.z);                                                   \
-  }
-        PPB_POST(0, 0, bx * by)
-        PPB_POST(0, 1, ax * by)
-        PPB_POST(1, 0, bx * ay)
-        PPB_POST(1, 1, ax * ay)
-#undef PPB_POST
-        if (mode == 1) {
-          float* wp = acc + (tg.iy + E + r) * wd + tg.ix + E + q;
-          wp[0] += v.x;
-          wp[wd * wd] += v.y;
-          wp[2 * wd * wd] += v.z;
-        } else if (v.x != 0.f || v.y != 0.f || v.z != 0.f) {
-          // footprint texel (r, q) is image texel (y0 + iy + r, x0 + ix + q), clamped to the edge
-          const size_t gi = (size_t)clampi(y0 + tg.iy + r, 0, H - 1) * W + clampi(x0 + tg.ix + q, 0, W - 1);
-          atomicAdd(&gcol[gi], v.x);
-          atomicAdd(&gcol[N + gi], v.y);
-          atomicAdd(&gcol[2 * N + gi], v.z);
-        }
+      // footprint texel t of the 17x17 (two per thread for t < 33)
+      const float w00 = bx * by, w10 = ax * by, w01 = bx * ay, w11 = ax * ay;
+      if (mode == 1) {
+        foot_texel<1>(kb, tid, w00, w10, w01, w11, tg, E, wd, acc, gcol, x0, y0, W, H, N);
+        if (tid < PPB_FOOT - 256) foot_texel<1>(kb, tid + 256, w00, w10, w01, w11, tg, E, wd, acc, gcol, x0, y0, W, H, N);
+      } else {
+        foot_texel<2>(kb, tid, w00, w10, w01, w11, tg, E, wd, acc, gcol, x0, y0, W, H, N);
+        if (tid < PPB_FOOT - 256) foot_texel<2>(kb, tid + 256, w00, w10, w01, w11, tg, E, wd, acc, gcol, x0, y0, W, H, N);
       }
     }
   } else if (scat) {
@@ -1257,6 +1285,7 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
       }
     }
   }
+  __syncthreads();  // the posts' last readers are done
   red[tid] = make_float2(gs, ga);
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
