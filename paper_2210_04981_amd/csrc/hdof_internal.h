@@ -161,6 +161,10 @@ __device__ inline V3 cross3(V3 a, V3 b) {
 __device__ inline float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 __device__ inline float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 
+// pixels per block of the batched per-pixel passes (queue fill, reduction,
+// traced pixels' composite): 16 per thread, so a block's view lookup is
+// paid once per 4096 pixels
+#define HDOF_BATCH_PX_BLOCK 4096
 // the view of unit g (a block or a tile) of a launch over a batch's views:
 // the last view whose first unit base[v] is <= g (base ascending, base[0] 0)
 __device__ inline int batch_view_of(const int* base, int n, int g) {

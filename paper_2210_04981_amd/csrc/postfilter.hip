@@ -489,12 +489,12 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
 
 // The batched form's gathers and traced pixels' composites, one launch
 // each over every view: a block finds its view by a binary search over the
-// views' first tiles (first 256-pixel blocks for the composite); a view's
+// views' first tiles (first pixel blocks for the composite); a view's
 // planes start at its px_base and its tile radii at its first tile.
 struct PPBatch {
   int n;
   int tile_base[HDOF_MAX_VIEWS + 1];  // [n]: all tiles
-  int blk_base[HDOF_MAX_VIEWS + 1];   // [n]: all 256-pixel blocks
+  int blk_base[HDOF_MAX_VIEWS + 1];   // [n]: all blocks of HDOF_BATCH_PX_BLOCK pixels
   float* out[HDOF_MAX_VIEWS];
 };
 
@@ -825,14 +825,13 @@ __global__ void k_composite_traced(CompK a) {
   if (p < a.N && a.spp[p] > 0) composite_at(a, p);
 }
 
-// every view's traced pixels in one launch; `a` holds the first view's
-// planes (all views' planes are concatenated from their px_base)
+// every view's traced pixels in one launch, HDOF_BATCH_PX_BLOCK pixels per
+// block; `a` holds the first view's planes (all views' planes are
+// concatenated from their px_base)
 __global__ void k_composite_traced_batch(CompK a, const BatchView* __restrict__ views, PPBatch b) {
   const int v = batch_view_of(b.blk_base, b.n, blockIdx.x);
   const int N = views[v].k.W * views[v].k.H;
-  const int p = (blockIdx.x - b.blk_base[v]) * blockDim.x + threadIdx.x;
   const size_t pb = (size_t)views[v].px_base;
-  if (p >= N || a.spp[pb + p] == 0) return;
   CompK c = a;
   c.color += 3 * pb;
   c.pp += 3 * pb;
@@ -844,7 +843,12 @@ __global__ void k_composite_traced_batch(CompK a, const BatchView* __restrict__ 
   c.l = views[v].l;
   c.N = N;
   c.out = b.out[v];
-  composite_at(c, p);
+  const int p0 = (blockIdx.x - b.blk_base[v]) * HDOF_BATCH_PX_BLOCK;
+  for (int i = threadIdx.x; i < HDOF_BATCH_PX_BLOCK; i += blockDim.x) {
+    const int p = p0 + i;
+    if (p >= N) break;
+    if (c.spp[p] > 0) composite_at(c, p);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1439,7 +1443,7 @@ hdof_status launch_composite_traced_batched(hdof_ctx* ctx, const float* color, c
   PPBatch b{};
   b.n = n_views;
   for (int v = 0; v < n_views; ++v) {
-    b.blk_base[v + 1] = b.blk_base[v] + cdiv(hviews[v].k.W * hviews[v].k.H, 256);
+    b.blk_base[v + 1] = b.blk_base[v] + cdiv(hviews[v].k.W * hviews[v].k.H, HDOF_BATCH_PX_BLOCK);
     b.out[v] = outs[v];
   }
   const CompK a{color, pp, depth, spp, rt.c_near, rt.c_far, rt.hit_ratio, hviews[0].l, 0, 1.0f / cp.h_t,

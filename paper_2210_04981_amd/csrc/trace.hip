@@ -856,8 +856,9 @@ __global__ void k_rt_reduce(const uint8_t* __restrict__ spp, const int* __restri
 }
 
 // The batched form's queue fill and reduction, one launch each over every
-// view: blocks of 256 pixels, view v's from blk_base[v] (blk_base[n] the
-// total), its pixels from its px_base and its queue entries from ebase[v].
+// view: blocks of HDOF_BATCH_PX_BLOCK pixels (256 threads, a pixel every
+// 256), view v's from blk_base[v] (blk_base[n] the total), its pixels from
+// its px_base and its queue entries from ebase[v].
 struct PxBatch {
   int n;
   int blk_base[HDOF_MAX_VIEWS + 1];
@@ -866,16 +867,21 @@ struct PxBatch {
 __global__ void k_queue_fill_batch(const uint8_t* __restrict__ spp, const int* __restrict__ offsets,
                                    const ViewK* __restrict__ views, PxBatch b, const int* __restrict__ ebase,
                                    long cap, int* __restrict__ queue, int* __restrict__ counter) {
-  const int gp = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gp < 8 * HDOF_SEG_STRIDE) counter[gp] = 0;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < 8 * HDOF_SEG_STRIDE; i += blockDim.x) counter[i] = 0;
   const int v = batch_view_of(b.blk_base, b.n, blockIdx.x);
   const int N = views[v].k.W * views[v].k.H, pb = views[v].px_base;
-  const int p = (blockIdx.x - b.blk_base[v]) * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const int s = spp[pb + p];
-  const long o = (long)offsets[pb + p] + ebase[v];
-  for (int j = 0; j < s; ++j)
-    if (o + j >= 0 && o + j < cap) queue[o + j] = pb + p;
+  const int e0 = ebase[v];
+  const int p0 = (blockIdx.x - b.blk_base[v]) * HDOF_BATCH_PX_BLOCK;
+  for (int i = threadIdx.x; i < HDOF_BATCH_PX_BLOCK; i += blockDim.x) {
+    const int p = p0 + i;
+    if (p >= N) break;
+    const int s = spp[pb + p];
+    if (s == 0) continue;
+    const long o = (long)offsets[pb + p] + e0;
+    for (int j = 0; j < s; ++j)
+      if (o + j >= 0 && o + j < cap) queue[o + j] = pb + p;
+  }
 }
 
 // the trace planes are written at traced pixels only (the composite reads
@@ -888,12 +894,18 @@ __global__ void k_rt_reduce_batch(const uint8_t* __restrict__ spp, const int* __
   const int v = batch_view_of(b.blk_base, b.n, blockIdx.x);
   const int N = views[v].k.W * views[v].k.H;
   const size_t pb = (size_t)views[v].px_base;
-  const int p = (blockIdx.x - b.blk_base[v]) * blockDim.x + threadIdx.x;
-  if (p >= N) return;
+  const LensK l = views[v].l;
+  const CamK k = views[v].k;
   VarFuse vf{};
   vf.sparse_rt = 1;
-  rt_reduce_px<false, false>(p, spp + pb, offsets + pb, N, ebase + v, ray_col, ray_z, cap, views[v].l, cn + 3 * pb,
-                             cf + 3 * pb, h + pb, m1 + pb, m2 + pb, views[v].k, 0u, 0u, 0u, nullptr, vf, nullptr);
+  const int p0 = (blockIdx.x - b.blk_base[v]) * HDOF_BATCH_PX_BLOCK;
+  for (int i = threadIdx.x; i < HDOF_BATCH_PX_BLOCK; i += blockDim.x) {
+    const int p = p0 + i;
+    if (p >= N) break;
+    if (spp[pb + p] == 0) continue;  // the planes are written at traced pixels only
+    rt_reduce_px<false, false>(p, spp + pb, offsets + pb, N, ebase + v, ray_col, ray_z, cap, l, cn + 3 * pb,
+                               cf + 3 * pb, h + pb, m1 + pb, m2 + pb, k, 0u, 0u, 0u, nullptr, vf, nullptr);
+  }
 }
 
 // batch: first queue entry of each view and the batch total
@@ -1041,7 +1053,8 @@ hdof_status launch_trace_batched(hdof_ctx* ctx, const hdof_scene* sc, const Ligh
   if ((s = reserve_trace(ctx, cap, true)) != HDOF_OK) return s;
   PxBatch pxb{};
   pxb.n = n_views;
-  for (int v = 0; v < n_views; ++v) pxb.blk_base[v + 1] = pxb.blk_base[v] + cdiv(hviews[v].k.W * hviews[v].k.H, 256);
+  for (int v = 0; v < n_views; ++v)
+    pxb.blk_base[v + 1] = pxb.blk_base[v] + cdiv(hviews[v].k.W * hviews[v].k.H, HDOF_BATCH_PX_BLOCK);
   hipLaunchKernelGGL(k_view_scan, dim3(1), dim3(64), 0, st, totals, n_views, ebase, grand);
   hipLaunchKernelGGL(k_queue_fill_batch, dim3(pxb.blk_base[n_views]), dim3(256), 0, st, spp, offsets,
                      (const ViewK*)views_dev, pxb, (const int*)ebase, (long)cap, (int*)ctx->queue.p,
