@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_
                                                    int* __restrict__ xpref, int* __restrict__ rowsum,
                                                    int* __restrict__ rowtot, const int* __restrict__ tsel,
                                                    MaskAuto au) {
-  __shared__ int part[256];
+  __shared__ int part[4];
   t = mask_tile_of(t, tsel);
   if (tsel) tile_max = t == 4 ? au.tm4 : (t == 8 ? au.tm8 : au.tm16);
   const int TW = (W + t - 1) / t, TH = (H + t - 1) / t;
@@ -256,22 +256,26 @@ __global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_
     tile_dil[ty * TW + tx] = m;
     local += m * min(t, W - tx * t);
   }
-  part[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    int v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  // inclusive scan of the threads' sums: within each wave by shuffles,
+  // then the four wave totals
+  const int lane = tid & 63, wave = tid >> 6;
+  int incl = local;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int n = __shfl_up(incl, o);
+    if (lane >= o) incl += n;
   }
-  int run = part[tid] - local;
+  if (lane == 63) part[wave] = incl;
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) incl += part[w];
+  const int row = part[0] + part[1] + part[2] + part[3];
+  int run = incl - local;
   for (int tx = lo; tx < hi; ++tx) {
     xpref[ty * TW + tx] = run;
     run += tile_dil[ty * TW + tx] * min(t, W - tx * t);
   }
   if (tid == 255) {
-    rowsum[ty] = part[255];
-    rowtot[ty] = part[255] * min(t, H - ty * t);
+    rowsum[ty] = row;
+    rowtot[ty] = row * min(t, H - ty * t);
   }
 }
 
@@ -316,11 +320,14 @@ __global__ void k_mask_write(int W, int H, int t, const int* __restrict__ tile_d
   offsets[p] = ybase[ty] + (y - ty * t) * rowsum[ty] + xpref[ty * TW + tx] + (x - tx * t) * S;
 }
 
-// Whole frames: the same write with the tile-row scan done per block (the
-// block sums the row totals before its tile row; the last row's first block
-// also writes the total), and the ray queue written here instead of by the
-// trace's queue fill (pixel index per entry, entries outside [0, cap)
-// dropped; the trace's work counters cleared).
+// Whole frames: the same write with the tile-row scan done per block, one
+// block per 256 columns of one tile row (the block sums the row totals
+// before its tile row; the last tile row's first block also writes the
+// total), and the ray queue written here instead of by the trace's queue
+// fill (pixel index per entry, entries outside [0, cap) dropped; the
+// trace's work counters cleared).  Launched over the tile rows of the
+// launch's tile edge t (tile 0: 4, the smallest); with the edge chosen on
+// the device, blocks past its tile rows exit.
 __global__ __launch_bounds__(256) void k_mask_write_queue(int W, int H, int t, int TH,
                                                           const int* __restrict__ tile_dil,
                                                           const int* __restrict__ xpref,
@@ -329,38 +336,45 @@ __global__ __launch_bounds__(256) void k_mask_write_queue(int W, int H, int t, i
                                                           int* __restrict__ offsets, int* __restrict__ total,
                                                           int* __restrict__ queue, long cap, int* __restrict__ counter,
                                                           const int* __restrict__ tsel) {
-  __shared__ int2 red[256];
-  const int tid = threadIdx.x;
+  __shared__ int2 red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tsel) {
     t = *tsel;
     TH = (H + t - 1) / t;
   }
-  const int x = blockIdx.x * blockDim.x + tid, y = blockIdx.y;
-  const int ty = y / t;
+  const int ty = blockIdx.y;
+  if (ty >= TH) return;
+  if (blockIdx.x == 0 && ty == 0)
+    for (int i = tid; i < 8 * HDOF_SEG_STRIDE; i += 256) counter[i] = 0;
   int before = 0, all = 0;
   for (int i = tid; i < TH; i += 256) {
     const int v = rowtot[i];
     if (i < ty) before += v;
     all += v;
   }
-  red[tid] = make_int2(before, all);
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] = make_int2(red[tid].x + red[tid + o].x, red[tid].y + red[tid + o].y);
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    before += __shfl_xor(before, o);
+    all += __shfl_xor(all, o);
   }
-  const int ybase = red[0].x;
-  if (blockIdx.x == 0 && y == H - 1 && tid == 0) *total = red[0].y;
-  const size_t p = (size_t)y * W + x;
-  if (p < 8 * HDOF_SEG_STRIDE) counter[p] = 0;
+  if (lane == 0) red[wave] = make_int2(before, all);
+  __syncthreads();
+  const int ybase = red[0].x + red[1].x + red[2].x + red[3].x;
+  if (blockIdx.x == 0 && ty == TH - 1 && tid == 0) *total = red[0].y + red[1].y + red[2].y + red[3].y;
+  const int x = blockIdx.x * blockDim.x + tid;
   if (x >= W) return;
   const int TW = (W + t - 1) / t, tx = x / t;
   const int S = tile_dil[ty * TW + tx];
-  const int o = ybase + (y - ty * t) * rowsum[ty] + xpref[ty * TW + tx] + (x - tx * t) * S;
-  spp[p] = (uint8_t)S;
-  offsets[p] = o;
-  for (int j = 0; j < S; ++j)
-    if ((long)o + j >= 0 && (long)o + j < cap) queue[o + j] = (int)p;
+  const int rs = rowsum[ty];
+  const int o0 = ybase + xpref[ty * TW + tx] + (x - tx * t) * S;
+  const int y1 = min(H, (ty + 1) * t);
+  for (int y = ty * t; y < y1; ++y) {
+    const size_t p = (size_t)y * W + x;
+    const int o = o0 + (y - ty * t) * rs;
+    spp[p] = (uint8_t)S;
+    offsets[p] = o;
+    for (int j = 0; j < S; ++j)
+      if ((long)o + j >= 0 && (long)o + j < cap) queue[o + j] = (int)p;
+  }
 }
 
 // history update after the trace
@@ -490,7 +504,7 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   hipLaunchKernelGGL(k_mask_rows, dim3(TH), dim3(256), 0, st, (const int*)ctx->mask_tile.p, W, H, t,
                      mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot, tsel, au);
   if (queue) {
-    hipLaunchKernelGGL(k_mask_write_queue, dim3(cdiv(W, 256), H), dim3(256), 0, st, W, H, t, TH,
+    hipLaunchKernelGGL(k_mask_write_queue, dim3(cdiv(W, 256), TH), dim3(256), 0, st, W, H, t, TH,
                        (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p, (const int*)rowsum,
                        (const int*)rowtot, spp, offsets, total, queue, cap, counter, tsel);
   } else {
