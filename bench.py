@@ -628,11 +628,14 @@ def bench_temporal(hdof, ctx, frames=60):
     keep = counts_keep(hdof, H, W)
     out = torch.empty(3, H, W, device="cuda")
     totals = torch.zeros(frames, dtype=torch.int32, device="cuda")
-    # the launch shape the autotuner picks for this workload class (timed on
-    # the path's first frame), restored afterwards
+    # the launch shape the autotuner picks for this workload class, timed on
+    # a frame of the path that carries the variance history (frame 10's
+    # camera after itself, so every timed frame reprojects the history the
+    # one before wrote: the variance term traces what it traces along the
+    # path, which a first frame does not), restored afterwards
     prior = hdof.hdof_get_tuning(ctx)
-    tuned, rep = hdof.hdof_autotune(ctx, sc, light, params, [(cams[0], lens, cfg.seed, 0, 0)], outs=[out],
-                                    stream=stream)
+    tuned, rep = hdof.hdof_autotune(ctx, sc, light, params, [(cams[10], lens, cfg.seed, 10, 0)], outs=[out],
+                                    stream=stream, prev=cams[10])
 
     def run(record=None):
         for t in range(frames):

@@ -520,21 +520,25 @@ hdof_status hdof_set_tuning(hdof_ctx* ctx, const hdof_tuning* tuning);
 hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
 
 /* The library's autotuner of the launch shape (not in the paper: its tile
- * and queue sizes are scheduling choices of this implementation).  It times the caller's workload -- hdof_frame on
- * views[0] with no previous camera when n_views = 1, hdof_frame_batched on
- * all views otherwise -- on `stream` under candidate tunings (coordinate
- * descent from the defaults over blocks_per_cu, refill, segments, wave,
- * and for single frames overlap and overlap_ray_quantum; a change is kept
- * when it is at least 0.5 % faster; each candidate is the median of
- * several timed runs), sets the fastest on the context and returns it in
- * *out.  The workload's outputs (views[v].d_out) are written, and for a
- * single frame the context's variance history is replaced (every timed
- * frame is a first frame).  cache_path (nullable): a JSON-lines file, one
+ * and queue sizes are scheduling choices of this implementation).  It times
+ * the caller's workload -- hdof_frame on views[0] when n_views = 1,
+ * hdof_frame_batched on all views otherwise -- on `stream` under candidate
+ * tunings (coordinate descent from the defaults over blocks_per_cu,
+ * refill, segments, wave, and for single frames overlap and
+ * overlap_ray_quantum; a change is kept when it is at least 0.5 % faster;
+ * each candidate is the median of several timed runs), sets the fastest on
+ * the context and returns it in *out.  The workload's outputs
+ * (views[v].d_out) are written.  prev (nullable, single frames only): every
+ * timed frame is hdof_frame(views[0].cam, prev), so it carries the
+ * variance history of the frame before it, as frames along a camera path
+ * do (the mask then also traces the pixels whose luminance varies); NULL:
+ * every timed frame is a first frame.  Either way the context's variance
+ * history is replaced.  cache_path (nullable): a JSON-lines file, one
  * object per workload class keyed by the device's architecture, its CU
  * count and the class (image sizes, spp_max, tiles, the scene's triangle
- * count as a power of two, view count, optional stages); an entry for the
- * class is applied without timing unless force != 0, and a search writes
- * (or replaces) its entry.  Not under stream capture
+ * count as a power of two, view count, optional stages, history); an entry
+ * for the class is applied without timing unless force != 0, and a search
+ * writes (or replaces) its entry.  Not under stream capture
  * (HDOF_ERR_UNSUPPORTED); not thread-safe per context or per cache file. */
 typedef struct {
   char key[256];        /* the workload class */
@@ -545,7 +549,7 @@ typedef struct {
 } hdof_autotune_report;
 hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
                           const hdof_frame_params* params, int32_t n_views, const hdof_view* views,
-                          const char* cache_path, int32_t force, hdof_tuning* out,
+                          const hdof_camera* prev, const char* cache_path, int32_t force, hdof_tuning* out,
                           hdof_autotune_report* report, hdof_stream stream);
 
 /* ---------------------------------------------------------------------- */

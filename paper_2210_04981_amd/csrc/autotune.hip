@@ -31,7 +31,7 @@
 namespace {
 
 std::string workload_key(const hdof_ctx* ctx, const hdof_scene* scene, const hdof_frame_params* p, int n_views,
-                         const hdof_view* views) {
+                         const hdof_view* views, bool history) {
   hipDeviceProp_t prop;
   char arch[64] = "unknown";
   if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
@@ -45,9 +45,10 @@ std::string workload_key(const hdof_ctx* ctx, const hdof_scene* scene, const hdo
   long px = 0;
   for (int v = 0; v < n_views; ++v) px += (long)views[v].cam.width * views[v].cam.height;
   if (n_views == 1)
-    snprintf(buf, sizeof buf, "%s|%d|frame %dx%d spp%d mtile%d pptile%d tris2^%d recon%d spatial%d spec%d", arch,
-             ctx->n_cu, views[0].cam.width, views[0].cam.height, p->mask.spp_max, p->mask.tile, p->pp.tile,
-             tris_log2, p->recon.enable, p->spatial.enable, scene->spec && p->comp.spec_y > 0.0f ? 1 : 0);
+    snprintf(buf, sizeof buf, "%s|%d|frame %dx%d spp%d mtile%d pptile%d tris2^%d recon%d spatial%d spec%d hist%d",
+             arch, ctx->n_cu, views[0].cam.width, views[0].cam.height, p->mask.spp_max, p->mask.tile, p->pp.tile,
+             tris_log2, p->recon.enable, p->spatial.enable, scene->spec && p->comp.spec_y > 0.0f ? 1 : 0,
+             history ? 1 : 0);
   else
     snprintf(buf, sizeof buf, "%s|%d|batch %d views %.1fMpx spp%d mtile%d pptile%d tris2^%d", arch, ctx->n_cu,
              n_views, (double)px / 1e6, p->mask.spp_max, p->mask.tile, p->pp.tile, tris_log2);
@@ -135,12 +136,13 @@ struct Workload {
   const hdof_frame_params* params;
   int n_views;
   const hdof_view* views;
+  const hdof_camera* prev;  // single frames: the previous camera (NULL: no history)
   hipStream_t st;
 
   hdof_status run() const {
     if (n_views == 1) {
       const hdof_view& v = views[0];
-      return hdof_frame(ctx, scene, &v.cam, nullptr, &v.lens, light, params, v.seed, v.frame, v.view, v.d_out,
+      return hdof_frame(ctx, scene, &v.cam, prev, &v.lens, light, params, v.seed, v.frame, v.view, v.d_out,
                         nullptr, st);
     }
     return hdof_frame_batched(ctx, scene, light, params, n_views, views, st);
@@ -170,19 +172,21 @@ hdof_status time_tuning(const Workload& w, const hdof_tuning& t, int warm, int r
 
 extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
                                      const hdof_frame_params* params, int32_t n_views, const hdof_view* views,
-                                     const char* cache_path, int32_t force, hdof_tuning* out,
-                                     hdof_autotune_report* report, hdof_stream stream) {
+                                     const hdof_camera* prev, const char* cache_path, int32_t force,
+                                     hdof_tuning* out, hdof_autotune_report* report, hdof_stream stream) {
   if (!ctx) return hdof_set_error(HDOF_ERR_INVALID_ARG, "context is NULL");
   if (!scene || !light || !params || !views || !out)
     return hdof_set_error(HDOF_ERR_INVALID_ARG, "scene, light, params, views and out must be non-NULL");
   if (n_views < 1 || n_views > HDOF_MAX_VIEWS)
     return hdof_set_error(HDOF_ERR_INVALID_ARG, "n_views must be in [1, %d]", HDOF_MAX_VIEWS);
+  if (prev && n_views != 1)
+    return hdof_set_error(HDOF_ERR_INVALID_ARG, "a previous camera applies to single frames only");
   hipStream_t st = (hipStream_t)stream;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HDOF_HIP(hipStreamIsCapturing(st, &cap));
   if (cap != hipStreamCaptureStatusNone)
     return hdof_set_error(HDOF_ERR_UNSUPPORTED, "the autotuner times its candidates: not under stream capture");
-  const std::string key = workload_key(ctx, scene, params, n_views, views);
+  const std::string key = workload_key(ctx, scene, params, n_views, views, prev != nullptr);
   hdof_autotune_report rep;
   memset(&rep, 0, sizeof rep);
   snprintf(rep.key, sizeof rep.key, "%s", key.c_str());
@@ -200,7 +204,7 @@ extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, con
       return HDOF_OK;
     }
   }
-  const Workload w{ctx, scene, light, params, n_views, views, st};
+  const Workload w{ctx, scene, light, params, n_views, views, prev, st};
   const bool frame = n_views == 1;
   // a batch is ~30x a frame: fewer repetitions of each candidate
   const int warm = frame ? 3 : 1, reps = frame ? 15 : 5;

@@ -156,7 +156,8 @@ _PROTOS = {
     "hdof_batch_destroy": (None, [P]),
     "hdof_set_tuning": (_S, [P, C.POINTER(Tuning)]),
     "hdof_get_tuning": (_S, [P, C.POINTER(Tuning)]),
-    "hdof_autotune": (_S, [P, P, C.POINTER(Light), C.POINTER(FrameParams), _i32, C.POINTER(View), C.c_char_p, _i32,
+    "hdof_autotune": (_S, [P, P, C.POINTER(Light), C.POINTER(FrameParams), _i32, C.POINTER(View), C.POINTER(Camera),
+                           C.c_char_p, _i32,
                            C.POINTER(Tuning), C.POINTER(AutotuneReport), P]),
     "hdof_postfilter_composite_backward": (_S, [P, P, P, P, RTBufs, C.POINTER(Camera), C.POINTER(Lens),
                                                 C.POINTER(PPParams), C.POINTER(CompositeParams), P, P, P, P]),
@@ -712,17 +713,20 @@ def hdof_set_tuning(ctx: Context, blocks_per_cu=10, refill=64, segments=8, wave=
 
 
 def hdof_autotune(ctx: Context, scene: Scene, lit: Light, params: FrameParams, views, outs=None,
-                  cache_path: str | None = None, force: bool = False, stream=None) -> tuple[dict, dict]:
+                  cache_path: str | None = None, force: bool = False, stream=None,
+                  prev: Camera | None = None) -> tuple[dict, dict]:
     """Search (or load from `cache_path`) the fastest launch shape for the
     workload: one view = hdof_frame, several = hdof_frame_batched; `views`
-    as for hdof_frame_batched.  Returns (tuning, report); the tuning is set
-    on the context."""
+    as for hdof_frame_batched.  prev (one view only): time frames that carry
+    the variance history, with this previous camera.  Returns (tuning,
+    report); the tuning is set on the context."""
     if outs is None:
         outs = [torch.empty(3, v[0].height, v[0].width, dtype=torch.float32, device="cuda") for v in views]
     arr = _views(views, outs)
     t = Tuning()
     rep = AutotuneReport()
     _check(_lib.hdof_autotune(ctx.handle, scene.handle, C.byref(lit), C.byref(params), len(views), arr,
+                              None if prev is None else C.byref(prev),
                               None if cache_path is None else str(cache_path).encode(), int(bool(force)),
                               C.byref(t), C.byref(rep), _stream(stream)), "hdof_autotune")
     tuning = dict(blocks_per_cu=t.blocks_per_cu, refill=t.refill, segments=t.segments, wave=t.wave,

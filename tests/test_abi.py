@@ -81,7 +81,7 @@ def test_null_arguments_rejected(hd):
     assert L.hdof_postfilter_noalloc(None, None, None, C.byref(cam), C.byref(lns), C.byref(pp), None, None) == INVALID
     fp = hd.FrameParams()
     t = hd.Tuning()
-    assert L.hdof_autotune(None, None, C.byref(lit), C.byref(fp), 1, None, None, 0, C.byref(t), None,
+    assert L.hdof_autotune(None, None, C.byref(lit), C.byref(fp), 1, None, None, None, 0, C.byref(t), None,
                            None) == INVALID
     h = C.c_void_p()
     assert L.hdof_build_bvh(None, None, None, 1, C.byref(h), None) == INVALID

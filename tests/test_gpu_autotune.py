@@ -92,3 +92,36 @@ def test_autotune_batch(hd, ctx, room):
     for a, b in zip(outs, ref):
         assert torch.equal(a, b)
     hd.hdof_set_tuning(ctx)
+
+
+def test_autotune_with_history(hd, ctx, room, tmp_path):
+    """With a previous camera every timed frame carries the variance
+    history; the class key says so, and a frame pair along the path under the
+    tuned shape equals the pair under the defaults bit for bit."""
+    print_case("autotune a 480x270 frame with history")
+    cfg = sg.config_temporal(480, 270)
+    params = hd.frame_params_of(cfg)
+    light = hd.light_of(cfg.light)
+    lens = hd.lens_of(cfg.lens)
+    c0, c1 = (hd.camera_of(sg.temporal_camera(t, 480, 270)) for t in (0, 1))
+
+    def pair():
+        hd.hdof_history_reset(ctx)
+        hd.hdof_frame(ctx, room, c0, None, lens, light, params, seed=cfg.seed, frame=0)
+        return hd.hdof_frame(ctx, room, c1, c0, lens, light, params, seed=cfg.seed, frame=1).clone()
+
+    hd.hdof_set_tuning(ctx)
+    ref = pair()
+    cache = tmp_path / "autotune.jsonl"
+    tuning, rep = hd.hdof_autotune(ctx, room, light, params, [(c1, lens, cfg.seed, 1, 0)], prev=c0,
+                                   cache_path=cache)
+    print(tuning, rep, flush=True)
+    assert rep["key"].endswith("hist1") and rep["candidates"] > 8
+    assert 0 < rep["best_ms"] <= rep["default_ms"]
+    _, rep0 = hd.hdof_autotune(ctx, room, light, params, [(c1, lens, cfg.seed, 1, 0)], cache_path=cache)
+    assert rep0["key"].endswith("hist0") and not rep0["from_cache"]
+    hd.hdof_set_tuning(ctx, **tuning)
+    out = pair()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    hd.hdof_set_tuning(ctx)
