@@ -1243,17 +1243,22 @@ __global__ __launch_bounds__(256) void k_ppc_backward(
     // bilinear weight of corner (dx, dy)
     // each tap's texel CoCs are requested one tap ahead (see fwd_taps)
     float4 cw = make_float4(0.f, 0.f, 0.f, 0.f);
+    // blocks start at different taps, so neighbouring blocks' atomics land
+    // on different texels at a time
+    const int rot = ntap > 0 ? (int)((blk * 17u) % (unsigned)ntap) : 0;
     if (scat && ntap > 0) {
-      const TapGeo t0 = tap_geo(Rv, taps[0]);
+      const TapGeo t0 = tap_geo(Rv, taps[rot]);
       cw = cocs_clamped(pack, W, H, x + t0.ix, y + t0.iy);
     }
     for (int kk = 0; kk < ntap; ++kk) {
-      const float4 u = taps[kk];
+      const int ki = kk + rot < ntap ? kk + rot : kk + rot - ntap;
+      const float4 u = taps[ki];
       const TapGeo tg = tap_geo(Rv, u);
       const float ax = tg.ax, ay = tg.ay, bx = 1.f - ax, by = 1.f - ay;
       float4 cwn = cw;
       if (scat && kk + 1 < ntap) {
-        const TapGeo tn = tap_geo(Rv, taps[kk + 1]);
+        const int kn = ki + 1 < ntap ? ki + 1 : 0;
+        const TapGeo tn = tap_geo(Rv, taps[kn]);
         cwn = cocs_clamped(pack, W, H, x + tn.ix, y + tn.iy);
       }
       float4 post = make_float4(0.f, 0.f, 0.f, 0.f);
