@@ -139,3 +139,38 @@ def test_tuning_does_not_change_results(hd, ctx, room):
     hd.hdof_set_tuning(ctx)
     assert hd.hdof_get_tuning(ctx) == dict(blocks_per_cu=10, refill=64, segments=8, wave=0, overlap=1,
                                            overlap_ray_quantum=140000)
+
+
+def _odd_views(hd, sizes, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for v in range(n):
+        w, h = sizes[v % len(sizes)]
+        cam = sg.look_camera((rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.0), rng.uniform(-10, 10), w, h)
+        lens = sg.lens_fnumber(0.05, [1.4, 2.0, 2.8][v % 3], rng.uniform(0.8, 5.0))
+        out.append((hd.camera_of(cam), hd.lens_of(lens), 23, 4, v))
+    return out
+
+
+@pytest.mark.parametrize("n", [11, 64])
+def test_batched_ragged_views_equal_plain_frames(hd, ctx, room, n):
+    """Views whose 16-pixel tile counts are not multiples of four (so a
+    quad-gather block's tiles straddle two views), a 1x1 view, views far
+    below one 4096-pixel block of the per-pixel passes, and the largest
+    batch (64 views: every step of the block-to-view search): each view
+    equals its plain frame bit for bit."""
+    sizes = [(33, 17), (1, 1), (17, 33), (50, 3), (129, 65), (7, 300), (65, 65), (31, 47)]
+    if n == 64:
+        sizes = [(24, 16), (33, 17), (16, 16), (17, 9), (9, 9)]
+    print_case(f"{n} ragged batched views")
+    cfg = sg.config_1080p()
+    views = _odd_views(hd, sizes, n, seed=n)
+    tiles = [((v[0].width + 15) // 16) * ((v[0].height + 15) // 16) for v in views]
+    assert any(t % 4 for t in tiles) and sum(tiles) % 4
+    outs = hd.hdof_frame_batched(ctx, room, hd.light_of(cfg.light), hd.frame_params_of(cfg), views)
+    torch.cuda.synchronize()
+    ctx.sync()
+    for i, v in enumerate(views):
+        ref = _plain(hd, ctx, room, cfg, v)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), f"view {i} ({v[0].width}x{v[0].height}) differs from the plain frame"
