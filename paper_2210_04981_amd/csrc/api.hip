@@ -1028,6 +1028,7 @@ static hdof_status batch_reserve(hdof_ctx* ctx, const hdof_frame_params* params,
   // mask scratch for the largest view (tile grids, reprojection planes): the
   // widest and the tallest view bound every grid, the most pixels the planes
   TRY(mask_reserve(ctx, L.max_w, L.max_h, params->mask));
+  TRY(mask_reserve_batched(ctx, L.n, L.hv, params->mask));
   TRY(hdof_ensure(ctx->rep_m1, sizeof(float) * L.max_px));
   TRY(hdof_ensure(ctx->rep_m2, sizeof(float) * L.max_px));
   TRY(hdof_ensure(ctx->rep_flags, L.max_px));
@@ -1092,6 +1093,9 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
                                   (float*)(a + L.o_pp), ctx->side));
     HDOF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
   }
+  // the masks: one launch per pass over every view with fixed mask tiles,
+  // per view with the tile scaled by the view's CoC
+  const bool mask1 = params->mask.tile > 0;
   for (int v = 0; v < L.n; ++v) {
     const BatchView& bv = L.hv[v];
     const size_t pb = (size_t)bv.px_base;
@@ -1103,9 +1107,13 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
     gb.tri_id = gball.tri_id + pb;
     gb.spec = nullptr;
     if (!ovl) TRY(launch_gbuffer(ctx, scene, bv.k, bv.l, li, gb, st));
-    TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
-                    (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l, false));
+    if (!mask1)
+      TRY(launch_mask(ctx, gb.depth, gb.normal, bv.k, nullptr, params->mask, (uint8_t*)(a + L.o_spp) + pb,
+                      (int32_t*)(a + L.o_offs) + pb, totals + v, st, nullptr, 0, nullptr, &bv.l, false));
   }
+  if (mask1)
+    TRY(launch_mask_batched(ctx, gball.depth, gball.normal, L.n, L.hv, ctx->b_views.p, params->mask,
+                            (uint8_t*)(a + L.o_spp), (int32_t*)(a + L.o_offs), totals, st));
   TRY(launch_trace_batched(ctx, scene, li, params->mask.spp_max, L.n, L.hv, ctx->b_views.p,
                            (const uint8_t*)(a + L.o_spp), (const int32_t*)(a + L.o_offs), totals, ebase, grand, rt,
                            st));

@@ -383,6 +383,14 @@ hdof_status launch_spatial(hdof_ctx* ctx, int W, int H, const uint8_t* spp, hdof
                            bool zero_untraced = false);
 // the mask's scratch for a W x H frame (tile 0: every candidate grid)
 hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp);
+// the batched form's masks (fixed mask tiles; no history), one launch per
+// pass over every view: counts and view-local offsets into each view's
+// spp/offsets planes (concatenated from px_base), each view's ray total
+// into totals[v]; views_dev is the device copy of hviews
+hdof_status mask_reserve_batched(hdof_ctx* ctx, int n_views, const BatchView* hviews, const hdof_mask_params& mp);
+hdof_status launch_mask_batched(hdof_ctx* ctx, const float* depth, const float* normal, int n_views,
+                                const BatchView* hviews, const void* views_dev, const hdof_mask_params& mp,
+                                uint8_t* spp, int32_t* offsets, int32_t* totals, hipStream_t st);
 // lens: needed for tile 0 (the mask tile scaled by the frame's maximum CoC);
 // write_rep false: the reprojected history is not written (no later
 // variance update of this frame reads it: batched views, captured frames)

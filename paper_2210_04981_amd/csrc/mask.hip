@@ -66,12 +66,11 @@ struct HistIn {
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 template <int GR>
-__global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ depth,
-                                                    const float* __restrict__ normal, CamK k, MaskK mk,
-                                                    HistIn hi, float* __restrict__ rep_m1,
-                                                    float* __restrict__ rep_m2,
-                                                    uint8_t* __restrict__ rep_flags, float* __restrict__ rep_z,
-                                                    int* __restrict__ tile_max, MaskAuto au) {
+__device__ __forceinline__ void mask_score_block(const float* __restrict__ depth, const float* __restrict__ normal,
+                                                 const CamK& k, const MaskK& mk, const HistIn& hi,
+                                                 float* __restrict__ rep_m1, float* __restrict__ rep_m2,
+                                                 uint8_t* __restrict__ rep_flags, float* __restrict__ rep_z,
+                                                 int* __restrict__ tile_max, const MaskAuto& au, int lb) {
   // (depth, nx, ny, nz) of one pixel per float4; all extents compile-time
   constexpr int AP = GR + 1, NIN = MT + 2 * AP;
   __shared__ float4 in[NIN][NIN];
@@ -80,9 +79,7 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
   __shared__ int sr[MT][MT];
   const int W = k.W, H = k.H;
   const size_t N = (size_t)W * H;
-  // blocks in XCD-contiguous order: the halo rows a block stages are mostly
-  // in the L2 of its own XCD already
-  const int BX = (W + MT - 1) / MT, lb = xcd_block(blockIdx.x, BX * ((H + MT - 1) / MT));
+  const int BX = (W + MT - 1) / MT;
   const int x0 = (lb % BX) * MT, y0 = (lb / BX) * MT;
   const int tid = threadIdx.x;
   // stage depth (clamped to zmax) and normal with clamp-to-edge
@@ -205,6 +202,44 @@ __global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ de
   }
 }
 
+// blocks in XCD-contiguous order: the halo rows a block stages are mostly
+// in the L2 of its own XCD already
+template <int GR>
+__global__ __launch_bounds__(256) void k_mask_score(const float* __restrict__ depth,
+                                                    const float* __restrict__ normal, CamK k, MaskK mk,
+                                                    HistIn hi, float* __restrict__ rep_m1,
+                                                    float* __restrict__ rep_m2,
+                                                    uint8_t* __restrict__ rep_flags, float* __restrict__ rep_z,
+                                                    int* __restrict__ tile_max, MaskAuto au) {
+  const int nb = ((k.W + MT - 1) / MT) * ((k.H + MT - 1) / MT);
+  mask_score_block<GR>(depth, normal, k, mk, hi, rep_m1, rep_m2, rep_flags, rep_z, tile_max, au,
+                       xcd_block(blockIdx.x, nb));
+}
+
+// The batched form's masks (fixed mask tiles), one launch per pass over
+// every view: view v's 16x16 score blocks start at blk[v], its tiles at
+// tile[v], its tile rows at row[v] and its blocks of HDOF_BATCH_PX_BLOCK
+// pixels at pix[v] ([n] the totals); its planes at its px_base.  No view
+// carries a history.
+struct MaskBatch {
+  int n;
+  int blk[HDOF_MAX_VIEWS + 1], tile[HDOF_MAX_VIEWS + 1], row[HDOF_MAX_VIEWS + 1], pix[HDOF_MAX_VIEWS + 1];
+};
+
+template <int GR>
+__global__ __launch_bounds__(256) void k_mask_score_batch(const float* __restrict__ depth,
+                                                          const float* __restrict__ normal,
+                                                          const BatchView* __restrict__ views, MaskK mk,
+                                                          int* __restrict__ tile_max, MaskBatch mb) {
+  const int g = xcd_block(blockIdx.x, mb.blk[mb.n]);
+  const int v = batch_view_of(mb.blk, mb.n, g);
+  const size_t pb = (size_t)views[v].px_base;
+  HistIn hi{};
+  hi.valid = 0;
+  mask_score_block<GR>(depth + pb, normal + 3 * pb, views[v].k, mk, hi, nullptr, nullptr, nullptr, nullptr,
+                       tile_max + mb.tile[v], MaskAuto{}, g - mb.blk[v]);
+}
+
 // tile 0: the frame's largest CoC radius R over the score blocks' maxima,
 // tile edge 4 (R < 16), 8 (R < 32) or 16
 __global__ __launch_bounds__(1024) void k_mask_pick(const float* __restrict__ blk_r, int nb, int* __restrict__ tsel) {
@@ -228,17 +263,12 @@ __device__ inline int mask_tile_of(int t, const int* __restrict__ tsel) { return
 // per tile row: dilated tile values, x-prefix of (value * tile width), row sum
 // (tile 0: launched for the rows of 4-pixel tiles; rows past the chosen
 // tile edge's grid exit)
-__global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_max, int W, int H,
-                                                   int t, int dil, int* __restrict__ tile_dil,
-                                                   int* __restrict__ xpref, int* __restrict__ rowsum,
-                                                   int* __restrict__ rowtot, const int* __restrict__ tsel,
-                                                   MaskAuto au) {
+__device__ __forceinline__ void mask_rows_block(const int* __restrict__ tile_max, int W, int H, int t, int dil,
+                                                int* __restrict__ tile_dil, int* __restrict__ xpref,
+                                                int* __restrict__ rowsum, int* __restrict__ rowtot, int ty) {
   __shared__ int part[4];
-  t = mask_tile_of(t, tsel);
-  if (tsel) tile_max = t == 4 ? au.tm4 : (t == 8 ? au.tm8 : au.tm16);
   const int TW = (W + t - 1) / t, TH = (H + t - 1) / t;
-  const int ty = blockIdx.x, tid = threadIdx.x;
-  if (ty >= TH) return;
+  const int tid = threadIdx.x;
   const int chunk = (TW + 255) / 256;
   const int lo = tid * chunk, hi = min(TW, lo + chunk);
   int local = 0;
@@ -279,12 +309,33 @@ __global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_
   }
 }
 
+__global__ __launch_bounds__(256) void k_mask_rows(const int* __restrict__ tile_max, int W, int H,
+                                                   int t, int dil, int* __restrict__ tile_dil,
+                                                   int* __restrict__ xpref, int* __restrict__ rowsum,
+                                                   int* __restrict__ rowtot, const int* __restrict__ tsel,
+                                                   MaskAuto au) {
+  t = mask_tile_of(t, tsel);
+  if (tsel) tile_max = t == 4 ? au.tm4 : (t == 8 ? au.tm8 : au.tm16);
+  if ((int)blockIdx.x >= (H + t - 1) / t) return;
+  mask_rows_block(tile_max, W, H, t, dil, tile_dil, xpref, rowsum, rowtot, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_mask_rows_batch(const int* __restrict__ tile_max,
+                                                         const BatchView* __restrict__ views, int t, int dil,
+                                                         int* __restrict__ tile_dil, int* __restrict__ xpref,
+                                                         int* __restrict__ rowsum, int* __restrict__ rowtot,
+                                                         MaskBatch mb) {
+  const int v = batch_view_of(mb.row, mb.n, blockIdx.x);
+  const int tb = mb.tile[v], rb = mb.row[v];
+  mask_rows_block(tile_max + tb, views[v].k.W, views[v].k.H, t, dil, tile_dil + tb, xpref + tb, rowsum + rb,
+                  rowtot + rb, blockIdx.x - rb);
+}
+
 // exclusive scan over tile rows (one block), total to the caller's buffer
-__global__ void k_mask_rowscan(const int* __restrict__ rowtot, int TH, int* __restrict__ ybase,
-                               int* __restrict__ total, int H, int t, const int* __restrict__ tsel) {
+__device__ __forceinline__ void mask_rowscan_block(const int* __restrict__ rowtot, int TH, int* __restrict__ ybase,
+                                                   int* __restrict__ total) {
   __shared__ int part[1024];
   const int tid = threadIdx.x;
-  if (tsel) TH = (H + *tsel - 1) / *tsel;
   const int chunk = (TH + 1023) / 1024;
   const int lo = tid * chunk, hi = min(TH, lo + chunk);
   int s = 0;
@@ -305,6 +356,19 @@ __global__ void k_mask_rowscan(const int* __restrict__ rowtot, int TH, int* __re
   if (tid == 1023) *total = part[1023];
 }
 
+__global__ void k_mask_rowscan(const int* __restrict__ rowtot, int TH, int* __restrict__ ybase,
+                               int* __restrict__ total, int H, int t, const int* __restrict__ tsel) {
+  if (tsel) TH = (H + *tsel - 1) / *tsel;
+  mask_rowscan_block(rowtot, TH, ybase, total);
+}
+
+// one block per view
+__global__ void k_mask_rowscan_batch(const int* __restrict__ rowtot, int* __restrict__ ybase,
+                                     int* __restrict__ totals, MaskBatch mb) {
+  const int v = blockIdx.x, rb = mb.row[v];
+  mask_rowscan_block(rowtot + rb, mb.row[v + 1] - rb, ybase + rb, totals + v);
+}
+
 __global__ void k_mask_write(int W, int H, int t, const int* __restrict__ tile_dil,
                              const int* __restrict__ xpref, const int* __restrict__ rowsum,
                              const int* __restrict__ ybase, uint8_t* __restrict__ spp,
@@ -318,6 +382,28 @@ __global__ void k_mask_write(int W, int H, int t, const int* __restrict__ tile_d
   size_t p = (size_t)y * W + x;
   spp[p] = (uint8_t)S;
   offsets[p] = ybase[ty] + (y - ty * t) * rowsum[ty] + xpref[ty * TW + tx] + (x - tx * t) * S;
+}
+
+// the batched form's counts and offsets, HDOF_BATCH_PX_BLOCK pixels per block
+__global__ __launch_bounds__(256) void k_mask_write_batch(const BatchView* __restrict__ views, int t,
+                                                          const int* __restrict__ tile_dil,
+                                                          const int* __restrict__ xpref,
+                                                          const int* __restrict__ rowsum,
+                                                          const int* __restrict__ ybase, uint8_t* __restrict__ spp,
+                                                          int* __restrict__ offsets, MaskBatch mb) {
+  const int v = batch_view_of(mb.pix, mb.n, blockIdx.x);
+  const int W = views[v].k.W, N = W * views[v].k.H;
+  const size_t pb = (size_t)views[v].px_base;
+  const int TW = (W + t - 1) / t, tb = mb.tile[v], rb = mb.row[v];
+  const int p0 = (blockIdx.x - mb.pix[v]) * HDOF_BATCH_PX_BLOCK;
+  for (int i = threadIdx.x; i < HDOF_BATCH_PX_BLOCK; i += blockDim.x) {
+    const int p = p0 + i;
+    if (p >= N) break;
+    const int x = p % W, y = p / W, tx = x / t, ty = y / t;
+    const int S = tile_dil[tb + ty * TW + tx];
+    spp[pb + p] = (uint8_t)S;
+    offsets[pb + p] = ybase[rb + ty] + (y - ty * t) * rowsum[rb + ty] + xpref[tb + ty * TW + tx] + (x - tx * t) * S;
+  }
 }
 
 // Whole frames: the same write with the tile-row scan done per block, one
@@ -432,6 +518,28 @@ hdof_status mask_reserve(hdof_ctx* ctx, int W, int H, const hdof_mask_params& mp
   return hdof_ensure(ctx->rep_flags, N);
 }
 
+// the score pass's constants; Gaussian taps exp(-i^2 / 2 sigma^2), radius
+// floor(3 sigma + 0.5), normalised
+static MaskK make_maskk(const hdof_mask_params& mp, const LensK* lens) {
+  MaskK mk;
+  const int gr = (int)floor(3.0 * mp.sigma + 0.5);
+  mk.gr = gr;  // above MAX_GR the launchers refuse the parameters
+  if (gr <= MAX_GR) {
+    double tw[2 * MAX_GR + 1], sum = 0.0;
+    for (int i = -gr; i <= gr; ++i) sum += (tw[i + gr] = exp(-(double)(i * i) / (2.0 * mp.sigma * mp.sigma)));
+    for (int i = 0; i <= 2 * gr; ++i) mk.taps[i] = (float)(tw[i] / sum);
+  }
+  mk.inv_tz = 1.0f / mp.tau_depth;
+  mk.inv_tn = 1.0f / mp.tau_normal;
+  mk.inv_tv = 1.0f / mp.tau_var;
+  mk.spp_max = mp.spp_max;
+  mk.tile = mp.tile;
+  mk.dilate = mp.dilate;
+  mk.coc_scale = lens ? lens->coc_scale : 0.0f;
+  mk.inv_s1 = lens ? lens->invS1 : 0.0f;
+  return mk;
+}
+
 hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, const CamK& k,
                         const CamK* prev, const hdof_mask_params& mp, uint8_t* spp, int32_t* offsets,
                         int32_t* total, hipStream_t st, int* queue, long cap, int* counter, const LensK* lens,
@@ -441,21 +549,8 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
   if (scaled && !lens) return hdof_set_error(HDOF_ERR_INVALID_ARG, "mask tile 0 (scaled by the CoC) needs the lens");
   const int t = scaled ? 4 : mp.tile;  // the grid the launches are sized for
   const int TH = cdiv(H, t);
-  MaskK mk;
-  // Gaussian taps exp(-i^2 / 2 sigma^2), radius floor(3 sigma + 0.5), normalised
-  int gr = (int)floor(3.0 * mp.sigma + 0.5);
-  double tw[2 * MAX_GR + 1], sum = 0.0;
-  for (int i = -gr; i <= gr; ++i) sum += (tw[i + gr] = exp(-(double)(i * i) / (2.0 * mp.sigma * mp.sigma)));
-  for (int i = 0; i <= 2 * gr; ++i) mk.taps[i] = (float)(tw[i] / sum);
-  mk.gr = gr;
-  mk.inv_tz = 1.0f / mp.tau_depth;
-  mk.inv_tn = 1.0f / mp.tau_normal;
-  mk.inv_tv = 1.0f / mp.tau_var;
-  mk.spp_max = mp.spp_max;
-  mk.tile = mp.tile;
-  mk.dilate = mp.dilate;
-  mk.coc_scale = lens ? lens->coc_scale : 0.0f;
-  mk.inv_s1 = lens ? lens->invS1 : 0.0f;
+  const MaskK mk = make_maskk(mp, lens);
+  const int gr = mk.gr;
   hdof_status s;
   if ((s = mask_reserve(ctx, W, H, mp)) != HDOF_OK) return s;
   HistIn hi{};
@@ -514,6 +609,64 @@ hdof_status launch_mask(hdof_ctx* ctx, const float* depth, const float* normal, 
                        (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p,
                        (const int*)rowsum, (const int*)ctx->mask_ybase.p, spp, offsets, tsel);
   }
+  HDOF_HIP(hipGetLastError());
+  return HDOF_OK;
+}
+
+static MaskBatch mask_batch_of(int n_views, const BatchView* hv, int t) {
+  MaskBatch mb{};
+  mb.n = n_views;
+  for (int v = 0; v < n_views; ++v) {
+    const int W = hv[v].k.W, H = hv[v].k.H;
+    mb.blk[v + 1] = mb.blk[v] + cdiv(W, MT) * cdiv(H, MT);
+    mb.tile[v + 1] = mb.tile[v] + cdiv(W, t) * cdiv(H, t);
+    mb.row[v + 1] = mb.row[v] + cdiv(H, t);
+    mb.pix[v + 1] = mb.pix[v] + cdiv((long)W * H, HDOF_BATCH_PX_BLOCK);
+  }
+  return mb;
+}
+
+hdof_status mask_reserve_batched(hdof_ctx* ctx, int n_views, const BatchView* hviews, const hdof_mask_params& mp) {
+  if (mp.tile <= 0) return HDOF_OK;
+  const MaskBatch mb = mask_batch_of(n_views, hviews, mp.tile);
+  const size_t tiles = (size_t)mb.tile[n_views], rows = (size_t)mb.row[n_views];
+  hdof_status s;
+  if ((s = hdof_ensure(ctx->mask_tile, sizeof(int) * tiles)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_tile_dil, sizeof(int) * tiles)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_xpref, sizeof(int) * tiles)) != HDOF_OK) return s;
+  if ((s = hdof_ensure(ctx->mask_rowsum, sizeof(int) * 2 * rows)) != HDOF_OK) return s;
+  return hdof_ensure(ctx->mask_ybase, sizeof(int) * rows);
+}
+
+hdof_status launch_mask_batched(hdof_ctx* ctx, const float* depth, const float* normal, int n_views,
+                                const BatchView* hviews, const void* views_dev, const hdof_mask_params& mp,
+                                uint8_t* spp, int32_t* offsets, int32_t* totals, hipStream_t st) {
+  if (mp.tile <= 0) return hdof_set_error(HDOF_ERR_INVALID_ARG, "batched masks: fixed mask tiles only");
+  const int t = mp.tile;
+  const MaskK mk = make_maskk(mp, nullptr);
+  const MaskBatch mb = mask_batch_of(n_views, hviews, t);
+  hdof_status s;
+  if ((s = mask_reserve_batched(ctx, n_views, hviews, mp)) != HDOF_OK) return s;
+  const BatchView* vd = (const BatchView*)views_dev;
+  int* rowsum = (int*)ctx->mask_rowsum.p;
+  int* rowtot = rowsum + mb.row[n_views];
+  switch (mk.gr) {
+#define CASE(R)                                                                                                  \
+  case R:                                                                                                        \
+    hipLaunchKernelGGL(k_mask_score_batch<R>, dim3(mb.blk[n_views]), dim3(256), 0, st, depth, normal, vd, mk,   \
+                       (int*)ctx->mask_tile.p, mb);                                                             \
+    break;
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+    default: return hdof_set_error(HDOF_ERR_INVALID_ARG, "Gaussian radius %d above %d", mk.gr, MAX_GR);
+  }
+  hipLaunchKernelGGL(k_mask_rows_batch, dim3(mb.row[n_views]), dim3(256), 0, st, (const int*)ctx->mask_tile.p, vd,
+                     t, mp.dilate, (int*)ctx->mask_tile_dil.p, (int*)ctx->mask_xpref.p, rowsum, rowtot, mb);
+  hipLaunchKernelGGL(k_mask_rowscan_batch, dim3(n_views), dim3(1024), 0, st, (const int*)rowtot,
+                     (int*)ctx->mask_ybase.p, totals, mb);
+  hipLaunchKernelGGL(k_mask_write_batch, dim3(mb.pix[n_views]), dim3(256), 0, st, vd, t,
+                     (const int*)ctx->mask_tile_dil.p, (const int*)ctx->mask_xpref.p, (const int*)rowsum,
+                     (const int*)ctx->mask_ybase.p, spp, offsets, mb);
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
