@@ -194,9 +194,11 @@ extern "C" hdof_status hdof_create(int device, hdof_ctx** out) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork2, hipEventDisableTiming);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     if (c->ev_join) hipEventDestroy(c->ev_join);
+    if (c->ev_fork2) hipEventDestroy(c->ev_fork2);
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->side) hipStreamDestroy(c->side);
     hipFree(c->d_counters);
@@ -237,6 +239,7 @@ extern "C" void hdof_destroy(hdof_ctx* ctx) {
   if (ctx->b_views_host) hipHostFree(ctx->b_views_host);
   if (ctx->b_views_done) hipEventDestroy(ctx->b_views_done);
   if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_fork2) hipEventDestroy(ctx->ev_fork2);
   if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
   if (ctx->side) hipStreamDestroy(ctx->side);
   if (ctx->d_flags) hipFree(ctx->d_flags);
@@ -934,6 +937,10 @@ extern "C" hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* t) {
 // batched form
 // ---------------------------------------------------------------------------
 
+#ifndef HDOF_BATCH_SPLIT
+#define HDOF_BATCH_SPLIT 2  // G-buffer chunks of the overlapped batch (1 or 2)
+#endif
+
 struct BatchLayout {
   int n;
   long npx, max_px;
@@ -1082,15 +1089,28 @@ static hdof_status batch_enqueue(hdof_ctx* ctx, const hdof_scene* scene, const h
   for (int v = 0; v < L.n; ++v) outs[v] = views[v].d_out;
   if (ovl) {
     TRY(postfilter_reserve(ctx, L.hv[0].k, L.hv[0].l, params->pp, st));  // tap table, before the fork
-    // one fork after the G-buffer: a replayed graph pays tens of
-    // microseconds per cross-stream dependency (forking per view, or per
-    // chunk of views after its G-buffers, was slower replayed: 32 views,
-    // 4 chunks 12.4 ms against 11.2)
-    TRY(launch_gbuffer_batched(ctx, scene, li, L.n, L.hv, ctx->b_views.p, gball, packs, ptiles, st));
-    HDOF_HIP(hipEventRecord(ctx->ev_fork, st));
-    HDOF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-    TRY(launch_postfilter_batched(ctx, packs, ptiles, L.n, L.hv, ctx->b_views.p, outs, params->pp,
-                                  (float*)(a + L.o_pp), ctx->side));
+    // the views in HDOF_BATCH_SPLIT chunks of about equal pixels, each a
+    // G-buffer launch and a fork of its gather, so the next chunk's G-buffer
+    // runs beside the gather (a replayed graph pays tens of microseconds per
+    // cross-stream dependency: forking per view was slower replayed)
+    int cut[3] = {0, L.n, L.n};
+    int nch = 1;
+    if (HDOF_BATCH_SPLIT > 1 && L.n > 1) {
+      int vs = 1;
+      while (vs < L.n - 1 && 2 * (long)L.hv[vs].px_base < L.npx) ++vs;
+      cut[1] = vs;
+      nch = 2;
+    }
+    const hipEvent_t evs[2] = {ctx->ev_fork, ctx->ev_fork2};
+    for (int c = 0; c < nch; ++c) {
+      const int v0 = cut[c], n = cut[c + 1] - cut[c];
+      const void* vt = (const char*)ctx->b_views.p + batch_view_bytes() * v0;
+      TRY(launch_gbuffer_batched(ctx, scene, li, n, L.hv + v0, vt, gball, packs, ptiles + L.tile_base[v0], st));
+      HDOF_HIP(hipEventRecord(evs[c], st));
+      HDOF_HIP(hipStreamWaitEvent(ctx->side, evs[c], 0));
+      TRY(launch_postfilter_batched(ctx, packs, ptiles + L.tile_base[v0], n, L.hv + v0, vt, outs + v0, params->pp,
+                                    (float*)(a + L.o_pp), ctx->side));
+    }
     HDOF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
   }
   // the masks: one launch per pass over every view with fixed mask tiles,

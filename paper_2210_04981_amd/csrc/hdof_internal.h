@@ -116,6 +116,7 @@ struct hdof_ctx {
   // frame's stream after the G-buffer and joined before the composite
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork2 = nullptr;  // the overlapped batch's second chunk
   // stage profiling: HDOF_PROF_SLOTS events per profiled frame (the stage
   // marks, then the end of an overlapped gather)
   bool prof_on = false, prof_in_frame = false;
