@@ -465,15 +465,20 @@ typedef struct {
 /* The batched form rejects params->recon.enable = 1 and
  * params->spatial.enable = 1 (HDOF_ERR_UNSUPPORTED): a reconstruction
  * history belongs to one view's camera path, and the spatial stage is not
- * batched.
- * Every view's G-buffer, mask, post-filter and composite (one launch each),
- * one device-side scan of the per-view ray totals, ONE queue over all views
- * and ONE persistent thin-lens trace launch for the whole batch.  With
- * 16-pixel post-filter tiles and the tuning's overlap on, every view's
- * gather runs on the context's second stream beside the masks and the
- * trace (as in hdof_frame), the composite after both.  No variance history
- * (each view is a first frame).  1 <= n_views <=
- * HDOF_MAX_VIEWS; all views share the scene, light and parameters. */
+ * batched; it takes the disk aperture only (blades = 0, sa = 0) and no
+ * specular rule.
+ * With 16-pixel post-filter tiles and the tuning's overlap on (the
+ * defaults): the views' G-buffers in two launches (two chunks of about
+ * equal pixels), each followed by ONE gather launch over its views' tiles
+ * on the context's second stream (with the untraced pixels' composite);
+ * meanwhile ONE launch per mask pass over every view (fixed mask tiles; the
+ * CoC-scaled tile runs per view), one device-side scan of the per-view ray
+ * totals, ONE queue fill, ONE persistent thin-lens trace launch and ONE
+ * reduction for the whole batch; after both, ONE composite launch over
+ * every view's traced pixels.  Otherwise a G-buffer, mask and post-filter
+ * with composite per view around the same single trace.  No variance
+ * history (each view is a first frame).  1 <= n_views <= HDOF_MAX_VIEWS;
+ * all views share the scene, light and parameters. */
 hdof_status hdof_frame_batched(hdof_ctx* ctx, const hdof_scene* scene, const hdof_light* light,
                                const hdof_frame_params* params, int32_t n_views,
                                const hdof_view* views, hdof_stream stream);
