@@ -476,6 +476,29 @@ __device__ __forceinline__ void gather16_tile(float4 (*stg)[PPG_G * PPG_TAPSZ], 
   }
 }
 
+// The tile at position L of an order that walks the tile grid in eight
+// rectangles (4 across, 2 down), each row by row.  An XCD's contiguous
+// share of positions (xcd_block) then covers about one rectangle, whose
+// footprints (up to R_cap + 1 pixels around it) stay in that XCD's L2,
+// instead of a full-width band of tile rows whose footprint rows exceed it
+// (the quad form: 77.3 -> 49.2 MB fetched per 1080p launch, 151 -> 147 us).
+__device__ __forceinline__ int rect_tile(int L, int TW, int TH) {
+  int base = 0;
+  for (int ry = 0; ry < 2; ++ry) {
+    const int y0 = TH * ry / 2, y1 = TH * (ry + 1) / 2;
+    for (int rx = 0; rx < 4; ++rx) {
+      const int x0 = TW * rx / 4, x1 = TW * (rx + 1) / 4;
+      const int n = (x1 - x0) * (y1 - y0);
+      if (L < base + n) {
+        const int o = L - base, w = x1 - x0;
+        return (y0 + o / w) * TW + x0 + o % w;
+      }
+      base += n;
+    }
+  }
+  return L;  // not reached for L < TW * TH
+}
+
 template <int FUSE, bool SA>
 __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ pack, const float* __restrict__ tile_r,
                                                      int K, float r_cap, const float4* __restrict__ taps, int n_taps,
@@ -483,6 +506,9 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   __shared__ float4 stg[PPG_BUFS][PPG_G * PPG_TAPSZ];
   __shared__ TapRec rec[PPG_BUFS][PPG_G];
   __shared__ float wred[4];
+  // band order (an XCD's share is a band of tile rows): the rectangle
+  // order cut this form's fetches from 57.9 to 41.4 MB but made the
+  // overlapped frame slower (0.3923 against 0.3896 ms)
   const int tile = xcd_block(blockIdx.x, ((W + 15) >> 4) * ((H + 15) >> 4));
   gather16_tile<FUSE, SA>(stg, rec, wred, pack, tile_r, K, r_cap, taps, n_taps, W, H, inv_ramp, out, fz, tile);
 }
@@ -666,8 +692,9 @@ __global__ __launch_bounds__(256) void k_pp_gather16q(const float4* __restrict__
   __shared__ float4 stg[4][2][PPG_TAPSZ];
   const int TW = (W + 15) >> 4, TH = (H + 15) >> 4;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int tile = xcd_block(blockIdx.x, (TW * TH + 3) >> 2) * 4 + wave;
-  if (tile >= TW * TH) return;
+  const int pos = xcd_block(blockIdx.x, (TW * TH + 3) >> 2) * 4 + wave;
+  if (pos >= TW * TH) return;
+  const int tile = rect_tile(pos, TW, TH);
   gather16q_tile<FUSE, SA>(stg[wave], pack, tile_r, K, r_cap, taps, n_taps, W, H, inv_ramp, out, fz, tile);
 }
 
