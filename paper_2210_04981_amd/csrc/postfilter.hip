@@ -513,37 +513,19 @@ __global__ __launch_bounds__(256) void k_pp_gather16(const float4* __restrict__ 
   gather16_tile<FUSE, SA>(stg, rec, wred, pack, tile_r, K, r_cap, taps, n_taps, W, H, inv_ramp, out, fz, tile);
 }
 
-// The batched form's gathers and traced pixels' composites, one launch
-// each over every view: a block finds its view by a binary search over the
-// views' first tiles (first pixel blocks for the composite); a view's
-// planes start at its px_base and its tile radii at its first tile.
+// The batched form's gathers (the quad form) and traced pixels'
+// composites, one launch each over every view: a wave (gather) or block
+// (composite) finds its view by a binary search over the views' first
+// tiles or first pixel blocks; a view's planes start at its px_base and its
+// tile radii at its first tile.  The quad form is the batch's: there the
+// gather sets the pace (32 views replayed 10.05 ms against 10.68 with the
+// four-wave form).
 struct PPBatch {
   int n;
   int tile_base[HDOF_MAX_VIEWS + 1];  // [n]: all tiles
   int blk_base[HDOF_MAX_VIEWS + 1];   // [n]: all blocks of HDOF_BATCH_PX_BLOCK pixels
   float* out[HDOF_MAX_VIEWS];
 };
-
-// FUSE 2 only (the overlapped form: every pixel by the untraced pixels'
-// rule; `pp_out` receives the filtered colour)
-template <bool SA>
-__global__ __launch_bounds__(256) void k_pp_gather16_batch(const float4* __restrict__ pack,
-                                                           const float* __restrict__ tile_r, int K, float r_cap,
-                                                           const float4* __restrict__ taps, int n_taps,
-                                                           float inv_ramp, float* __restrict__ pp_out,
-                                                           const BatchView* __restrict__ views, PPBatch b) {
-  __shared__ float4 stg[PPG_BUFS][PPG_G * PPG_TAPSZ];
-  __shared__ TapRec rec[PPG_BUFS][PPG_G];
-  __shared__ float wred[4];
-  const int g = xcd_block(blockIdx.x, b.tile_base[b.n]);
-  const int v = batch_view_of(b.tile_base, b.n, g);
-  const int W = views[v].k.W, H = views[v].k.H;
-  const size_t pb = (size_t)views[v].px_base;
-  FuseK fz{};
-  fz.out = b.out[v];
-  gather16_tile<2, SA>(stg, rec, wred, pack + pb, tile_r + b.tile_base[v], K, r_cap, taps, n_taps, W, H, inv_ramp,
-                       pp_out + 3 * pb, fz, g - b.tile_base[v]);
-}
 
 // The gather radius of tile (tx, ty) reduced by one wave (uniform result).
 __device__ __forceinline__ float wave_dilated_radius(const float* __restrict__ tile_r, int TW, int TH, int tx,
@@ -1476,12 +1458,6 @@ hdof_status launch_postfilter(hdof_ctx* ctx, const float* color, const float* de
   return postfilter_run(ctx, S, color, depth, k, l, pp, out, st, packed, fuse);
 }
 
-// the batched gather in the quad form (it is the batch's critical path:
-// 32 views, replayed 10.05 ms against 10.68 with the four-wave form); 0:
-// the four-wave form
-#ifndef HDOF_BATCH_QUAD
-#define HDOF_BATCH_QUAD 1
-#endif
 hdof_status launch_postfilter_batched(hdof_ctx* ctx, const float4* pack, const float* tile_r, int n_views,
                                       const BatchView* hviews, const void* views_dev, float* const* outs,
                                       const hdof_pp_params& pp, float* pp_out, hipStream_t st) {
@@ -1496,17 +1472,10 @@ hdof_status launch_postfilter_batched(hdof_ctx* ctx, const float4* pack, const f
     b.out[v] = outs[v];
   }
   const int K = (int)ceil((double)pp.r_cap / 16);
-#if HDOF_BATCH_QUAD
   auto kern = sa ? k_pp_gather16q_batch<true> : k_pp_gather16q_batch<false>;
   hipLaunchKernelGGL(kern, dim3((b.tile_base[n_views] + 3) / 4), dim3(256), 0, st, pack, tile_r, K, pp.r_cap,
                      (const float4*)ctx->pp_taps.p, pp.n_taps, 1.0f / pp.bg_ramp_px, pp_out,
                      (const BatchView*)views_dev, b);
-#else
-  auto kern = sa ? k_pp_gather16_batch<true> : k_pp_gather16_batch<false>;
-  hipLaunchKernelGGL(kern, dim3(b.tile_base[n_views]), dim3(256), 0, st, pack, tile_r, K, pp.r_cap,
-                     (const float4*)ctx->pp_taps.p, pp.n_taps, 1.0f / pp.bg_ramp_px, pp_out,
-                     (const BatchView*)views_dev, b);
-#endif
   HDOF_HIP(hipGetLastError());
   return HDOF_OK;
 }
