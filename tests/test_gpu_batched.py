@@ -174,3 +174,22 @@ def test_batched_ragged_views_equal_plain_frames(hd, ctx, room, n):
         ref = _plain(hd, ctx, room, cfg, v)
         torch.cuda.synchronize()
         assert torch.equal(outs[i], ref), f"view {i} ({v[0].width}x{v[0].height}) differs from the plain frame"
+
+
+@pytest.mark.parametrize("tile", [0, 4])
+def test_batched_mask_tiles_equal_plain_frames(hd, ctx, room, tile):
+    """The batch with another mask tile: 4-pixel tiles (the single-launch
+    masks) and the CoC-scaled tile (per-view masks); each view equals its
+    plain frame bit for bit."""
+    from dataclasses import replace
+    print_case(f"batched views, mask tile {tile}")
+    cfg = sg.config_1080p()
+    cfg = replace(cfg, mask=replace(cfg.mask, tile=tile))
+    views = _odd_views(hd, [(97, 61), (160, 90), (33, 17)], 5, seed=40 + tile)
+    outs = hd.hdof_frame_batched(ctx, room, hd.light_of(cfg.light), hd.frame_params_of(cfg), views)
+    torch.cuda.synchronize()
+    ctx.sync()
+    for i, v in enumerate(views):
+        ref = _plain(hd, ctx, room, cfg, v)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), f"view {i} differs from the plain frame (mask tile {tile})"
