@@ -424,12 +424,6 @@ hdof_status postfilter_reserve(hdof_ctx* ctx, const CamK& k, const LensK& l, con
 hdof_status postfilter_noalloc_init(int device, void** out);
 hdof_status launch_postfilter_noalloc(hdof_ctx* ctx, const float* color, const float* depth, const CamK& k,
                                       const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st);
-// the 16-pixel-tile gather over texels a G-buffer packed into `pack` with
-// its tile radii in `tile_r` (the batched form: one pack per view); the
-// context's tap table must already hold this tap count and aperture
-hdof_status launch_postfilter_packed(hdof_ctx* ctx, const float4* pack, const float* tile_r, const CamK& k,
-                                     const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
-                                     const PostFuse* fuse);
 // the batched form's gathers over every view in one launch (16-pixel
 // tiles; each view's pixels by the composite's untraced rule into outs[v],
 // its filtered colour into pp_out from its px_base), and its traced pixels'

@@ -1499,14 +1499,6 @@ hdof_status launch_composite_traced_batched(hdof_ctx* ctx, const float* color, c
   return HDOF_OK;
 }
 
-hdof_status launch_postfilter_packed(hdof_ctx* ctx, const float4* pack, const float* tile_r, const CamK& k,
-                                     const LensK& l, const hdof_pp_params& pp, float* out, hipStream_t st,
-                                     const PostFuse* fuse) {
-  if (pp.tile != 16) return hdof_set_error(HDOF_ERR_INVALID_ARG, "packed gather: 16-pixel tiles only");
-  const PPScratch S{(float4*)pack, (float*)tile_r, nullptr, (float4*)ctx->pp_taps.p};
-  return postfilter_run(ctx, S, nullptr, nullptr, k, l, pp, out, st, true, fuse);
-}
-
 // ---------------------------------------------------------------------------
 // The post-filter without allocation: its intermediates live in `scratch`,
 // one file-scope device array per device (tap table, tile radii, dilated
