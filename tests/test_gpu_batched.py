@@ -152,13 +152,14 @@ def _odd_views(hd, sizes, n, seed):
     return out
 
 
-@pytest.mark.parametrize("n", [11, 64])
+@pytest.mark.parametrize("n", [1, 2, 11, 64])
 def test_batched_ragged_views_equal_plain_frames(hd, ctx, room, n):
     """Views whose 16-pixel tile counts are not multiples of four (so a
     quad-gather block's tiles straddle two views), a 1x1 view, views far
-    below one 4096-pixel block of the per-pixel passes, and the largest
-    batch (64 views: every step of the block-to-view search): each view
-    equals its plain frame bit for bit."""
+    below one 4096-pixel block of the per-pixel passes, the largest batch
+    (64 views: every step of the block-to-view search), and batches of one
+    and two views (no split of the G-buffer launches, one view per chunk):
+    each view equals its plain frame bit for bit."""
     sizes = [(33, 17), (1, 1), (17, 33), (50, 3), (129, 65), (7, 300), (65, 65), (31, 47)]
     if n == 64:
         sizes = [(24, 16), (33, 17), (16, 16), (17, 9), (9, 9)]
