@@ -22,19 +22,29 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hdof_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# HDOF_ORACLE_SANITIZED=1: the AddressSanitizer + UndefinedBehaviorSanitizer
+# build (its runtime must be preloaded; see tests/test_oracle_sanitized.py)
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+_SANITIZED = os.environ.get("HDOF_ORACLE_SANITIZED") == "1"
 
 ZMAX = 1.0e4
 VALID, NEW = 1, 2
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle shared library with gcc (-O2, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle shared library with gcc (-O2, OpenMP); sanitize:
+    the checking build (-O1, AddressSanitizer and UndefinedBehaviorSanitizer,
+    any report fatal)."""
+    out = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        checks = ",".join(("address", "undefined"))  # host code (gcc), the oracle only
+        opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=" + checks,
+               "-fno-sanitize-recover=all"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -43,9 +53,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        path = _LIB_SAN if _SANITIZED else _LIB
+        if not os.path.exists(path):
+            build(force=True, sanitize=_SANITIZED)
+        L = C.CDLL(path)
         P = C.c_void_p
         i32, i64, u64, f64 = C.c_int, C.c_int64, C.c_uint64, C.c_double
         L.or_scene_create.restype = P
