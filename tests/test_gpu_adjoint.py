@@ -67,16 +67,22 @@ def _gpu_backward(hd, ctx, cam, lens, col, z, spp, cn, cf, hit, pp, cp, g):
     return gc.cpu().numpy().astype(np.float64), gl.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("case", ["small0", "small1", "room", "room640"])
+@pytest.mark.parametrize("case", ["small0", "small1", "room", "room640", "room_t45", "room_t2"])
 def test_backward_matches_oracle_adjoint(hd, ctx, case):
-    """16-pixel tiles scatter through an LDS window (ceil R <= 23), per-tap
-    LDS footprints (larger R) or global atomics (border tiles); room640 has
-    all three, room the first and last, the small cases use 8-pixel tiles."""
+    """16-pixel tiles scatter through an LDS window (ceil R <= 21) or per-tap
+    footprints added to global memory (larger R); room640 has both, room
+    mostly the second; room_t45 and room_t2 take other tap counts (each
+    block starts its transpose at tap (17 block) mod n_taps, and the texels
+    are requested one tap ahead); the small cases use 8-pixel tiles (global
+    atomics per pixel and tap)."""
     print_case(f"adjoint {case}")
     if case == "room":
         args = _room()
     elif case == "room640":
         args = _room(3, 640, 360)
+    elif case.startswith("room_t"):
+        args = list(_room(5, 320, 176))
+        args[8] = sg.PPParams(n_taps=int(case[6:]), tile=16, r_cap=args[8].r_cap, bg_ramp_px=args[8].bg_ramp_px)
     else:
         args = _small(int(case[-1]))
     gc, gl = _gpu_backward(hd, ctx, *args)
