@@ -543,7 +543,9 @@ hdof_status hdof_get_tuning(hdof_ctx* ctx, hdof_tuning* tuning);
  * count and the class (image sizes, spp_max, tiles, the scene's triangle
  * count as a power of two, view count, optional stages, history); an entry
  * for the class is applied without timing unless force != 0, and a search
- * writes (or replaces) its entry.  Not under stream capture
+ * writes (or replaces) its entry.  A search that fails (a candidate's
+ * frame returns an error) leaves the context's tuning as it was on entry
+ * and writes no cache entry.  Not under stream capture
  * (HDOF_ERR_UNSUPPORTED); not thread-safe per context or per cache file. */
 typedef struct {
   char key[256];        /* the workload class */

@@ -205,6 +205,7 @@ extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, con
     }
   }
   const Workload w{ctx, scene, light, params, n_views, views, prev, st};
+  const hdof_tuning entry = ctx->tune;  // restored when the search fails
   const bool frame = n_views == 1;
   // a batch is ~30x a frame: fewer repetitions of each candidate
   const int warm = frame ? 3 : 1, reps = frame ? 15 : 5;
@@ -271,7 +272,7 @@ extern "C" hdof_status hdof_autotune(hdof_ctx* ctx, const hdof_scene* scene, con
   }
   for (auto& e : ev) hipEventDestroy(e);
   if (s != HDOF_OK) {
-    hdof_set_tuning(ctx, &defaults);
+    ctx->tune = entry;
     return s;
   }
   s = hdof_set_tuning(ctx, &best);

@@ -125,3 +125,24 @@ def test_autotune_with_history(hd, ctx, room, tmp_path):
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     hd.hdof_set_tuning(ctx)
+
+
+def test_failed_search_keeps_callers_tuning(hd, ctx, room, tmp_path):
+    """A workload whose frame is rejected (focus distance below the focal
+    length) fails the search before any candidate; the tuning the caller
+    had set stays on the context and no cache entry is written."""
+    print_case("autotune of a rejected workload")
+    cfg = sg.config_1080p(320, 180)
+    params = hd.frame_params_of(cfg)
+    light = hd.light_of(cfg.light)
+    lens = hd.lens_of(cfg.lens)
+    lens.focus_distance = 0.5 * lens.focal_length
+    custom = dict(blocks_per_cu=6, refill=32, segments=2, wave=0, overlap=0, overlap_ray_quantum=100000)
+    hd.hdof_set_tuning(ctx, **custom)
+    cache = tmp_path / "autotune.jsonl"
+    with pytest.raises(hd.HdofError) as ei:
+        hd.hdof_autotune(ctx, room, light, params, [(hd.camera_of(cfg.camera), lens, 0, 0, 0)], cache_path=cache)
+    assert ei.value.status == 1  # HDOF_ERR_INVALID_ARG
+    assert hd.hdof_get_tuning(ctx) == custom
+    assert not cache.exists()
+    hd.hdof_set_tuning(ctx)
