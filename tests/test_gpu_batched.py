@@ -194,3 +194,22 @@ def test_batched_mask_tiles_equal_plain_frames(hd, ctx, room, tile):
         ref = _plain(hd, ctx, room, cfg, v)
         torch.cuda.synchronize()
         assert torch.equal(outs[i], ref), f"view {i} differs from the plain frame (mask tile {tile})"
+
+
+def test_batched_views_with_nothing_traced(hd, ctx, room):
+    """Mask thresholds no edge reaches and no history: no view traces a
+    pixel, so the batch's one persistent trace runs on an empty queue; each
+    view equals its plain frame bit for bit, and that frame is the
+    post-filtered image composited without traced pixels."""
+    from dataclasses import replace
+    print_case("batched views, nothing traced")
+    cfg = sg.config_1080p()
+    cfg = replace(cfg, mask=replace(cfg.mask, tau_depth=1e30, tau_normal=1e30))
+    views = _odd_views(hd, [(97, 61), (160, 90), (33, 17)], 4, seed=77)
+    outs = hd.hdof_frame_batched(ctx, room, hd.light_of(cfg.light), hd.frame_params_of(cfg), views)
+    torch.cuda.synchronize()
+    ctx.sync()
+    for i, v in enumerate(views):
+        ref = _plain(hd, ctx, room, cfg, v)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), f"view {i} differs from the plain frame (nothing traced)"

@@ -62,6 +62,34 @@ def test_frame_matches_oracle(hd, ctx, which):
     sc.close()
 
 
+@pytest.mark.parametrize("overlap", [1, 0])
+def test_frame_with_nothing_traced(hd, ctx, overlap):
+    """Mask thresholds no edge reaches and no history: the mask traces no
+    pixel (every count 0, total 0), the persistent trace runs on an empty
+    queue, the kept trace planes stay zero, and the frame equals the
+    oracle's, whose composite then takes only post-filtered pixels; in the
+    overlapped and the single-stream frame."""
+    from dataclasses import replace
+    print_case(f"frame with nothing traced, overlap {overlap}")
+    scene = sg.living_room_scene(0)
+    cfg = sg.config_1080p(320, 180)
+    cfg = replace(cfg, mask=replace(cfg.mask, tau_depth=1e30, tau_normal=1e30))
+    sc = upload_scene(hd, ctx, scene)
+    hd.hdof_set_tuning(ctx, overlap=overlap)
+    hd.hdof_history_reset(ctx)
+    g = run_frame(hd, ctx, sc, cfg)
+    hd.hdof_set_tuning(ctx)
+    assert g["total"] == 0 and not g["spp"].any() and not g["offsets"].any()
+    for k in ("c_near", "c_far", "hit_ratio", "lum_m1", "lum_m2"):
+        assert not g[k].any(), k
+    ref = oracle.frame(oracle.Scene(scene.verts, scene.albedo), cfg)
+    assert ref["mask"]["total"] == 0 and not ref["spp"].any()
+    info = compare_frame(g, ref, cfg)
+    print(info)
+    assert info["compared"] >= MIN_COMPARED["room_320x180"], info
+    sc.close()
+
+
 def test_zero_aperture_frame_is_gbuffer_bitwise(hd, ctx):
     print_case("invariant A=0")
     scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.0)
