@@ -125,6 +125,32 @@ def test_full_mask_override_is_full_rt(hd, ctx):
     sc.close()
 
 
+@pytest.mark.parametrize("spp_max", [1, 255])
+def test_frame_at_ray_count_limits(hd, ctx, spp_max):
+    """Every pixel traced at the smallest and the largest ray count a pixel
+    can hold (one byte: 255, a queue of 1.04M entries at 64x64), against
+    the oracle's frame.  A pixel with a ray the oracle flags (a hit within
+    its band of an edge or a tie) is left out of the end-to-end comparison;
+    at 255 rays per pixel that is 15 % of the pixels (0.4 % at 8), so the
+    bar is the unflagged share, and the stage-isolated post-filter and
+    composite still cover every pixel."""
+    print_case(f"frame with every pixel at spp_max {spp_max}")
+    scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.2)
+    cfg.mask.tau_depth = cfg.mask.tau_normal = 1e-12
+    cfg.mask.tile, cfg.mask.dilate = 16, 8   # one tile with any edge covers the image
+    cfg.mask.spp_max = spp_max
+    sc = upload_scene(hd, ctx, scene)
+    hd.hdof_history_reset(ctx)
+    g = run_frame(hd, ctx, sc, cfg)
+    assert np.all(g["spp"] == spp_max) and g["total"] == spp_max * g["spp"].size
+    ref = oracle.frame(oracle.Scene(scene.verts, scene.albedo), cfg)
+    info = compare_frame(g, ref, cfg)
+    amb = float((ref["rt"]["px_amb"] != 0).mean())
+    print(info, "flagged-ray pixels", amb)
+    assert info["compared"] >= min(MIN_COMPARED["tiny"], 1.0 - amb - 0.01), info
+    sc.close()
+
+
 def test_trace_independent_of_other_pixels(hd, ctx):
     """A pixel's traced result depends only on its own count: halving every
     other pixel's count leaves it bitwise unchanged."""
