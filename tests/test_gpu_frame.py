@@ -90,6 +90,27 @@ def test_frame_with_nothing_traced(hd, ctx, overlap):
     sc.close()
 
 
+@pytest.mark.parametrize("wh", [(1, 1), (1, 37), (53, 1), (17, 9), (15, 16)])
+def test_frame_at_degenerate_sizes(hd, ctx, wh):
+    """Images of one pixel, one column, one row, and below one 16-pixel
+    tile, in the benchmark's frame form, against the oracle's frame: the
+    end-to-end comparison where no flagged G-buffer hit or ray reaches, and
+    the stage-isolated post-filter and composite at every pixel."""
+    W, H = wh
+    print_case(f"frame at {W}x{H}")
+    hd.hdof_set_tuning(ctx)
+    scene, cfg = sg.living_room_scene(0), sg.config_1080p(W, H)
+    sc = upload_scene(hd, ctx, scene)
+    hd.hdof_history_reset(ctx)
+    g = run_frame(hd, ctx, sc, cfg)
+    ref = oracle.frame(oracle.Scene(scene.verts, scene.albedo), cfg)
+    info = compare_frame(g, ref, cfg)
+    print(info)
+    assert g["out"].shape == (3, H, W) and np.isfinite(g["out"]).all()
+    assert "out_iso_err" in info
+    sc.close()
+
+
 def test_zero_aperture_frame_is_gbuffer_bitwise(hd, ctx):
     print_case("invariant A=0")
     scene, cfg = sg.tiny_scene(0), sg.config_tiny(aperture_override=0.0)
