@@ -320,7 +320,7 @@ hdof_status launch_bvh_build(hdof_ctx* ctx, const float* verts, const float* alb
                              hdof_scene* sc, hipStream_t st);
 hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
                            const LightK& li, hdof_gbuffer_bufs out, hipStream_t st, float4* pack = nullptr,
-                           float* tile_r = nullptr);
+                           float* tile_r = nullptr, hipEvent_t done = nullptr);
 struct BatchView {
   CamK k;
   LensK l;
@@ -414,6 +414,9 @@ struct PostFuse {
   // pixel and reads none of spp, rt, pps (the trace may still be writing
   // them); a sparse composite then rewrites the traced pixels
   bool untraced_only;
+  // nullable (untraced_only): an event the gather's own dispatch completes,
+  // so no separate marker follows it on its stream
+  hipEvent_t done;
 };
 // the post-filter's scratch and tap table for this image and lens, on st
 // (a frame that runs the gather on another stream calls it before forking)

@@ -13,6 +13,8 @@
 // k_composite: focus zone / near / far rules, one pass over the pixels.
 #include "hdof_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <mutex>
 
 namespace {
@@ -1416,9 +1418,14 @@ hdof_status postfilter_run(hdof_ctx* ctx, const PPScratch& S, const float* color
       // beside the trace (the overlapped frame) the four-wave form: the quad
       // form finishes sooner but takes the trace's issue slots on the way
       auto kern = sa ? k_pp_gather16<2, true> : k_pp_gather16<2, false>;
-      hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)S.pack,
-                         (const float*)S.tile, K, pp.r_cap, (const float4*)S.taps, pp.n_taps, W, H,
-                         1.0f / pp.bg_ramp_px, out, fz);
+      if (fuse->done)
+        hipExtLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, nullptr, fuse->done, 0,
+                              (const float4*)S.pack, (const float*)S.tile, K, pp.r_cap, (const float4*)S.taps,
+                              pp.n_taps, W, H, 1.0f / pp.bg_ramp_px, out, fz);
+      else
+        hipLaunchKernelGGL(kern, dim3(TW * TH), dim3(256), 0, st, (const float4*)S.pack,
+                           (const float*)S.tile, K, pp.r_cap, (const float4*)S.taps, pp.n_taps, W, H,
+                           1.0f / pp.bg_ramp_px, out, fz);
     } else if (fuse) {
       fz = FuseK{fuse->spp, fuse->rt.c_near, fuse->rt.c_far, fuse->rt.hit_ratio, 1.0f / fuse->cp.h_t,
                  fuse->cp.rt_override, fuse->out, fuse->pps,

@@ -17,6 +17,8 @@
 // then a per-pixel reduction in fixed sample order (deterministic).
 #include "hdof_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace {
 
 struct Ray {
@@ -964,14 +966,24 @@ TraceArgs base_args(hdof_ctx* ctx, const hdof_scene* sc, const LightK& li, size_
 
 }  // namespace
 
+// done (nullable): an event the G-buffer's own dispatch completes (its
+// completion signal, with no marker packet between it and the next kernel
+// on st)
 hdof_status launch_gbuffer(hdof_ctx* ctx, const hdof_scene* sc, const CamK& k, const LensK& l,
-                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st, float4* pack, float* tile_r) {
+                           const LightK& li, hdof_gbuffer_bufs out, hipStream_t st, float4* pack, float* tile_r,
+                           hipEvent_t done) {
   int nb = cdiv(k.W, 16) * cdiv(k.H, 16);
   auto kern = ctx->count_on ? (pack ? k_gbuffer<true, true> : k_gbuffer<true, false>)
                             : (pack ? k_gbuffer<false, true> : k_gbuffer<false, false>);
-  hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
-                     (const float2*)sc->spec, sc->spec ? out.spec : nullptr, k, l, li, out.depth, out.normal,
-                     out.albedo, out.color, out.tri_id, ctx->d_flags, ctx->d_counters, pack, tile_r);
+  if (done)
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, nullptr, done, 0, sc->nodes, sc->tris, sc->n_nodes,
+                          sc->albedo, (const float2*)sc->spec, sc->spec ? out.spec : nullptr, k, l, li, out.depth,
+                          out.normal, out.albedo, out.color, out.tri_id, ctx->d_flags, ctx->d_counters, pack,
+                          tile_r);
+  else
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, sc->nodes, sc->tris, sc->n_nodes, sc->albedo,
+                       (const float2*)sc->spec, sc->spec ? out.spec : nullptr, k, l, li, out.depth, out.normal,
+                       out.albedo, out.color, out.tri_id, ctx->d_flags, ctx->d_counters, pack, tile_r);
   // a Lambertian scene has no specular part: its plane is 0
   if (!sc->spec && out.spec) hipLaunchKernelGGL(k_zero_f, dim3(cdiv(k.W * k.H, 256)), dim3(256), 0, st, out.spec,
                                                 k.W * k.H);

@@ -293,3 +293,32 @@ def test_frame_without_kept_planes(hd, ctx, overlap):
         assert torch.equal(outs[True][t], outs[False][t]), t
     hd.hdof_set_tuning(ctx)
     sc.close()
+
+
+def test_overlapped_frames_alternating_cameras(hd, ctx):
+    """1080p overlapped frames that alternate between two cameras, enqueued
+    back to back: the gather on the second stream must wait for its own
+    frame's G-buffer (a gather that started early would read the previous
+    frame's packed texels, another camera's) and the composite for its own
+    gather.  Each frame equals the single-stream frame of its camera bit
+    for bit."""
+    print_case("overlapped frames alternating cameras")
+    cfg = sg.config_1080p()
+    W, H = cfg.camera.width, cfg.camera.height
+    sc = upload_scene(hd, ctx, sg.living_room_scene(0))
+    params = hd.frame_params_of(cfg)
+    lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
+    cams = [hd.camera_of(cfg.camera), hd.camera_of(sg.temporal_camera(30, W, H))]
+    hd.hdof_set_tuning(ctx, overlap=0)
+    refs = [hd.hdof_frame(ctx, sc, c, None, lens, light, params, frame=0) for c in cams]
+    torch.cuda.synchronize()
+    assert not torch.equal(refs[0], refs[1])
+    hd.hdof_set_tuning(ctx)
+    outs = [torch.empty(3, H, W, device=DEV) for _ in range(6)]
+    for i, o in enumerate(outs):
+        hd.hdof_frame(ctx, sc, cams[i % 2], None, lens, light, params, frame=0, out=o)
+    torch.cuda.synchronize()
+    ctx.sync()
+    for i, o in enumerate(outs):
+        assert torch.equal(o, refs[i % 2]), i
+    sc.close()
