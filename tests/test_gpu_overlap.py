@@ -8,11 +8,12 @@ a HIP graph replays to the eager result; under capture a frame refuses a
 history and its replays leave the context's history unchanged."""
 import ctypes
 
+import numpy as np
 import pytest
 import torch
 
 import scenegen as sg
-from gpu_common import DEV, print_case, to_dev, upload_scene
+from gpu_common import DEV, history_numpy, print_case, to_dev, upload_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -277,7 +278,7 @@ def test_frame_without_kept_planes(hd, ctx, overlap):
     lens, light = hd.lens_of(cfg.lens), hd.light_of(cfg.light)
     cams = [hd.camera_of(sg.temporal_camera(t, W, H)) for t in range(3)]
     hd.hdof_set_tuning(ctx, overlap=overlap)
-    outs = {}
+    outs, hists = {}, {}
     for kept in (True, False):
         hd.hdof_history_reset(ctx)
         res = []
@@ -289,8 +290,11 @@ def test_frame_without_kept_planes(hd, ctx, overlap):
         torch.cuda.synchronize()
         ctx.sync()
         outs[kept] = res
+        hists[kept] = history_numpy(hd, ctx, H, W)
     for t in range(len(cams)):
         assert torch.equal(outs[True][t], outs[False][t]), t
+    for name in ("lum_m1", "lum_m2", "flags", "depth"):
+        assert np.array_equal(hists[True][name], hists[False][name]), name
     hd.hdof_set_tuning(ctx)
     sc.close()
 
